@@ -1,0 +1,168 @@
+"""Pins for the numpy partition reference (NeutronSparse Sec. 5.2.2, Sec. 6.1):
+hand-worked examples, the printed tie rules of Eq. 5, coverage, the
+reduction cases and an FP64 re-execution of the decomposition."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import plan_ref as pr
+from paper_2606_22482_amd import synth
+
+
+def csr_from_dense_pattern(P, vals=None):
+    m, k = P.shape
+    rows, cols = np.nonzero(P)
+    v = (np.arange(1, rows.size + 1, dtype=np.float32) if vals is None else vals)
+    return synth.csr_from_coo(m, k, rows, cols, v, "f32")
+
+
+def execute_plan_f64(plan, A, B, kind="bf16"):
+    """Re-execute the decomposition in FP64: tiles from bitmap + packed values,
+    remainder from its CSR entries."""
+    C = np.zeros((A.m, B.shape[1]))
+    Bd = B.astype(np.float64)
+    tv = (plan.tile_vals.astype(np.uint32) << 16).view(np.float32).astype(np.float64) \
+        if kind == "bf16" else plan.tile_vals.view(np.float16).astype(np.float64)
+    for t in range(plan.tile_window.size):
+        slots = plan.windows[plan.tile_window[t]]
+        q = plan.tile_val_ptr[t]
+        for s, r in enumerate(slots):
+            word = int(plan.tile_bitmap[t, s])
+            for j in range(plan.kt):
+                if word >> j & 1:
+                    assert r >= 0
+                    C[r] += tv[q] * Bd[plan.tile_cols[t, j]]
+                    q += 1
+        assert q == plan.tile_val_ptr[t + 1]
+    rows = np.repeat(np.arange(A.m), np.diff(A.rowptr))
+    for p in plan.rem_src:
+        C[rows[p]] += float(A.vals[p]) * Bd[A.colidx[p]]
+    return C
+
+
+def test_hand_example_one_dense_block():
+    # rows 0..15 hold the dense block of columns 0..31 plus one private column 40+r
+    P = np.zeros((32, 64), dtype=bool)
+    P[:16, :32] = True
+    for r in range(16):
+        P[r, 40 + r] = True
+    P[20, 3] = True   # a row outside the block, length 1
+    A = csr_from_dense_pattern(P)
+    plan = pr.build_plan(A.rowptr, A.colidx, A.vals, k=64, mode=pr.MODE_MIXED, window_h=16,
+                         t_row=1, alpha_c=1 / 16, alpha=0.5, row_order=pr.ORDER_COMPACTED)
+    # row stage: rows 0..15 (Len 33 > 1) pass; row 20 (Len 1 <= 1) stays vector
+    assert plan.windows.shape == (1, 16)
+    assert list(plan.windows[0]) == list(range(16))
+    # column stage: columns 0..31 counted 16 > floor(16/16) = 1; private columns counted 1
+    assert plan.tile_cols.shape == (1, 32)
+    assert list(plan.tile_cols[0]) == list(range(32))
+    assert np.all(plan.tile_bitmap == 0xFFFFFFFF)
+    # remainder: one private entry per block row, the whole of row 20
+    rem_rows = np.repeat(np.arange(32), np.diff(A.rowptr))[plan.rem_src]
+    assert sorted(rem_rows.tolist()) == list(range(16)) + [20]
+    assert set(A.colidx[plan.rem_src].tolist()) == set(range(40, 56)) | {3}
+    assert list(plan.vector_rows) == list(range(16, 32))
+    # packed values in row-major bit order: row r's 32 block values in column order
+    want = np.concatenate([A.vals[A.rowptr[r]:A.rowptr[r] + 32] for r in range(16)])
+    assert np.array_equal(plan.tile_vals, pr.f32_to_bf16_bits(want))
+
+
+def test_eq5_ties():
+    # Len == t_row -> vector (Len <= Thres); count == floor(alpha_c*H) -> vector;
+    # density == alpha -> matrix engine.
+    P = np.zeros((16, 32), dtype=bool)
+    P[:8, :4] = True          # rows 0..7: Len 4
+    P[8:12, :2] = True        # rows 8..11: Len 2 (tie with t_row = 2 -> vector)
+    A = csr_from_dense_pattern(P)
+    plan = pr.build_plan(A.rowptr, A.colidx, A.vals, k=32, mode=pr.MODE_MIXED, window_h=16,
+                         t_row=2, alpha_c=8 / 16 - 1 / 16, alpha=32 / (16 * 32),
+                         row_order=pr.ORDER_COMPACTED)
+    # window = rows 0..7; columns 0..3 have count 8 > floor(7/16*16) = 7
+    assert list(plan.windows[0][:8]) == list(range(8)) and np.all(plan.windows[0][8:] == -1)
+    assert list(plan.tile_cols[0][:4]) == [0, 1, 2, 3]
+    # tile nnz 32 == alpha * 16 * 32 -> kept
+    assert plan.tile_val_ptr[-1] == 32
+    # raise the column threshold to exactly the count: columns leave, window dissolves
+    plan2 = pr.build_plan(A.rowptr, A.colidx, A.vals, k=32, mode=pr.MODE_MIXED, window_h=16,
+                          t_row=2, alpha_c=8 / 16, alpha=0.0, row_order=pr.ORDER_COMPACTED)
+    assert plan2.windows.shape[0] == 0 and plan2.rem_src.size == A.nnz
+    # density just above the tile's: demoted
+    plan3 = pr.build_plan(A.rowptr, A.colidx, A.vals, k=32, mode=pr.MODE_MIXED, window_h=16,
+                          t_row=2, alpha_c=0.0, alpha=np.nextafter(np.float32(32 / 512),
+                                                                    np.float32(1)),
+                          row_order=pr.ORDER_COMPACTED)
+    assert plan3.tile_window.size == 0
+
+
+@pytest.mark.parametrize("order", [pr.ORDER_ORIGINAL_RANGES, pr.ORDER_COMPACTED,
+                                   pr.ORDER_LENGTH_SORTED])
+@pytest.mark.parametrize("H", [16, 32])
+def test_coverage_and_reexecution(order, H):
+    A = synth.random_csr(300, 200, 0.06, 3, int_values=(-2, 2), dup_frac=0.05, empty_rows=0.05)
+    B = synth.int_dense(1, (200, 6), -8, 8)
+    plan = pr.build_plan(A.rowptr, A.colidx, A.vals, k=200, mode=pr.MODE_MIXED, window_h=H,
+                         t_row=8, alpha_c=1 / H, alpha=0.02, row_order=order, seg=7)
+    assert np.all(pr.coverage(plan) == 1)
+    assert plan.tile_window.size > 0
+    ref = A  # integer values: every path is exact
+    dense = np.zeros((A.m, A.k))
+    np.add.at(dense, (np.repeat(np.arange(A.m), np.diff(A.rowptr)), A.colidx), A.vals)
+    assert np.array_equal(execute_plan_f64(plan, ref, B), dense @ B.astype(np.float64))
+    # every row is in exactly one kept window slot or in the vector rows
+    in_win = plan.windows[plan.windows >= 0]
+    assert np.unique(in_win).size == in_win.size
+    assert np.array_equal(np.sort(np.concatenate([in_win, plan.vector_rows])),
+                          np.arange(A.m))
+    # segments: ceil(remainder length / seg) for rows longer than seg
+    rem_len = np.diff(plan.rem_ptr)
+    assert np.array_equal(plan.nseg, np.where(rem_len > 7, -(-rem_len // 7), 0))
+
+
+def test_length_sorted_and_original_ranges_order():
+    A = synth.random_csr(100, 100, 0.05, 4)
+    lens = np.diff(A.rowptr)
+    plan = pr.build_plan(A.rowptr, A.colidx, A.vals, k=100, mode=pr.MODE_MIXED, window_h=16,
+                         t_row=-1, alpha_c=0.0, alpha=0.0, row_order=pr.ORDER_LENGTH_SORTED)
+    order = sorted(range(100), key=lambda r: (-lens[r], r))
+    got = [r for r in plan.windows.reshape(-1) if r >= 0]
+    assert got == order
+    plan = pr.build_plan(A.rowptr, A.colidx, A.vals, k=100, mode=pr.MODE_MIXED, window_h=16,
+                         t_row=2, alpha_c=0.0, alpha=0.0, row_order=pr.ORDER_ORIGINAL_RANGES)
+    for w, slots in enumerate(plan.windows):
+        for s, r in enumerate(slots):
+            assert r == -1 or r % 16 == s
+
+
+def test_reductions_plain_and_mfma_only():
+    A = synth.random_csr(200, 150, 0.05, 5, dup_frac=0.05)
+    # alpha > 1: no tile can be kept, so the partition is the plain one
+    p = pr.build_plan(A.rowptr, A.colidx, A.vals, k=150, mode=pr.MODE_MIXED, window_h=16,
+                      t_row=-1, alpha_c=0.0, alpha=1.5)
+    assert p.tile_window.size == 0 and np.array_equal(p.rem_src, np.arange(A.nnz))
+    assert np.array_equal(p.vector_rows, np.arange(A.m))
+    q = pr.build_plan(A.rowptr, A.colidx, A.vals, k=150, mode=pr.MODE_PLAIN)
+    assert np.array_equal(q.rem_src, p.rem_src) and np.array_equal(q.rem_ptr, p.rem_ptr)
+    # matrix engine only: every entry except repeated (row, col) pairs is in a tile
+    z = pr.build_plan(A.rowptr, A.colidx, A.vals, k=150, mode=pr.MODE_MFMA_ONLY, window_h=16)
+    rows = np.repeat(np.arange(A.m), np.diff(A.rowptr))
+    key = rows * 150 + A.colidx
+    _, first = np.unique(key, return_index=True)
+    assert z.tile_src.size == first.size
+    assert np.array_equal(np.sort(z.rem_src), np.setdiff1d(np.arange(A.nnz), first))
+
+
+def test_bf16_rounding_matches_torch():
+    rng = np.random.default_rng(0)
+    x = np.concatenate([
+        rng.standard_normal(100000).astype(np.float32),
+        (rng.integers(0, 2**32, 100000, dtype=np.uint64).astype(np.uint32)).view(np.float32),
+        np.array([0.0, -0.0, np.inf, -np.inf, 1.0 + 2**-8, 1.0 + 3 * 2**-8, 3.4e38],
+                 dtype=np.float32),
+    ])
+    x = x[~np.isnan(x)]
+    ours = pr.f32_to_bf16_bits(x)
+    ref = torch.from_numpy(x).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(ours, ref)
+    # NaN stays NaN
+    nan_bits = pr.f32_to_bf16_bits(np.array([np.nan], dtype=np.float32))[0]
+    assert (nan_bits & 0x7F80) == 0x7F80 and (nan_bits & 0x7F) != 0
