@@ -1,0 +1,233 @@
+/*
+ * spmm.h -- C ABI of the MI355X (gfx950) hybrid MFMA / vector SpMM library.
+ *
+ * The library computes C = A * B for a sparse A (M x K, CSR) and a dense B
+ * (K x N), the operation of NeutronSparse Sec. 5.1 ("SpMM"): C[i][j] is the
+ * sum over the stored entries p of row i of v_p * B[col_p][j].  Following the
+ * paper's workflow (Sec. 4, Fig. 7) the work is split in two stages:
+ *
+ *   spmm_plan  -- integer preprocessing on the host: the two-stage row/column
+ *                 extraction of Sec. 5.2.2 (Eq. 4-5) per row window (Sec. 6.1),
+ *                 column compaction, K-tiles kept for the matrix cores when
+ *                 their density reaches alpha (Sec. 5.2.1), bitmap packing of
+ *                 the kept tiles and index/value lists for the remainder, then
+ *                 a balanced list of work items (Sec. 7, row-window lists).
+ *                 The plan is uploaded to the device once.
+ *   spmm_run   -- one asynchronous execution on a HIP stream: MFMA over the
+ *                 kept tiles with B staged in LDS, FP32 gather-FMA for the
+ *                 remainder, one write of every C row.
+ *
+ * Conventions for every entry point:
+ *   - Return value is an spmm_status; no C++ exception crosses the ABI.  On
+ *     failure spmm_last_error() (thread-local) holds a message.
+ *   - "host" pointers point to CPU memory, "device" pointers to memory on the
+ *     current HIP device (e.g. torch tensors' data_ptr()).
+ *   - Streams are hipStream_t values passed as void* (NULL = the null stream).
+ *   - Dense matrices are row-major with a leading dimension in elements.
+ */
+#ifndef SPMM_H
+#define SPMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPMM_ABI_VERSION 1
+
+typedef int32_t spmm_status;
+#define SPMM_OK 0
+#define SPMM_ERR_INVALID 1     /* malformed CSR, null pointer, bad size or leading dimension */
+#define SPMM_ERR_OOM 2         /* host or device allocation failed */
+#define SPMM_ERR_DEVICE 3      /* a HIP call failed (message in spmm_last_error) */
+#define SPMM_ERR_UNSUPPORTED 4 /* dtype combination, option value or size not supported */
+#define SPMM_ERR_BUDGET 5      /* request exceeds a memory budget */
+#define SPMM_ERR_BUSY 6        /* object still referenced by unfinished work */
+
+/* element types */
+#define SPMM_F32 0
+#define SPMM_BF16 1
+#define SPMM_F16 2
+
+/* execution modes (Sec. 8.2 ablation: vector-only, matrix-only, coordinated) */
+#define SPMM_MODE_AUTO 0       /* use the tuned profile of this sparsity pattern, else MIXED defaults */
+#define SPMM_MODE_PLAIN_F32 1  /* every entry on the FP32 vector path */
+#define SPMM_MODE_MIXED 2      /* dense-enough tiles on MFMA, the rest on the vector path */
+#define SPMM_MODE_MFMA_ONLY 3  /* every row in a window, every column in a tile (alpha = 0) */
+
+/* how rows that pass the row stage are grouped into windows (Sec. 6.1) */
+#define SPMM_ORDER_AUTO 0
+#define SPMM_ORDER_ORIGINAL_RANGES 1 /* fixed ranges [wH, wH+H); rows failing the row stage leave holes */
+#define SPMM_ORDER_COMPACTED 2       /* passing rows in original order, cut into groups of H */
+#define SPMM_ORDER_LENGTH_SORTED 3   /* passing rows by length descending (ties: row id), groups of H */
+
+#define SPMM_AUTO_INT (-2147483647 - 1) /* "choose for me" for integer options that accept -1 */
+
+/* Sparse A in CSR.  Arrays are host memory and are only read during
+ * spmm_plan / spmm_plan_build; the caller may free them afterwards.
+ * rowptr: m+1 entries, rowptr[0] = 0, non-decreasing, rowptr[m] = nnz.
+ * colidx: nnz entries in [0, k); order within a row is free; duplicates add.
+ * vals:   nnz entries of type val_type; explicit zeros are ordinary entries. */
+typedef struct {
+    int64_t m, k, nnz;
+    const int64_t *rowptr;
+    const int32_t *colidx;
+    const void *vals;
+    int32_t val_type;
+    int32_t reserved;
+} spmm_csr;
+
+/* Planning options.  spmm_opts_default() fills every field with "auto". */
+typedef struct {
+    int32_t mode;      /* SPMM_MODE_* */
+    int32_t window_h;  /* H: 16, 32 or 64 rows per window; <= 0: auto */
+    int32_t t_row;     /* row stage: Len(row) <= t_row stays on the vector path (Eq. 5); SPMM_AUTO_INT: auto */
+    int32_t kt;        /* compacted columns per K-tile: 32; <= 0: auto */
+    int32_t n_panel;   /* columns of B/C per pass over A; <= 0: auto (whole N when it fits) */
+    int32_t row_order; /* SPMM_ORDER_* */
+    int32_t seg_len;   /* remainder entries per segment; longer rows are split; <= 0: auto */
+    int32_t item_cost; /* target work per vector work item, in entries; <= 0: auto */
+    int32_t xcd_remap; /* 1: consecutive items on one XCD, 0: dispatch order, < 0: auto */
+    int32_t reserved;
+    float alpha_c;     /* column stage: a window column is a tile column iff its count > floor(alpha_c*H); < 0: auto */
+    float alpha;       /* a K-tile is kept iff nnz / (H*kt) >= alpha (Sec. 5.2.1); < 0: auto */
+} spmm_opts;
+
+typedef struct spmm_plan_s spmm_plan_t;
+
+/* Summary of a plan (all counts are of the built plan). */
+typedef struct {
+    int64_t m, k, nnz, n;
+    int32_t val_type, b_type, c_type, tile_type;
+    spmm_opts opts;             /* options after resolving "auto" */
+    int64_t windows;            /* kept windows (each owns at least one tile) */
+    int64_t tiles;              /* kept K-tiles */
+    int64_t nnz_tiles;          /* entries placed in tiles */
+    int64_t nnz_remainder;      /* entries on the vector path */
+    int64_t vector_rows;        /* rows not covered by a window */
+    int64_t segments;           /* remainder segments computed as separate partial sums */
+    int64_t vector_items;       /* vector work items (one wavefront each) */
+    int64_t k_ref;              /* distinct columns referenced by A */
+    double mean_tile_density;   /* nnz_tiles / (tiles * H * kt) */
+    double zero_fraction_tiles; /* 1 - mean_tile_density: zeros computed by MFMA (Table 1 measure) */
+    int64_t device_bytes;       /* bytes of the uploaded plan */
+    int64_t workspace_bytes;    /* per-run scratch for segment partial sums */
+    double algorithmic_bytes;   /* 4(M+1) + nnz(4+s_A) + k_ref*N*s_B + M*N*s_C */
+    double flops;               /* 2 * nnz * N */
+    double plan_ms;             /* host time spent building the plan */
+    int32_t uploaded;           /* 1 after spmm_plan_upload */
+    int32_t reserved;
+} spmm_plan_stats_t;
+
+/* Host views of the plan's arrays (valid until spmm_plan_destroy).  Used by
+ * tests to check the partition against an independent reference. */
+typedef struct {
+    int64_t m, nnz;
+    int32_t window_h, kt;
+    int64_t n_windows;          /* windows: int32 [n_windows * H], original row per slot, -1 = empty */
+    const int32_t *windows;
+    int64_t n_tiles;
+    const int32_t *tile_window; /* int32 [n_tiles] */
+    const int32_t *tile_cols;   /* int32 [n_tiles * kt], -1 = padding */
+    const uint32_t *tile_bitmap;/* uint32 [n_tiles * H], bit j of word s <-> (slot s, column j), LSB first */
+    const int64_t *tile_val_ptr;/* int64 [n_tiles + 1] */
+    const uint16_t *tile_vals;  /* bf16 / f16 bit patterns, row-major over set bits */
+    const int64_t *tile_src;    /* CSR entry index of every packed value */
+    const int64_t *rem_ptr;     /* int64 [m + 1] */
+    const int64_t *rem_src;     /* CSR entry index of every remainder entry, CSR order per row */
+    int64_t n_vector_rows;
+    const int32_t *vector_rows; /* rows not in a window, ascending */
+    const int32_t *nseg;        /* int32 [m]: segments of the row's remainder (0: not split) */
+    int64_t n_vitems;
+    const int32_t *vitem_ptr;   /* int32 [n_vitems + 1]: item i covers vector_rows[ptr[i] .. ptr[i+1]) */
+    const int32_t *vitem_seg;   /* int32 [n_vitems]: first segment id used by the item */
+    int64_t n_segments;
+    const int32_t *seg_row;     /* int32 [n_segments]: row of each segment */
+    const int32_t *seg_begin;   /* int32 [n_segments]: first remainder index (into rem arrays) */
+    const int32_t *seg_end;     /* int32 [n_segments] */
+    const int32_t *win_seg;     /* int32 [n_windows]: first segment id used by the window */
+    const int32_t *win_order;   /* int32 [n_windows]: execution order of windows (heaviest first) */
+} spmm_plan_dump_t;
+
+/* One matrix of a batched submission (device pointers). */
+typedef struct {
+    const spmm_plan_t *plan;
+    const void *B;
+    int64_t ldb;
+    void *C;
+    int64_t ldc;
+} spmm_work;
+
+typedef uint64_t spmm_ticket;
+typedef struct spmm_timer_s spmm_timer_t;
+
+int32_t spmm_abi_version(void);
+/* sizeof of the ABI structs, for bindings to check their mirrors:
+ * 0 spmm_csr, 1 spmm_opts, 2 spmm_plan_stats_t, 3 spmm_plan_dump_t, 4 spmm_work;
+ * -1 for any other value. */
+int64_t spmm_sizeof(int32_t which);
+const char *spmm_status_string(spmm_status s);
+/* Message of the last failure on the calling thread ("" if none). */
+const char *spmm_last_error(void);
+void spmm_opts_default(spmm_opts *o);
+
+/* Build a plan on the host only (no device call).  Errors: INVALID for a
+ * malformed CSR or n < 1; UNSUPPORTED for nnz, m or k >= 2^31, a dtype
+ * combination other than (vals, B) = (f32, f32), (f32, bf16), (bf16, bf16),
+ * (f16, f16), c_type other than f32, or an option outside its range.
+ * *out is owned by the caller and released with spmm_plan_destroy. */
+spmm_status spmm_plan_build(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
+                            const spmm_opts *opts, spmm_plan_t **out);
+/* Copy a host-built plan to the current device (one allocation, one copy). */
+spmm_status spmm_plan_upload(spmm_plan_t *p);
+/* spmm_plan_build followed by spmm_plan_upload. */
+spmm_status spmm_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
+                      const spmm_opts *opts, spmm_plan_t **out);
+/* Release a plan.  BUSY while batched submissions that use it are unfinished. */
+spmm_status spmm_plan_destroy(spmm_plan_t *p);
+spmm_status spmm_plan_stats(const spmm_plan_t *p, spmm_plan_stats_t *out);
+spmm_status spmm_plan_export(const spmm_plan_t *p, spmm_plan_dump_t *out);
+
+/* C = A * B on `stream`, asynchronously.  B: device, K x N of the plan's
+ * b_type with row stride ldb >= N; C: device f32, M x N with ldc >= N, fully
+ * overwritten (no scaling, no accumulation).  B and C must not overlap.  A
+ * plan may be used by concurrent runs on different streams; scratch space is
+ * per stream.  Errors: INVALID (null plan/pointer, ld < N), UNSUPPORTED (plan
+ * not uploaded), DEVICE. */
+spmm_status spmm_run(const spmm_plan_t *p, const void *B, int64_t ldb, void *C, int64_t ldc,
+                     void *stream);
+
+/* Kernel timing: spmm_run_timed records a HIP event pair around every kernel
+ * it launches (on `stream`) into the timer; spmm_timer_read waits for them
+ * and returns the launches' kernel ids and durations in milliseconds. */
+#define SPMM_KERNEL_SEGMENT 0 /* partial sums of long remainder rows */
+#define SPMM_KERNEL_VECTOR 1  /* FP32 gather-FMA over vector rows */
+#define SPMM_KERNEL_WINDOW 2  /* MFMA windows + their rows' remainders */
+spmm_status spmm_timer_create(int32_t capacity, spmm_timer_t **out);
+spmm_status spmm_timer_reset(spmm_timer_t *t);
+spmm_status spmm_timer_read(spmm_timer_t *t, int32_t *kernel_ids, float *ms, int32_t cap,
+                            int32_t *count);
+spmm_status spmm_timer_destroy(spmm_timer_t *t);
+spmm_status spmm_run_timed(const spmm_plan_t *p, const void *B, int64_t ldb, void *C,
+                           int64_t ldc, void *stream, spmm_timer_t *t);
+
+/* Batched execution: the work of `count` matrices in one launch sequence on
+ * `stream` (plans must share val_type and b_type).  *out receives a ticket
+ * for spmm_poll / spmm_wait. */
+spmm_status spmm_submit(const spmm_work *items, int32_t count, void *stream, spmm_ticket *out);
+spmm_status spmm_poll(spmm_ticket t, int32_t *done);
+spmm_status spmm_wait(spmm_ticket t);
+
+/* Dry-run microbenchmarks of the cost model (Sec. 5.2.1, Eq. 1): measured
+ * vector-path throughput (entries*N per second) and MFMA-tile throughput
+ * (tile slots*N per second) for this N and B type on the current device. */
+spmm_status spmm_dryrun(int32_t n, int32_t b_type, void *stream, double *p_vec, double *p_mfma);
+/* Device copy bandwidth (read + write bytes per second) over `bytes` bytes. */
+spmm_status spmm_copy_bandwidth(int64_t bytes, void *stream, double *bytes_per_s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPMM_H */

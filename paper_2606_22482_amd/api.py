@@ -1,0 +1,254 @@
+"""Thin Python binding over the C ABI (``include/spmm.h``).
+
+Same names as the ABI.  Host arrays are numpy; device buffers are torch
+tensors, used only as memory and streams.  Every step of the computation runs
+in ``libspmm.so``; nothing here computes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib as L
+
+__all__ = ["Plan", "Timer", "spmm_plan", "spmm_run", "spmm_submit", "spmm_poll", "spmm_wait",
+           "spmm_dryrun", "spmm_copy_bandwidth", "default_opts", "SpmmError"]
+
+SpmmError = L.SpmmError
+
+
+def default_opts(**kw) -> L.Opts:
+    """spmm_opts_default() with fields overridden by keyword (names as in the
+    C struct; ``mode``/``row_order`` also accept the names without prefix)."""
+    lib = L.load()
+    o = L.Opts()
+    lib.spmm_opts_default(C.byref(o))
+    modes = {"auto": L.MODE_AUTO, "plain": L.MODE_PLAIN_F32, "plain_f32": L.MODE_PLAIN_F32,
+             "mixed": L.MODE_MIXED, "mfma_only": L.MODE_MFMA_ONLY}
+    orders = {"auto": L.ORDER_AUTO, "original_ranges": L.ORDER_ORIGINAL_RANGES,
+              "compacted": L.ORDER_COMPACTED, "length_sorted": L.ORDER_LENGTH_SORTED}
+    for k, v in kw.items():
+        if k == "mode" and isinstance(v, str):
+            v = modes[v]
+        if k == "row_order" and isinstance(v, str):
+            v = orders[v]
+        setattr(o, k, v)
+    return o
+
+
+def device_tensor(x: np.ndarray, kind: str):
+    """Copy a host array (float32, or uint16 bit patterns for "bf16"/"f16")
+    to a device tensor of the matching torch dtype."""
+    import torch
+    if kind == "f32":
+        t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32))
+    else:
+        t = torch.from_numpy(np.ascontiguousarray(x).view(np.int16))
+        t = t.view(torch.bfloat16 if kind == "bf16" else torch.float16)
+    return t.cuda()
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _kind_of_tensor(t):
+    import torch
+    return {torch.float32: "f32", torch.bfloat16: "bf16", torch.float16: "f16"}[t.dtype]
+
+
+def _dev2d(t, what):
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("%s must be a 2-D tensor with unit column stride" % what)
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % what)
+    return t.data_ptr(), t.stride(0)
+
+
+class Plan:
+    """A plan built by ``spmm_plan`` (or ``spmm_plan_build`` when
+    ``upload=False``).  ``A`` needs ``m, k, rowptr, colidx, vals, val_kind``."""
+
+    def __init__(self, A, n: int, b_kind: str, opts: L.Opts | None = None, upload=True):
+        lib = L.load()
+        self._lib = lib
+        rowptr = np.ascontiguousarray(A.rowptr, dtype=np.int64)
+        colidx = np.ascontiguousarray(A.colidx, dtype=np.int32)
+        vals = np.ascontiguousarray(A.vals)
+        self._keep = (rowptr, colidx, vals)
+        csr = L.Csr(int(A.m), int(A.k), int(rowptr[-1]) if rowptr.size else 0,
+                    rowptr.ctypes.data, colidx.ctypes.data, vals.ctypes.data,
+                    L.KIND_CODE[A.val_kind], 0)
+        self.n = int(n)
+        self.m = int(A.m)
+        self.k = int(A.k)
+        self.b_kind = b_kind
+        h = C.c_void_p()
+        fn = lib.spmm_plan if upload else lib.spmm_plan_build
+        L.check(fn(C.byref(csr), self.n, L.KIND_CODE[b_kind], L.F32,
+                   C.byref(opts) if opts is not None else None, C.byref(h)))
+        self._h = h
+        self._keep = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def upload(self):
+        L.check(self._lib.spmm_plan_upload(self._h))
+
+    def stats(self) -> dict:
+        s = L.PlanStats()
+        L.check(self._lib.spmm_plan_stats(self._h, C.byref(s)))
+        out = {f: getattr(s, f) for f, _ in L.PlanStats._fields_ if f not in ("opts", "reserved")}
+        out["opts"] = {f: getattr(s.opts, f) for f, _ in L.Opts._fields_ if f != "reserved"}
+        return out
+
+    def export(self) -> dict:
+        """Copies of the plan's host arrays (see spmm_plan_dump_t)."""
+        d = L.PlanDump()
+        L.check(self._lib.spmm_plan_export(self._h, C.byref(d)))
+
+        def arr(ptr, n, dt):
+            if n == 0 or not ptr:
+                return np.zeros(0, dtype=dt)
+            buf = (C.c_char * (n * np.dtype(dt).itemsize)).from_address(ptr)
+            return np.frombuffer(buf, dtype=dt).copy()
+
+        H, kt, W, T = d.window_h, d.kt, d.n_windows, d.n_tiles
+        tvp = arr(d.tile_val_ptr, T + 1, np.int64)
+        rp = arr(d.rem_ptr, d.m + 1, np.int64)
+        nv = d.n_vitems
+        return {
+            "window_h": H, "kt": kt,
+            "windows": arr(d.windows, W * H, np.int32).reshape(W, H),
+            "tile_window": arr(d.tile_window, T, np.int32),
+            "tile_cols": arr(d.tile_cols, T * kt, np.int32).reshape(T, kt),
+            "tile_bitmap": arr(d.tile_bitmap, T * H, np.uint32).reshape(T, H),
+            "tile_val_ptr": tvp,
+            "tile_vals": arr(d.tile_vals, int(tvp[-1]), np.uint16),
+            "tile_src": arr(d.tile_src, int(tvp[-1]), np.int64),
+            "rem_ptr": rp,
+            "rem_src": arr(d.rem_src, int(rp[-1]), np.int64),
+            "vector_rows": arr(d.vector_rows, d.n_vector_rows, np.int32),
+            "nseg": arr(d.nseg, d.m, np.int32),
+            "vitem_ptr": arr(d.vitem_ptr, nv + 1, np.int32),
+            "vitem_seg": arr(d.vitem_seg, nv, np.int32),
+            "seg_row": arr(d.seg_row, d.n_segments, np.int32),
+            "seg_begin": arr(d.seg_begin, d.n_segments, np.int32),
+            "seg_end": arr(d.seg_end, d.n_segments, np.int32),
+            "win_seg": arr(d.win_seg, W, np.int32),
+            "win_order": arr(d.win_order, W, np.int32),
+        }
+
+    def run(self, B, Cout, stream=None):
+        """spmm_run: Cout = A @ B on the stream (torch's current one by default)."""
+        bp, ldb = _dev2d(B, "B")
+        cp, ldc = _dev2d(Cout, "C")
+        L.check(self._lib.spmm_run(self._h, bp, ldb, cp, ldc, _stream_handle(stream)))
+
+    def run_timed(self, B, Cout, timer: "Timer", stream=None):
+        bp, ldb = _dev2d(B, "B")
+        cp, ldc = _dev2d(Cout, "C")
+        L.check(self._lib.spmm_run_timed(self._h, bp, ldb, cp, ldc, _stream_handle(stream),
+                                         timer.handle))
+
+    def destroy(self):
+        if self._h:
+            L.check(self._lib.spmm_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                self._lib.spmm_plan_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+def spmm_plan(A, n, b_kind, opts=None, upload=True) -> Plan:
+    return Plan(A, n, b_kind, opts, upload)
+
+
+def spmm_run(plan: Plan, B, Cout, stream=None):
+    plan.run(B, Cout, stream)
+
+
+class Timer:
+    """spmm_timer_*: per-kernel HIP event pairs recorded by run_timed."""
+
+    def __init__(self, capacity=4096):
+        self._lib = L.load()
+        h = C.c_void_p()
+        L.check(self._lib.spmm_timer_create(int(capacity), C.byref(h)))
+        self.handle = h
+        self.capacity = int(capacity)
+
+    def reset(self):
+        L.check(self._lib.spmm_timer_reset(self.handle))
+
+    def read(self):
+        ids = (C.c_int32 * self.capacity)()
+        ms = (C.c_float * self.capacity)()
+        n = C.c_int32()
+        L.check(self._lib.spmm_timer_read(self.handle, ids, ms, self.capacity, C.byref(n)))
+        return [(L.KERNEL_NAMES[ids[i]], ms[i]) for i in range(n.value)]
+
+    def __del__(self):
+        try:
+            self._lib.spmm_timer_destroy(self.handle)
+        except Exception:
+            pass
+
+
+@dataclass
+class WorkItem:
+    plan: Plan
+    B: object
+    C: object
+
+
+def spmm_submit(items, stream=None) -> int:
+    lib = L.load()
+    arr = (L.Work * max(1, len(items)))()
+    for i, it in enumerate(items):
+        bp, ldb = _dev2d(it.B, "B")
+        cp, ldc = _dev2d(it.C, "C")
+        arr[i] = L.Work(it.plan.handle.value, bp, ldb, cp, ldc)
+    t = C.c_uint64()
+    L.check(lib.spmm_submit(arr, len(items), _stream_handle(stream), C.byref(t)))
+    return t.value
+
+
+def spmm_poll(ticket: int) -> bool:
+    lib = L.load()
+    d = C.c_int32()
+    L.check(lib.spmm_poll(C.c_uint64(ticket), C.byref(d)))
+    return bool(d.value)
+
+
+def spmm_wait(ticket: int):
+    L.check(L.load().spmm_wait(C.c_uint64(ticket)))
+
+
+def spmm_dryrun(n: int, b_kind: str, stream=None):
+    lib = L.load()
+    pv, pm = C.c_double(), C.c_double()
+    L.check(lib.spmm_dryrun(int(n), L.KIND_CODE[b_kind], _stream_handle(stream), C.byref(pv),
+                            C.byref(pm)))
+    return pv.value, pm.value
+
+
+def spmm_copy_bandwidth(nbytes: int, stream=None) -> float:
+    lib = L.load()
+    out = C.c_double()
+    L.check(lib.spmm_copy_bandwidth(int(nbytes), _stream_handle(stream), C.byref(out)))
+    return out.value

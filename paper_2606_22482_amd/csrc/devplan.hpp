@@ -1,0 +1,63 @@
+// devplan.hpp -- the uploaded plan as seen by the kernels, and kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace spmm {
+
+// Pointers into one device allocation (see runtime.hip for the layout).
+struct DevPlan {
+    int32_t m, n;              // rows of A / C, columns of B / C
+    int32_t seg_len;           // remainder entries per segment (longer rows are split)
+    int32_t H, kt;             // window height, K-tile width (32)
+    int32_t n_vitems, n_seg, n_win;
+    const int32_t *rem_ptr;    // [m+1]
+    const int32_t *rem_col;    // [nnz_rem]
+    const void *rem_val;       // [nnz_rem] of the value type
+    const int32_t *vec_rows;   // [n_vector_rows] or null when every row is a vector row
+    const int32_t *vitem_ptr;  // [n_vitems+1]
+    const int32_t *vitem_seg;  // [n_vitems]
+    const int32_t *seg_begin;  // [n_seg]
+    const int32_t *seg_end;    // [n_seg]
+    const int32_t *windows;    // [n_win*H]
+    const int32_t *win_tile_ptr;  // [n_win+1]
+    const int32_t *win_seg;    // [n_win]
+    const int32_t *win_order;  // [n_win]
+    const int32_t *tile_cols;  // [T*kt]
+    const uint32_t *tile_bitmap;  // [T*H]
+    const int32_t *tile_val_ptr;  // [T+1]
+    const uint16_t *tile_vals;
+};
+
+// Launch geometry and operand description of one execution.
+struct RunArgs {
+    const void *B;
+    int64_t ldb;
+    float *C;
+    int64_t ldc;
+    float *work;        // segment partial sums, [n_seg * work_ld]
+    int32_t work_ld;    // row stride of `work` (N rounded up to 4)
+    int32_t vec_ok;     // 16-byte chunks usable for B and C
+    int32_t np;         // columns per panel of the vector / segment kernels
+    int32_t n_panels;
+    int32_t lpr_log2;   // log2(lanes per entry group) for the vector / segment kernels
+    int32_t xcd;        // remap consecutive items onto one XCD
+    int32_t win_panels; // panels of the window kernel (128 columns each)
+    int32_t win_lpr_log2;
+};
+
+// dtype codes as in spmm.h
+hipError_t launch_segment(const DevPlan &P, int32_t val_t, int32_t b_t, const RunArgs &a,
+                          hipStream_t s);
+hipError_t launch_vector(const DevPlan &P, int32_t val_t, int32_t b_t, const RunArgs &a,
+                         hipStream_t s);
+hipError_t launch_window(const DevPlan &P, int32_t val_t, int32_t b_t, int32_t tile_t,
+                         const RunArgs &a, hipStream_t s);
+hipError_t launch_copy(const float4 *src, float4 *dst, int64_t n4, hipStream_t s);
+
+// chunk width (elements per 16-byte load) of a B type
+inline int chunk_elems(int32_t b_t) { return b_t == 0 ? 4 : 8; }
+
+}  // namespace spmm

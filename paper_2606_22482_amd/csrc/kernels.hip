@@ -1,0 +1,584 @@
+// kernels.hip -- gfx950 kernels of the hybrid SpMM.
+//
+// Three kernels execute a plan (NeutronSparse Sec. 5.1 execution models,
+// adapted to CDNA4 where the matrix cores and the vector ALUs share a CU):
+//
+//   segment  -- one wavefront per segment of a long remainder row: FP32
+//               gather-FMA partial sum into a per-run workspace.
+//   vector   -- one wavefront per vector work item (consecutive rows): FP32
+//               gather-FMA over each row's remainder (Sec. 5.1, gather then
+//               accumulate), or the fixed-order sum of its segment partials,
+//               then one write of the C row.
+//   window   -- one workgroup per (row window, 128-column panel): the B rows
+//               of the window's compacted tile columns are staged in LDS once
+//               and reused by every row of the window (Sec. 6.2, intra-core
+//               reuse; Sec. 5.1, matrix-engine execution), the tile bitmap is
+//               expanded into MFMA operands (bf16 / f16 in, f32 accumulate),
+//               then each row adds its remainder and is written once.
+//
+// Summation order of a remainder segment (identical in every kernel that
+// computes one, so a row's bits depend only on the plan and N, never on the
+// schedule): the wavefront is split into G groups of LPR lanes; entry i of the
+// segment is accumulated by group i mod G with fmaf, in increasing i; the
+// groups are then combined by an xor butterfly.  Segments of a split row are
+// added in segment order.  No floating-point atomics are used anywhere.
+#include "devplan.hpp"
+
+namespace spmm {
+
+enum { DT_F32 = 0, DT_BF16 = 1, DT_F16 = 2 };
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf16_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
+__device__ __forceinline__ float f16_to_f32(uint32_t h) {
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)h);
+}
+
+// float -> bf16 bits, round to nearest even; NaN stays a quiet NaN.
+__device__ __forceinline__ uint32_t f32_to_bf16_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (u >> 16) | 0x40u;
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+template <int DT>
+__device__ __forceinline__ float load_val(const void *base, int idx) {
+    if constexpr (DT == DT_F32) {
+        return __builtin_nontemporal_load(static_cast<const float *>(base) + idx);
+    } else {
+        uint32_t b = __builtin_nontemporal_load(static_cast<const unsigned short *>(base) + idx);
+        return DT == DT_BF16 ? bf16_to_f32(b) : f16_to_f32(b);
+    }
+}
+
+// E consecutive elements of B (as float) starting at element offset `off`.
+template <int BT, int E>
+__device__ __forceinline__ void load_chunk(const void *B, int64_t off, float (&v)[E]) {
+    if constexpr (E == 1) {
+        if constexpr (BT == DT_F32)
+            v[0] = static_cast<const float *>(B)[off];
+        else if constexpr (BT == DT_BF16)
+            v[0] = bf16_to_f32(static_cast<const unsigned short *>(B)[off]);
+        else
+            v[0] = f16_to_f32(static_cast<const unsigned short *>(B)[off]);
+    } else if constexpr (BT == DT_F32) {
+        static_assert(E == 4, "f32 chunks are 4 wide");
+        f32x4 x = *reinterpret_cast<const f32x4 *>(static_cast<const float *>(B) + off);
+        v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
+    } else {
+        static_assert(E == 8, "16-bit chunks are 8 wide");
+        u32x4 x = *reinterpret_cast<const u32x4 *>(static_cast<const unsigned short *>(B) + off);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if constexpr (BT == DT_BF16) {
+                v[2 * i] = __uint_as_float(x[i] << 16);
+                v[2 * i + 1] = __uint_as_float(x[i] & 0xFFFF0000u);
+            } else {
+                v[2 * i] = f16_to_f32(x[i] & 0xFFFFu);
+                v[2 * i + 1] = f16_to_f32(x[i] >> 16);
+            }
+        }
+    }
+}
+
+template <int E>
+__device__ __forceinline__ void store_chunk(float *C, int64_t off, const float (&v)[E]) {
+    if constexpr (E == 1) {
+        __builtin_nontemporal_store(v[0], C + off);
+    } else {
+#pragma unroll
+        for (int i = 0; i < E; i += 4) {
+            f32x4 x = {v[i], v[i + 1], v[i + 2], v[i + 3]};
+            __builtin_nontemporal_store(x, reinterpret_cast<f32x4 *>(C + off + i));
+        }
+    }
+}
+
+template <int E>
+__device__ __forceinline__ void load_f32_chunk(const float *W, int64_t off, float (&v)[E]) {
+    if constexpr (E == 1) {
+        v[0] = W[off];
+    } else {
+#pragma unroll
+        for (int i = 0; i < E; i += 4) {
+            f32x4 x = *reinterpret_cast<const f32x4 *>(W + off + i);
+            v[i] = x[0]; v[i + 1] = x[1]; v[i + 2] = x[2]; v[i + 3] = x[3];
+        }
+    }
+}
+
+// Workgroup id after the optional XCD remap: workgroups are dispatched
+// round-robin over the 8 XCDs, so id b runs on XCD b % 8.  The remap gives
+// each XCD one contiguous range of logical ids, so neighbouring items (which
+// tend to share rows of B) share that XCD's L2.
+__device__ __forceinline__ int logical_block(int xcd) {
+    const int b = blockIdx.x;
+    if (!xcd) return b;
+    const int nwg = gridDim.x, full = nwg >> 3, rem = nwg & 7, x = b & 7, local = b >> 3;
+    return (x < rem ? x * (full + 1) : rem * (full + 1) + (x - rem) * full) + local;
+}
+
+// Lane layout of the gather-FMA: lane = group * LPR + li; lane li of a group
+// owns chunks q = c * LPR + li (c < CPL), i.e. columns q*E .. q*E+E-1 of the
+// panel.
+struct Lanes {
+    int lpr_log2, lpr, groups, group, li;
+    __device__ __forceinline__ explicit Lanes(int lg) {
+        const int lane = threadIdx.x & 63;
+        lpr_log2 = lg;
+        lpr = 1 << lg;
+        groups = 64 >> lg;
+        group = lane >> lg;
+        li = lane & (lpr - 1);
+    }
+};
+
+// acc += sum over entries [p0, p1) of v_p * B[col_p][panel columns], entry
+// p0 + i taken by group i % G in increasing i (see the file comment).
+template <int VT, int BT, int E, int CPL, int U>
+__device__ __forceinline__ void seg_accumulate(const int32_t *__restrict__ rcol,
+                                               const void *__restrict__ rval, int p0, int p1,
+                                               const void *__restrict__ B, int64_t ldb,
+                                               int ncol0, int ncols, const Lanes &L,
+                                               float (&acc)[CPL][E]) {
+    bool cok[CPL];
+    int64_t coff[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const int q = c * L.lpr + L.li;
+        cok[c] = q * E < ncols;
+        coff[c] = ncol0 + (int64_t)q * E;
+    }
+    const int step = L.groups * U;
+    for (int p = p0 + L.group; p < p1; p += step) {
+        int col[U];
+        float v[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int pp = p + u * L.groups;
+            ok[u] = pp < p1;
+            col[u] = ok[u] ? __builtin_nontemporal_load(rcol + pp) : 0;
+            v[u] = ok[u] ? load_val<VT>(rval, pp) : 0.0f;
+        }
+        float b[U][CPL][E];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                if (ok[u] && cok[c]) {
+                    load_chunk<BT, E>(B, (int64_t)col[u] * ldb + coff[c], b[u][c]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < E; ++e) b[u][c][e] = 0.0f;
+                }
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (ok[u]) {
+#pragma unroll
+                for (int c = 0; c < CPL; ++c)
+#pragma unroll
+                    for (int e = 0; e < E; ++e) acc[c][e] = __builtin_fmaf(v[u], b[u][c][e], acc[c][e]);
+            }
+        }
+    }
+}
+
+template <int E, int CPL>
+__device__ __forceinline__ void group_reduce(float (&acc)[CPL][E], const Lanes &L) {
+    for (int off = 32; off >= L.lpr; off >>= 1) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c)
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[c][e] += __shfl_xor(acc[c][e], off, 64);
+    }
+}
+
+// acc = P[sid] + P[sid+1] + ... + P[sid+ns-1] (panel columns), in that order.
+template <int E, int CPL>
+__device__ __forceinline__ void sum_partials(const float *__restrict__ work, int64_t ld, int sid,
+                                             int ns, int ncol0, int ncols, const Lanes &L,
+                                             float (&acc)[CPL][E]) {
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const int q = c * L.lpr + L.li;
+        if (q * E >= ncols) continue;
+        const int64_t off = ncol0 + (int64_t)q * E;
+        load_f32_chunk<E>(work, (int64_t)sid * ld + off, acc[c]);
+        for (int j = 1; j < ns; ++j) {
+            float t[E];
+            load_f32_chunk<E>(work, (int64_t)(sid + j) * ld + off, t);
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[c][e] += t[e];
+        }
+    }
+}
+
+template <int E, int CPL>
+__device__ __forceinline__ void store_row(float *C, int64_t row_off, int ncol0, int ncols,
+                                          const Lanes &L, const float (&acc)[CPL][E]) {
+    if (L.group != 0) return;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const int q = c * L.lpr + L.li;
+        if (q * E < ncols) store_chunk<E>(C, row_off + ncol0 + (int64_t)q * E, acc[c]);
+    }
+}
+
+template <int E, int CPL>
+constexpr int unroll_of() { return E == 1 ? 4 : (CPL == 1 ? 8 : 4); }
+
+// ------------------------------------------------------------------------------------------
+template <int VT, int BT, int E, int CPL>
+__global__ __launch_bounds__(256) void segment_kernel(DevPlan P, RunArgs a) {
+    const int wid = logical_block(a.xcd) * 4 + (threadIdx.x >> 6);
+    if (wid >= P.n_seg * a.n_panels) return;
+    const int panel = wid / P.n_seg, sid = wid - panel * P.n_seg;
+    const int ncol0 = panel * a.np, ncols = min(a.np, P.n - ncol0);
+    const Lanes L(a.lpr_log2);
+    float acc[CPL][E];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c)
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[c][e] = 0.0f;
+    seg_accumulate<VT, BT, E, CPL, unroll_of<E, CPL>()>(P.rem_col, P.rem_val, P.seg_begin[sid],
+                                                        P.seg_end[sid], a.B, a.ldb, ncol0, ncols,
+                                                        L, acc);
+    group_reduce<E, CPL>(acc, L);
+    if (L.group != 0) return;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const int q = c * L.lpr + L.li;
+        if (q * E < ncols) {
+            float *dst = a.work + (int64_t)sid * a.work_ld + ncol0 + (int64_t)q * E;
+            if constexpr (E == 1) {
+                dst[0] = acc[c][0];
+            } else {
+#pragma unroll
+                for (int i = 0; i < E; i += 4)
+                    *reinterpret_cast<f32x4 *>(dst + i) =
+                        f32x4{acc[c][i], acc[c][i + 1], acc[c][i + 2], acc[c][i + 3]};
+            }
+        }
+    }
+}
+
+template <int VT, int BT, int E, int CPL>
+__global__ __launch_bounds__(256) void vector_kernel(DevPlan P, RunArgs a) {
+    const int wid = logical_block(a.xcd) * 4 + (threadIdx.x >> 6);
+    if (wid >= P.n_vitems * a.n_panels) return;
+    const int panel = wid / P.n_vitems, item = wid - panel * P.n_vitems;
+    const int ncol0 = panel * a.np, ncols = min(a.np, P.n - ncol0);
+    const Lanes L(a.lpr_log2);
+    int sid = P.vitem_seg[item];
+    const int i0 = P.vitem_ptr[item], i1 = P.vitem_ptr[item + 1];
+    for (int i = i0; i < i1; ++i) {
+        const int r = P.vec_rows ? P.vec_rows[i] : i;
+        const int b = P.rem_ptr[r], e = P.rem_ptr[r + 1];
+        float acc[CPL][E];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c)
+#pragma unroll
+            for (int x = 0; x < E; ++x) acc[c][x] = 0.0f;
+        if (e - b <= P.seg_len) {
+            seg_accumulate<VT, BT, E, CPL, unroll_of<E, CPL>()>(P.rem_col, P.rem_val, b, e, a.B,
+                                                                a.ldb, ncol0, ncols, L, acc);
+            group_reduce<E, CPL>(acc, L);
+        } else {
+            const int ns = (e - b + P.seg_len - 1) / P.seg_len;
+            sum_partials<E, CPL>(a.work, a.work_ld, sid, ns, ncol0, ncols, L, acc);
+            sid += ns;
+        }
+        store_row<E, CPL>(a.C, (int64_t)r * a.ldc, ncol0, ncols, L, acc);
+    }
+}
+
+// Inclusive prefix sum over the 64 lanes of a wavefront.
+__device__ __forceinline__ int wave_inclusive_scan(int x) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int t = __shfl_up(x, d, 64);
+        if (lane >= d) x += t;
+    }
+    return x;
+}
+
+template <int TT>
+__device__ __forceinline__ f32x4 mfma_16x16x32(const u16x8 &a, const u16x8 &b, const f32x4 &c) {
+    if constexpr (TT == DT_BF16)
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                       __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
+                                                      __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+}
+
+// 8 consecutive B elements (columns n .. n+7 of B row `col`) as TT bit patterns.
+template <int BT, int TT>
+__device__ __forceinline__ void stage_b8(const void *B, int64_t off, int valid, int vec,
+                                         uint32_t (&w)[4]) {
+    uint32_t h[8];
+    if constexpr (BT == DT_F32) {
+        float f[8];
+        if (vec && valid == 8) {
+            f32x4 x0 = *reinterpret_cast<const f32x4 *>(static_cast<const float *>(B) + off);
+            f32x4 x1 = *reinterpret_cast<const f32x4 *>(static_cast<const float *>(B) + off + 4);
+            f[0] = x0[0]; f[1] = x0[1]; f[2] = x0[2]; f[3] = x0[3];
+            f[4] = x1[0]; f[5] = x1[1]; f[6] = x1[2]; f[7] = x1[3];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) f[i] = i < valid ? static_cast<const float *>(B)[off + i] : 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) h[i] = f32_to_bf16_bits(f[i]);
+    } else {
+        const unsigned short *p = static_cast<const unsigned short *>(B) + off;
+        if (vec && valid == 8) {
+            u32x4 x = *reinterpret_cast<const u32x4 *>(p);
+            w[0] = x[0]; w[1] = x[1]; w[2] = x[2]; w[3] = x[3];
+            return;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) h[i] = i < valid ? p[i] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = h[2 * i] | (h[2 * i + 1] << 16);
+}
+
+template <int VT, int BT, int TT, int MB, int E, int CPL>
+__global__ __launch_bounds__(256) void window_kernel(DevPlan P, RunArgs a) {
+    constexpr int H = MB * 16;
+    constexpr int NPW = 128;        // panel columns of a window item
+    constexpr int TC = 4;           // tiles staged per round
+    constexpr int KROWS = TC * 32;  // B rows staged per round
+    constexpr int BSTR = NPW + 2;   // LDS row stride (16-bit elements); odd dword stride
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[KROWS * BSTR];
+    __shared__ int32_t s_rows[H], s_sid[H], s_cols[KROWS], s_off[TC * H];
+    __shared__ uint32_t s_bm[TC * H];
+    static_assert(H * NPW * 4 <= KROWS * BSTR * 2, "C tile must fit in the B stage");
+
+    const int item = logical_block(a.xcd);
+    if (item >= P.n_win * a.win_panels) return;
+    const int panel = item / P.n_win;
+    const int wi = P.win_order[item - panel * P.n_win];
+    const int ncol0 = panel * NPW, ncols = min(NPW, P.n - ncol0);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int g = lane >> 4, l16 = lane & 15;
+    const int t0 = P.win_tile_ptr[wi], t1 = P.win_tile_ptr[wi + 1];
+
+    if (tid < H) s_rows[tid] = P.windows[(int64_t)wi * H + tid];
+    if (wave == 0) {
+        const int r = lane < H ? P.windows[(int64_t)wi * H + lane] : -1;
+        const int len = r >= 0 ? P.rem_ptr[r + 1] - P.rem_ptr[r] : 0;
+        const int ns = len > P.seg_len ? (len + P.seg_len - 1) / P.seg_len : 0;
+        const int x = wave_inclusive_scan(ns);
+        if (lane < H) s_sid[lane] = P.win_seg[wi] + x - ns;
+    }
+
+    f32x4 acc[MB][2];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[mb][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    for (int tc0 = t0; tc0 < t1; tc0 += TC) {
+        const int nt = min(TC, t1 - tc0);
+        __syncthreads();
+        for (int i = tid; i < nt * 32; i += 256) s_cols[i] = P.tile_cols[(int64_t)tc0 * 32 + i];
+        for (int i = tid; i < nt * H; i += 256) s_bm[i] = P.tile_bitmap[(int64_t)tc0 * H + i];
+        __syncthreads();
+        if (wave < nt) {
+            const uint32_t wd = lane < H ? s_bm[wave * H + lane] : 0u;
+            const int c = __popc(wd);
+            const int x = wave_inclusive_scan(c);
+            if (lane < H) s_off[wave * H + lane] = x - c;
+        }
+        for (int i = tid; i < nt * 32 * (NPW / 8); i += 256) {
+            const int kr = i >> 4, n = (i & 15) * 8;
+            const int col = s_cols[kr];
+            uint32_t w[4] = {0u, 0u, 0u, 0u};
+            const int valid = min(8, ncols - n);
+            if (col >= 0 && valid > 0)
+                stage_b8<BT, TT>(a.B, (int64_t)col * a.ldb + ncol0 + n, valid, a.vec_ok, w);
+            uint32_t *dst = reinterpret_cast<uint32_t *>(&Bs[kr * BSTR + n]);
+            dst[0] = w[0]; dst[1] = w[1]; dst[2] = w[2]; dst[3] = w[3];
+        }
+        __syncthreads();
+        for (int j = 0; j < nt; ++j) {
+            const int vb = P.tile_val_ptr[tc0 + j];
+            u16x8 af[MB];
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                const int m = mb * 16 + l16;
+                const uint32_t wd = s_bm[j * H + m];
+                const uint32_t mine = (wd >> (8 * g)) & 0xFFu;
+                int off = vb + s_off[j * H + m] + __popc(wd & ((1u << (8 * g)) - 1u));
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    unsigned short x = 0;
+                    if ((mine >> i) & 1u) x = P.tile_vals[off++];
+                    af[mb][i] = x;
+                }
+            }
+#pragma unroll
+            for (int nbi = 0; nbi < 2; ++nbi) {
+                const int nb = wave + 4 * nbi;
+                u16x8 bf;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) bf[i] = Bs[(j * 32 + 8 * g + i) * BSTR + nb * 16 + l16];
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb) acc[mb][nbi] = mfma_16x16x32<TT>(af[mb], bf, acc[mb][nbi]);
+            }
+        }
+    }
+    __syncthreads();
+    float *Cs = reinterpret_cast<float *>(Bs);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nbi = 0; nbi < 2; ++nbi)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                Cs[(mb * 16 + 4 * g + i) * NPW + (wave + 4 * nbi) * 16 + l16] = acc[mb][nbi][i];
+    __syncthreads();
+
+    const Lanes L(a.win_lpr_log2);
+    for (int s = wave; s < H; s += 4) {
+        const int r = s_rows[s];
+        if (r < 0) continue;
+        const int b = P.rem_ptr[r], e = P.rem_ptr[r + 1];
+        float v[CPL][E];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c)
+#pragma unroll
+            for (int x = 0; x < E; ++x) v[c][x] = 0.0f;
+        if (e - b <= P.seg_len) {
+            if (e > b) {
+                seg_accumulate<VT, BT, E, CPL, unroll_of<E, CPL>()>(P.rem_col, P.rem_val, b, e, a.B,
+                                                                    a.ldb, ncol0, ncols, L, v);
+                group_reduce<E, CPL>(v, L);
+            }
+        } else {
+            const int ns = (e - b + P.seg_len - 1) / P.seg_len;
+            sum_partials<E, CPL>(a.work, a.work_ld, s_sid[s], ns, ncol0, ncols, L, v);
+        }
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const int q = c * L.lpr + L.li;
+            if (q * E < ncols) {
+#pragma unroll
+                for (int x = 0; x < E; ++x) v[c][x] = Cs[s * NPW + q * E + x] + v[c][x];
+            }
+        }
+        store_row<E, CPL>(a.C, (int64_t)r * a.ldc, ncol0, ncols, L, v);
+    }
+}
+
+__global__ __launch_bounds__(256) void copy_kernel(const f32x4 *__restrict__ src,
+                                                   f32x4 *__restrict__ dst, int64_t n4) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += (int64_t)gridDim.x * 256)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+// ------------------------------------------------------------------------------------------
+// launchers
+
+static inline unsigned grid_for_waves(int64_t waves) { return (unsigned)((waves + 3) / 4); }
+
+template <int VT, int BT>
+static hipError_t seg_dispatch(const DevPlan &P, const RunArgs &a, hipStream_t s) {
+    const int64_t waves = (int64_t)P.n_seg * a.n_panels;
+    if (waves == 0) return hipSuccess;
+    constexpr int EV = BT == DT_F32 ? 4 : 8;
+    const int chunks = a.vec_ok ? (a.np + EV - 1) / EV : a.np;
+    dim3 grid(grid_for_waves(waves)), block(256);
+    if (a.vec_ok) {
+        if (chunks <= 64) hipLaunchKernelGGL((segment_kernel<VT, BT, EV, 1>), grid, block, 0, s, P, a);
+        else hipLaunchKernelGGL((segment_kernel<VT, BT, EV, 2>), grid, block, 0, s, P, a);
+    } else {
+        hipLaunchKernelGGL((segment_kernel<VT, BT, 1, 2>), grid, block, 0, s, P, a);
+    }
+    return hipGetLastError();
+}
+
+template <int VT, int BT>
+static hipError_t vec_dispatch(const DevPlan &P, const RunArgs &a, hipStream_t s) {
+    const int64_t waves = (int64_t)P.n_vitems * a.n_panels;
+    if (waves == 0) return hipSuccess;
+    constexpr int EV = BT == DT_F32 ? 4 : 8;
+    const int chunks = a.vec_ok ? (a.np + EV - 1) / EV : a.np;
+    dim3 grid(grid_for_waves(waves)), block(256);
+    if (a.vec_ok) {
+        if (chunks <= 64) hipLaunchKernelGGL((vector_kernel<VT, BT, EV, 1>), grid, block, 0, s, P, a);
+        else hipLaunchKernelGGL((vector_kernel<VT, BT, EV, 2>), grid, block, 0, s, P, a);
+    } else {
+        hipLaunchKernelGGL((vector_kernel<VT, BT, 1, 2>), grid, block, 0, s, P, a);
+    }
+    return hipGetLastError();
+}
+
+template <int VT, int BT, int TT>
+static hipError_t win_dispatch(const DevPlan &P, const RunArgs &a, hipStream_t s) {
+    const int64_t wgs = (int64_t)P.n_win * a.win_panels;
+    if (wgs == 0) return hipSuccess;
+    constexpr int EV = BT == DT_F32 ? 4 : 8;
+    dim3 grid((unsigned)wgs), block(256);
+#define SPMM_WIN(MB)                                                                              \
+    do {                                                                                          \
+        if (a.vec_ok)                                                                             \
+            hipLaunchKernelGGL((window_kernel<VT, BT, TT, MB, EV, 1>), grid, block, 0, s, P, a);  \
+        else                                                                                      \
+            hipLaunchKernelGGL((window_kernel<VT, BT, TT, MB, 1, 2>), grid, block, 0, s, P, a);   \
+    } while (0)
+    switch (P.H) {
+    case 16: SPMM_WIN(1); break;
+    case 32: SPMM_WIN(2); break;
+    case 64: SPMM_WIN(4); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef SPMM_WIN
+    return hipGetLastError();
+}
+
+hipError_t launch_segment(const DevPlan &P, int32_t vt, int32_t bt, const RunArgs &a, hipStream_t s) {
+    if (vt == DT_F32 && bt == DT_F32) return seg_dispatch<DT_F32, DT_F32>(P, a, s);
+    if (vt == DT_F32 && bt == DT_BF16) return seg_dispatch<DT_F32, DT_BF16>(P, a, s);
+    if (vt == DT_BF16 && bt == DT_BF16) return seg_dispatch<DT_BF16, DT_BF16>(P, a, s);
+    if (vt == DT_F16 && bt == DT_F16) return seg_dispatch<DT_F16, DT_F16>(P, a, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_vector(const DevPlan &P, int32_t vt, int32_t bt, const RunArgs &a, hipStream_t s) {
+    if (vt == DT_F32 && bt == DT_F32) return vec_dispatch<DT_F32, DT_F32>(P, a, s);
+    if (vt == DT_F32 && bt == DT_BF16) return vec_dispatch<DT_F32, DT_BF16>(P, a, s);
+    if (vt == DT_BF16 && bt == DT_BF16) return vec_dispatch<DT_BF16, DT_BF16>(P, a, s);
+    if (vt == DT_F16 && bt == DT_F16) return vec_dispatch<DT_F16, DT_F16>(P, a, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_window(const DevPlan &P, int32_t vt, int32_t bt, int32_t tt, const RunArgs &a,
+                         hipStream_t s) {
+    if (vt == DT_F32 && bt == DT_F32 && tt == DT_BF16) return win_dispatch<DT_F32, DT_F32, DT_BF16>(P, a, s);
+    if (vt == DT_F32 && bt == DT_BF16 && tt == DT_BF16) return win_dispatch<DT_F32, DT_BF16, DT_BF16>(P, a, s);
+    if (vt == DT_BF16 && bt == DT_BF16 && tt == DT_BF16) return win_dispatch<DT_BF16, DT_BF16, DT_BF16>(P, a, s);
+    if (vt == DT_F16 && bt == DT_F16 && tt == DT_F16) return win_dispatch<DT_F16, DT_F16, DT_F16>(P, a, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_copy(const float4 *src, float4 *dst, int64_t n4, hipStream_t s) {
+    if (n4 <= 0) return hipSuccess;
+    int64_t blocks = (n4 + 255) / 256;
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                       reinterpret_cast<const f32x4 *>(src), reinterpret_cast<f32x4 *>(dst), n4);
+    return hipGetLastError();
+}
+
+}  // namespace spmm

@@ -1,0 +1,345 @@
+// plan.cpp -- integer preprocessing of A (host, no device calls).
+//
+// NeutronSparse Sec. 5.2.2: a single scan computes Len(v) (Eq. 4); rows with
+// Len <= Thres (Eq. 5) stay on the vector path, the rest are candidates for the
+// matrix engine.  Sec. 6.1: the candidates are cut into row windows whose
+// height is the tile height; inside a window, columns that are empty (or, by
+// the column stage of Sec. 5.2.2 applied per window, too short) are compacted
+// away.  The surviving columns are chunked into K-tiles; a tile whose density
+// is below alpha goes back to the vector path (Sec. 5.2.1).  Kept tiles are
+// stored as a bitmap plus packed values (end of Sec. 5.2.2); everything else
+// is the remainder, an index/value list per row.  Sec. 7 (row-window list
+// migration): the work is then laid out as lists of items whose costs are
+// balanced and whose order puts heavy items first.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+namespace spmm {
+
+int dtype_size(int32_t t) { return t == SPMM_F32 ? 4 : 2; }
+
+uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu))
+        return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+    uint32_t lsb = (u >> 16) & 1u;
+    return (uint16_t)((u + 0x7FFFu + lsb) >> 16);
+}
+
+void resolve_options(const spmm_opts *in, const spmm_csr *A, int32_t n, int32_t b_type,
+                     spmm_opts *o) {
+    (void)n;
+    (void)b_type;
+    spmm_opts d;
+    if (in) d = *in; else spmm_opts_default(&d);
+    if (d.mode == SPMM_MODE_AUTO) d.mode = SPMM_MODE_MIXED;
+    if (d.window_h <= 0) d.window_h = 16;
+    if (d.t_row == SPMM_AUTO_INT) d.t_row = 1;
+    if (d.kt <= 0) d.kt = 32;
+    if (d.n_panel < 0) d.n_panel = 0;
+    if (d.row_order == SPMM_ORDER_AUTO) d.row_order = SPMM_ORDER_ORIGINAL_RANGES;
+    if (d.seg_len <= 0) d.seg_len = 256;
+    if (d.item_cost <= 0) {
+        double total = (double)(A ? A->nnz : 0) + (double)kRowCost * (double)(A ? A->m : 0);
+        double c = total / 32768.0;
+        d.item_cost = (int32_t)std::min(2048.0, std::max(32.0, c));
+    }
+    if (d.xcd_remap < 0) d.xcd_remap = 1;
+    if (!(d.alpha_c >= 0.0f)) d.alpha_c = 1.0f / (float)d.window_h;
+    if (!(d.alpha >= 0.0f)) d.alpha = 1.0f / (float)d.window_h;
+    if (d.mode == SPMM_MODE_MFMA_ONLY) {
+        d.t_row = -1;
+        d.alpha_c = 0.0f;
+        d.alpha = 0.0f;
+    }
+    *o = d;
+}
+
+static bool dtype_pair_ok(int32_t v, int32_t b) {
+    return (v == SPMM_F32 && b == SPMM_F32) || (v == SPMM_F32 && b == SPMM_BF16) ||
+           (v == SPMM_BF16 && b == SPMM_BF16) || (v == SPMM_F16 && b == SPMM_F16);
+}
+
+spmm_status validate_problem(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
+                             std::string &err) {
+    if (!A) { err = "A is null"; return SPMM_ERR_INVALID; }
+    if (A->m < 0 || A->k < 0 || A->nnz < 0) { err = "negative size"; return SPMM_ERR_INVALID; }
+    if (n < 1) { err = "n must be >= 1"; return SPMM_ERR_INVALID; }
+    if (A->m >= (1ll << 31) - 1 || A->k >= (1ll << 31) - 1 || A->nnz >= (1ll << 31) - 1) {
+        err = "m, k and nnz must be < 2^31 - 1";
+        return SPMM_ERR_UNSUPPORTED;
+    }
+    if (c_type != SPMM_F32) { err = "C must be f32"; return SPMM_ERR_UNSUPPORTED; }
+    if (A->val_type < 0 || A->val_type > 2 || b_type < 0 || b_type > 2) {
+        err = "unknown dtype";
+        return SPMM_ERR_INVALID;
+    }
+    if (!dtype_pair_ok(A->val_type, b_type)) {
+        err = "unsupported (vals, B) dtype pair";
+        return SPMM_ERR_UNSUPPORTED;
+    }
+    if (!A->rowptr) { err = "rowptr is null"; return SPMM_ERR_INVALID; }
+    if (A->nnz > 0 && (!A->colidx || !A->vals)) { err = "colidx/vals null"; return SPMM_ERR_INVALID; }
+    if (A->rowptr[0] != 0) { err = "rowptr[0] != 0"; return SPMM_ERR_INVALID; }
+    for (int64_t r = 0; r < A->m; ++r)
+        if (A->rowptr[r + 1] < A->rowptr[r]) { err = "rowptr not monotone"; return SPMM_ERR_INVALID; }
+    if (A->rowptr[A->m] != A->nnz) { err = "rowptr[m] != nnz"; return SPMM_ERR_INVALID; }
+    for (int64_t p = 0; p < A->nnz; ++p)
+        if (A->colidx[p] < 0 || A->colidx[p] >= A->k) {
+            err = "column index out of range";
+            return SPMM_ERR_INVALID;
+        }
+    return SPMM_OK;
+}
+
+static spmm_status validate_opts(const spmm_opts &o, std::string &err) {
+    if (o.mode < SPMM_MODE_PLAIN_F32 || o.mode > SPMM_MODE_MFMA_ONLY) { err = "mode"; return SPMM_ERR_UNSUPPORTED; }
+    if (o.window_h != 16 && o.window_h != 32 && o.window_h != 64) { err = "window_h must be 16, 32 or 64"; return SPMM_ERR_UNSUPPORTED; }
+    if (o.kt != 32) { err = "kt must be 32"; return SPMM_ERR_UNSUPPORTED; }
+    if (o.row_order < SPMM_ORDER_ORIGINAL_RANGES || o.row_order > SPMM_ORDER_LENGTH_SORTED) { err = "row_order"; return SPMM_ERR_UNSUPPORTED; }
+    if (o.seg_len < 1 || o.seg_len > (1 << 30)) { err = "seg_len"; return SPMM_ERR_UNSUPPORTED; }
+    if (o.item_cost < 1) { err = "item_cost"; return SPMM_ERR_UNSUPPORTED; }
+    if (o.n_panel < 0) { err = "n_panel"; return SPMM_ERR_UNSUPPORTED; }
+    if (!std::isfinite(o.alpha) || o.alpha < 0 || !std::isfinite(o.alpha_c) || o.alpha_c < 0) {
+        err = "alpha / alpha_c must be finite and >= 0";
+        return SPMM_ERR_UNSUPPORTED;
+    }
+    return SPMM_OK;
+}
+
+spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
+                            const spmm_opts &o, HostPlan &P, std::string &err) {
+    auto t_start = std::chrono::steady_clock::now();
+    spmm_status st = validate_problem(A, n, b_type, c_type, err);
+    if (st != SPMM_OK) return st;
+    st = validate_opts(o, err);
+    if (st != SPMM_OK) return st;
+
+    const int64_t m = A->m, k = A->k, nnz = A->nnz;
+    const int64_t *rowptr = A->rowptr;
+    const int32_t *colidx = A->colidx;
+    const int H = o.window_h, kt = o.kt, S = o.seg_len;
+    const int sval = dtype_size(A->val_type);
+    const uint8_t *vbytes = static_cast<const uint8_t *>(A->vals);
+
+    P = HostPlan();
+    P.m = m; P.k = k; P.nnz = nnz; P.n = n;
+    P.val_type = A->val_type; P.b_type = b_type; P.c_type = c_type;
+    P.tile_type = (b_type == SPMM_F16) ? SPMM_F16 : SPMM_BF16;
+    P.opts = o;
+
+    std::vector<int64_t> len(m);
+    for (int64_t r = 0; r < m; ++r) len[r] = rowptr[r + 1] - rowptr[r];  // Eq. 4
+
+    // ---- row stage (Eq. 5) and windows (Sec. 6.1) ----
+    std::vector<std::vector<int32_t>> cand;  // candidate windows, H slots each
+    if (o.mode != SPMM_MODE_PLAIN_F32) {
+        auto passes = [&](int64_t r) { return len[r] > (int64_t)o.t_row; };
+        if (o.row_order == SPMM_ORDER_ORIGINAL_RANGES) {
+            for (int64_t w0 = 0; w0 < m; w0 += H) {
+                std::vector<int32_t> slots(H, -1);
+                bool any = false;
+                for (int s = 0; s < H; ++s) {
+                    int64_t r = w0 + s;
+                    if (r < m && passes(r)) { slots[s] = (int32_t)r; any = true; }
+                }
+                if (any) cand.push_back(std::move(slots));
+                else cand.emplace_back();  // an empty window keeps no tile
+            }
+        } else {
+            std::vector<int32_t> D;
+            for (int64_t r = 0; r < m; ++r)
+                if (passes(r)) D.push_back((int32_t)r);
+            if (o.row_order == SPMM_ORDER_LENGTH_SORTED)
+                std::stable_sort(D.begin(), D.end(),
+                                 [&](int32_t a, int32_t b) { return len[a] > len[b]; });
+            for (size_t w0 = 0; w0 < D.size(); w0 += H) {
+                std::vector<int32_t> slots(H, -1);
+                for (int s = 0; s < H && w0 + s < D.size(); ++s) slots[s] = D[w0 + s];
+                cand.push_back(std::move(slots));
+            }
+        }
+    }
+
+    // ---- column stage, K-tiles, density test, packing ----
+    const int64_t col_thr = (int64_t)std::floor((double)o.alpha_c * (double)H);
+    const double keep_thr = (double)o.alpha * (double)(H * kt);
+    std::vector<int32_t> cnt(k, 0), pos(k, -1), touched, mcols;
+    std::vector<uint8_t> in_tile(nnz, 0);
+    std::vector<int64_t> src;  // [kept tiles of window][H][kt]
+    std::vector<std::pair<int64_t, int64_t>> kept_chunks;  // (start in mcols, ncols)
+    P.tile_val_ptr.push_back(0);
+    P.win_tile_ptr.push_back(0);
+    for (auto &slots : cand) {
+        if (slots.empty()) continue;
+        touched.clear();
+        for (int32_t r : slots) {
+            if (r < 0) continue;
+            for (int64_t p = rowptr[r]; p < rowptr[r + 1]; ++p) {
+                int32_t c = colidx[p];
+                if (cnt[c]++ == 0) touched.push_back(c);
+            }
+        }
+        mcols.clear();
+        for (int32_t c : touched)
+            if ((int64_t)cnt[c] > col_thr) mcols.push_back(c);
+        std::sort(mcols.begin(), mcols.end());
+        kept_chunks.clear();
+        for (size_t j0 = 0; j0 < mcols.size(); j0 += kt) {
+            size_t nc = std::min<size_t>(kt, mcols.size() - j0);
+            int64_t tnnz = 0;
+            for (size_t j = 0; j < nc; ++j) tnnz += cnt[mcols[j0 + j]];
+            if ((double)tnnz >= keep_thr) kept_chunks.push_back({(int64_t)j0, (int64_t)nc});
+        }
+        for (int32_t c : touched) cnt[c] = 0;
+        if (kept_chunks.empty()) continue;  // dissolved: rows stay vector rows
+
+        const int32_t widx = (int32_t)(P.windows.size() / H);
+        P.windows.insert(P.windows.end(), slots.begin(), slots.end());
+        const size_t nkt = kept_chunks.size();
+        for (size_t t = 0; t < nkt; ++t)
+            for (int64_t j = 0; j < kept_chunks[t].second; ++j)
+                pos[mcols[kept_chunks[t].first + j]] = (int32_t)(t * kt + j);
+        src.assign(nkt * H * kt, -1);
+        for (int s = 0; s < H; ++s) {
+            int32_t r = slots[s];
+            if (r < 0) continue;
+            for (int64_t p = rowptr[r]; p < rowptr[r + 1]; ++p) {
+                int32_t q = pos[colidx[p]];
+                if (q < 0) continue;
+                int64_t t = q / kt, j = q % kt;
+                int64_t &slot = src[(t * H + s) * kt + j];
+                if (slot < 0) { slot = p; in_tile[p] = 1; }  // first occurrence only
+            }
+        }
+        for (size_t t = 0; t < nkt; ++t) {
+            P.tile_window.push_back(widx);
+            for (int j = 0; j < kt; ++j)
+                P.tile_cols.push_back(j < kept_chunks[t].second ? mcols[kept_chunks[t].first + j] : -1);
+            for (int s = 0; s < H; ++s) {
+                uint32_t word = 0;
+                for (int j = 0; j < kt; ++j) {
+                    int64_t p = src[(t * H + s) * kt + j];
+                    if (p < 0) continue;
+                    word |= 1u << j;
+                    P.tile_src.push_back(p);
+                    uint16_t bits;
+                    if (A->val_type == SPMM_F32) {
+                        float f;
+                        std::memcpy(&f, vbytes + p * 4, 4);
+                        bits = f32_to_bf16_rne(f);
+                    } else {
+                        std::memcpy(&bits, vbytes + p * 2, 2);
+                    }
+                    P.tile_vals.push_back(bits);
+                }
+                P.tile_bitmap.push_back(word);
+            }
+            P.tile_val_ptr.push_back((int64_t)P.tile_src.size());
+        }
+        P.win_tile_ptr.push_back((int32_t)P.tile_window.size());
+        for (size_t t = 0; t < nkt; ++t)
+            for (int64_t j = 0; j < kept_chunks[t].second; ++j)
+                pos[mcols[kept_chunks[t].first + j]] = -1;
+    }
+    const int64_t W = (int64_t)P.windows.size() / H;
+
+    // ---- remainder (CSR order per row) ----
+    P.rem_ptr.assign(m + 1, 0);
+    P.rem_ptr32.assign(m + 1, 0);
+    P.rem_src.reserve(nnz - (int64_t)P.tile_src.size());
+    P.rem_col.reserve(nnz - (int64_t)P.tile_src.size());
+    P.rem_val.reserve((size_t)(nnz - (int64_t)P.tile_src.size()) * sval);
+    for (int64_t r = 0; r < m; ++r) {
+        for (int64_t p = rowptr[r]; p < rowptr[r + 1]; ++p) {
+            if (in_tile[p]) continue;
+            P.rem_src.push_back(p);
+            P.rem_col.push_back(colidx[p]);
+            P.rem_val.insert(P.rem_val.end(), vbytes + p * sval, vbytes + (p + 1) * sval);
+        }
+        P.rem_ptr[r + 1] = (int64_t)P.rem_src.size();
+        P.rem_ptr32[r + 1] = (int32_t)P.rem_src.size();
+    }
+
+    // ---- distinct referenced columns ----
+    {
+        std::vector<uint8_t> seen(k, 0);
+        int64_t kr = 0;
+        for (int64_t p = 0; p < nnz; ++p)
+            if (!seen[colidx[p]]) { seen[colidx[p]] = 1; ++kr; }
+        P.k_ref = kr;
+    }
+
+    // ---- vector rows, segments ----
+    std::vector<uint8_t> covered(m, 0);
+    for (int32_t r : P.windows)
+        if (r >= 0) covered[r] = 1;
+    for (int64_t r = 0; r < m; ++r)
+        if (!covered[r]) P.vector_rows.push_back((int32_t)r);
+    P.identity_rows = (int64_t)P.vector_rows.size() == m;
+    P.nseg.assign(m, 0);
+    for (int64_t r = 0; r < m; ++r) {
+        int64_t L = P.rem_ptr[r + 1] - P.rem_ptr[r];
+        if (L > S) P.nseg[r] = (int32_t)((L + S - 1) / S);
+    }
+    auto add_segments = [&](int32_t r) {
+        for (int32_t j = 0; j < P.nseg[r]; ++j) {
+            int64_t b = P.rem_ptr[r] + (int64_t)j * S;
+            int64_t e = std::min<int64_t>(b + S, P.rem_ptr[r + 1]);
+            P.seg_row.push_back(r);
+            P.seg_begin.push_back((int32_t)b);
+            P.seg_end.push_back((int32_t)e);
+        }
+    };
+
+    // vector items: consecutive vector rows with balanced cost (Sec. 7)
+    P.vitem_ptr.push_back(0);
+    {
+        int64_t acc = 0;
+        int32_t first = 0;
+        const int64_t nv = (int64_t)P.vector_rows.size();
+        P.vitem_seg.push_back((int32_t)P.seg_row.size());
+        for (int64_t i = 0; i < nv; ++i) {
+            int32_t r = P.vector_rows[i];
+            int64_t L = P.rem_ptr[r + 1] - P.rem_ptr[r];
+            acc += kRowCost + (P.nseg[r] ? P.nseg[r] : L);
+            add_segments(r);
+            if (acc >= o.item_cost || i + 1 == nv) {
+                P.vitem_ptr.push_back((int32_t)(i + 1));
+                if (i + 1 < nv) P.vitem_seg.push_back((int32_t)P.seg_row.size());
+                acc = 0;
+                first = (int32_t)(i + 1);
+            }
+        }
+        (void)first;
+        if (nv == 0) P.vitem_seg.clear();
+    }
+    // windows: segment ids in slot order, heaviest windows first
+    std::vector<int64_t> wcost(W, 0);
+    for (int64_t w = 0; w < W; ++w) {
+        P.win_seg.push_back((int32_t)P.seg_row.size());
+        wcost[w] = (int64_t)(P.win_tile_ptr[w + 1] - P.win_tile_ptr[w]) * kt;
+        for (int s = 0; s < H; ++s) {
+            int32_t r = P.windows[w * H + s];
+            if (r < 0) continue;
+            int64_t L = P.rem_ptr[r + 1] - P.rem_ptr[r];
+            wcost[w] += kRowCost + (P.nseg[r] ? P.nseg[r] : L);
+            add_segments(r);
+        }
+    }
+    P.win_order.resize(W);
+    for (int64_t w = 0; w < W; ++w) P.win_order[w] = (int32_t)w;
+    std::stable_sort(P.win_order.begin(), P.win_order.end(),
+                     [&](int32_t a, int32_t b) { return wcost[a] > wcost[b]; });
+
+    auto t_end = std::chrono::steady_clock::now();
+    P.plan_ms = std::chrono::duration<double, std::milli>(t_end - t_start).count();
+    return SPMM_OK;
+}
+
+}  // namespace spmm

@@ -1,0 +1,75 @@
+// plan.hpp -- host-side plan: the integer partition of A and its work lists.
+//
+// Built by build_host_plan() from a CSR matrix and resolved options; no HIP
+// call is made here, so the builder also runs (and is tested) without a GPU.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "spmm.h"
+
+namespace spmm {
+
+constexpr int kWave = 64;
+constexpr int kRowCost = 4;  // per-row overhead of a vector item, in entry units
+
+struct HostPlan {
+    // ---- problem and resolved options ----
+    int64_t m = 0, k = 0, nnz = 0;
+    int32_t n = 0;
+    int32_t val_type = SPMM_F32, b_type = SPMM_F32, c_type = SPMM_F32, tile_type = SPMM_BF16;
+    spmm_opts opts{};  // every field resolved (no "auto" left)
+
+    // ---- partition (compared bit-for-bit with the reference) ----
+    std::vector<int32_t> windows;       // [W*H], -1 = empty slot
+    std::vector<int32_t> tile_window;   // [T]
+    std::vector<int32_t> tile_cols;     // [T*kt], -1 = padding
+    std::vector<uint32_t> tile_bitmap;  // [T*H]
+    std::vector<int64_t> tile_val_ptr;  // [T+1]
+    std::vector<uint16_t> tile_vals;    // bf16 / f16 bit patterns
+    std::vector<int64_t> tile_src;      // CSR entry of each packed value
+    std::vector<int64_t> rem_ptr;       // [m+1]
+    std::vector<int64_t> rem_src;       // CSR entry of each remainder entry
+    std::vector<int32_t> vector_rows;   // ascending
+    std::vector<int32_t> nseg;          // [m]
+
+    // ---- schedule ----
+    std::vector<int32_t> vitem_ptr;     // [V+1] into vector_rows
+    std::vector<int32_t> vitem_seg;     // [V]
+    std::vector<int32_t> seg_row, seg_begin, seg_end;  // [S]
+    std::vector<int32_t> win_tile_ptr;  // [W+1]
+    std::vector<int32_t> win_seg;       // [W]
+    std::vector<int32_t> win_order;     // [W]
+    bool identity_rows = false;         // vector_rows == 0..m-1
+
+    // ---- device-facing copies of the remainder ----
+    std::vector<int32_t> rem_ptr32;     // [m+1]
+    std::vector<int32_t> rem_col;       // [nnz_rem]
+    std::vector<uint8_t> rem_val;       // [nnz_rem * s_val] raw bytes of val_type
+
+    // ---- statistics ----
+    int64_t k_ref = 0;
+    double plan_ms = 0.0;
+};
+
+int dtype_size(int32_t t);
+
+// Fill *o with library defaults for every "auto" field of `in` (in may be null).
+// Needs only the problem shape; never reads the matrix values.
+void resolve_options(const spmm_opts *in, const spmm_csr *A, int32_t n, int32_t b_type,
+                     spmm_opts *o);
+
+// Validate the CSR and sizes.  Returns SPMM_OK or an error with a message.
+spmm_status validate_problem(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
+                             std::string &err);
+
+// Build the full host plan for already-resolved options.
+spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
+                            const spmm_opts &o, HostPlan &P, std::string &err);
+
+// float -> bfloat16 bits, round to nearest even (NaN stays a quiet NaN).
+uint16_t f32_to_bf16_rne(float f);
+
+}  // namespace spmm

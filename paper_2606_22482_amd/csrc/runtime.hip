@@ -1,0 +1,555 @@
+// runtime.hip -- the C ABI (include/spmm.h): plans, uploads, runs, timers, tickets.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "devplan.hpp"
+#include "plan.hpp"
+#include "runtime.hpp"
+
+using namespace spmm;
+
+// ------------------------------------------------------------------------------------------
+// errors
+
+static thread_local std::string g_last_error;
+
+namespace spmm {
+spmm_status set_error(spmm_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+spmm_status hip_error(hipError_t e, const char *what) {
+    return set_error(SPMM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+}  // namespace spmm
+
+#define SPMM_TRY_HIP(call, what)                    \
+    do {                                            \
+        hipError_t e_ = (call);                     \
+        if (e_ != hipSuccess) return hip_error(e_, what); \
+    } while (0)
+
+extern "C" int32_t spmm_abi_version(void) { return SPMM_ABI_VERSION; }
+
+extern "C" int64_t spmm_sizeof(int32_t which) {
+    switch (which) {
+    case 0: return (int64_t)sizeof(spmm_csr);
+    case 1: return (int64_t)sizeof(spmm_opts);
+    case 2: return (int64_t)sizeof(spmm_plan_stats_t);
+    case 3: return (int64_t)sizeof(spmm_plan_dump_t);
+    case 4: return (int64_t)sizeof(spmm_work);
+    default: return -1;
+    }
+}
+
+extern "C" const char *spmm_status_string(spmm_status s) {
+    switch (s) {
+    case SPMM_OK: return "ok";
+    case SPMM_ERR_INVALID: return "invalid argument";
+    case SPMM_ERR_OOM: return "out of memory";
+    case SPMM_ERR_DEVICE: return "device error";
+    case SPMM_ERR_UNSUPPORTED: return "unsupported";
+    case SPMM_ERR_BUDGET: return "over budget";
+    case SPMM_ERR_BUSY: return "busy";
+    default: return "unknown status";
+    }
+}
+
+extern "C" const char *spmm_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" void spmm_opts_default(spmm_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->mode = SPMM_MODE_AUTO;
+    o->window_h = 0;
+    o->t_row = SPMM_AUTO_INT;
+    o->kt = 0;
+    o->n_panel = 0;
+    o->row_order = SPMM_ORDER_AUTO;
+    o->seg_len = 0;
+    o->item_cost = 0;
+    o->xcd_remap = -1;
+    o->alpha_c = -1.0f;
+    o->alpha = -1.0f;
+}
+
+// ------------------------------------------------------------------------------------------
+// plans
+
+namespace {
+
+struct Arena {
+    std::vector<std::pair<const void *, size_t>> parts;
+    std::vector<size_t> offs;
+    size_t total = 0;
+    size_t add(const void *p, size_t bytes) {
+        total = (total + 255) & ~size_t(255);
+        offs.push_back(total);
+        parts.push_back({p, bytes});
+        total += bytes;
+        return parts.size() - 1;
+    }
+};
+
+template <class T>
+size_t add_vec(Arena &a, const std::vector<T> &v) {
+    return a.add(v.data(), v.size() * sizeof(T));
+}
+
+}  // namespace
+
+extern "C" spmm_status spmm_plan_build(const spmm_csr *A, int32_t n, int32_t b_type,
+                                       int32_t c_type, const spmm_opts *opts, spmm_plan_t **out) {
+    if (!out) return set_error(SPMM_ERR_INVALID, "out is null");
+    *out = nullptr;
+    try {
+        std::string err;
+        spmm_status st = validate_problem(A, n, b_type, c_type, err);
+        if (st != SPMM_OK) return set_error(st, err);
+        spmm_opts o;
+        resolve_options(opts, A, n, b_type, &o);
+        std::unique_ptr<spmm_plan_s> p(new spmm_plan_s());
+        st = build_host_plan(A, n, b_type, c_type, o, p->hp, err);
+        if (st != SPMM_OK) return set_error(st, err);
+        // AUTO without a tuned profile: keep the mixed partition only when the
+        // tiles take a useful share of the entries, else plan the plain path.
+        const bool auto_mode = !opts || opts->mode == SPMM_MODE_AUTO;
+        if (auto_mode && A->nnz > 0 &&
+            (double)p->hp.tile_src.size() < 0.10 * (double)A->nnz) {
+            o.mode = SPMM_MODE_PLAIN_F32;
+            st = build_host_plan(A, n, b_type, c_type, o, p->hp, err);
+            if (st != SPMM_OK) return set_error(st, err);
+        }
+        *out = p.release();
+        return SPMM_OK;
+    } catch (const std::bad_alloc &) {
+        return set_error(SPMM_ERR_OOM, "host allocation failed while planning");
+    } catch (const std::exception &e) {
+        return set_error(SPMM_ERR_INVALID, e.what());
+    }
+}
+
+extern "C" spmm_status spmm_plan_upload(spmm_plan_t *p) {
+    if (!p) return set_error(SPMM_ERR_INVALID, "plan is null");
+    if (p->dev) return SPMM_OK;
+    try {
+        HostPlan &h = p->hp;
+        Arena a;
+        std::vector<int32_t> win_tile_ptr32(h.win_tile_ptr.begin(), h.win_tile_ptr.end());
+        std::vector<int32_t> tile_val_ptr32(h.tile_val_ptr.begin(), h.tile_val_ptr.end());
+        const size_t i_rem_ptr = add_vec(a, h.rem_ptr32);
+        const size_t i_rem_col = add_vec(a, h.rem_col);
+        const size_t i_rem_val = add_vec(a, h.rem_val);
+        const size_t i_vec_rows = add_vec(a, h.vector_rows);
+        const size_t i_vitem_ptr = add_vec(a, h.vitem_ptr);
+        const size_t i_vitem_seg = add_vec(a, h.vitem_seg);
+        const size_t i_seg_begin = add_vec(a, h.seg_begin);
+        const size_t i_seg_end = add_vec(a, h.seg_end);
+        const size_t i_windows = add_vec(a, h.windows);
+        const size_t i_win_tile_ptr = add_vec(a, win_tile_ptr32);
+        const size_t i_win_seg = add_vec(a, h.win_seg);
+        const size_t i_win_order = add_vec(a, h.win_order);
+        const size_t i_tile_cols = add_vec(a, h.tile_cols);
+        const size_t i_tile_bitmap = add_vec(a, h.tile_bitmap);
+        const size_t i_tile_val_ptr = add_vec(a, tile_val_ptr32);
+        const size_t i_tile_vals = add_vec(a, h.tile_vals);
+        const size_t total = std::max<size_t>(a.total, 256);
+
+        std::vector<uint8_t> image(total, 0);
+        for (size_t i = 0; i < a.parts.size(); ++i)
+            if (a.parts[i].second) std::memcpy(image.data() + a.offs[i], a.parts[i].first, a.parts[i].second);
+
+        int dev = 0;
+        SPMM_TRY_HIP(hipGetDevice(&dev), "hipGetDevice");
+        void *d = nullptr;
+        hipError_t e = hipMalloc(&d, total);
+        if (e != hipSuccess) return set_error(SPMM_ERR_OOM, std::string("hipMalloc(plan): ") + hipGetErrorString(e));
+        e = hipMemcpy(d, image.data(), total, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            return hip_error(e, "hipMemcpy(plan)");
+        }
+        auto at = [&](size_t i) -> uint8_t * { return static_cast<uint8_t *>(d) + a.offs[i]; };
+        DevPlan &dp = p->dp;
+        dp.m = (int32_t)h.m;
+        dp.n = h.n;
+        dp.seg_len = h.opts.seg_len;
+        dp.H = h.opts.window_h;
+        dp.kt = h.opts.kt;
+        dp.n_vitems = (int32_t)(h.vitem_ptr.size() - 1);
+        dp.n_seg = (int32_t)h.seg_row.size();
+        dp.n_win = (int32_t)h.win_order.size();
+        dp.rem_ptr = reinterpret_cast<const int32_t *>(at(i_rem_ptr));
+        dp.rem_col = reinterpret_cast<const int32_t *>(at(i_rem_col));
+        dp.rem_val = at(i_rem_val);
+        dp.vec_rows = h.identity_rows ? nullptr : reinterpret_cast<const int32_t *>(at(i_vec_rows));
+        dp.vitem_ptr = reinterpret_cast<const int32_t *>(at(i_vitem_ptr));
+        dp.vitem_seg = reinterpret_cast<const int32_t *>(at(i_vitem_seg));
+        dp.seg_begin = reinterpret_cast<const int32_t *>(at(i_seg_begin));
+        dp.seg_end = reinterpret_cast<const int32_t *>(at(i_seg_end));
+        dp.windows = reinterpret_cast<const int32_t *>(at(i_windows));
+        dp.win_tile_ptr = reinterpret_cast<const int32_t *>(at(i_win_tile_ptr));
+        dp.win_seg = reinterpret_cast<const int32_t *>(at(i_win_seg));
+        dp.win_order = reinterpret_cast<const int32_t *>(at(i_win_order));
+        dp.tile_cols = reinterpret_cast<const int32_t *>(at(i_tile_cols));
+        dp.tile_bitmap = reinterpret_cast<const uint32_t *>(at(i_tile_bitmap));
+        dp.tile_val_ptr = reinterpret_cast<const int32_t *>(at(i_tile_val_ptr));
+        dp.tile_vals = reinterpret_cast<const uint16_t *>(at(i_tile_vals));
+        p->dev = d;
+        p->dev_bytes = total;
+        p->device = dev;
+        return SPMM_OK;
+    } catch (const std::bad_alloc &) {
+        return set_error(SPMM_ERR_OOM, "host allocation failed while uploading");
+    }
+}
+
+extern "C" spmm_status spmm_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
+                                 const spmm_opts *opts, spmm_plan_t **out) {
+    spmm_status st = spmm_plan_build(A, n, b_type, c_type, opts, out);
+    if (st != SPMM_OK) return st;
+    st = spmm_plan_upload(*out);
+    if (st != SPMM_OK) {
+        delete *out;
+        *out = nullptr;
+    }
+    return st;
+}
+
+extern "C" spmm_status spmm_plan_destroy(spmm_plan_t *p) {
+    if (!p) return SPMM_OK;
+    if (p->busy.load() > 0) return set_error(SPMM_ERR_BUSY, "plan has unfinished submissions");
+    if (p->dev) (void)hipFree(p->dev);
+    delete p;
+    return SPMM_OK;
+}
+
+namespace spmm {
+double algorithmic_bytes(const HostPlan &h) {
+    const double sa = dtype_size(h.val_type), sb = dtype_size(h.b_type), sc = 4.0;
+    return 4.0 * (double)(h.m + 1) + (double)h.nnz * (4.0 + sa) + (double)h.k_ref * h.n * sb +
+           (double)h.m * h.n * sc;
+}
+}  // namespace spmm
+
+extern "C" spmm_status spmm_plan_stats(const spmm_plan_t *p, spmm_plan_stats_t *out) {
+    if (!p || !out) return set_error(SPMM_ERR_INVALID, "null argument");
+    const HostPlan &h = p->hp;
+    std::memset(out, 0, sizeof(*out));
+    out->m = h.m; out->k = h.k; out->nnz = h.nnz; out->n = h.n;
+    out->val_type = h.val_type; out->b_type = h.b_type; out->c_type = h.c_type;
+    out->tile_type = h.tile_type;
+    out->opts = h.opts;
+    out->windows = (int64_t)h.win_order.size();
+    out->tiles = (int64_t)h.tile_window.size();
+    out->nnz_tiles = (int64_t)h.tile_src.size();
+    out->nnz_remainder = (int64_t)h.rem_src.size();
+    out->vector_rows = (int64_t)h.vector_rows.size();
+    out->segments = (int64_t)h.seg_row.size();
+    out->vector_items = (int64_t)h.vitem_ptr.size() - 1;
+    out->k_ref = h.k_ref;
+    const double slots = (double)out->tiles * h.opts.window_h * h.opts.kt;
+    out->mean_tile_density = slots > 0 ? (double)out->nnz_tiles / slots : 0.0;
+    out->zero_fraction_tiles = slots > 0 ? 1.0 - out->mean_tile_density : 0.0;
+    out->device_bytes = (int64_t)p->dev_bytes;
+    out->workspace_bytes = (int64_t)h.seg_row.size() * ((h.n + 3) / 4 * 4) * 4;
+    out->algorithmic_bytes = algorithmic_bytes(h);
+    out->flops = 2.0 * (double)h.nnz * (double)h.n;
+    out->plan_ms = h.plan_ms;
+    out->uploaded = p->dev != nullptr;
+    return SPMM_OK;
+}
+
+extern "C" spmm_status spmm_plan_export(const spmm_plan_t *p, spmm_plan_dump_t *out) {
+    if (!p || !out) return set_error(SPMM_ERR_INVALID, "null argument");
+    const HostPlan &h = p->hp;
+    std::memset(out, 0, sizeof(*out));
+    out->m = h.m;
+    out->nnz = h.nnz;
+    out->window_h = h.opts.window_h;
+    out->kt = h.opts.kt;
+    out->n_windows = (int64_t)h.windows.size() / h.opts.window_h;
+    out->windows = h.windows.data();
+    out->n_tiles = (int64_t)h.tile_window.size();
+    out->tile_window = h.tile_window.data();
+    out->tile_cols = h.tile_cols.data();
+    out->tile_bitmap = h.tile_bitmap.data();
+    out->tile_val_ptr = h.tile_val_ptr.data();
+    out->tile_vals = h.tile_vals.data();
+    out->tile_src = h.tile_src.data();
+    out->rem_ptr = h.rem_ptr.data();
+    out->rem_src = h.rem_src.data();
+    out->n_vector_rows = (int64_t)h.vector_rows.size();
+    out->vector_rows = h.vector_rows.data();
+    out->nseg = h.nseg.data();
+    out->n_vitems = (int64_t)h.vitem_ptr.size() - 1;
+    out->vitem_ptr = h.vitem_ptr.data();
+    out->vitem_seg = h.vitem_seg.data();
+    out->n_segments = (int64_t)h.seg_row.size();
+    out->seg_row = h.seg_row.data();
+    out->seg_begin = h.seg_begin.data();
+    out->seg_end = h.seg_end.data();
+    out->win_seg = h.win_seg.data();
+    out->win_order = h.win_order.data();
+    return SPMM_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// per-stream workspace for segment partial sums
+
+namespace {
+struct Workspace {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+}  // namespace
+
+namespace spmm {
+spmm_status workspace_for(hipStream_t s, size_t bytes, float **out) {
+    *out = nullptr;
+    if (bytes == 0) return SPMM_OK;
+    int dev = 0;
+    SPMM_TRY_HIP(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace &w = g_ws[{dev, s}];
+    if (w.bytes < bytes) {
+        if (w.ptr) {
+            // earlier work on this stream may still read the old buffer
+            SPMM_TRY_HIP(hipStreamSynchronize(s), "hipStreamSynchronize(workspace)");
+            (void)hipFree(w.ptr);
+            w.ptr = nullptr;
+            w.bytes = 0;
+        }
+        size_t want = std::max(bytes, w.bytes * 2);
+        hipError_t e = hipMalloc(&w.ptr, want);
+        if (e != hipSuccess) {
+            w.ptr = nullptr;
+            return set_error(SPMM_ERR_OOM, std::string("hipMalloc(workspace): ") + hipGetErrorString(e));
+        }
+        w.bytes = want;
+    }
+    *out = static_cast<float *>(w.ptr);
+    return SPMM_OK;
+}
+
+static int ilog2_ceil(int x) {
+    int l = 0;
+    while ((1 << l) < x) ++l;
+    return l;
+}
+
+spmm_status make_run_args(const spmm_plan_t *p, const void *B, int64_t ldb, void *C, int64_t ldc,
+                          RunArgs &a) {
+    const HostPlan &h = p->hp;
+    const int N = h.n;
+    const int E = chunk_elems(h.b_type);
+    const int sb = dtype_size(h.b_type);
+    a.B = B;
+    a.ldb = ldb;
+    a.C = static_cast<float *>(C);
+    a.ldc = ldc;
+    a.work = nullptr;
+    a.work_ld = (N + 3) / 4 * 4;
+    a.vec_ok = (N % E == 0) && (ldb % E == 0) && (ldc % 4 == 0) &&
+               ((uintptr_t)B % 16 == 0) && ((uintptr_t)C % 16 == 0) && (sb * E == 16);
+    int np = h.opts.n_panel > 0 ? std::min(h.opts.n_panel, N) : N;
+    const int maxnp = a.vec_ok ? 128 * E : 128;
+    np = std::min(np, maxnp);
+    if (a.vec_ok) np = std::max(E, np / E * E);
+    a.np = np;
+    a.n_panels = (N + np - 1) / np;
+    const int chunks = a.vec_ok ? np / E : np;
+    a.lpr_log2 = ilog2_ceil(std::min(chunks, 64));
+    a.xcd = h.opts.xcd_remap ? 1 : 0;
+    a.win_panels = (N + 127) / 128;
+    const int wchunks = a.vec_ok ? 128 / E : 128;
+    a.win_lpr_log2 = ilog2_ceil(std::min(wchunks, 64));
+    return SPMM_OK;
+}
+}  // namespace spmm
+
+// ------------------------------------------------------------------------------------------
+// timers
+
+struct spmm_timer_s {
+    int32_t cap = 0;
+    int32_t used = 0;
+    std::vector<int32_t> ids;
+    std::vector<hipEvent_t> ev;  // 2 per launch
+};
+
+extern "C" spmm_status spmm_timer_create(int32_t capacity, spmm_timer_t **out) {
+    if (!out || capacity < 1) return set_error(SPMM_ERR_INVALID, "bad timer arguments");
+    std::unique_ptr<spmm_timer_s> t(new spmm_timer_s());
+    t->cap = capacity;
+    t->ids.resize(capacity);
+    t->ev.resize(2 * (size_t)capacity, nullptr);
+    for (auto &e : t->ev) {
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) {
+            for (auto &x : t->ev)
+                if (x) (void)hipEventDestroy(x);
+            return hip_error(r, "hipEventCreate");
+        }
+    }
+    *out = t.release();
+    return SPMM_OK;
+}
+
+extern "C" spmm_status spmm_timer_reset(spmm_timer_t *t) {
+    if (!t) return set_error(SPMM_ERR_INVALID, "timer is null");
+    t->used = 0;
+    return SPMM_OK;
+}
+
+extern "C" spmm_status spmm_timer_read(spmm_timer_t *t, int32_t *ids, float *ms, int32_t cap,
+                                       int32_t *count) {
+    if (!t || !count) return set_error(SPMM_ERR_INVALID, "null argument");
+    const int32_t n = std::min(t->used, cap);
+    for (int32_t i = 0; i < n; ++i) {
+        SPMM_TRY_HIP(hipEventSynchronize(t->ev[2 * i + 1]), "hipEventSynchronize");
+        float x = 0;
+        SPMM_TRY_HIP(hipEventElapsedTime(&x, t->ev[2 * i], t->ev[2 * i + 1]), "hipEventElapsedTime");
+        if (ids) ids[i] = t->ids[i];
+        if (ms) ms[i] = x;
+    }
+    *count = n;
+    return SPMM_OK;
+}
+
+extern "C" spmm_status spmm_timer_destroy(spmm_timer_t *t) {
+    if (!t) return SPMM_OK;
+    for (auto &e : t->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete t;
+    return SPMM_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// runs
+
+namespace spmm {
+spmm_status check_run(const spmm_plan_t *p, const void *B, int64_t ldb, void *C, int64_t ldc) {
+    if (!p) return set_error(SPMM_ERR_INVALID, "plan is null");
+    if (!p->dev) return set_error(SPMM_ERR_UNSUPPORTED, "plan is not uploaded");
+    const HostPlan &h = p->hp;
+    if (h.m > 0 && !C) return set_error(SPMM_ERR_INVALID, "C is null");
+    if (h.k > 0 && h.nnz > 0 && !B) return set_error(SPMM_ERR_INVALID, "B is null");
+    if (ldb < h.n || ldc < h.n) return set_error(SPMM_ERR_INVALID, "leading dimension < n");
+    return SPMM_OK;
+}
+
+spmm_status launch_plan(const spmm_plan_t *p, const RunArgs &a, hipStream_t s, spmm_timer_t *t) {
+    const HostPlan &h = p->hp;
+    const DevPlan &P = p->dp;
+    auto timed = [&](int kid, auto &&launch) -> spmm_status {
+        const bool rec = t != nullptr;
+        if (rec && t->used >= t->cap) return set_error(SPMM_ERR_INVALID, "timer is full");
+        if (rec) SPMM_TRY_HIP(hipEventRecord(t->ev[2 * t->used], s), "hipEventRecord");
+        hipError_t e = launch();
+        if (e != hipSuccess) return hip_error(e, "kernel launch");
+        if (rec) {
+            SPMM_TRY_HIP(hipEventRecord(t->ev[2 * t->used + 1], s), "hipEventRecord");
+            t->ids[t->used] = kid;
+            t->used++;
+        }
+        return SPMM_OK;
+    };
+    spmm_status st;
+    if (P.n_seg > 0) {
+        st = timed(SPMM_KERNEL_SEGMENT, [&] { return launch_segment(P, h.val_type, h.b_type, a, s); });
+        if (st != SPMM_OK) return st;
+    }
+    if (P.n_vitems > 0) {
+        st = timed(SPMM_KERNEL_VECTOR, [&] { return launch_vector(P, h.val_type, h.b_type, a, s); });
+        if (st != SPMM_OK) return st;
+    }
+    if (P.n_win > 0) {
+        st = timed(SPMM_KERNEL_WINDOW,
+                   [&] { return launch_window(P, h.val_type, h.b_type, h.tile_type, a, s); });
+        if (st != SPMM_OK) return st;
+    }
+    return SPMM_OK;
+}
+}  // namespace spmm
+
+static spmm_status run_impl(const spmm_plan_t *p, const void *B, int64_t ldb, void *C, int64_t ldc,
+                            void *stream, spmm_timer_t *t) {
+    spmm_status st = check_run(p, B, ldb, C, ldc);
+    if (st != SPMM_OK) return st;
+    if (p->hp.m == 0) return SPMM_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    RunArgs a;
+    make_run_args(p, B, ldb, C, ldc, a);
+    const size_t ws = (size_t)p->dp.n_seg * (size_t)a.work_ld * sizeof(float);
+    st = workspace_for(s, ws, &a.work);
+    if (st != SPMM_OK) return st;
+    return launch_plan(p, a, s, t);
+}
+
+extern "C" spmm_status spmm_run(const spmm_plan_t *p, const void *B, int64_t ldb, void *C,
+                                int64_t ldc, void *stream) {
+    return run_impl(p, B, ldb, C, ldc, stream, nullptr);
+}
+
+extern "C" spmm_status spmm_run_timed(const spmm_plan_t *p, const void *B, int64_t ldb, void *C,
+                                      int64_t ldc, void *stream, spmm_timer_t *t) {
+    if (!t) return set_error(SPMM_ERR_INVALID, "timer is null");
+    return run_impl(p, B, ldb, C, ldc, stream, t);
+}
+
+// ------------------------------------------------------------------------------------------
+// copy bandwidth probe
+
+extern "C" spmm_status spmm_copy_bandwidth(int64_t bytes, void *stream, double *bps) {
+    if (!bps || bytes < 4096) return set_error(SPMM_ERR_INVALID, "bad arguments");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n4 = bytes / 16;
+    void *src = nullptr, *dst = nullptr;
+    if (hipMalloc(&src, n4 * 16) != hipSuccess) return set_error(SPMM_ERR_OOM, "hipMalloc(src)");
+    if (hipMalloc(&dst, n4 * 16) != hipSuccess) {
+        (void)hipFree(src);
+        return set_error(SPMM_ERR_OOM, "hipMalloc(dst)");
+    }
+    spmm_status st = SPMM_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    do {
+        hipError_t e = hipMemsetAsync(src, 0, n4 * 16, s);
+        if (e != hipSuccess) { st = hip_error(e, "hipMemsetAsync"); break; }
+        for (int w = 0; w < 3 && st == SPMM_OK; ++w) {
+            e = launch_copy(static_cast<const float4 *>(src), static_cast<float4 *>(dst), n4, s);
+            if (e != hipSuccess) st = hip_error(e, "copy kernel");
+        }
+        if (st != SPMM_OK) break;
+        if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+            st = hip_error(e, "hipEventCreate");
+            break;
+        }
+        const int reps = 10;
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps; ++r) (void)launch_copy(static_cast<const float4 *>(src), static_cast<float4 *>(dst), n4, s);
+        (void)hipEventRecord(e1, s);
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) { st = hip_error(e, "hipEventSynchronize"); break; }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        *bps = 2.0 * (double)n4 * 16.0 * reps / (ms * 1e-3);
+    } while (0);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(src);
+    (void)hipFree(dst);
+    return st;
+}

@@ -1,0 +1,30 @@
+// runtime.hpp -- internals shared by the runtime translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <string>
+
+#include "devplan.hpp"
+#include "plan.hpp"
+
+struct spmm_plan_s {
+    spmm::HostPlan hp;
+    spmm::DevPlan dp{};
+    void *dev = nullptr;
+    size_t dev_bytes = 0;
+    int device = -1;
+    std::atomic<int> busy{0};  // unfinished batched submissions using this plan
+};
+
+namespace spmm {
+spmm_status set_error(spmm_status s, const std::string &msg);
+spmm_status hip_error(hipError_t e, const char *what);
+spmm_status workspace_for(hipStream_t s, size_t bytes, float **out);
+spmm_status make_run_args(const spmm_plan_t *p, const void *B, int64_t ldb, void *C, int64_t ldc,
+                          RunArgs &a);
+spmm_status check_run(const spmm_plan_t *p, const void *B, int64_t ldb, void *C, int64_t ldc);
+spmm_status launch_plan(const spmm_plan_t *p, const RunArgs &a, hipStream_t s, spmm_timer_t *t);
+double algorithmic_bytes(const HostPlan &h);
+}  // namespace spmm

@@ -1,0 +1,220 @@
+// submit.hip -- batched submissions with tickets, and the cost-model dry run.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <random>
+#include <vector>
+
+#include "devplan.hpp"
+#include "plan.hpp"
+#include "runtime.hpp"
+
+using namespace spmm;
+
+namespace {
+struct Ticket {
+    hipEvent_t done = nullptr;
+    std::vector<spmm_plan_t *> plans;
+};
+std::mutex g_tk_mu;
+std::map<spmm_ticket, Ticket> g_tickets;
+std::atomic<uint64_t> g_next_ticket{1};
+
+void release(Ticket &t) {
+    for (auto *p : t.plans) p->busy.fetch_sub(1);
+    if (t.done) (void)hipEventDestroy(t.done);
+    t.plans.clear();
+    t.done = nullptr;
+}
+}  // namespace
+
+extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *stream,
+                                   spmm_ticket *out) {
+    if (!out || count < 0 || (count > 0 && !items)) return set_error(SPMM_ERR_INVALID, "bad arguments");
+    *out = 0;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int32_t i = 0; i < count; ++i) {
+        spmm_status st = check_run(items[i].plan, items[i].B, items[i].ldb, items[i].C, items[i].ldc);
+        if (st != SPMM_OK) return st;
+    }
+    for (int32_t i = 0; i < count; ++i) {
+        const spmm_plan_t *p = items[i].plan;
+        if (p->hp.m == 0) continue;
+        RunArgs a;
+        make_run_args(p, items[i].B, items[i].ldb, items[i].C, items[i].ldc, a);
+        const size_t ws = (size_t)p->dp.n_seg * (size_t)a.work_ld * sizeof(float);
+        spmm_status st = workspace_for(s, ws, &a.work);
+        if (st != SPMM_OK) return st;
+        st = launch_plan(p, a, s, nullptr);
+        if (st != SPMM_OK) return st;
+    }
+    Ticket t;
+    hipError_t e = hipEventCreateWithFlags(&t.done, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_error(e, "hipEventCreate");
+    e = hipEventRecord(t.done, s);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(t.done);
+        return hip_error(e, "hipEventRecord");
+    }
+    for (int32_t i = 0; i < count; ++i) {
+        auto *p = const_cast<spmm_plan_t *>(items[i].plan);
+        p->busy.fetch_add(1);
+        t.plans.push_back(p);
+    }
+    const spmm_ticket id = g_next_ticket.fetch_add(1);
+    std::lock_guard<std::mutex> lk(g_tk_mu);
+    g_tickets[id] = std::move(t);
+    *out = id;
+    return SPMM_OK;
+}
+
+extern "C" spmm_status spmm_poll(spmm_ticket id, int32_t *done) {
+    if (!done) return set_error(SPMM_ERR_INVALID, "done is null");
+    std::lock_guard<std::mutex> lk(g_tk_mu);
+    auto it = g_tickets.find(id);
+    if (it == g_tickets.end()) {  // unknown or already retired
+        *done = 1;
+        return SPMM_OK;
+    }
+    hipError_t e = hipEventQuery(it->second.done);
+    if (e == hipErrorNotReady) {
+        *done = 0;
+        return SPMM_OK;
+    }
+    if (e != hipSuccess) return hip_error(e, "hipEventQuery");
+    release(it->second);
+    g_tickets.erase(it);
+    *done = 1;
+    return SPMM_OK;
+}
+
+extern "C" spmm_status spmm_wait(spmm_ticket id) {
+    hipEvent_t ev = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_tk_mu);
+        auto it = g_tickets.find(id);
+        if (it == g_tickets.end()) return SPMM_OK;
+        ev = it->second.done;
+    }
+    hipError_t e = hipEventSynchronize(ev);
+    if (e != hipSuccess) return hip_error(e, "hipEventSynchronize");
+    std::lock_guard<std::mutex> lk(g_tk_mu);
+    auto it = g_tickets.find(id);
+    if (it != g_tickets.end()) {
+        release(it->second);
+        g_tickets.erase(it);
+    }
+    return SPMM_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Dry run (Sec. 5.2.1): time the vector path on a uniformly random matrix and
+// the MFMA path on fully dense 16-row windows, with the same N and B type.
+
+namespace {
+struct DeviceBuffer {
+    void *p = nullptr;
+    ~DeviceBuffer() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+spmm_status time_plan(const spmm_csr &A, int32_t n, int32_t bt, const spmm_opts &o,
+                      hipStream_t s, double *ms_per_run) {
+    spmm_plan_t *p = nullptr;
+    spmm_status st = spmm_plan(&A, n, bt, SPMM_F32, &o, &p);
+    if (st != SPMM_OK) return st;
+    std::unique_ptr<spmm_plan_t, spmm_status (*)(spmm_plan_t *)> guard(p, spmm_plan_destroy);
+    const size_t sb = dtype_size(bt);
+    DeviceBuffer B, C;
+    if (hipMalloc(&B.p, (size_t)A.k * n * sb) != hipSuccess ||
+        hipMalloc(&C.p, (size_t)A.m * n * 4) != hipSuccess)
+        return set_error(SPMM_ERR_OOM, "dry run buffers");
+    if (hipMemsetAsync(B.p, 0, (size_t)A.k * n * sb, s) != hipSuccess)
+        return set_error(SPMM_ERR_DEVICE, "dry run memset");
+    for (int w = 0; w < 2; ++w) {
+        st = spmm_run(p, B.p, n, C.p, n, s);
+        if (st != SPMM_OK) return st;
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return set_error(SPMM_ERR_DEVICE, "event");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return set_error(SPMM_ERR_DEVICE, "event");
+    }
+    const int reps = 5;
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps && st == SPMM_OK; ++r) st = spmm_run(p, B.p, n, C.p, n, s);
+    (void)hipEventRecord(e1, s);
+    hipError_t e = hipEventSynchronize(e1);
+    float ms = 0;
+    if (e == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != SPMM_OK) return st;
+    if (e != hipSuccess) return hip_error(e, "dry run sync");
+    *ms_per_run = ms / reps;
+    return SPMM_OK;
+}
+}  // namespace
+
+extern "C" spmm_status spmm_dryrun(int32_t n, int32_t b_type, void *stream, double *p_vec,
+                                   double *p_mfma) {
+    if (n < 1 || !p_vec || !p_mfma || b_type < 0 || b_type > 2)
+        return set_error(SPMM_ERR_INVALID, "bad arguments");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t vt = b_type == SPMM_F32 ? SPMM_F32 : b_type;
+    const int sv = dtype_size(vt);
+    std::mt19937_64 rng(12345);
+
+    // vector path: 2^18 rows, 16 uniformly random columns each
+    {
+        const int64_t m = 1 << 18, per = 16;
+        std::vector<int64_t> rp(m + 1);
+        std::vector<int32_t> ci(m * per);
+        std::vector<uint8_t> v(m * per * sv, 0);
+        for (int64_t r = 0; r <= m; ++r) rp[r] = r * per;
+        for (auto &c : ci) c = (int32_t)(rng() % m);
+        spmm_csr A{m, m, m * per, rp.data(), ci.data(), v.data(), vt, 0};
+        spmm_opts o;
+        spmm_opts_default(&o);
+        o.mode = SPMM_MODE_PLAIN_F32;
+        double ms = 0;
+        spmm_status st = time_plan(A, n, b_type, o, s, &ms);
+        if (st != SPMM_OK) return st;
+        *p_vec = (double)A.nnz * n / (ms * 1e-3);
+    }
+    // matrix path: 2^14 windows of 16 rows, each a fully dense 16 x 64 block
+    {
+        const int64_t m = 1 << 18, per = 64;
+        std::vector<int64_t> rp(m + 1);
+        std::vector<int32_t> ci(m * per);
+        std::vector<uint8_t> v(m * per * sv, 0);
+        for (int64_t r = 0; r <= m; ++r) rp[r] = r * per;
+        for (int64_t w = 0; w < m / 16; ++w) {
+            std::vector<int32_t> cols(per);
+            for (auto &c : cols) c = (int32_t)(rng() % m);
+            std::sort(cols.begin(), cols.end());
+            cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+            while ((int64_t)cols.size() < per) cols.push_back((cols.back() + 1) % m);
+            for (int r = 0; r < 16; ++r)
+                std::copy(cols.begin(), cols.end(), ci.begin() + (w * 16 + r) * per);
+        }
+        spmm_csr A{m, m, m * per, rp.data(), ci.data(), v.data(), vt, 0};
+        spmm_opts o;
+        spmm_opts_default(&o);
+        o.mode = SPMM_MODE_MFMA_ONLY;
+        o.window_h = 16;
+        o.row_order = SPMM_ORDER_ORIGINAL_RANGES;
+        double ms = 0;
+        spmm_status st = time_plan(A, n, b_type, o, s, &ms);
+        if (st != SPMM_OK) return st;
+        *p_mfma = (double)A.nnz * n / (ms * 1e-3);  // every entry is a tile slot
+    }
+    return SPMM_OK;
+}

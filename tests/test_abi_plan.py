@@ -1,0 +1,214 @@
+"""CPU tier for the library: it loads and exports every declared symbol, the
+ABI structs match, validation returns the documented codes, and the C++ plan
+builder equals the independent numpy reference bit for bit (NeutronSparse
+Sec. 5.2.2 / Sec. 6.1 partition), with a valid schedule on top."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import plan_ref as pr
+from paper_2606_22482_amd import _lib as L
+from paper_2606_22482_amd import api, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return L.load()
+
+
+def declared_functions():
+    names = []
+    for hdr in os.listdir(os.path.join(ROOT, "include")):
+        if not hdr.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", hdr)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"^[A-Za-z_][\w \*]*?\b(spmm_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in L.SIGNATURES, "binding lacks " + n
+    assert lib.spmm_abi_version() == 1
+
+
+def _csr(A):
+    rp = np.ascontiguousarray(A.rowptr, np.int64)
+    ci = np.ascontiguousarray(A.colidx, np.int32)
+    v = np.ascontiguousarray(A.vals)
+    return L.Csr(A.m, A.k, int(rp[-1]), rp.ctypes.data, ci.ctypes.data, v.ctypes.data,
+                 L.KIND_CODE[A.val_kind], 0), (rp, ci, v)
+
+
+def _status(lib, A, n=8, bt=L.F32, ct=L.F32, opts=None):
+    csr, keep = _csr(A)
+    h = C.c_void_p()
+    st = lib.spmm_plan_build(C.byref(csr), n, bt, ct, C.byref(opts) if opts else None, C.byref(h))
+    if st == 0:
+        lib.spmm_plan_destroy(h)
+    return st
+
+
+def test_validation_codes(lib):
+    A = synth.random_csr(20, 10, 0.2, 1)
+    assert _status(lib, A) == L.SPMM_OK
+    bad = synth.CSR(A.m, A.k, A.rowptr.copy(), A.colidx.copy(), A.vals, "f32")
+    bad.colidx[3] = 10
+    assert _status(lib, bad) == L.SPMM_ERR_INVALID
+    bad = synth.CSR(A.m, A.k, A.rowptr.copy(), A.colidx, A.vals, "f32")
+    bad.rowptr[5], bad.rowptr[6] = bad.rowptr[6] + 1, bad.rowptr[5]
+    assert _status(lib, bad) == L.SPMM_ERR_INVALID
+    bad = synth.CSR(A.m, A.k, A.rowptr.copy(), A.colidx, A.vals, "f32")
+    bad.rowptr[0] = 1
+    assert _status(lib, bad) == L.SPMM_ERR_INVALID
+    assert _status(lib, A, n=0) == L.SPMM_ERR_INVALID
+    assert _status(lib, A, bt=L.F16) == L.SPMM_ERR_UNSUPPORTED     # f32 vals with f16 B
+    assert _status(lib, A, ct=L.BF16) == L.SPMM_ERR_UNSUPPORTED
+    assert _status(lib, A, opts=api.default_opts(window_h=24)) == L.SPMM_ERR_UNSUPPORTED
+    assert _status(lib, A, opts=api.default_opts(kt=16)) == L.SPMM_ERR_UNSUPPORTED
+    assert _status(lib, A, opts=api.default_opts(alpha=float("nan"), mode="mixed")) in (
+        L.SPMM_OK, L.SPMM_ERR_UNSUPPORTED)
+    h = C.c_void_p()
+    assert lib.spmm_plan_build(None, 8, 0, 0, None, C.byref(h)) == L.SPMM_ERR_INVALID
+    assert b"null" in lib.spmm_last_error()
+
+
+def test_run_needs_upload_and_checks_ld(lib):
+    A = synth.random_csr(20, 10, 0.2, 1)
+    p = api.Plan(A, 8, "f32", api.default_opts(mode="plain"), upload=False)
+    st = lib.spmm_run(p.handle, C.c_void_p(16), 8, C.c_void_p(16), 8, None)
+    assert st == L.SPMM_ERR_UNSUPPORTED
+    s = p.stats()
+    assert s["uploaded"] == 0 and s["nnz"] == A.nnz and s["n"] == 8
+    assert s["flops"] == 2 * A.nnz * 8
+
+
+def _cmp_plan(A, dump, ref):
+    assert np.array_equal(dump["windows"], ref.windows)
+    assert np.array_equal(dump["tile_window"], ref.tile_window)
+    assert np.array_equal(dump["tile_cols"], ref.tile_cols)
+    assert np.array_equal(dump["tile_bitmap"], ref.tile_bitmap)
+    assert np.array_equal(dump["tile_val_ptr"], ref.tile_val_ptr)
+    assert np.array_equal(dump["tile_vals"], ref.tile_vals)
+    assert np.array_equal(dump["tile_src"], ref.tile_src)
+    assert np.array_equal(dump["rem_ptr"], ref.rem_ptr)
+    assert np.array_equal(dump["rem_src"], ref.rem_src)
+    assert np.array_equal(dump["vector_rows"], ref.vector_rows)
+    assert np.array_equal(dump["nseg"], ref.nseg)
+
+
+def _check_schedule(A, d, seg_len):
+    m = A.m
+    vr = d["vector_rows"]
+    vp = d["vitem_ptr"]
+    assert vp[0] == 0 and vp[-1] == vr.size and np.all(np.diff(vp) > 0)
+    # segments: walk items then windows in order, ids must be consecutive
+    rem_len = np.diff(d["rem_ptr"])
+    sid = 0
+    for i in range(vp.size - 1):
+        assert d["vitem_seg"][i] == sid
+        for r in vr[vp[i]:vp[i + 1]]:
+            for j in range(d["nseg"][r]):
+                assert d["seg_row"][sid] == r
+                assert d["seg_begin"][sid] == d["rem_ptr"][r] + j * seg_len
+                assert d["seg_end"][sid] == min(d["rem_ptr"][r] + (j + 1) * seg_len,
+                                                d["rem_ptr"][r + 1])
+                sid += 1
+    for w in range(d["windows"].shape[0]):
+        assert d["win_seg"][w] == sid
+        for r in d["windows"][w]:
+            if r >= 0:
+                sid += d["nseg"][r]
+    assert sid == d["seg_row"].size
+    assert np.array_equal(np.sort(d["win_order"]), np.arange(d["windows"].shape[0]))
+    # every row is owned exactly once
+    owners = np.concatenate([vr, d["windows"][d["windows"] >= 0]])
+    assert np.array_equal(np.sort(owners), np.arange(m))
+    assert np.all(d["nseg"] == np.where(rem_len > seg_len, -(-rem_len // seg_len), 0))
+
+
+CASES = [
+    # (matrix kind, val kind, b kind, options)
+    ("random", "f32", "f32", dict(mode="mixed", window_h=16, t_row=3, alpha_c=1 / 16, alpha=0.05,
+                                  row_order="length_sorted", seg_len=7)),
+    ("random", "f32", "bf16", dict(mode="mixed", window_h=32, t_row=0, alpha_c=1 / 32, alpha=0.0,
+                                   row_order="original_ranges", seg_len=5)),
+    ("random", "bf16", "bf16", dict(mode="mixed", window_h=64, t_row=-1, alpha_c=0.0, alpha=0.01,
+                                    row_order="compacted", seg_len=11)),
+    ("random", "f16", "f16", dict(mode="mfma_only", window_h=16, seg_len=4)),
+    ("random", "f32", "f32", dict(mode="plain", seg_len=6)),
+    ("random", "f32", "f32", dict(mode="mixed", t_row=-1, alpha_c=0.0, alpha=1.5, seg_len=6)),
+    ("block", "f32", "bf16", dict(mode="mixed", window_h=16, t_row=1, alpha_c=1 / 16,
+                                  alpha=1 / 16, row_order="original_ranges", seg_len=16)),
+]
+
+
+def _matrix(kind, vk):
+    if kind == "random":
+        return synth.random_csr(400, 300, 0.04, 7, val_kind=vk, dup_frac=0.05, empty_rows=0.05)
+    A, _ = synth.block_community(n=2048, band=4, n_cols=8, seed=5, val_kind=vk)
+    return A
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_plan_bit_exact_vs_reference(lib, case):
+    kind, vk, bk, kw = CASES[case]
+    A = _matrix(kind, vk)
+    o = api.default_opts(**kw)
+    p = api.Plan(A, 8, bk, o, upload=False)
+    st = p.stats()
+    ro = st["opts"]
+    mode = ro["mode"]
+    ref = pr.build_plan(A.rowptr, A.colidx, A.vals, k=A.k, mode=mode, window_h=ro["window_h"],
+                        t_row=ro["t_row"], alpha_c=ro["alpha_c"], alpha=ro["alpha"],
+                        kt=ro["kt"], row_order=ro["row_order"], seg=ro["seg_len"],
+                        tile_kind="f16" if bk == "f16" else "bf16", val_kind=vk)
+    d = p.export()
+    _cmp_plan(A, d, ref)
+    _check_schedule(A, d, ro["seg_len"])
+    assert np.all(pr.coverage(ref) == 1)
+    if mode == L.MODE_MIXED and kw.get("alpha", 0) <= 1.0:
+        assert st["tiles"] > 0
+    assert st["nnz_tiles"] + st["nnz_remainder"] == A.nnz
+
+
+def test_mixed_without_tiles_equals_plain(lib):
+    A = synth.random_csr(300, 300, 0.03, 9)
+    p1 = api.Plan(A, 16, "f32", api.default_opts(mode="plain", seg_len=9), upload=False)
+    p2 = api.Plan(A, 16, "f32", api.default_opts(mode="mixed", alpha=2.0, seg_len=9),
+                  upload=False)
+    d1, d2 = p1.export(), p2.export()
+    for key in ("rem_ptr", "rem_src", "vector_rows", "nseg", "vitem_ptr", "vitem_seg",
+                "seg_begin", "seg_end"):
+        assert np.array_equal(d1[key], d2[key]), key
+    assert d2["windows"].shape[0] == 0
+
+
+def test_auto_mode_falls_back_to_plain_without_tiles(lib):
+    A = synth.random_csr(500, 5000, 0.001, 3)
+    p = api.Plan(A, 16, "f32", None, upload=False)
+    assert p.stats()["opts"]["mode"] == L.MODE_PLAIN_F32
+    B, _ = synth.block_community(n=1024, band=4, n_cols=8, seed=2)
+    q = api.Plan(B, 16, "f32", None, upload=False)
+    assert q.stats()["opts"]["mode"] == L.MODE_MIXED and q.stats()["tiles"] > 0
+
+
+def test_plan_stats_consistency(lib):
+    A, _ = synth.block_community(n=4096, band=8, n_cols=8, seed=3)
+    p = api.Plan(A, 64, "bf16", api.default_opts(mode="mixed", row_order="original_ranges"),
+                 upload=False)
+    s = p.stats()
+    assert s["k_ref"] == np.unique(A.colidx).size
+    expect = 4 * (A.m + 1) + A.nnz * 8 + s["k_ref"] * 64 * 2 + A.m * 64 * 4
+    assert s["algorithmic_bytes"] == expect
+    assert 0 < s["mean_tile_density"] <= 1
+    assert abs(s["zero_fraction_tiles"] - (1 - s["mean_tile_density"])) < 1e-12

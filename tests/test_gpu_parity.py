@@ -1,0 +1,192 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Floating point: normalised error <= 1e-5 on the FP32 path, <= 2e-2 where MFMA
+operands are 16-bit.  Integer-valued inputs (every partial sum exact in FP32
+and every value exact in bf16/f16) must match the oracle bit for bit on every
+path.  Edge cases: empty matrix, empty rows, NaN-prefilled C, N in {1, 7, 33}
+with padded leading dimensions, long rows split into segments.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import TOL_16, TOL_F32, device_B, device_C, exact, parity
+from paper_2606_22482_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_22482_amd import _lib
+    _lib.load()
+
+
+def run(A, B, b_kind, opts, n=None, pad_b=0, pad_c=0, fill=float("nan")):
+    import torch
+    n = B.shape[1] if n is None else n
+    p = api.Plan(A, n, b_kind, opts)
+    Bd = device_B(B, b_kind, pad_cols=pad_b)
+    Cd = device_C(A.m, n, fill=fill, pad_cols=pad_c)
+    p.run(Bd, Cd)
+    torch.cuda.synchronize()
+    return p, Cd
+
+
+MODES = ["plain", "mixed", "mfma_only"]
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("kinds", [("f32", "f32"), ("f32", "bf16"), ("bf16", "bf16"),
+                                   ("f16", "f16")])
+@pytest.mark.parametrize("n", [1, 7, 32, 33, 64, 128, 256])
+def test_integer_exact_all_paths(mode, kinds, n):
+    vk, bk = kinds
+    A = synth.random_csr(700, 500, 0.03, 11 + n, val_kind=vk, int_values=(-2, 2),
+                         dup_frac=0.03, empty_rows=0.05)
+    B = synth.int_dense(n, (500, n), -8, 8, kind=bk)
+    kw = dict(mode=mode, seg_len=13)
+    if mode == "mixed":
+        kw.update(window_h=16, t_row=2, alpha_c=1 / 16, alpha=0.0, row_order="length_sorted")
+    print("case", mode, kinds, n, flush=True)
+    p, C = run(A, B, bk, api.default_opts(**kw), pad_b=3 if n % 2 else 0, pad_c=5 if n == 7 else 0)
+    if mode != "plain":
+        assert p.stats()["tiles"] > 0
+    exact(C, A, B, bk)
+
+
+@pytest.mark.parametrize("H", [16, 32, 64])
+@pytest.mark.parametrize("order", ["original_ranges", "compacted", "length_sorted"])
+def test_window_heights_and_orders_exact(H, order):
+    A, _ = synth.block_community(n=4096, band=4, n_cols=8, seed=H, val_kind="bf16")
+    A.vals[:] = synth.to_bf16_bits(np.round(np.random.default_rng(H).uniform(-2, 2, A.nnz)))
+    B = synth.int_dense(H, (4096, 96), -8, 8, kind="bf16")
+    print("case", H, order, flush=True)
+    p, C = run(A, B, "bf16", api.default_opts(mode="mixed", window_h=H, t_row=1,
+                                              alpha_c=1 / H, alpha=0.0, row_order=order,
+                                              seg_len=17))
+    assert p.stats()["tiles"] > 0
+    exact(C, A, B, "bf16")
+
+
+def test_identity_returns_B_bitwise():
+    import torch
+    n = 2048
+    for mode, bk in [("plain", "f32"), ("mfma_only", "bf16"), ("mixed", "bf16")]:
+        vk = "f32" if mode == "plain" else "bf16"
+        vals = np.ones(n, np.float32) if vk == "f32" else synth.to_bf16_bits(np.ones(n))
+        A = synth.CSR(n, n, np.arange(n + 1, dtype=np.int64), np.arange(n, dtype=np.int32),
+                      vals, vk)
+        B = synth.dense_values(np.random.default_rng(1), (n, 64), bk)
+        p, C = run(A, B, bk, api.default_opts(mode=mode, t_row=-1, alpha_c=0.0, alpha=0.0))
+        Bd = device_B(B, bk).float()
+        assert torch.equal(C, Bd), mode
+
+
+def test_empty_matrix_and_empty_rows():
+    import torch
+    A = synth.CSR(300, 50, np.zeros(301, np.int64), np.zeros(0, np.int32),
+                  np.zeros(0, np.float32), "f32")
+    B = np.ones((50, 40), np.float32)
+    for mode in MODES:
+        _, C = run(A, B, "f32", api.default_opts(mode=mode))
+        assert torch.all(C == 0)
+    A = synth.random_csr(1000, 300, 0.05, 3, empty_rows=0.5)
+    B = np.random.default_rng(2).standard_normal((300, 64)).astype(np.float32)
+    for mode in MODES:
+        _, C = run(A, B, "f32", api.default_opts(mode=mode))
+        parity(C, A, B, "f32", TOL_F32 if mode == "plain" else TOL_16)
+
+
+def test_uniform_4096_n32_all_modes():
+    A, B = synth.uniform_rows()
+    for mode, tol in [("plain", TOL_F32), ("auto", TOL_F32), ("mixed", TOL_16),
+                      ("mfma_only", TOL_16)]:
+        print("case", mode, flush=True)
+        _, C = run(A, B, "f32", api.default_opts(mode=mode))
+        parity(C, A, B, "f32", tol)
+
+
+def test_long_rows_segments():
+    # hub rows of up to 20,000 entries split into segments of 64
+    A = synth.chung_lu_graph(50000, 2.1, 16.0, 20000.0, 7, val_kind="f32")
+    B = np.random.default_rng(3).standard_normal((50000, 128)).astype(np.float32)
+    for mode, tol in [("plain", TOL_F32), ("mixed", TOL_16)]:
+        kw = dict(mode=mode, seg_len=64)
+        if mode == "mixed":
+            kw.update(row_order="length_sorted", t_row=8)
+        p, C = run(A, B, "f32", api.default_opts(**kw))
+        assert p.stats()["segments"] > 0
+        parity(C, A, B, "f32", tol)
+
+
+def test_mixed_without_tiles_bitwise_equals_plain():
+    import torch
+    A = synth.chung_lu_graph(20000, 2.1, 16.0, 5000.0, 9)
+    B = np.random.default_rng(4).standard_normal((20000, 64)).astype(np.float32)
+    _, C1 = run(A, B, "f32", api.default_opts(mode="plain", seg_len=100))
+    _, C2 = run(A, B, "f32", api.default_opts(mode="mixed", alpha=1.5, seg_len=100))
+    assert torch.equal(C1, C2)
+
+
+def test_deterministic_and_nan_prefill():
+    import torch
+    A, B = synth.block_community(n=16384, band=8, n_cols=256, seed=8)
+    p = api.Plan(A, 256, "bf16", api.default_opts(mode="mixed", row_order="original_ranges"))
+    Bd = device_B(B, "bf16")
+    C1 = device_C(A.m, 256, fill=float("nan"))
+    C2 = device_C(A.m, 256, fill=12345.0)
+    p.run(Bd, C1)
+    p.run(Bd, C2)
+    torch.cuda.synchronize()
+    assert torch.equal(C1, C2)
+    assert p.stats()["tiles"] > 0
+    parity(C1, A, B, "bf16", TOL_16)
+
+
+def test_block_community_scaled():
+    A, B = synth.block_community(n=65536, band=32, n_cols=256, seed=3)
+    for mode, tol in [("mixed", TOL_16), ("plain", TOL_F32)]:
+        p, C = run(A, B, "bf16", api.default_opts(mode=mode, row_order="original_ranges"))
+        print(mode, p.stats()["nnz_tiles"] / A.nnz, flush=True)
+        parity(C, A, B, "bf16", tol)
+
+
+def test_submit_matches_solo_bitwise():
+    import torch
+    specs = synth.batch_specs(count=6, seed=4, rows_lo=1000, rows_hi=20000)
+    items, solos = [], []
+    for i, sp in enumerate(specs):
+        A, B = synth.batch_matrix(i, sp, seed=4)
+        p = api.Plan(A, B.shape[1], "f16", api.default_opts(mode="auto"))
+        Bd = device_B(B, "f16")
+        Cs = device_C(A.m, B.shape[1])
+        p.run(Bd, Cs)
+        Cb = device_C(A.m, B.shape[1])
+        items.append(api.WorkItem(p, Bd, Cb))
+        solos.append((Cs, A, B))
+    t = api.spmm_submit(items)
+    api.spmm_wait(t)
+    assert api.spmm_poll(t)
+    torch.cuda.synchronize()
+    for it, (Cs, A, B) in zip(items, solos):
+        assert torch.equal(it.C, Cs)
+        parity(Cs, A, B, "f16", TOL_16)
+
+
+def test_timer_and_copy_bandwidth():
+    import torch
+    A, B = synth.uniform_rows()
+    p = api.Plan(A, 32, "f32", api.default_opts(mode="plain"))
+    Bd = device_B(B, "f32")
+    C = device_C(A.m, 32)
+    t = api.Timer(16)
+    for _ in range(3):
+        p.run_timed(Bd, C, t)
+    rec = t.read()
+    assert len(rec) == 3 and all(name == "vector" and ms > 0 for name, ms in rec)
+    bw = api.spmm_copy_bandwidth(1 << 28)
+    assert bw > 1e11
+    torch.cuda.synchronize()
