@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--modes", default="plain,mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--opts", default="", help="extra plan options, k=v[,k=v]")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run the device copy kernel over this many bytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         raise SystemExit("bench.py measures one GPU: this build has no multi-GPU path "
@@ -125,6 +127,11 @@ def main():
 
     _lib.load()
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        bw = api.spmm_copy_bandwidth(args.copy_probe)
+        print(json.dumps({"copy_bytes": args.copy_probe, "copy_launches": 13,
+                          "read_plus_write_GBps": round(bw / 1e9, 1)}), flush=True)
+        return
     t0 = time.perf_counter()
     A, B, b_kind, wname = workload(args.workload)
     n = B.shape[1]
