@@ -89,7 +89,10 @@ typedef struct {
     int32_t seg_len;   /* remainder entries per segment; longer rows are split; <= 0: auto */
     int32_t item_cost; /* target work per vector work item, in entries; <= 0: auto */
     int32_t xcd_remap; /* 1: consecutive items on one XCD, 0: dispatch order, < 0: auto */
-    int32_t reserved;
+    int32_t hot_cols;  /* B rows gathered with the default (cacheable) policy: the most-gathered
+                          columns, at most this many; the rest are gathered non-temporally
+                          (Sec. 6.2.1, hot B rows cached, the rest bypassing).  < 0: auto (80% of
+                          one XCD's 4 MiB L2 in B-panel rows); 0: none */
     float alpha_c;     /* column stage: a window column is a tile column iff its count > floor(alpha_c*H); < 0: auto */
     float alpha;       /* a K-tile is kept iff nnz / (H*kt) >= alpha (Sec. 5.2.1); < 0: auto */
 } spmm_opts;
@@ -109,6 +112,7 @@ typedef struct {
     int64_t segments;           /* remainder segments computed as separate partial sums */
     int64_t vector_items;       /* vector work items (one wavefront each) */
     int64_t k_ref;              /* distinct columns referenced by A */
+    int64_t hot_cols;           /* columns gathered with the cacheable policy */
     double mean_tile_density;   /* nnz_tiles / (tiles * H * kt) */
     double zero_fraction_tiles; /* 1 - mean_tile_density: zeros computed by MFMA (Table 1 measure) */
     int64_t device_bytes;       /* bytes of the uploaded plan */
@@ -148,6 +152,7 @@ typedef struct {
     const int32_t *seg_end;     /* int32 [n_segments] */
     const int32_t *win_seg;     /* int32 [n_windows]: first segment id used by the window */
     const int32_t *win_order;   /* int32 [n_windows]: execution order of windows (heaviest first) */
+    const int32_t *rem_col_dev; /* int32 [nnz_remainder]: device column array, bit 31 set for hot columns */
 } spmm_plan_dump_t;
 
 /* One matrix of a batched submission (device pointers). */

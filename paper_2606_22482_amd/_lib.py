@@ -29,7 +29,7 @@ class Opts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("window_h", C.c_int32), ("t_row", C.c_int32),
                 ("kt", C.c_int32), ("n_panel", C.c_int32), ("row_order", C.c_int32),
                 ("seg_len", C.c_int32), ("item_cost", C.c_int32), ("xcd_remap", C.c_int32),
-                ("reserved", C.c_int32), ("alpha_c", C.c_float), ("alpha", C.c_float)]
+                ("hot_cols", C.c_int32), ("alpha_c", C.c_float), ("alpha", C.c_float)]
 
 
 class PlanStats(C.Structure):
@@ -39,6 +39,7 @@ class PlanStats(C.Structure):
                 ("windows", C.c_int64), ("tiles", C.c_int64), ("nnz_tiles", C.c_int64),
                 ("nnz_remainder", C.c_int64), ("vector_rows", C.c_int64),
                 ("segments", C.c_int64), ("vector_items", C.c_int64), ("k_ref", C.c_int64),
+                ("hot_cols", C.c_int64),
                 ("mean_tile_density", C.c_double), ("zero_fraction_tiles", C.c_double),
                 ("device_bytes", C.c_int64), ("workspace_bytes", C.c_int64),
                 ("algorithmic_bytes", C.c_double), ("flops", C.c_double),
@@ -55,7 +56,8 @@ class PlanDump(C.Structure):
                 ("vector_rows", C.c_void_p), ("nseg", C.c_void_p), ("n_vitems", C.c_int64),
                 ("vitem_ptr", C.c_void_p), ("vitem_seg", C.c_void_p),
                 ("n_segments", C.c_int64), ("seg_row", C.c_void_p), ("seg_begin", C.c_void_p),
-                ("seg_end", C.c_void_p), ("win_seg", C.c_void_p), ("win_order", C.c_void_p)]
+                ("seg_end", C.c_void_p), ("win_seg", C.c_void_p), ("win_order", C.c_void_p),
+                ("rem_col_dev", C.c_void_p)]
 
 
 class Work(C.Structure):

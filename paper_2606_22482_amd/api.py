@@ -146,6 +146,7 @@ class Plan:
             "seg_end": arr(d.seg_end, d.n_segments, np.int32),
             "win_seg": arr(d.win_seg, W, np.int32),
             "win_order": arr(d.win_order, W, np.int32),
+            "rem_col_dev": arr(d.rem_col_dev, int(rp[-1]), np.int32),
         }
 
     def run(self, B, Cout, stream=None):

@@ -57,22 +57,30 @@ __device__ __forceinline__ float load_val(const void *base, int idx) {
 }
 
 // E consecutive elements of B (as float) starting at element offset `off`.
-template <int BT, int E>
+// NT selects the non-temporal cache policy (the line is streamed through L2
+// and is the first to be evicted), used for B rows outside the hot set.
+template <bool NT, class T>
+__device__ __forceinline__ T ld(const T *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <int BT, int E, bool NT = false>
 __device__ __forceinline__ void load_chunk(const void *B, int64_t off, float (&v)[E]) {
     if constexpr (E == 1) {
         if constexpr (BT == DT_F32)
-            v[0] = static_cast<const float *>(B)[off];
+            v[0] = ld<NT>(static_cast<const float *>(B) + off);
         else if constexpr (BT == DT_BF16)
-            v[0] = bf16_to_f32(static_cast<const unsigned short *>(B)[off]);
+            v[0] = bf16_to_f32(ld<NT>(static_cast<const unsigned short *>(B) + off));
         else
-            v[0] = f16_to_f32(static_cast<const unsigned short *>(B)[off]);
+            v[0] = f16_to_f32(ld<NT>(static_cast<const unsigned short *>(B) + off));
     } else if constexpr (BT == DT_F32) {
         static_assert(E == 4, "f32 chunks are 4 wide");
-        f32x4 x = *reinterpret_cast<const f32x4 *>(static_cast<const float *>(B) + off);
+        f32x4 x = ld<NT>(reinterpret_cast<const f32x4 *>(static_cast<const float *>(B) + off));
         v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
     } else {
         static_assert(E == 8, "16-bit chunks are 8 wide");
-        u32x4 x = *reinterpret_cast<const u32x4 *>(static_cast<const unsigned short *>(B) + off);
+        u32x4 x = ld<NT>(reinterpret_cast<const u32x4 *>(static_cast<const unsigned short *>(B) + off));
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             if constexpr (BT == DT_BF16) {
@@ -171,8 +179,12 @@ __device__ __forceinline__ void seg_accumulate(const int32_t *__restrict__ rcol,
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
-                if (ok[u] && cok[c]) {
-                    load_chunk<BT, E>(B, (int64_t)col[u] * ldb + coff[c], b[u][c]);
+                // bit 31 of a column marks a hot B row (cacheable gather)
+                const int64_t boff = (int64_t)(col[u] & 0x7FFFFFFF) * ldb + coff[c];
+                if (ok[u] && cok[c] && col[u] < 0) {
+                    load_chunk<BT, E, false>(B, boff, b[u][c]);
+                } else if (ok[u] && cok[c]) {
+                    load_chunk<BT, E, true>(B, boff, b[u][c]);
                 } else {
 #pragma unroll
                     for (int e = 0; e < E; ++e) b[u][c][e] = 0.0f;

@@ -33,8 +33,6 @@ uint16_t f32_to_bf16_rne(float f) {
 
 void resolve_options(const spmm_opts *in, const spmm_csr *A, int32_t n, int32_t b_type,
                      spmm_opts *o) {
-    (void)n;
-    (void)b_type;
     spmm_opts d;
     if (in) d = *in; else spmm_opts_default(&d);
     if (d.mode == SPMM_MODE_AUTO) d.mode = SPMM_MODE_MIXED;
@@ -50,6 +48,11 @@ void resolve_options(const spmm_opts *in, const spmm_csr *A, int32_t n, int32_t 
         d.item_cost = (int32_t)std::min(2048.0, std::max(32.0, c));
     }
     if (d.xcd_remap < 0) d.xcd_remap = 1;
+    if (d.hot_cols < 0) {
+        // Sec. 6.2.1: stage the hottest B rows in the shared cache, capped at 80% of it
+        const int np = d.n_panel > 0 ? std::min(d.n_panel, std::max(n, 1)) : std::max(n, 1);
+        d.hot_cols = (int32_t)(kHotFraction * kL2BytesPerXcd / ((double)np * dtype_size(b_type)));
+    }
     if (!(d.alpha_c >= 0.0f)) d.alpha_c = 1.0f / (float)d.window_h;
     if (!(d.alpha >= 0.0f)) d.alpha = 1.0f / (float)d.window_h;
     if (d.mode == SPMM_MODE_MFMA_ONLY) {
@@ -105,6 +108,7 @@ static spmm_status validate_opts(const spmm_opts &o, std::string &err) {
     if (o.seg_len < 1 || o.seg_len > (1 << 30)) { err = "seg_len"; return SPMM_ERR_UNSUPPORTED; }
     if (o.item_cost < 1) { err = "item_cost"; return SPMM_ERR_UNSUPPORTED; }
     if (o.n_panel < 0) { err = "n_panel"; return SPMM_ERR_UNSUPPORTED; }
+    if (o.hot_cols < 0) { err = "hot_cols"; return SPMM_ERR_UNSUPPORTED; }
     if (!std::isfinite(o.alpha) || o.alpha < 0 || !std::isfinite(o.alpha_c) || o.alpha_c < 0) {
         err = "alpha / alpha_c must be finite and >= 0";
         return SPMM_ERR_UNSUPPORTED;
@@ -264,6 +268,25 @@ spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_
         }
         P.rem_ptr[r + 1] = (int64_t)P.rem_src.size();
         P.rem_ptr32[r + 1] = (int32_t)P.rem_src.size();
+    }
+
+    // ---- hot columns: the most-gathered B rows of the vector path (ties: lower id) ----
+    if (o.hot_cols > 0 && !P.rem_col.empty()) {
+        std::vector<int32_t> gcount(k, 0);
+        std::vector<int32_t> used;
+        for (int32_t c : P.rem_col)
+            if (gcount[c]++ == 0) used.push_back(c);
+        auto hotter = [&](int32_t a, int32_t b) {
+            return gcount[a] != gcount[b] ? gcount[a] > gcount[b] : a < b;
+        };
+        size_t nh = std::min<size_t>((size_t)o.hot_cols, used.size());
+        if (nh < used.size())
+            std::nth_element(used.begin(), used.begin() + nh, used.end(), hotter);
+        std::vector<uint8_t> hot(k, 0);
+        for (size_t i = 0; i < nh; ++i) hot[used[i]] = 1;
+        for (auto &c : P.rem_col)
+            if (hot[c]) c = (int32_t)((uint32_t)c | 0x80000000u);
+        P.hot_cols = (int64_t)nh;
     }
 
     // ---- distinct referenced columns ----

@@ -46,15 +46,19 @@ struct HostPlan {
 
     // ---- device-facing copies of the remainder ----
     std::vector<int32_t> rem_ptr32;     // [m+1]
-    std::vector<int32_t> rem_col;       // [nnz_rem]
+    std::vector<int32_t> rem_col;       // [nnz_rem], bit 31 set for hot columns
     std::vector<uint8_t> rem_val;       // [nnz_rem * s_val] raw bytes of val_type
 
     // ---- statistics ----
     int64_t k_ref = 0;
+    int64_t hot_cols = 0;               // columns flagged for cacheable gathers
     double plan_ms = 0.0;
 };
 
 int dtype_size(int32_t t);
+
+constexpr double kL2BytesPerXcd = 4.0 * 1024 * 1024;  // gfx950: 4 MiB L2 per XCD
+constexpr double kHotFraction = 0.8;                   // cap of the cached B working set
 
 // Fill *o with library defaults for every "auto" field of `in` (in may be null).
 // Needs only the problem shape; never reads the matrix values.

@@ -80,6 +80,7 @@ extern "C" void spmm_opts_default(spmm_opts *o) {
     o->seg_len = 0;
     o->item_cost = 0;
     o->xcd_remap = -1;
+    o->hot_cols = -1;
     o->alpha_c = -1.0f;
     o->alpha = -1.0f;
 }
@@ -259,6 +260,7 @@ extern "C" spmm_status spmm_plan_stats(const spmm_plan_t *p, spmm_plan_stats_t *
     out->segments = (int64_t)h.seg_row.size();
     out->vector_items = (int64_t)h.vitem_ptr.size() - 1;
     out->k_ref = h.k_ref;
+    out->hot_cols = h.hot_cols;
     const double slots = (double)out->tiles * h.opts.window_h * h.opts.kt;
     out->mean_tile_density = slots > 0 ? (double)out->nnz_tiles / slots : 0.0;
     out->zero_fraction_tiles = slots > 0 ? 1.0 - out->mean_tile_density : 0.0;
@@ -302,6 +304,7 @@ extern "C" spmm_status spmm_plan_export(const spmm_plan_t *p, spmm_plan_dump_t *
     out->seg_end = h.seg_end.data();
     out->win_seg = h.win_seg.data();
     out->win_order = h.win_order.data();
+    out->rem_col_dev = h.rem_col.data();
     return SPMM_OK;
 }
 

@@ -212,3 +212,23 @@ def test_plan_stats_consistency(lib):
     assert s["algorithmic_bytes"] == expect
     assert 0 < s["mean_tile_density"] <= 1
     assert abs(s["zero_fraction_tiles"] - (1 - s["mean_tile_density"])) < 1e-12
+
+
+def test_hot_columns_are_most_gathered(lib):
+    A = synth.chung_lu_graph(5000, 2.1, 16.0, 800.0, 4)
+    for hot in (0, 37, 10 ** 9):
+        p = api.Plan(A, 64, "f32", api.default_opts(mode="plain", hot_cols=hot), upload=False)
+        d = p.export()
+        dev = d["rem_col_dev"]
+        cols = A.colidx[d["rem_src"]]
+        assert np.array_equal(dev & 0x7FFFFFFF, cols)
+        flagged = np.unique(cols[dev < 0])
+        counts = np.bincount(cols, minlength=A.k)
+        used = np.nonzero(counts)[0]
+        order = sorted(used.tolist(), key=lambda c: (-counts[c], c))
+        want = np.sort(np.array(order[:min(hot, used.size)], dtype=np.int64))
+        assert np.array_equal(flagged, want)
+        assert p.stats()["hot_cols"] == want.size
+    # auto: 80% of a 4 MiB L2 in rows of N * 4 bytes
+    p = api.Plan(A, 64, "f32", api.default_opts(mode="plain"), upload=False)
+    assert p.stats()["opts"]["hot_cols"] == int(0.8 * 4 * 1024 * 1024 / (64 * 4))
