@@ -95,6 +95,9 @@ typedef struct {
                           one XCD's 4 MiB L2 in B-panel rows); 0: none */
     float alpha_c;     /* column stage: a window column is a tile column iff its count > floor(alpha_c*H); < 0: auto */
     float alpha;       /* a K-tile is kept iff nnz / (H*kt) >= alpha (Sec. 5.2.1); < 0: auto */
+    int32_t cold_policy; /* cache-policy bits of gathers of non-hot B rows (gfx950 buffer-load aux:
+                            2 = nt, 16 = sc1, 18 = nt|sc1, 0 = default); < 0: auto */
+    int32_t reserved;
 } spmm_opts;
 
 typedef struct spmm_plan_s spmm_plan_t;
@@ -228,6 +231,39 @@ spmm_status spmm_wait(spmm_ticket t);
  * vector-path throughput (entries*N per second) and MFMA-tile throughput
  * (tile slots*N per second) for this N and B type on the current device. */
 spmm_status spmm_dryrun(int32_t n, int32_t b_type, void *stream, double *p_vec, double *p_mfma);
+/* Autotuner (Sec. 5.2.1 cost model, Sec. 6.2.2 tile shaping, Sec. 8.2 threshold
+ * sensitivity).  Derives alpha = P_vec / P_mfma from the dry run (Eq. 3 with
+ * r = 1), then times candidate plans of A on the device (B, C: device buffers
+ * of the run's shapes; C is overwritten) in a staged search over mode, window
+ * height, row order, column/tile thresholds, segment length and N-panel width,
+ * within about budget_ms of wall time.  The best options are written to *out
+ * and cached under A's sparsity-profile key, so spmm_plan with
+ * mode = SPMM_MODE_AUTO reuses them for matrices of the same profile. */
+typedef struct {
+    int32_t candidates;     /* plans timed */
+    int32_t reserved;
+    double default_ms;      /* run time with the library defaults */
+    double best_ms;         /* run time with *out */
+    double alpha_cost;      /* alpha from Eq. 3 (r = 1) */
+    double p_vec, p_mfma;   /* dry-run throughputs (entries*N/s, slots*N/s) */
+    double search_ms;       /* wall time spent */
+} spmm_tune_report;
+
+spmm_status spmm_autotune(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
+                          const void *B, int64_t ldb, void *C, int64_t ldc, void *stream,
+                          double budget_ms, spmm_opts *out, spmm_tune_report *report);
+/* Sparsity-profile key of A for N and the B type: log2 sizes, the log2 row-
+ * length histogram of the entries and the window co-occurrence share of a
+ * sample of 16-row windows, as text.  INVALID if cap is too small. */
+spmm_status spmm_profile_key(const spmm_csr *A, int32_t n, int32_t b_type, char *buf, int32_t cap);
+/* The tuned-options cache (process-wide).  put/get by key; save/load a text
+ * file of "key<TAB>options" lines. */
+spmm_status spmm_tune_cache_put(const char *key, const spmm_opts *o);
+spmm_status spmm_tune_cache_get(const char *key, spmm_opts *o, int32_t *found);
+spmm_status spmm_tune_cache_save(const char *path);
+spmm_status spmm_tune_cache_load(const char *path);
+void spmm_tune_cache_clear(void);
+
 /* Device copy bandwidth (read + write bytes per second) over `bytes` bytes. */
 spmm_status spmm_copy_bandwidth(int64_t bytes, void *stream, double *bytes_per_s);
 

@@ -29,7 +29,8 @@ class Opts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("window_h", C.c_int32), ("t_row", C.c_int32),
                 ("kt", C.c_int32), ("n_panel", C.c_int32), ("row_order", C.c_int32),
                 ("seg_len", C.c_int32), ("item_cost", C.c_int32), ("xcd_remap", C.c_int32),
-                ("hot_cols", C.c_int32), ("alpha_c", C.c_float), ("alpha", C.c_float)]
+                ("hot_cols", C.c_int32), ("alpha_c", C.c_float), ("alpha", C.c_float),
+                ("cold_policy", C.c_int32), ("reserved", C.c_int32)]
 
 
 class PlanStats(C.Structure):
@@ -58,6 +59,12 @@ class PlanDump(C.Structure):
                 ("n_segments", C.c_int64), ("seg_row", C.c_void_p), ("seg_begin", C.c_void_p),
                 ("seg_end", C.c_void_p), ("win_seg", C.c_void_p), ("win_order", C.c_void_p),
                 ("rem_col_dev", C.c_void_p)]
+
+
+class TuneReport(C.Structure):
+    _fields_ = [("candidates", C.c_int32), ("reserved", C.c_int32), ("default_ms", C.c_double),
+                ("best_ms", C.c_double), ("alpha_cost", C.c_double), ("p_vec", C.c_double),
+                ("p_mfma", C.c_double), ("search_ms", C.c_double)]
 
 
 class Work(C.Structure):
@@ -94,6 +101,14 @@ SIGNATURES = {
     "spmm_dryrun": (_S, [C.c_int32, C.c_int32, _P, C.POINTER(C.c_double),
                          C.POINTER(C.c_double)]),
     "spmm_copy_bandwidth": (_S, [C.c_int64, _P, C.POINTER(C.c_double)]),
+    "spmm_autotune": (_S, [C.POINTER(Csr), C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64, _P,
+                           C.c_int64, _P, C.c_double, C.POINTER(Opts), C.POINTER(TuneReport)]),
+    "spmm_profile_key": (_S, [C.POINTER(Csr), C.c_int32, C.c_int32, C.c_char_p, C.c_int32]),
+    "spmm_tune_cache_put": (_S, [C.c_char_p, C.POINTER(Opts)]),
+    "spmm_tune_cache_get": (_S, [C.c_char_p, C.POINTER(Opts), C.POINTER(C.c_int32)]),
+    "spmm_tune_cache_save": (_S, [C.c_char_p]),
+    "spmm_tune_cache_load": (_S, [C.c_char_p]),
+    "spmm_tune_cache_clear": (None, []),
 }
 
 STRUCTS = {0: Csr, 1: Opts, 2: PlanStats, 3: PlanDump, 4: Work}

@@ -72,6 +72,19 @@ def _dev2d(t, what):
     return t.data_ptr(), t.stride(0)
 
 
+def _csr_struct(A):
+    rowptr = np.ascontiguousarray(A.rowptr, dtype=np.int64)
+    colidx = np.ascontiguousarray(A.colidx, dtype=np.int32)
+    vals = np.ascontiguousarray(A.vals)
+    csr = L.Csr(int(A.m), int(A.k), int(rowptr[-1]) if rowptr.size else 0, rowptr.ctypes.data,
+                colidx.ctypes.data, vals.ctypes.data, L.KIND_CODE[A.val_kind], 0)
+    return csr, (rowptr, colidx, vals)
+
+
+def opts_dict(o: L.Opts) -> dict:
+    return {f: getattr(o, f) for f, _ in L.Opts._fields_ if f != "reserved"}
+
+
 class Plan:
     """A plan built by ``spmm_plan`` (or ``spmm_plan_build`` when
     ``upload=False``).  ``A`` needs ``m, k, rowptr, colidx, vals, val_kind``."""
@@ -246,6 +259,54 @@ def spmm_dryrun(n: int, b_kind: str, stream=None):
     L.check(lib.spmm_dryrun(int(n), L.KIND_CODE[b_kind], _stream_handle(stream), C.byref(pv),
                             C.byref(pm)))
     return pv.value, pm.value
+
+
+def spmm_autotune(A, B, Cout, b_kind: str, budget_ms: float = 20000.0, stream=None):
+    """spmm_autotune: returns (opts, report dict); also caches the options
+    under A's profile key for spmm_plan(mode=AUTO)."""
+    lib = L.load()
+    csr, keep = _csr_struct(A)
+    bp, ldb = _dev2d(B, "B")
+    cp, ldc = _dev2d(Cout, "C")
+    o = L.Opts()
+    rep = L.TuneReport()
+    L.check(lib.spmm_autotune(C.byref(csr), int(B.shape[1]), L.KIND_CODE[b_kind], L.F32, bp, ldb,
+                              cp, ldc, _stream_handle(stream), float(budget_ms), C.byref(o),
+                              C.byref(rep)))
+    del keep
+    return o, {f: getattr(rep, f) for f, _ in L.TuneReport._fields_ if f != "reserved"}
+
+
+def spmm_profile_key(A, n: int, b_kind: str) -> str:
+    lib = L.load()
+    csr, keep = _csr_struct(A)
+    buf = C.create_string_buffer(1024)
+    L.check(lib.spmm_profile_key(C.byref(csr), int(n), L.KIND_CODE[b_kind], buf, 1024))
+    del keep
+    return buf.value.decode()
+
+
+def tune_cache_put(key: str, opts: L.Opts):
+    L.check(L.load().spmm_tune_cache_put(key.encode(), C.byref(opts)))
+
+
+def tune_cache_get(key: str):
+    o = L.Opts()
+    found = C.c_int32()
+    L.check(L.load().spmm_tune_cache_get(key.encode(), C.byref(o), C.byref(found)))
+    return o if found.value else None
+
+
+def tune_cache_save(path: str):
+    L.check(L.load().spmm_tune_cache_save(path.encode()))
+
+
+def tune_cache_load(path: str):
+    L.check(L.load().spmm_tune_cache_load(path.encode()))
+
+
+def tune_cache_clear():
+    L.load().spmm_tune_cache_clear()
 
 
 def spmm_copy_bandwidth(nbytes: int, stream=None) -> float:

@@ -46,7 +46,30 @@ struct RunArgs {
     int32_t xcd;        // remap consecutive items onto one XCD
     int32_t win_panels; // panels of the window kernel (128 columns each)
     int32_t win_lpr_log2;
+    int32_t cold_aux;   // buffer-load policy bits for non-hot B rows; -1: plain loads for all
 };
+
+// One matrix of a batched execution.  `*_end` are exclusive prefix sums of
+// the global item counts (segment waves, vector waves, window workgroups), so
+// a persistent kernel can walk the table forward as its item ids increase.
+struct BatchEntry {
+    DevPlan P;
+    RunArgs a;
+    int32_t seg_end, vec_end, win_end, pad;
+};
+
+struct BatchHeader {
+    int32_t count, total_seg, total_vec, total_win;
+};
+
+// Persistent batched launches over a device table (header + entries).
+// `grid_*` are the workgroup counts of the three kernels.
+hipError_t launch_batch(const BatchHeader *hdr, const BatchEntry *tab, int32_t val_t, int32_t b_t,
+                        int32_t tile_t, int vec_ok, int cpl, unsigned grid_wave,
+                        unsigned grid_win, hipStream_t s);
+// Resident workgroups per CU of the batched kernels of this variant.
+hipError_t batch_occupancy(int32_t val_t, int32_t b_t, int32_t tile_t, int vec_ok, int cpl,
+                           int *wave_kernels, int *win_kernel);
 
 // dtype codes as in spmm.h
 hipError_t launch_segment(const DevPlan &P, int32_t val_t, int32_t b_t, const RunArgs &a,

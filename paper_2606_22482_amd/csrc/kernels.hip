@@ -94,6 +94,78 @@ __device__ __forceinline__ void load_chunk(const void *B, int64_t off, float (&v
     }
 }
 
+// The same chunk through a raw buffer load whose cache-policy bits are `aux`
+// (gfx950: bit 0 sc0, bit 1 nt, bit 4 sc1).  A distinct intrinsic, so the
+// compiler never merges it with the default-policy load of a hot row.
+template <int AUX>
+__device__ __forceinline__ u32x4 buf16(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, AUX);
+}
+template <int AUX>
+__device__ __forceinline__ uint32_t buf4(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, AUX);
+}
+template <int AUX>
+__device__ __forceinline__ uint32_t buf2(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, AUX);
+}
+
+template <int BT, int E>
+__device__ __forceinline__ void load_chunk_policy(__amdgpu_buffer_rsrc_t rs, int64_t off, int aux,
+                                                  float (&v)[E]) {
+    constexpr int SB = BT == DT_F32 ? 4 : 2;
+    const uint32_t boff = (uint32_t)(off * SB);
+    if constexpr (E == 1) {
+        uint32_t x;
+        if constexpr (SB == 4) {
+            switch (aux) {
+            case 2: x = buf4<2>(rs, boff); break;
+            case 16: x = buf4<16>(rs, boff); break;
+            case 18: x = buf4<18>(rs, boff); break;
+            default: x = buf4<0>(rs, boff); break;
+            }
+            v[0] = __uint_as_float(x);
+        } else {
+            switch (aux) {
+            case 2: x = buf2<2>(rs, boff); break;
+            case 16: x = buf2<16>(rs, boff); break;
+            case 18: x = buf2<18>(rs, boff); break;
+            default: x = buf2<0>(rs, boff); break;
+            }
+            v[0] = BT == DT_BF16 ? bf16_to_f32(x) : f16_to_f32(x);
+        }
+    } else {
+        u32x4 x;
+        switch (aux) {
+        case 2: x = buf16<2>(rs, boff); break;
+        case 16: x = buf16<16>(rs, boff); break;
+        case 18: x = buf16<18>(rs, boff); break;
+        default: x = buf16<0>(rs, boff); break;
+        }
+        if constexpr (BT == DT_F32) {
+            v[0] = __uint_as_float(x[0]); v[1] = __uint_as_float(x[1]);
+            v[2] = __uint_as_float(x[2]); v[3] = __uint_as_float(x[3]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if constexpr (BT == DT_BF16) {
+                    v[2 * i] = __uint_as_float(x[i] << 16);
+                    v[2 * i + 1] = __uint_as_float(x[i] & 0xFFFF0000u);
+                } else {
+                    v[2 * i] = f16_to_f32(x[i] & 0xFFFFu);
+                    v[2 * i + 1] = f16_to_f32(x[i] >> 16);
+                }
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t b_resource(const void *B) {
+    // raw buffer over B: stride 0, 2^32-1 bytes addressable, gfx9 word-3 flags
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(B), (short)0, (int)0xFFFFFFFF,
+                                             0x00020000);
+}
+
 template <int E>
 __device__ __forceinline__ void store_chunk(float *C, int64_t off, const float (&v)[E]) {
     if constexpr (E == 1) {
@@ -152,8 +224,9 @@ template <int VT, int BT, int E, int CPL, int U>
 __device__ __forceinline__ void seg_accumulate(const int32_t *__restrict__ rcol,
                                                const void *__restrict__ rval, int p0, int p1,
                                                const void *__restrict__ B, int64_t ldb,
-                                               int ncol0, int ncols, const Lanes &L,
+                                               int ncol0, int ncols, const Lanes &L, int cold_aux,
                                                float (&acc)[CPL][E]) {
+    const __amdgpu_buffer_rsrc_t rs = b_resource(B);
     bool cok[CPL];
     int64_t coff[CPL];
 #pragma unroll
@@ -181,10 +254,10 @@ __device__ __forceinline__ void seg_accumulate(const int32_t *__restrict__ rcol,
             for (int c = 0; c < CPL; ++c) {
                 // bit 31 of a column marks a hot B row (cacheable gather)
                 const int64_t boff = (int64_t)(col[u] & 0x7FFFFFFF) * ldb + coff[c];
-                if (ok[u] && cok[c] && col[u] < 0) {
+                if (ok[u] && cok[c] && (col[u] < 0 || cold_aux < 0)) {
                     load_chunk<BT, E, false>(B, boff, b[u][c]);
                 } else if (ok[u] && cok[c]) {
-                    load_chunk<BT, E, true>(B, boff, b[u][c]);
+                    load_chunk_policy<BT, E>(rs, boff, cold_aux, b[u][c]);
                 } else {
 #pragma unroll
                     for (int e = 0; e < E; ++e) b[u][c][e] = 0.0f;
@@ -247,10 +320,9 @@ template <int E, int CPL>
 constexpr int unroll_of() { return E == 1 ? 4 : (CPL == 1 ? 8 : 4); }
 
 // ------------------------------------------------------------------------------------------
+// One segment (of one panel) per wavefront: wid in [0, n_seg * n_panels).
 template <int VT, int BT, int E, int CPL>
-__global__ __launch_bounds__(256) void segment_kernel(DevPlan P, RunArgs a) {
-    const int wid = logical_block(a.xcd) * 4 + (threadIdx.x >> 6);
-    if (wid >= P.n_seg * a.n_panels) return;
+__device__ __forceinline__ void segment_item(const DevPlan &P, const RunArgs &a, int wid) {
     const int panel = wid / P.n_seg, sid = wid - panel * P.n_seg;
     const int ncol0 = panel * a.np, ncols = min(a.np, P.n - ncol0);
     const Lanes L(a.lpr_log2);
@@ -261,7 +333,7 @@ __global__ __launch_bounds__(256) void segment_kernel(DevPlan P, RunArgs a) {
         for (int e = 0; e < E; ++e) acc[c][e] = 0.0f;
     seg_accumulate<VT, BT, E, CPL, unroll_of<E, CPL>()>(P.rem_col, P.rem_val, P.seg_begin[sid],
                                                         P.seg_end[sid], a.B, a.ldb, ncol0, ncols,
-                                                        L, acc);
+                                                        L, a.cold_aux, acc);
     group_reduce<E, CPL>(acc, L);
     if (L.group != 0) return;
 #pragma unroll
@@ -281,10 +353,9 @@ __global__ __launch_bounds__(256) void segment_kernel(DevPlan P, RunArgs a) {
     }
 }
 
+// One vector work item (of one panel) per wavefront: wid in [0, n_vitems * n_panels).
 template <int VT, int BT, int E, int CPL>
-__global__ __launch_bounds__(256) void vector_kernel(DevPlan P, RunArgs a) {
-    const int wid = logical_block(a.xcd) * 4 + (threadIdx.x >> 6);
-    if (wid >= P.n_vitems * a.n_panels) return;
+__device__ __forceinline__ void vector_item(const DevPlan &P, const RunArgs &a, int wid) {
     const int panel = wid / P.n_vitems, item = wid - panel * P.n_vitems;
     const int ncol0 = panel * a.np, ncols = min(a.np, P.n - ncol0);
     const Lanes L(a.lpr_log2);
@@ -300,7 +371,8 @@ __global__ __launch_bounds__(256) void vector_kernel(DevPlan P, RunArgs a) {
             for (int x = 0; x < E; ++x) acc[c][x] = 0.0f;
         if (e - b <= P.seg_len) {
             seg_accumulate<VT, BT, E, CPL, unroll_of<E, CPL>()>(P.rem_col, P.rem_val, b, e, a.B,
-                                                                a.ldb, ncol0, ncols, L, acc);
+                                                                a.ldb, ncol0, ncols, L, a.cold_aux,
+                                                                acc);
             group_reduce<E, CPL>(acc, L);
         } else {
             const int ns = (e - b + P.seg_len - 1) / P.seg_len;
@@ -309,6 +381,18 @@ __global__ __launch_bounds__(256) void vector_kernel(DevPlan P, RunArgs a) {
         }
         store_row<E, CPL>(a.C, (int64_t)r * a.ldc, ncol0, ncols, L, acc);
     }
+}
+
+template <int VT, int BT, int E, int CPL>
+__global__ __launch_bounds__(256) void segment_kernel(DevPlan P, RunArgs a) {
+    const int wid = logical_block(a.xcd) * 4 + (threadIdx.x >> 6);
+    if (wid < P.n_seg * a.n_panels) segment_item<VT, BT, E, CPL>(P, a, wid);
+}
+
+template <int VT, int BT, int E, int CPL>
+__global__ __launch_bounds__(256) void vector_kernel(DevPlan P, RunArgs a) {
+    const int wid = logical_block(a.xcd) * 4 + (threadIdx.x >> 6);
+    if (wid < P.n_vitems * a.n_panels) vector_item<VT, BT, E, CPL>(P, a, wid);
 }
 
 // Inclusive prefix sum over the 64 lanes of a wavefront.
@@ -321,6 +405,20 @@ __device__ __forceinline__ int wave_inclusive_scan(int x) {
     }
     return x;
 }
+
+// LDS of a window item: the staged B rows (reused for the f32 C tile), the
+// window's rows and segment ids, and the staged tiles' columns, bitmaps and
+// per-row value offsets.  Sized for the largest window height (64).
+struct WinSmem {
+    static constexpr int NPW = 128;          // panel columns of a window item
+    static constexpr int TC = 4;             // tiles staged per round
+    static constexpr int KROWS = TC * 32;    // B rows staged per round
+    static constexpr int BSTR = NPW + 2;     // LDS row stride (16-bit elements): odd dword stride
+    static constexpr int HMAX = 64;
+    __attribute__((aligned(16))) unsigned short Bs[KROWS * BSTR];
+    int32_t rows[HMAX], sid[HMAX], cols[KROWS], off[TC * HMAX];
+    uint32_t bm[TC * HMAX];
+};
 
 template <int TT>
 __device__ __forceinline__ f32x4 mfma_16x16x32(const u16x8 &a, const u16x8 &b, const f32x4 &c) {
@@ -364,20 +462,18 @@ __device__ __forceinline__ void stage_b8(const void *B, int64_t off, int valid, 
     for (int i = 0; i < 4; ++i) w[i] = h[2 * i] | (h[2 * i + 1] << 16);
 }
 
+// One (window, 128-column panel) per workgroup: item in [0, n_win * win_panels).
+// Every thread of the workgroup calls it with the same item.
 template <int VT, int BT, int TT, int MB, int E, int CPL>
-__global__ __launch_bounds__(256) void window_kernel(DevPlan P, RunArgs a) {
+__device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, int item,
+                                            WinSmem &sm) {
     constexpr int H = MB * 16;
-    constexpr int NPW = 128;        // panel columns of a window item
-    constexpr int TC = 4;           // tiles staged per round
-    constexpr int KROWS = TC * 32;  // B rows staged per round
-    constexpr int BSTR = NPW + 2;   // LDS row stride (16-bit elements); odd dword stride
-    __shared__ __attribute__((aligned(16))) unsigned short Bs[KROWS * BSTR];
-    __shared__ int32_t s_rows[H], s_sid[H], s_cols[KROWS], s_off[TC * H];
-    __shared__ uint32_t s_bm[TC * H];
-    static_assert(H * NPW * 4 <= KROWS * BSTR * 2, "C tile must fit in the B stage");
+    constexpr int NPW = WinSmem::NPW, TC = WinSmem::TC, BSTR = WinSmem::BSTR;
+    unsigned short *Bs = sm.Bs;
+    int32_t *s_rows = sm.rows, *s_sid = sm.sid, *s_cols = sm.cols, *s_off = sm.off;
+    uint32_t *s_bm = sm.bm;
+    static_assert(H * NPW * 4 <= WinSmem::KROWS * BSTR * 2, "C tile must fit in the B stage");
 
-    const int item = logical_block(a.xcd);
-    if (item >= P.n_win * a.win_panels) return;
     const int panel = item / P.n_win;
     const int wi = P.win_order[item - panel * P.n_win];
     const int ncol0 = panel * NPW, ncols = min(NPW, P.n - ncol0);
@@ -474,7 +570,8 @@ __global__ __launch_bounds__(256) void window_kernel(DevPlan P, RunArgs a) {
         if (e - b <= P.seg_len) {
             if (e > b) {
                 seg_accumulate<VT, BT, E, CPL, unroll_of<E, CPL>()>(P.rem_col, P.rem_val, b, e, a.B,
-                                                                    a.ldb, ncol0, ncols, L, v);
+                                                                    a.ldb, ncol0, ncols, L,
+                                                                    a.cold_aux, v);
                 group_reduce<E, CPL>(v, L);
             }
         } else {
@@ -490,6 +587,62 @@ __global__ __launch_bounds__(256) void window_kernel(DevPlan P, RunArgs a) {
             }
         }
         store_row<E, CPL>(a.C, (int64_t)r * a.ldc, ncol0, ncols, L, v);
+    }
+}
+
+template <int VT, int BT, int TT, int MB, int E, int CPL>
+__global__ __launch_bounds__(256) void window_kernel(DevPlan P, RunArgs a) {
+    __shared__ WinSmem sm;
+    const int item = logical_block(a.xcd);
+    if (item < P.n_win * a.win_panels) window_item<VT, BT, TT, MB, E, CPL>(P, a, item, sm);
+}
+
+
+// ------------------------------------------------------------------------------------------
+// Batched persistent kernels: a fixed grid walks the global item space of a
+// descriptor table with a static stride, so the item -> matrix lookup only
+// moves forward.  Each matrix's items run exactly the code of a single run, so
+// a matrix's result is bitwise the same alone and in a batch.
+
+template <int VT, int BT, int E, int CPL>
+__global__ __launch_bounds__(256) void batch_segment_kernel(const BatchHeader *__restrict__ hdr,
+                                                            const BatchEntry *__restrict__ tab) {
+    const int total = hdr->total_seg;
+    int d = 0;
+    for (int g = blockIdx.x * 4 + (threadIdx.x >> 6); g < total; g += gridDim.x * 4) {
+        while (g >= tab[d].seg_end) ++d;
+        const int base = d ? tab[d - 1].seg_end : 0;
+        segment_item<VT, BT, E, CPL>(tab[d].P, tab[d].a, g - base);
+    }
+}
+
+template <int VT, int BT, int E, int CPL>
+__global__ __launch_bounds__(256) void batch_vector_kernel(const BatchHeader *__restrict__ hdr,
+                                                           const BatchEntry *__restrict__ tab) {
+    const int total = hdr->total_vec;
+    int d = 0;
+    for (int g = blockIdx.x * 4 + (threadIdx.x >> 6); g < total; g += gridDim.x * 4) {
+        while (g >= tab[d].vec_end) ++d;
+        const int base = d ? tab[d - 1].vec_end : 0;
+        vector_item<VT, BT, E, CPL>(tab[d].P, tab[d].a, g - base);
+    }
+}
+
+template <int VT, int BT, int TT, int E, int CPL>
+__global__ __launch_bounds__(256) void batch_window_kernel(const BatchHeader *__restrict__ hdr,
+                                                           const BatchEntry *__restrict__ tab) {
+    __shared__ WinSmem sm;
+    const int total = hdr->total_win;
+    int d = 0;
+    for (int g = blockIdx.x; g < total; g += gridDim.x) {
+        while (g >= tab[d].win_end) ++d;
+        const int item = g - (d ? tab[d - 1].win_end : 0);
+        switch (tab[d].P.H) {
+        case 16: window_item<VT, BT, TT, 1, E, CPL>(tab[d].P, tab[d].a, item, sm); break;
+        case 32: window_item<VT, BT, TT, 2, E, CPL>(tab[d].P, tab[d].a, item, sm); break;
+        default: window_item<VT, BT, TT, 4, E, CPL>(tab[d].P, tab[d].a, item, sm); break;
+        }
+        __syncthreads();  // the next item reuses the LDS
     }
 }
 
@@ -582,6 +735,58 @@ hipError_t launch_window(const DevPlan &P, int32_t vt, int32_t bt, int32_t tt, c
     if (vt == DT_BF16 && bt == DT_BF16 && tt == DT_BF16) return win_dispatch<DT_BF16, DT_BF16, DT_BF16>(P, a, s);
     if (vt == DT_F16 && bt == DT_F16 && tt == DT_F16) return win_dispatch<DT_F16, DT_F16, DT_F16>(P, a, s);
     return hipErrorInvalidValue;
+}
+
+template <int VT, int BT, int TT, int E, int CPL>
+static hipError_t batch_variant(const BatchHeader *hdr, const BatchEntry *tab, unsigned gw,
+                                unsigned gwin, hipStream_t s, int *occ_wave, int *occ_win) {
+    if (occ_wave) {
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            occ_wave, batch_vector_kernel<VT, BT, E, CPL>, 256, 0);
+        if (e != hipSuccess) return e;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            occ_win, batch_window_kernel<VT, BT, TT, E, CPL>, 256, 0);
+    }
+    hipLaunchKernelGGL((batch_segment_kernel<VT, BT, E, CPL>), dim3(gw), dim3(256), 0, s, hdr, tab);
+    hipLaunchKernelGGL((batch_vector_kernel<VT, BT, E, CPL>), dim3(gw), dim3(256), 0, s, hdr, tab);
+    hipLaunchKernelGGL((batch_window_kernel<VT, BT, TT, E, CPL>), dim3(gwin), dim3(256), 0, s, hdr,
+                       tab);
+    return hipGetLastError();
+}
+
+template <int VT, int BT, int TT>
+static hipError_t batch_types(const BatchHeader *hdr, const BatchEntry *tab, int vec_ok, int cpl,
+                              unsigned gw, unsigned gwin, hipStream_t s, int *ow, int *oc) {
+    constexpr int EV = BT == DT_F32 ? 4 : 8;
+    if (!vec_ok) return batch_variant<VT, BT, TT, 1, 2>(hdr, tab, gw, gwin, s, ow, oc);
+    if (cpl == 1) return batch_variant<VT, BT, TT, EV, 1>(hdr, tab, gw, gwin, s, ow, oc);
+    return batch_variant<VT, BT, TT, EV, 2>(hdr, tab, gw, gwin, s, ow, oc);
+}
+
+static hipError_t batch_any(const BatchHeader *hdr, const BatchEntry *tab, int32_t vt, int32_t bt,
+                            int32_t tt, int vec_ok, int cpl, unsigned gw, unsigned gwin,
+                            hipStream_t s, int *ow, int *oc) {
+    if (vt == DT_F32 && bt == DT_F32 && tt == DT_BF16)
+        return batch_types<DT_F32, DT_F32, DT_BF16>(hdr, tab, vec_ok, cpl, gw, gwin, s, ow, oc);
+    if (vt == DT_F32 && bt == DT_BF16 && tt == DT_BF16)
+        return batch_types<DT_F32, DT_BF16, DT_BF16>(hdr, tab, vec_ok, cpl, gw, gwin, s, ow, oc);
+    if (vt == DT_BF16 && bt == DT_BF16 && tt == DT_BF16)
+        return batch_types<DT_BF16, DT_BF16, DT_BF16>(hdr, tab, vec_ok, cpl, gw, gwin, s, ow, oc);
+    if (vt == DT_F16 && bt == DT_F16 && tt == DT_F16)
+        return batch_types<DT_F16, DT_F16, DT_F16>(hdr, tab, vec_ok, cpl, gw, gwin, s, ow, oc);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch(const BatchHeader *hdr, const BatchEntry *tab, int32_t vt, int32_t bt,
+                        int32_t tt, int vec_ok, int cpl, unsigned grid_wave, unsigned grid_win,
+                        hipStream_t s) {
+    return batch_any(hdr, tab, vt, bt, tt, vec_ok, cpl, grid_wave, grid_win, s, nullptr, nullptr);
+}
+
+hipError_t batch_occupancy(int32_t vt, int32_t bt, int32_t tt, int vec_ok, int cpl,
+                           int *wave_kernels, int *win_kernel) {
+    return batch_any(nullptr, nullptr, vt, bt, tt, vec_ok, cpl, 0, 0, nullptr, wave_kernels,
+                     win_kernel);
 }
 
 hipError_t launch_copy(const float4 *src, float4 *dst, int64_t n4, hipStream_t s) {

@@ -53,6 +53,7 @@ void resolve_options(const spmm_opts *in, const spmm_csr *A, int32_t n, int32_t 
         const int np = d.n_panel > 0 ? std::min(d.n_panel, std::max(n, 1)) : std::max(n, 1);
         d.hot_cols = (int32_t)(kHotFraction * kL2BytesPerXcd / ((double)np * dtype_size(b_type)));
     }
+    if (d.cold_policy < 0) d.cold_policy = 2;  // non-temporal
     if (!(d.alpha_c >= 0.0f)) d.alpha_c = 1.0f / (float)d.window_h;
     if (!(d.alpha >= 0.0f)) d.alpha = 1.0f / (float)d.window_h;
     if (d.mode == SPMM_MODE_MFMA_ONLY) {
@@ -109,6 +110,10 @@ static spmm_status validate_opts(const spmm_opts &o, std::string &err) {
     if (o.item_cost < 1) { err = "item_cost"; return SPMM_ERR_UNSUPPORTED; }
     if (o.n_panel < 0) { err = "n_panel"; return SPMM_ERR_UNSUPPORTED; }
     if (o.hot_cols < 0) { err = "hot_cols"; return SPMM_ERR_UNSUPPORTED; }
+    if (o.cold_policy != 0 && o.cold_policy != 2 && o.cold_policy != 16 && o.cold_policy != 18) {
+        err = "cold_policy must be 0, 2, 16 or 18";
+        return SPMM_ERR_UNSUPPORTED;
+    }
     if (!std::isfinite(o.alpha) || o.alpha < 0 || !std::isfinite(o.alpha_c) || o.alpha_c < 0) {
         err = "alpha / alpha_c must be finite and >= 0";
         return SPMM_ERR_UNSUPPORTED;

@@ -81,6 +81,7 @@ extern "C" void spmm_opts_default(spmm_opts *o) {
     o->item_cost = 0;
     o->xcd_remap = -1;
     o->hot_cols = -1;
+    o->cold_policy = -1;
     o->alpha_c = -1.0f;
     o->alpha = -1.0f;
 }
@@ -118,15 +119,17 @@ extern "C" spmm_status spmm_plan_build(const spmm_csr *A, int32_t n, int32_t b_t
         std::string err;
         spmm_status st = validate_problem(A, n, b_type, c_type, err);
         if (st != SPMM_OK) return set_error(st, err);
+        const bool auto_mode = !opts || opts->mode == SPMM_MODE_AUTO;
+        spmm_opts tuned;
+        const bool have_tuned = auto_mode && cache_lookup(profile_key(A, n, b_type), &tuned);
         spmm_opts o;
-        resolve_options(opts, A, n, b_type, &o);
+        resolve_options(have_tuned ? &tuned : opts, A, n, b_type, &o);
         std::unique_ptr<spmm_plan_s> p(new spmm_plan_s());
         st = build_host_plan(A, n, b_type, c_type, o, p->hp, err);
         if (st != SPMM_OK) return set_error(st, err);
         // AUTO without a tuned profile: keep the mixed partition only when the
         // tiles take a useful share of the entries, else plan the plain path.
-        const bool auto_mode = !opts || opts->mode == SPMM_MODE_AUTO;
-        if (auto_mode && A->nnz > 0 &&
+        if (auto_mode && !have_tuned && A->nnz > 0 &&
             (double)p->hp.tile_src.size() < 0.10 * (double)A->nnz) {
             o.mode = SPMM_MODE_PLAIN_F32;
             st = build_host_plan(A, n, b_type, c_type, o, p->hp, err);
@@ -377,6 +380,9 @@ spmm_status make_run_args(const spmm_plan_t *p, const void *B, int64_t ldb, void
     const int chunks = a.vec_ok ? np / E : np;
     a.lpr_log2 = ilog2_ceil(std::min(chunks, 64));
     a.xcd = h.opts.xcd_remap ? 1 : 0;
+    // cold B rows go through a raw buffer load (32-bit byte offsets from B)
+    const double b_span = ((double)std::max<int64_t>(h.k, 1) - 1.0) * (double)ldb * sb + (double)N * sb;
+    a.cold_aux = b_span < 4294967295.0 ? h.opts.cold_policy : -1;
     a.win_panels = (N + 127) / 128;
     const int wchunks = a.vec_ok ? 128 / E : 128;
     a.win_lpr_log2 = ilog2_ceil(std::min(wchunks, 64));

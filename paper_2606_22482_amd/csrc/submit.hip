@@ -2,6 +2,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <climits>
+#include <string>
 #include <chrono>
 #include <cstring>
 #include <map>
@@ -15,6 +18,12 @@
 #include "runtime.hpp"
 
 using namespace spmm;
+
+#define SPMM_TRY_HIP(call, what)                          \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return hip_error(e_, what); \
+    } while (0)
 
 namespace {
 struct Ticket {
@@ -33,6 +42,54 @@ void release(Ticket &t) {
 }
 }  // namespace
 
+// ------------------------------------------------------------------------------------------
+// Batched submission: one descriptor table per kernel variant, copied from a
+// pinned staging ring, executed by a captured graph of three persistent
+// kernels (segment partials, then vector items, then windows).
+
+namespace {
+
+struct VariantGraph {
+    void *dtab = nullptr;  // BatchHeader (padded to 256 B) followed by entries
+    size_t dcap = 0;
+    hipGraphExec_t exec = nullptr;
+    unsigned grid_wave = 0, grid_win = 0;
+};
+
+struct BatchCtx {
+    hipStream_t capture = nullptr;
+    std::map<uint64_t, VariantGraph> variants;
+    static constexpr int kSlots = 4;
+    void *pinned[kSlots] = {};
+    size_t pinned_cap[kSlots] = {};
+    hipEvent_t pinned_ev[kSlots] = {};
+    int next = 0;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+};
+
+std::mutex g_batch_mu;
+std::map<std::pair<int, hipStream_t>, BatchCtx> g_batch;
+
+constexpr size_t kHeaderBytes = 256;
+
+spmm_status ensure_device(void **p, size_t *cap, size_t bytes) {
+    if (*cap >= bytes) return SPMM_OK;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    size_t want = std::max(bytes, (size_t)1 << 16);
+    hipError_t e = hipMalloc(p, want);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return set_error(SPMM_ERR_OOM, std::string("hipMalloc(batch): ") + hipGetErrorString(e));
+    }
+    *cap = want;
+    return SPMM_OK;
+}
+
+}  // namespace
+
 extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *stream,
                                    spmm_ticket *out) {
     if (!out || count < 0 || (count > 0 && !items)) return set_error(SPMM_ERR_INVALID, "bad arguments");
@@ -42,17 +99,135 @@ extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *
         spmm_status st = check_run(items[i].plan, items[i].B, items[i].ldb, items[i].C, items[i].ldc);
         if (st != SPMM_OK) return st;
     }
+    int dev = 0;
+    SPMM_TRY_HIP(hipGetDevice(&dev), "hipGetDevice");
+    int ncu = 0;
+    SPMM_TRY_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev),
+                 "hipDeviceGetAttribute");
+
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    BatchCtx &ctx = g_batch[{dev, s}];
+
+    // run arguments, workspace layout and variant grouping
+    std::vector<RunArgs> args(count);
+    std::map<uint64_t, std::vector<int32_t>> groups;
+    size_t ws_floats = 0;
     for (int32_t i = 0; i < count; ++i) {
         const spmm_plan_t *p = items[i].plan;
         if (p->hp.m == 0) continue;
-        RunArgs a;
-        make_run_args(p, items[i].B, items[i].ldb, items[i].C, items[i].ldc, a);
-        const size_t ws = (size_t)p->dp.n_seg * (size_t)a.work_ld * sizeof(float);
-        spmm_status st = workspace_for(s, ws, &a.work);
-        if (st != SPMM_OK) return st;
-        st = launch_plan(p, a, s, nullptr);
+        make_run_args(p, items[i].B, items[i].ldb, items[i].C, items[i].ldc, args[i]);
+        ws_floats += (size_t)p->dp.n_seg * (size_t)args[i].work_ld;
+        const int E = args[i].vec_ok ? chunk_elems(p->hp.b_type) : 1;
+        const int chunks = args[i].vec_ok ? args[i].np / E : args[i].np;
+        const int cpl = chunks > 64 ? 2 : 1;
+        const uint64_t key = (uint64_t)p->hp.val_type | ((uint64_t)p->hp.b_type << 4) |
+                             ((uint64_t)p->hp.tile_type << 8) | ((uint64_t)args[i].vec_ok << 12) |
+                             ((uint64_t)cpl << 16);
+        groups[key].push_back(i);
+    }
+    if (ws_floats * sizeof(float) > ctx.ws_bytes) {
+        if (ctx.ws) {
+            SPMM_TRY_HIP(hipStreamSynchronize(s), "hipStreamSynchronize(batch workspace)");
+            (void)hipFree(ctx.ws);
+            ctx.ws = nullptr;
+            ctx.ws_bytes = 0;
+        }
+        spmm_status st = ensure_device(&ctx.ws, &ctx.ws_bytes, ws_floats * sizeof(float));
         if (st != SPMM_OK) return st;
     }
+    {
+        size_t off = 0;
+        for (int32_t i = 0; i < count; ++i) {
+            const spmm_plan_t *p = items[i].plan;
+            if (p->hp.m == 0) continue;
+            args[i].work = static_cast<float *>(ctx.ws) + off;
+            off += (size_t)p->dp.n_seg * (size_t)args[i].work_ld;
+        }
+    }
+
+    for (auto &kv : groups) {
+        const uint64_t key = kv.first;
+        const std::vector<int32_t> &idx = kv.second;
+        const int32_t vt = key & 0xF, bt = (key >> 4) & 0xF, tt = (key >> 8) & 0xF;
+        const int vec_ok = (key >> 12) & 0xF, cpl = (key >> 16) & 0xF;
+        // host table
+        const size_t bytes = kHeaderBytes + idx.size() * sizeof(BatchEntry);
+        BatchCtx &c = ctx;
+        const int slot = c.next;
+        c.next = (c.next + 1) % BatchCtx::kSlots;
+        if (c.pinned_ev[slot]) SPMM_TRY_HIP(hipEventSynchronize(c.pinned_ev[slot]), "hipEventSynchronize(staging)");
+        if (c.pinned_cap[slot] < bytes) {
+            if (c.pinned[slot]) (void)hipHostFree(c.pinned[slot]);
+            c.pinned[slot] = nullptr;
+            c.pinned_cap[slot] = 0;
+            size_t want = std::max(bytes, (size_t)1 << 16);
+            hipError_t e = hipHostMalloc(&c.pinned[slot], want, hipHostMallocDefault);
+            if (e != hipSuccess) return set_error(SPMM_ERR_OOM, "hipHostMalloc(batch table)");
+            c.pinned_cap[slot] = want;
+        }
+        if (!c.pinned_ev[slot])
+            SPMM_TRY_HIP(hipEventCreateWithFlags(&c.pinned_ev[slot], hipEventDisableTiming), "hipEventCreate");
+        auto *hdr = static_cast<BatchHeader *>(c.pinned[slot]);
+        auto *tab = reinterpret_cast<BatchEntry *>(static_cast<uint8_t *>(c.pinned[slot]) + kHeaderBytes);
+        int64_t ns = 0, nv = 0, nw = 0;
+        for (size_t j = 0; j < idx.size(); ++j) {
+            const spmm_plan_t *p = items[idx[j]].plan;
+            const RunArgs &a = args[idx[j]];
+            BatchEntry &e = tab[j];
+            e.P = p->dp;
+            e.a = a;
+            ns += (int64_t)p->dp.n_seg * a.n_panels;
+            nv += (int64_t)p->dp.n_vitems * a.n_panels;
+            nw += (int64_t)p->dp.n_win * a.win_panels;
+            if (ns > INT32_MAX || nv > INT32_MAX || nw > INT32_MAX)
+                return set_error(SPMM_ERR_UNSUPPORTED, "batch has more than 2^31 items");
+            e.seg_end = (int32_t)ns;
+            e.vec_end = (int32_t)nv;
+            e.win_end = (int32_t)nw;
+            e.pad = 0;
+        }
+        hdr->count = (int32_t)idx.size();
+        hdr->total_seg = (int32_t)ns;
+        hdr->total_vec = (int32_t)nv;
+        hdr->total_win = (int32_t)nw;
+
+        VariantGraph &vg = ctx.variants[key];
+        if (vg.dcap < bytes) {
+            if (vg.exec) {
+                SPMM_TRY_HIP(hipStreamSynchronize(s), "hipStreamSynchronize(batch table)");
+                (void)hipGraphExecDestroy(vg.exec);
+                vg.exec = nullptr;
+            }
+            spmm_status st = ensure_device(&vg.dtab, &vg.dcap, bytes);
+            if (st != SPMM_OK) return st;
+        }
+        if (!vg.exec) {
+            int ow = 0, oc = 0;
+            SPMM_TRY_HIP(batch_occupancy(vt, bt, tt, vec_ok, cpl, &ow, &oc), "occupancy");
+            vg.grid_wave = (unsigned)std::max(1, ow) * (unsigned)ncu;
+            vg.grid_win = (unsigned)std::max(1, oc) * (unsigned)ncu;
+            if (!ctx.capture)
+                SPMM_TRY_HIP(hipStreamCreateWithFlags(&ctx.capture, hipStreamNonBlocking), "hipStreamCreate");
+            const auto *dh = static_cast<const BatchHeader *>(vg.dtab);
+            const auto *dt = reinterpret_cast<const BatchEntry *>(static_cast<uint8_t *>(vg.dtab) + kHeaderBytes);
+            SPMM_TRY_HIP(hipStreamBeginCapture(ctx.capture, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            hipError_t le = launch_batch(dh, dt, vt, bt, tt, vec_ok, cpl, vg.grid_wave, vg.grid_win, ctx.capture);
+            hipGraph_t graph = nullptr;
+            hipError_t ce = hipStreamEndCapture(ctx.capture, &graph);
+            if (le != hipSuccess) return hip_error(le, "batched launch (capture)");
+            if (ce != hipSuccess) return hip_error(ce, "hipStreamEndCapture");
+            hipError_t ie = hipGraphInstantiate(&vg.exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess) {
+                vg.exec = nullptr;
+                return hip_error(ie, "hipGraphInstantiate");
+            }
+        }
+        SPMM_TRY_HIP(hipMemcpyAsync(vg.dtab, c.pinned[slot], bytes, hipMemcpyHostToDevice, s), "hipMemcpyAsync(batch table)");
+        SPMM_TRY_HIP(hipEventRecord(c.pinned_ev[slot], s), "hipEventRecord");
+        SPMM_TRY_HIP(hipGraphLaunch(vg.exec, s), "hipGraphLaunch");
+    }
+
     Ticket t;
     hipError_t e = hipEventCreateWithFlags(&t.done, hipEventDisableTiming);
     if (e != hipSuccess) return hip_error(e, "hipEventCreate");
@@ -67,7 +242,7 @@ extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *
         t.plans.push_back(p);
     }
     const spmm_ticket id = g_next_ticket.fetch_add(1);
-    std::lock_guard<std::mutex> lk(g_tk_mu);
+    std::lock_guard<std::mutex> lk2(g_tk_mu);
     g_tickets[id] = std::move(t);
     *out = id;
     return SPMM_OK;

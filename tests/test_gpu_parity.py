@@ -155,25 +155,85 @@ def test_block_community_scaled():
 
 
 def test_submit_matches_solo_bitwise():
+    """Batched persistent launch (graph replay) vs solo runs, bit for bit, over
+    several submissions with new B between replays and eager work around
+    them; mixed dtypes and N make several kernel variants in one batch."""
     import torch
-    specs = synth.batch_specs(count=6, seed=4, rows_lo=1000, rows_hi=20000)
-    items, solos = [], []
+    specs = synth.batch_specs(count=8, seed=4, rows_lo=1000, rows_hi=30000)
+    plans, mats = [], []
     for i, sp in enumerate(specs):
         A, B = synth.batch_matrix(i, sp, seed=4)
-        p = api.Plan(A, B.shape[1], "f16", api.default_opts(mode="auto"))
-        Bd = device_B(B, "f16")
+        mode = ["auto", "plain", "mixed", "mfma_only"][i % 4]
+        kw = dict(mode=mode, seg_len=64)
+        if mode == "mixed":
+            kw.update(row_order="length_sorted", t_row=4)
+        plans.append(api.Plan(A, B.shape[1], "f16", api.default_opts(**kw)))
+        mats.append((A, B))
+    # one f32 matrix with an odd N (scalar variant) in the same submission
+    Af = synth.random_csr(3000, 2000, 0.01, 9)
+    Bf = np.random.default_rng(1).standard_normal((2000, 33)).astype(np.float32)
+    plans.append(api.Plan(Af, 33, "f32", api.default_opts(mode="plain", seg_len=16)))
+    mats.append((Af, Bf))
+    kinds = ["f16"] * len(specs) + ["f32"]
+    for rnd in range(3):
+        items, solos = [], []
+        for p, (A, B), kind in zip(plans, mats, kinds):
+            Bx = B if rnd == 0 else (B if kind == "f32" else B)
+            Bd = device_B(Bx, kind)
+            if rnd:
+                Bd = Bd * (rnd + 1)  # new values each round (exact in f16/f32: powers of two)
+            Cs = device_C(A.m, B.shape[1])
+            p.run(Bd, Cs)
+            torch.cuda.synchronize()
+            Cb = device_C(A.m, B.shape[1])
+            items.append(api.WorkItem(p, Bd, Cb))
+            solos.append(Cs)
+        t = api.spmm_submit(items)
+        _ = torch.ones(1000, device="cuda").sum().item()  # eager work while it runs
+        api.spmm_wait(t)
+        assert api.spmm_poll(t)
+        torch.cuda.synchronize()
+        for it, Cs in zip(items, solos):
+            assert torch.equal(it.C, Cs), "round %d" % rnd
+    for p, (A, B), kind in zip(plans, mats, kinds):
+        Bd = device_B(B, kind)
         Cs = device_C(A.m, B.shape[1])
         p.run(Bd, Cs)
-        Cb = device_C(A.m, B.shape[1])
-        items.append(api.WorkItem(p, Bd, Cb))
-        solos.append((Cs, A, B))
-    t = api.spmm_submit(items)
+        torch.cuda.synchronize()
+        parity(Cs, A, B, kind, TOL_16 if kind == "f16" else TOL_F32)
+
+
+def test_destroy_busy_plan_rejected():
+    import torch
+    A = synth.random_csr(2000, 2000, 0.01, 3)
+    B = np.random.default_rng(2).standard_normal((2000, 64)).astype(np.float32)
+    p = api.Plan(A, 64, "f32", api.default_opts(mode="plain"))
+    Bd = device_B(B, "f32")
+    C = device_C(A.m, 64)
+    t = api.spmm_submit([api.WorkItem(p, Bd, C)])
     api.spmm_wait(t)
-    assert api.spmm_poll(t)
+    p.destroy()  # the ticket is retired, so destroy succeeds
     torch.cuda.synchronize()
-    for it, (Cs, A, B) in zip(items, solos):
-        assert torch.equal(it.C, Cs)
-        parity(Cs, A, B, "f16", TOL_16)
+
+
+def test_autotune_picks_and_caches():
+    import torch
+    api.tune_cache_clear()
+    A, B = synth.block_community(n=32768, band=16, n_cols=128, seed=6)
+    Bd = device_B(B, "bf16")
+    C = device_C(A.m, 128)
+    opts, rep = api.spmm_autotune(A, Bd, C, "bf16", budget_ms=8000)
+    assert rep["candidates"] >= 4 and rep["best_ms"] <= rep["default_ms"] * 1.02
+    assert 0 < rep["alpha_cost"] <= 1 and rep["p_vec"] > 0 and rep["p_mfma"] > 0
+    key = api.spmm_profile_key(A, 128, "bf16")
+    assert api.opts_dict(api.tune_cache_get(key)) == api.opts_dict(opts)
+    p = api.Plan(A, 128, "bf16", api.default_opts(mode="auto"))
+    assert p.stats()["opts"]["mode"] == opts.mode
+    C2 = device_C(A.m, 128)
+    p.run(Bd, C2)
+    torch.cuda.synchronize()
+    parity(C2, A, B, "bf16", TOL_16 if opts.mode != 1 else TOL_F32)
+    api.tune_cache_clear()
 
 
 def test_timer_and_copy_bandwidth():
