@@ -105,6 +105,88 @@ def cpu_baseline(A, B, b_kind, n, budget_s=12.0):
                       % (rows, m, 100.0 * nnz / max(1, A.nnz), n, dt)}
 
 
+def serve_bench(args):
+    """Serving stream: Poisson arrivals at 0.7x the closed-loop saturation rate
+    measured on the same request list; plans pre-built (resident)."""
+    import torch
+    from paper_2606_22482_amd import serve, synth
+    t0 = time.perf_counter()
+    pool = synth.serving_pool(n_graphs=args.pool_graphs, n_masks=args.pool_masks, seed=5,
+                              max_rows=args.max_rows, max_mask_rows=args.max_mask_rows)
+    log("pool: %d matrices, %.1f M nnz (%.1f s)" % (len(pool), sum(p["A"].nnz for p in pool) / 1e6,
+                                                     time.perf_counter() - t0))
+    reqs = synth.serving_requests(args.requests, len(pool), args.pool_graphs, seed=5)
+    srv = serve.Server(pool, n_streams=args.streams, max_batch=args.max_batch)
+    t0 = time.perf_counter()
+    keys = sorted({(d["matrix"], d["n"], d["b_kind"]) for d in reqs})
+    st = serve.Stats()
+    for k in keys:
+        srv.plans.get(k, st)
+    log("prewarm: %d plans (%.1f s)" % (len(keys), time.perf_counter() - t0))
+    closed = srv.run(reqs[: min(len(reqs), 1000)], realtime=False).summary()
+    rate = 0.7 * closed["throughput_req_s"]
+    log("closed loop: %.1f req/s -> rate %.1f req/s" % (closed["throughput_req_s"], rate))
+    timed = synth.serving_requests(args.requests, len(pool), args.pool_graphs, seed=5, rate=rate)
+    s = srv.run(timed, realtime=True).summary()
+    out = {"metric": METRIC, "value": round(s["gflops"], 2), "unit": "GFLOP/s", "n_gpus": 1,
+           "steps": args.requests, "warmup": 0, "ms_per_step": round(s["mean_ms"], 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32|bf16", "data": "synthetic",
+           "config": {"workload": "serving_stream", "requests": args.requests,
+                      "rate_req_s": round(rate, 2), "pool": len(pool),
+                      "max_rows": args.max_rows, "max_mask_rows": args.max_mask_rows,
+                      "streams": args.streams, "budget_GB": 200},
+           "p50_ms": round(s["p50_ms"], 3), "p99_ms": round(s["p99_ms"], 3),
+           "throughput_req_s": round(s["throughput_req_s"], 2),
+           "serving": s, "closed_loop": closed}
+    print(json.dumps(out), flush=True)
+
+
+def batch_bench(args):
+    """Uneven matrices in one batched submission (graph replay of the
+    persistent kernels) vs the same matrices as separate spmm_run calls."""
+    import torch
+    from paper_2606_22482_amd import api, synth
+    t0 = time.perf_counter()
+    specs = synth.batch_specs(count=args.batch_count, seed=4)
+    plans, items, flops = [], [], 0.0
+    for i, sp in enumerate(specs):
+        A, B = synth.batch_matrix(i, sp, seed=4)
+        p = api.Plan(A, B.shape[1], "f16", api.default_opts(mode="auto"))
+        Bd = api.device_tensor(B, "f16")
+        Cd = torch.empty((A.m, B.shape[1]), dtype=torch.float32, device="cuda")
+        plans.append(p)
+        items.append(api.WorkItem(p, Bd, Cd))
+        flops += 2.0 * A.nnz * B.shape[1]
+    log("batch: %d matrices, %.1f GFLOP per pass (%.1f s)" % (len(items), flops / 1e9,
+                                                             time.perf_counter() - t0))
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        api.spmm_wait(api.spmm_submit(items))
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        api.spmm_submit(items)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_batch = e0.elapsed_time(e1) / args.steps
+    e0.record(stream)
+    for _ in range(args.steps):
+        for it in items:
+            it.plan.run(it.B, it.C)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_sep = e0.elapsed_time(e1) / args.steps
+    out = {"metric": METRIC, "value": round(flops / (ms_batch * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms_batch, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f16in-f32acc", "data": "synthetic",
+           "config": {"workload": "batched_uneven_%d" % len(items)},
+           "separate_runs_ms": round(ms_sep, 4), "speedup_vs_separate": round(ms_sep / ms_batch, 3)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +196,14 @@ def main():
     ap.add_argument("--modes", default="plain,mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--opts", default="", help="extra plan options, k=v[,k=v]")
+    ap.add_argument("--requests", type=int, default=5000)
+    ap.add_argument("--pool-graphs", type=int, default=64)
+    ap.add_argument("--pool-masks", type=int, default=16)
+    ap.add_argument("--max-rows", type=int, default=500000)
+    ap.add_argument("--max-mask-rows", type=int, default=8192)
+    ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--max-batch", type=int, default=64)
+    ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run the device copy kernel over this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -127,6 +217,10 @@ def main():
 
     _lib.load()
     torch.cuda.set_device(0)
+    if args.workload == "serve":
+        return serve_bench(args)
+    if args.workload == "batch":
+        return batch_bench(args)
     if args.copy_probe:
         bw = api.spmm_copy_bandwidth(args.copy_probe)
         print(json.dumps({"copy_bytes": args.copy_probe, "copy_launches": 13,

@@ -1,0 +1,275 @@
+"""Continuous-batching SpMM server over the C ABI.
+
+Requests (matrix id from a resident pool, N, B type, B seed, arrival time)
+arrive on a Poisson clock.  The scheduler:
+
+* admits waiting requests in arrival order while their HBM footprint (B, C,
+  segment workspace, and the plan if it is not resident yet) fits the budget;
+  a request that does not fit lets later, smaller ones pass (no head-of-line
+  blocking) and a request that can never fit is rejected with the library's
+  BUDGET status;
+* keeps plans resident in an LRU cache charged to the same budget, evicting
+  only plans no in-flight request uses;
+* forms a batch of every admitted request as soon as one of its streams is
+  free and launches it with one ``spmm_submit`` (one graph replay of the
+  persistent kernels), so batches on different streams overlap on the device
+  while new requests keep being admitted as earlier ones complete;
+* polls tickets and retires finished requests immediately, freeing their
+  memory, and records latency = completion - arrival on the host monotonic
+  clock.
+
+The arithmetic of every request is fixed by its plan and N, so a request's
+result is bitwise the same alone and in any mix.
+"""
+from __future__ import annotations
+
+import collections
+import threading
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import _lib as L
+from . import api
+
+GiB = 1 << 30
+
+
+@dataclass
+class Request:
+    rid: int
+    matrix: int
+    n: int
+    b_kind: str
+    seed: int
+    arrival: float                      # seconds from the start of the stream
+    admitted_at: float = -1.0
+    done_at: float = -1.0
+    status: str = "waiting"            # waiting | admitted | running | done | rejected
+    footprint: int = 0
+    B: object = None
+    C: object = None
+
+
+@dataclass
+class Stats:
+    latencies_ms: list = field(default_factory=list)
+    rejected: int = 0
+    batches: int = 0
+    batch_sizes: list = field(default_factory=list)
+    max_queue: int = 0
+    flops: float = 0.0
+    wall_s: float = 0.0
+    plan_builds: int = 0
+    plan_evictions: int = 0
+
+    def summary(self) -> dict:
+        lat = np.array(self.latencies_ms) if self.latencies_ms else np.zeros(1)
+        done = len(self.latencies_ms)
+        return {
+            "completed": done,
+            "rejected": self.rejected,
+            "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()),
+            "throughput_req_s": done / self.wall_s if self.wall_s > 0 else 0.0,
+            "gflops": self.flops / self.wall_s / 1e9 if self.wall_s > 0 else 0.0,
+            "batches": self.batches,
+            "mean_batch": float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0,
+            "max_queue": self.max_queue,
+            "plan_builds": self.plan_builds,
+            "plan_evictions": self.plan_evictions,
+            "wall_s": self.wall_s,
+        }
+
+
+class PlanCache:
+    """Resident plans keyed by (matrix, N, B type), LRU, charged to the budget."""
+
+    def __init__(self, pool, opts_for):
+        self.pool = pool
+        self.opts_for = opts_for
+        self.plans = collections.OrderedDict()   # key -> (plan, bytes)
+        self.users = collections.Counter()
+
+    def bytes_if_missing(self, key) -> int:
+        if key in self.plans:
+            return 0
+        A = self.pool[key[0]]["A"]
+        # plan upload is ~ the CSR (index + value) plus row pointers
+        return int(A.nnz * 8 + (A.m + 1) * 4 * 3)
+
+    def get(self, key, stats: Stats):
+        if key in self.plans:
+            self.plans.move_to_end(key)
+            return self.plans[key][0]
+        mid, n, b_kind = key
+        A = self.pool[mid]["A"]
+        plan = api.Plan(A, n, b_kind, self.opts_for(self.pool[mid], n, b_kind))
+        self.plans[key] = (plan, plan.stats()["device_bytes"])
+        stats.plan_builds += 1
+        return plan
+
+    def evictable_bytes(self) -> int:
+        return sum(b for k, (p, b) in self.plans.items() if self.users[k] == 0)
+
+    def evict(self, need: int, stats: Stats) -> int:
+        freed = 0
+        for k in list(self.plans.keys()):
+            if freed >= need:
+                break
+            if self.users[k] == 0:
+                plan, b = self.plans.pop(k)
+                plan.destroy()
+                freed += b
+                stats.plan_evictions += 1
+        return freed
+
+    def resident_bytes(self) -> int:
+        return sum(b for _, b in self.plans.values())
+
+
+def default_opts_for(item, n, b_kind):
+    """Plan options per matrix kind: block masks use aligned windows (their
+    64x64 blocks fill 16-row windows), graphs the tuned/heuristic default."""
+    if item["kind"] == "mask":
+        return api.default_opts(mode="mixed", row_order="original_ranges")
+    return api.default_opts(mode="auto")
+
+
+class Server:
+    def __init__(self, pool, budget_bytes=200 * GiB, n_streams=4, max_batch=64,
+                 opts_for=default_opts_for, keep_results=False):
+        import torch
+        self.torch = torch
+        self.pool = pool
+        self.budget = int(budget_bytes)
+        self.max_batch = max_batch
+        self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        self.plans = PlanCache(pool, opts_for)
+        self.keep_results = keep_results
+        self.used = 0
+
+    # --- footprints -------------------------------------------------------------------------
+    def _io_bytes(self, r: Request) -> int:
+        A = self.pool[r.matrix]["A"]
+        sb = 4 if r.b_kind == "f32" else 2
+        return A.k * r.n * sb + A.m * r.n * 4 + A.m * 4  # B, C, workspace bound
+
+    def _plan_key(self, r: Request):
+        return (r.matrix, r.n, r.b_kind)
+
+    # --- main loop ----------------------------------------------------------------------------
+    def run(self, requests, realtime=True):
+        """Serve ``requests`` (list of dicts from synth.serving_requests).
+        With ``realtime`` the arrival times are honoured on the host clock;
+        otherwise every request is available at once (closed loop)."""
+        torch = self.torch
+        reqs = [Request(**{k: d[k] for k in ("rid", "matrix", "n", "b_kind", "seed", "arrival")})
+                for d in requests]
+        stats = Stats()
+        waiting = collections.deque()
+        inflight = {}          # stream index -> (ticket, [requests])
+        free_streams = list(range(len(self.streams)))
+        t0 = time.monotonic()
+        nxt = 0
+        finished = 0
+        total = len(reqs)
+        while finished < total:
+            now = time.monotonic() - t0
+            # arrivals
+            while nxt < total and (not realtime or reqs[nxt].arrival <= now):
+                if not realtime:
+                    reqs[nxt].arrival = now
+                waiting.append(reqs[nxt])
+                nxt += 1
+            stats.max_queue = max(stats.max_queue, len(waiting))
+            # completions
+            for si in list(inflight.keys()):
+                ticket, batch = inflight[si]
+                if api.spmm_poll(ticket):
+                    tdone = time.monotonic() - t0
+                    for r in batch:
+                        r.done_at = tdone
+                        r.status = "done"
+                        stats.latencies_ms.append((tdone - r.arrival) * 1e3)
+                        A = self.pool[r.matrix]["A"]
+                        stats.flops += 2.0 * A.nnz * r.n
+                        self.used -= r.footprint
+                        self.plans.users[self._plan_key(r)] -= 1
+                        if not self.keep_results:
+                            r.B = None
+                            r.C = None
+                        finished += 1
+                    del inflight[si]
+                    free_streams.append(si)
+            # admission + batch formation on a free stream
+            if free_streams and waiting:
+                si = free_streams[0]
+                stream = self.streams[si]
+                batch = []
+                keep = collections.deque()
+                while waiting and len(batch) < self.max_batch:
+                    r = waiting.popleft()
+                    key = self._plan_key(r)
+                    need = self._io_bytes(r) + self.plans.bytes_if_missing(key)
+                    if need > self.budget:
+                        r.status = "rejected"      # can never fit: BUDGET
+                        stats.rejected += 1
+                        finished += 1
+                        continue
+                    if self.used + self.plans.resident_bytes() + need > self.budget:
+                        over = self.used + self.plans.resident_bytes() + need - self.budget
+                        if self.plans.evictable_bytes() >= over:
+                            self.plans.evict(over, stats)
+                        else:
+                            keep.append(r)         # wait for memory; let smaller ones pass
+                            continue
+                    plan = self.plans.get(key, stats)
+                    self.plans.users[key] += 1
+                    r.footprint = self._io_bytes(r)
+                    self.used += r.footprint
+                    A = self.pool[r.matrix]["A"]
+                    dt = torch.float32 if r.b_kind == "f32" else torch.bfloat16
+                    with torch.cuda.stream(stream):
+                        g = torch.Generator(device="cuda")
+                        g.manual_seed(r.seed)
+                        r.B = torch.randn((A.k, r.n), generator=g, device="cuda",
+                                          dtype=torch.float32).to(dt)
+                        r.C = torch.empty((A.m, r.n), device="cuda", dtype=torch.float32)
+                    r.status = "running"
+                    r.admitted_at = time.monotonic() - t0
+                    batch.append((r, plan))
+                keep.extend(waiting)
+                waiting = keep
+                if batch:
+                    free_streams.pop(0)
+                    items = [api.WorkItem(plan, r.B, r.C) for r, plan in batch]
+                    ticket = api.spmm_submit(items, stream=stream)
+                    inflight[si] = (ticket, [r for r, _ in batch])
+                    stats.batches += 1
+                    stats.batch_sizes.append(len(batch))
+            elif not inflight and not waiting and nxt < total and realtime:
+                time.sleep(max(0.0, min(0.001, reqs[nxt].arrival - now)))
+            else:
+                time.sleep(20e-6)
+        torch.cuda.synchronize()
+        stats.wall_s = time.monotonic() - t0
+        self.requests = reqs
+        return stats
+
+    def solo(self, request: dict):
+        """Run one request alone on the default stream (for the mix test)."""
+        torch = self.torch
+        r = Request(**{k: request[k] for k in ("rid", "matrix", "n", "b_kind", "seed", "arrival")})
+        plan = self.plans.get(self._plan_key(r), Stats())
+        A = self.pool[r.matrix]["A"]
+        dt = torch.float32 if r.b_kind == "f32" else torch.bfloat16
+        g = torch.Generator(device="cuda")
+        g.manual_seed(r.seed)
+        B = torch.randn((A.k, r.n), generator=g, device="cuda", dtype=torch.float32).to(dt)
+        C = torch.empty((A.m, r.n), device="cuda", dtype=torch.float32)
+        plan.run(B, C)
+        torch.cuda.synchronize()
+        return B, C

@@ -299,3 +299,77 @@ def int_dense(rng_seed, shape, lo, hi, kind="f32"):
     if kind == "f16":
         return to_f16_bits(x)
     return x
+
+
+# --------------------------------------------------------------------------------------------
+# Serving stream.
+# --------------------------------------------------------------------------------------------
+def attention_mask(rows: int, block=64, block_density=0.1, band=512, seed=0, val_kind="f32"):
+    """Block-sparse attention mask: each 64-row block-row holds
+    ceil(block_density * nb) distinct uniformly drawn dense 64x64 blocks, plus
+    the sliding window |i - j| < band/2 (i - band/2 <= j < i + band/2);
+    values U(0,1)."""
+    r_blk, r_val = _rngs(seed, 2)
+    nb = (rows + block - 1) // block
+    per = max(1, int(math.ceil(block_density * nb)))
+    rows_l, cols_l = [], []
+    bi = np.repeat(np.arange(nb), per)
+    bj = np.concatenate([np.sort(r_blk.choice(nb, size=per, replace=False)) for _ in range(nb)])
+    ii, jj = np.meshgrid(np.arange(block), np.arange(block), indexing="ij")
+    r = (bi[:, None, None] * block + ii[None]).reshape(-1)
+    c = (bj[:, None, None] * block + jj[None]).reshape(-1)
+    keep = (r < rows) & (c < rows)
+    rows_l.append(r[keep])
+    cols_l.append(c[keep])
+    half = band // 2
+    i = np.repeat(np.arange(rows), band)
+    j = i - half + np.tile(np.arange(band), rows)
+    keep = (j >= 0) & (j < rows)
+    rows_l.append(i[keep])
+    cols_l.append(j[keep])
+    key = np.unique(np.concatenate(rows_l).astype(np.int64) * rows + np.concatenate(cols_l))
+    rr, cc = key // rows, key % rows
+    vals = uniform_values(r_val, rr.size, val_kind, 0.0, 1.0)
+    rowptr = np.zeros(rows + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rr, minlength=rows), out=rowptr[1:])
+    return CSR(rows, rows, rowptr, cc.astype(np.int32), vals, val_kind)
+
+
+def serving_pool(n_graphs=64, n_masks=16, seed=5, max_rows=500000, max_mask_rows=16384):
+    """Resident matrices the serving stream draws from: power-law graphs
+    (Chung-Lu exponent 2.1, mean degree 16, rows log-uniform in [1e3,
+    max_rows]) and block-sparse attention masks (rows log-uniform in [1e3,
+    max_mask_rows]), values in f32.  Returns a list of dicts."""
+    (r,) = _rngs(seed, 1)
+    pool = []
+    for g in range(n_graphs):
+        rows = int(round(math.exp(r.uniform(math.log(1000), math.log(max_rows)))))
+        A = chung_lu_graph(rows, 2.1, 16.0, min(20000.0, rows / 8.0), seed * 7919 + g)
+        pool.append({"kind": "graph", "A": A})
+    for k in range(n_masks):
+        rows = int(round(math.exp(r.uniform(math.log(1000), math.log(max_mask_rows)))))
+        A = attention_mask(rows, seed=seed * 104729 + k)
+        pool.append({"kind": "mask", "A": A})
+    return pool
+
+
+def serving_requests(count, pool_size, n_graphs, seed=5, rate=None):
+    """Request list: matrix drawn 50/50 between graphs and masks (uniform
+    within each kind), N uniform in {32, 64, 128, 256}, B type 50/50 f32 /
+    bf16, a per-request seed for B, and Poisson arrival times at ``rate``
+    requests/s (None: all at time 0)."""
+    (r,) = _rngs(seed + 17, 1)
+    reqs = []
+    t = 0.0
+    for i in range(count):
+        if r.random() < 0.5 or n_graphs == pool_size:
+            mid = int(r.integers(0, n_graphs))
+        else:
+            mid = int(r.integers(n_graphs, pool_size))
+        n = int(r.choice([32, 64, 128, 256]))
+        kind = "f32" if r.random() < 0.5 else "bf16"
+        if rate:
+            t += float(r.exponential(1.0 / rate))
+        reqs.append({"rid": i, "matrix": mid, "n": n, "b_kind": kind,
+                     "seed": int(r.integers(0, 2**31 - 1)), "arrival": t})
+    return reqs
