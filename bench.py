@@ -204,6 +204,8 @@ def main():
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--max-batch", type=int, default=64)
     ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--copy-plain", action="store_true",
+                    help="with --copy-probe: use torch's plain copy kernel instead")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run the device copy kernel over this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -221,6 +223,16 @@ def main():
         return serve_bench(args)
     if args.workload == "batch":
         return batch_bench(args)
+    if args.copy_probe and args.copy_plain:
+        # torch's elementwise copy (plain loads and stores) over the same bytes
+        a = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_probe, "copy_launches": 3, "kind": "torch"}),
+              flush=True)
+        return
     if args.copy_probe:
         bw = api.spmm_copy_bandwidth(args.copy_probe)
         print(json.dumps({"copy_bytes": args.copy_probe, "copy_launches": 13,
