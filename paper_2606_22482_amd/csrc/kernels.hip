@@ -407,17 +407,19 @@ __device__ __forceinline__ int wave_inclusive_scan(int x) {
 }
 
 // LDS of a window item: the staged B rows (reused for the f32 C tile), the
-// window's rows and segment ids, and the staged tiles' columns, bitmaps and
-// per-row value offsets.  Sized for the largest window height (64).
+// window's rows, remainder ranges and segment ids, and the staged tiles'
+// columns, bitmaps, per-row value offsets and packed values.  MB = H / 16.
+template <int MB>
 struct WinSmem {
     static constexpr int NPW = 128;          // panel columns of a window item
     static constexpr int TC = 4;             // tiles staged per round
     static constexpr int KROWS = TC * 32;    // B rows staged per round
     static constexpr int BSTR = NPW + 2;     // LDS row stride (16-bit elements): odd dword stride
-    static constexpr int HMAX = 64;
+    static constexpr int H = MB * 16;
     __attribute__((aligned(16))) unsigned short Bs[KROWS * BSTR];
-    int32_t rows[HMAX], sid[HMAX], cols[KROWS], off[TC * HMAX];
-    uint32_t bm[TC * HMAX];
+    unsigned short vals[TC * H * 32];
+    int32_t rows[H], rb[H], re[H], sid[H], cols[KROWS], off[TC * H];
+    uint32_t bm[TC * H];
 };
 
 template <int TT>
@@ -463,16 +465,21 @@ __device__ __forceinline__ void stage_b8(const void *B, int64_t off, int valid, 
 }
 
 // One (window, 128-column panel) per workgroup: item in [0, n_win * win_panels).
-// Every thread of the workgroup calls it with the same item.
-template <int VT, int BT, int TT, int MB, int E, int CPL>
+// Every thread of the workgroup calls it with the same item.  Per round of up
+// to TC tiles: (1) the tiles' columns, bitmaps and packed values and the
+// window's row metadata are loaded together; (2) the B rows of the tile
+// columns are loaded (all loads issued before any LDS write) and stored
+// converted to the tile type; (3) MFMA from LDS only.  Then each row adds its
+// remainder and is written once.
+template <int VT, int BT, int TT, int MB, int E, int CPL, int SMB>
 __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, int item,
-                                            WinSmem &sm) {
+                                            WinSmem<SMB> &sm) {
     constexpr int H = MB * 16;
-    constexpr int NPW = WinSmem::NPW, TC = WinSmem::TC, BSTR = WinSmem::BSTR;
+    using S = WinSmem<SMB>;
+    constexpr int NPW = S::NPW, TC = S::TC, BSTR = S::BSTR, KROWS = S::KROWS;
+    static_assert(MB <= SMB, "LDS sized for a smaller window");
+    static_assert(H * NPW * 4 <= KROWS * BSTR * 2, "C tile must fit in the B stage");
     unsigned short *Bs = sm.Bs;
-    int32_t *s_rows = sm.rows, *s_sid = sm.sid, *s_cols = sm.cols, *s_off = sm.off;
-    uint32_t *s_bm = sm.bm;
-    static_assert(H * NPW * 4 <= WinSmem::KROWS * BSTR * 2, "C tile must fit in the B stage");
 
     const int panel = item / P.n_win;
     const int wi = P.win_order[item - panel * P.n_win];
@@ -481,13 +488,19 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
     const int g = lane >> 4, l16 = lane & 15;
     const int t0 = P.win_tile_ptr[wi], t1 = P.win_tile_ptr[wi + 1];
 
-    if (tid < H) s_rows[tid] = P.windows[(int64_t)wi * H + tid];
     if (wave == 0) {
         const int r = lane < H ? P.windows[(int64_t)wi * H + lane] : -1;
-        const int len = r >= 0 ? P.rem_ptr[r + 1] - P.rem_ptr[r] : 0;
+        const int b = r >= 0 ? P.rem_ptr[r] : 0;
+        const int e = r >= 0 ? P.rem_ptr[r + 1] : 0;
+        const int len = e - b;
         const int ns = len > P.seg_len ? (len + P.seg_len - 1) / P.seg_len : 0;
         const int x = wave_inclusive_scan(ns);
-        if (lane < H) s_sid[lane] = P.win_seg[wi] + x - ns;
+        if (lane < H) {
+            sm.rows[lane] = r;
+            sm.rb[lane] = b;
+            sm.re[lane] = e;
+            sm.sid[lane] = P.win_seg[wi] + x - ns;
+        }
     }
 
     f32x4 acc[MB][2];
@@ -499,39 +512,50 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
     for (int tc0 = t0; tc0 < t1; tc0 += TC) {
         const int nt = min(TC, t1 - tc0);
         __syncthreads();
-        for (int i = tid; i < nt * 32; i += 256) s_cols[i] = P.tile_cols[(int64_t)tc0 * 32 + i];
-        for (int i = tid; i < nt * H; i += 256) s_bm[i] = P.tile_bitmap[(int64_t)tc0 * H + i];
+        const int v0 = P.tile_val_ptr[tc0], nv = P.tile_val_ptr[tc0 + nt] - v0;
+        for (int i = tid; i < nt * 32; i += 256) sm.cols[i] = P.tile_cols[(int64_t)tc0 * 32 + i];
+        for (int i = tid; i < nt * H; i += 256) sm.bm[i] = P.tile_bitmap[(int64_t)tc0 * H + i];
+        for (int i = tid; i < nv; i += 256) sm.vals[i] = P.tile_vals[v0 + i];
         __syncthreads();
         if (wave < nt) {
-            const uint32_t wd = lane < H ? s_bm[wave * H + lane] : 0u;
+            const uint32_t wd = lane < H ? sm.bm[wave * H + lane] : 0u;
             const int c = __popc(wd);
             const int x = wave_inclusive_scan(c);
-            if (lane < H) s_off[wave * H + lane] = x - c;
+            // offset of the row's first value inside the staged round
+            if (lane < H) sm.off[wave * H + lane] = P.tile_val_ptr[tc0 + wave] - v0 + x - c;
         }
-        for (int i = tid; i < nt * 32 * (NPW / 8); i += 256) {
-            const int kr = i >> 4, n = (i & 15) * 8;
-            const int col = s_cols[kr];
-            uint32_t w[4] = {0u, 0u, 0u, 0u};
+        constexpr int PER = KROWS * (NPW / 8) / 256;  // 16-byte staging chunks per thread
+        uint32_t w[PER][4];
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            const int i = tid + it * 256, kr = i >> 4, n = (i & 15) * 8;
+            w[it][0] = w[it][1] = w[it][2] = w[it][3] = 0u;
+            const int col = kr < nt * 32 ? sm.cols[kr] : -1;
             const int valid = min(8, ncols - n);
             if (col >= 0 && valid > 0)
-                stage_b8<BT, TT>(a.B, (int64_t)col * a.ldb + ncol0 + n, valid, a.vec_ok, w);
-            uint32_t *dst = reinterpret_cast<uint32_t *>(&Bs[kr * BSTR + n]);
-            dst[0] = w[0]; dst[1] = w[1]; dst[2] = w[2]; dst[3] = w[3];
+                stage_b8<BT, TT>(a.B, (int64_t)col * a.ldb + ncol0 + n, valid, a.vec_ok, w[it]);
+        }
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            const int i = tid + it * 256, kr = i >> 4, n = (i & 15) * 8;
+            if (kr < nt * 32) {
+                uint32_t *dst = reinterpret_cast<uint32_t *>(&Bs[kr * BSTR + n]);
+                dst[0] = w[it][0]; dst[1] = w[it][1]; dst[2] = w[it][2]; dst[3] = w[it][3];
+            }
         }
         __syncthreads();
         for (int j = 0; j < nt; ++j) {
-            const int vb = P.tile_val_ptr[tc0 + j];
             u16x8 af[MB];
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) {
                 const int m = mb * 16 + l16;
-                const uint32_t wd = s_bm[j * H + m];
+                const uint32_t wd = sm.bm[j * H + m];
                 const uint32_t mine = (wd >> (8 * g)) & 0xFFu;
-                int off = vb + s_off[j * H + m] + __popc(wd & ((1u << (8 * g)) - 1u));
+                int off = sm.off[j * H + m] + __popc(wd & ((1u << (8 * g)) - 1u));
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     unsigned short x = 0;
-                    if ((mine >> i) & 1u) x = P.tile_vals[off++];
+                    if ((mine >> i) & 1u) x = sm.vals[off++];
                     af[mb][i] = x;
                 }
             }
@@ -559,9 +583,9 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
 
     const Lanes L(a.win_lpr_log2);
     for (int s = wave; s < H; s += 4) {
-        const int r = s_rows[s];
+        const int r = sm.rows[s];
         if (r < 0) continue;
-        const int b = P.rem_ptr[r], e = P.rem_ptr[r + 1];
+        const int b = sm.rb[s], e = sm.re[s];
         float v[CPL][E];
 #pragma unroll
         for (int c = 0; c < CPL; ++c)
@@ -576,7 +600,7 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
             }
         } else {
             const int ns = (e - b + P.seg_len - 1) / P.seg_len;
-            sum_partials<E, CPL>(a.work, a.work_ld, s_sid[s], ns, ncol0, ncols, L, v);
+            sum_partials<E, CPL>(a.work, a.work_ld, sm.sid[s], ns, ncol0, ncols, L, v);
         }
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
@@ -592,9 +616,9 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
 
 template <int VT, int BT, int TT, int MB, int E, int CPL>
 __global__ __launch_bounds__(256) void window_kernel(DevPlan P, RunArgs a) {
-    __shared__ WinSmem sm;
+    __shared__ WinSmem<MB> sm;
     const int item = logical_block(a.xcd);
-    if (item < P.n_win * a.win_panels) window_item<VT, BT, TT, MB, E, CPL>(P, a, item, sm);
+    if (item < P.n_win * a.win_panels) window_item<VT, BT, TT, MB, E, CPL, MB>(P, a, item, sm);
 }
 
 
@@ -631,16 +655,16 @@ __global__ __launch_bounds__(256) void batch_vector_kernel(const BatchHeader *__
 template <int VT, int BT, int TT, int E, int CPL>
 __global__ __launch_bounds__(256) void batch_window_kernel(const BatchHeader *__restrict__ hdr,
                                                            const BatchEntry *__restrict__ tab) {
-    __shared__ WinSmem sm;
+    __shared__ WinSmem<4> sm;
     const int total = hdr->total_win;
     int d = 0;
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
         while (g >= tab[d].win_end) ++d;
         const int item = g - (d ? tab[d - 1].win_end : 0);
         switch (tab[d].P.H) {
-        case 16: window_item<VT, BT, TT, 1, E, CPL>(tab[d].P, tab[d].a, item, sm); break;
-        case 32: window_item<VT, BT, TT, 2, E, CPL>(tab[d].P, tab[d].a, item, sm); break;
-        default: window_item<VT, BT, TT, 4, E, CPL>(tab[d].P, tab[d].a, item, sm); break;
+        case 16: window_item<VT, BT, TT, 1, E, CPL, 4>(tab[d].P, tab[d].a, item, sm); break;
+        case 32: window_item<VT, BT, TT, 2, E, CPL, 4>(tab[d].P, tab[d].a, item, sm); break;
+        default: window_item<VT, BT, TT, 4, E, CPL, 4>(tab[d].P, tab[d].a, item, sm); break;
         }
         __syncthreads();  // the next item reuses the LDS
     }
