@@ -97,7 +97,8 @@ typedef struct {
     float alpha;       /* a K-tile is kept iff nnz / (H*kt) >= alpha (Sec. 5.2.1); < 0: auto */
     int32_t cold_policy; /* cache-policy bits of gathers of non-hot B rows (gfx950 buffer-load aux:
                             2 = nt, 16 = sc1, 18 = nt|sc1, 0 = default); < 0: auto */
-    int32_t reserved;
+    int32_t pipeline;  /* vector kernel: 1 = prefetch the next row during the current row's gathers,
+                          0 = row by row (identical results); < 0: auto */
 } spmm_opts;
 
 typedef struct spmm_plan_s spmm_plan_t;

@@ -82,7 +82,7 @@ def _csr_struct(A):
 
 
 def opts_dict(o: L.Opts) -> dict:
-    return {f: getattr(o, f) for f, _ in L.Opts._fields_ if f != "reserved"}
+    return {f: getattr(o, f) for f, _ in L.Opts._fields_}
 
 
 class Plan:

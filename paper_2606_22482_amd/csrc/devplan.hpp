@@ -47,6 +47,7 @@ struct RunArgs {
     int32_t win_panels; // panels of the window kernel (128 columns each)
     int32_t win_lpr_log2;
     int32_t cold_aux;   // buffer-load policy bits for non-hot B rows; -1: plain loads for all
+    int32_t pipeline;   // vector kernel prefetches the next row while gathering the current one
 };
 
 // One matrix of a batched execution.  `*_end` are exclusive prefix sums of

@@ -218,6 +218,68 @@ struct Lanes {
     }
 };
 
+// Entries p, p + G, ..., p + (U-1)G of a group (masked at p1): columns and values.
+template <int VT, int U>
+__device__ __forceinline__ void load_entries(const int32_t *__restrict__ rcol,
+                                             const void *__restrict__ rval, int p, int p1,
+                                             const Lanes &L, int (&col)[U], float (&v)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int pp = p + u * L.groups;
+        const bool ok = pp < p1;
+        col[u] = ok ? __builtin_nontemporal_load(rcol + pp) : 0;
+        v[u] = ok ? load_val<VT>(rval, pp) : 0.0f;
+    }
+}
+
+// Gathers the B rows of U loaded entries (hot rows cacheable, the others with
+// the cold policy) and accumulates them in entry order.
+template <int BT, int E, int CPL, int U>
+__device__ __forceinline__ void gather_fma(const int (&col)[U], const float (&v)[U], int p, int p1,
+                                           const void *__restrict__ B,
+                                           __amdgpu_buffer_rsrc_t rs, int64_t ldb,
+                                           const bool (&cok)[CPL], const int64_t (&coff)[CPL],
+                                           const Lanes &L, int cold_aux, float (&acc)[CPL][E]) {
+    float b[U][CPL][E];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const bool ok = p + u * L.groups < p1;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            // bit 31 of a column marks a hot B row (cacheable gather)
+            const int64_t boff = (int64_t)(col[u] & 0x7FFFFFFF) * ldb + coff[c];
+            if (ok && cok[c] && (col[u] < 0 || cold_aux < 0)) {
+                load_chunk<BT, E, false>(B, boff, b[u][c]);
+            } else if (ok && cok[c]) {
+                load_chunk_policy<BT, E>(rs, boff, cold_aux, b[u][c]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < E; ++e) b[u][c][e] = 0.0f;
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if (p + u * L.groups < p1) {
+#pragma unroll
+            for (int c = 0; c < CPL; ++c)
+#pragma unroll
+                for (int e = 0; e < E; ++e) acc[c][e] = __builtin_fmaf(v[u], b[u][c][e], acc[c][e]);
+        }
+    }
+}
+
+template <int E, int CPL>
+__device__ __forceinline__ void chunk_layout(int ncol0, int ncols, const Lanes &L, bool (&cok)[CPL],
+                                             int64_t (&coff)[CPL]) {
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const int q = c * L.lpr + L.li;
+        cok[c] = q * E < ncols;
+        coff[c] = ncol0 + (int64_t)q * E;
+    }
+}
+
 // acc += sum over entries [p0, p1) of v_p * B[col_p][panel columns], entry
 // p0 + i taken by group i % G in increasing i (see the file comment).
 template <int VT, int BT, int E, int CPL, int U>
@@ -229,49 +291,13 @@ __device__ __forceinline__ void seg_accumulate(const int32_t *__restrict__ rcol,
     const __amdgpu_buffer_rsrc_t rs = b_resource(B);
     bool cok[CPL];
     int64_t coff[CPL];
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) {
-        const int q = c * L.lpr + L.li;
-        cok[c] = q * E < ncols;
-        coff[c] = ncol0 + (int64_t)q * E;
-    }
+    chunk_layout<E, CPL>(ncol0, ncols, L, cok, coff);
     const int step = L.groups * U;
     for (int p = p0 + L.group; p < p1; p += step) {
         int col[U];
         float v[U];
-        bool ok[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int pp = p + u * L.groups;
-            ok[u] = pp < p1;
-            col[u] = ok[u] ? __builtin_nontemporal_load(rcol + pp) : 0;
-            v[u] = ok[u] ? load_val<VT>(rval, pp) : 0.0f;
-        }
-        float b[U][CPL][E];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                // bit 31 of a column marks a hot B row (cacheable gather)
-                const int64_t boff = (int64_t)(col[u] & 0x7FFFFFFF) * ldb + coff[c];
-                if (ok[u] && cok[c] && (col[u] < 0 || cold_aux < 0)) {
-                    load_chunk<BT, E, false>(B, boff, b[u][c]);
-                } else if (ok[u] && cok[c]) {
-                    load_chunk_policy<BT, E>(rs, boff, cold_aux, b[u][c]);
-                } else {
-#pragma unroll
-                    for (int e = 0; e < E; ++e) b[u][c][e] = 0.0f;
-                }
-            }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (ok[u]) {
-#pragma unroll
-                for (int c = 0; c < CPL; ++c)
-#pragma unroll
-                    for (int e = 0; e < E; ++e) acc[c][e] = __builtin_fmaf(v[u], b[u][c][e], acc[c][e]);
-            }
-        }
+        load_entries<VT, U>(rcol, rval, p, p1, L, col, v);
+        gather_fma<BT, E, CPL, U>(col, v, p, p1, B, rs, ldb, cok, coff, L, cold_aux, acc);
     }
 }
 
@@ -383,6 +409,103 @@ __device__ __forceinline__ void vector_item(const DevPlan &P, const RunArgs &a, 
     }
 }
 
+// Vector work item with a software pipeline across its rows: while a row's
+// B rows are being gathered, the next row's pointers and first batch of
+// (column, value) are already in flight.  Each row's entries are consumed in
+// exactly the order of vector_item, so the results are bitwise identical.
+template <int VT, int BT, int E, int CPL>
+__device__ __forceinline__ void vector_item_pipelined(const DevPlan &P, const RunArgs &a, int wid) {
+    constexpr int U = unroll_of<E, CPL>();
+    const int panel = wid / P.n_vitems, item = wid - panel * P.n_vitems;
+    const int ncol0 = panel * a.np, ncols = min(a.np, P.n - ncol0);
+    const Lanes L(a.lpr_log2);
+    const int step = L.groups * U;
+    const __amdgpu_buffer_rsrc_t rs = b_resource(a.B);
+    bool cok[CPL];
+    int64_t coff[CPL];
+    chunk_layout<E, CPL>(ncol0, ncols, L, cok, coff);
+    int sid = P.vitem_seg[item];
+    const int i0 = P.vitem_ptr[item], i1 = P.vitem_ptr[item + 1];
+
+    int r = P.vec_rows ? P.vec_rows[i0] : i0;
+    int b = P.rem_ptr[r], e = P.rem_ptr[r + 1];
+    int col[U];
+    float v[U];
+    load_entries<VT, U>(P.rem_col, P.rem_val, b + L.group, e - b <= P.seg_len ? e : b, L, col, v);
+    for (int i = i0; i < i1; ++i) {
+        int nr = r, nb = 0, ne = 0;
+        if (i + 1 < i1) {
+            nr = P.vec_rows ? P.vec_rows[i + 1] : i + 1;
+            nb = P.rem_ptr[nr];
+            ne = P.rem_ptr[nr + 1];
+        }
+        float acc[CPL][E];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c)
+#pragma unroll
+            for (int x = 0; x < E; ++x) acc[c][x] = 0.0f;
+        int ncl[U];
+        float nv[U];
+        if (e - b <= P.seg_len) {
+            float bv[U][CPL][E];
+            // gathers of this row's first batch
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool ok = b + L.group + u * L.groups < e;
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    const int64_t boff = (int64_t)(col[u] & 0x7FFFFFFF) * a.ldb + coff[c];
+                    if (ok && cok[c] && (col[u] < 0 || a.cold_aux < 0)) {
+                        load_chunk<BT, E, false>(a.B, boff, bv[u][c]);
+                    } else if (ok && cok[c]) {
+                        load_chunk_policy<BT, E>(rs, boff, a.cold_aux, bv[u][c]);
+                    } else {
+#pragma unroll
+                        for (int x = 0; x < E; ++x) bv[u][c][x] = 0.0f;
+                    }
+                }
+            }
+            // the next row's first batch, in flight behind the gathers
+            load_entries<VT, U>(P.rem_col, P.rem_val, nb + L.group, ne - nb <= P.seg_len ? ne : nb,
+                                L, ncl, nv);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (b + L.group + u * L.groups < e) {
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c)
+#pragma unroll
+                        for (int x = 0; x < E; ++x)
+                            acc[c][x] = __builtin_fmaf(v[u], bv[u][c][x], acc[c][x]);
+                }
+            }
+            // the rest of a row longer than one batch, continuing the same order
+            for (int p = b + step + L.group; p < e; p += step) {
+                int c2[U];
+                float v2[U];
+                load_entries<VT, U>(P.rem_col, P.rem_val, p, e, L, c2, v2);
+                gather_fma<BT, E, CPL, U>(c2, v2, p, e, a.B, rs, a.ldb, cok, coff, L, a.cold_aux,
+                                          acc);
+            }
+            group_reduce<E, CPL>(acc, L);
+        } else {
+            load_entries<VT, U>(P.rem_col, P.rem_val, nb + L.group, ne - nb <= P.seg_len ? ne : nb,
+                                L, ncl, nv);
+            const int ns = (e - b + P.seg_len - 1) / P.seg_len;
+            sum_partials<E, CPL>(a.work, a.work_ld, sid, ns, ncol0, ncols, L, acc);
+            sid += ns;
+        }
+        store_row<E, CPL>(a.C, (int64_t)r * a.ldc, ncol0, ncols, L, acc);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            col[u] = ncl[u];
+            v[u] = nv[u];
+        }
+        r = nr;
+        b = nb;
+        e = ne;
+    }
+}
+
 template <int VT, int BT, int E, int CPL>
 __global__ __launch_bounds__(256) void segment_kernel(DevPlan P, RunArgs a) {
     const int wid = logical_block(a.xcd) * 4 + (threadIdx.x >> 6);
@@ -392,7 +515,9 @@ __global__ __launch_bounds__(256) void segment_kernel(DevPlan P, RunArgs a) {
 template <int VT, int BT, int E, int CPL>
 __global__ __launch_bounds__(256) void vector_kernel(DevPlan P, RunArgs a) {
     const int wid = logical_block(a.xcd) * 4 + (threadIdx.x >> 6);
-    if (wid < P.n_vitems * a.n_panels) vector_item<VT, BT, E, CPL>(P, a, wid);
+    if (wid >= P.n_vitems * a.n_panels) return;
+    if (a.pipeline) vector_item_pipelined<VT, BT, E, CPL>(P, a, wid);
+    else vector_item<VT, BT, E, CPL>(P, a, wid);
 }
 
 // Inclusive prefix sum over the 64 lanes of a wavefront.
@@ -648,7 +773,8 @@ __global__ __launch_bounds__(256) void batch_vector_kernel(const BatchHeader *__
     for (int g = blockIdx.x * 4 + (threadIdx.x >> 6); g < total; g += gridDim.x * 4) {
         while (g >= tab[d].vec_end) ++d;
         const int base = d ? tab[d - 1].vec_end : 0;
-        vector_item<VT, BT, E, CPL>(tab[d].P, tab[d].a, g - base);
+        if (tab[d].a.pipeline) vector_item_pipelined<VT, BT, E, CPL>(tab[d].P, tab[d].a, g - base);
+        else vector_item<VT, BT, E, CPL>(tab[d].P, tab[d].a, g - base);
     }
 }
 

@@ -82,6 +82,7 @@ extern "C" void spmm_opts_default(spmm_opts *o) {
     o->xcd_remap = -1;
     o->hot_cols = -1;
     o->cold_policy = -1;
+    o->pipeline = -1;
     o->alpha_c = -1.0f;
     o->alpha = -1.0f;
 }
@@ -383,6 +384,7 @@ spmm_status make_run_args(const spmm_plan_t *p, const void *B, int64_t ldb, void
     // cold B rows go through a raw buffer load (32-bit byte offsets from B)
     const double b_span = ((double)std::max<int64_t>(h.k, 1) - 1.0) * (double)ldb * sb + (double)N * sb;
     a.cold_aux = b_span < 4294967295.0 ? h.opts.cold_policy : -1;
+    a.pipeline = h.opts.pipeline > 0 ? 1 : 0;
     a.win_panels = (N + 127) / 128;
     const int wchunks = a.vec_ok ? 128 / E : 128;
     a.win_lpr_log2 = ilog2_ceil(std::min(wchunks, 64));

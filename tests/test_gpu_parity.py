@@ -131,6 +131,22 @@ def test_mixed_without_tiles_bitwise_equals_plain():
     assert torch.equal(C1, C2)
 
 
+@pytest.mark.parametrize("n,kind", [(128, "f32"), (64, "f32"), (33, "f32"), (256, "bf16")])
+def test_pipelined_vector_kernel_bitwise_equals_row_by_row(n, kind):
+    import torch
+    A = synth.chung_lu_graph(30000, 2.1, 16.0, 3000.0, 12)
+    B = synth.dense_values(np.random.default_rng(5), (30000, n), kind)
+    outs = []
+    for pipe in (0, 1):
+        for hot in (0, -1):
+            _, C = run(A, B, kind, api.default_opts(mode="plain", seg_len=50, pipeline=pipe,
+                                                    hot_cols=hot))
+            outs.append(C)
+    for C in outs[1:]:
+        assert torch.equal(outs[0], C)
+    parity(outs[0], A, B, kind, TOL_F32)
+
+
 def test_deterministic_and_nan_prefill():
     import torch
     A, B = synth.block_community(n=16384, band=8, n_cols=256, seed=8)
