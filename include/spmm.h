@@ -157,6 +157,11 @@ typedef struct {
     const int32_t *win_seg;     /* int32 [n_windows]: first segment id used by the window */
     const int32_t *win_order;   /* int32 [n_windows]: execution order of windows (heaviest first) */
     const int32_t *rem_col_dev; /* int32 [nnz_remainder]: device column array, bit 31 set for hot columns */
+    int64_t n_wparts;           /* window partial items: tiles of a window beyond its first 16 */
+    const int32_t *win_part;    /* int32 [n_windows + 1]: partial items of window w */
+    const int32_t *wpart_win;   /* int32 [n_wparts] */
+    const int32_t *wpart_t0;    /* int32 [n_wparts]: first tile */
+    const int32_t *wpart_t1;    /* int32 [n_wparts]: end tile */
 } spmm_plan_dump_t;
 
 /* One matrix of a batched submission (device pointers). */
@@ -213,6 +218,7 @@ spmm_status spmm_run(const spmm_plan_t *p, const void *B, int64_t ldb, void *C, 
 #define SPMM_KERNEL_SEGMENT 0 /* partial sums of long remainder rows */
 #define SPMM_KERNEL_VECTOR 1  /* FP32 gather-FMA over vector rows */
 #define SPMM_KERNEL_WINDOW 2  /* MFMA windows + their rows' remainders */
+#define SPMM_KERNEL_WINDOW_PARTIAL 3 /* MFMA partial results of windows' extra tiles */
 spmm_status spmm_timer_create(int32_t capacity, spmm_timer_t **out);
 spmm_status spmm_timer_reset(spmm_timer_t *t);
 spmm_status spmm_timer_read(spmm_timer_t *t, int32_t *kernel_ids, float *ms, int32_t cap,

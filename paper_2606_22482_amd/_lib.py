@@ -15,7 +15,7 @@ MODE_AUTO, MODE_PLAIN_F32, MODE_MIXED, MODE_MFMA_ONLY = 0, 1, 2, 3
 ORDER_AUTO, ORDER_ORIGINAL_RANGES, ORDER_COMPACTED, ORDER_LENGTH_SORTED = 0, 1, 2, 3
 AUTO_INT = -(2 ** 31)
 KERNEL_SEGMENT, KERNEL_VECTOR, KERNEL_WINDOW = 0, 1, 2
-KERNEL_NAMES = {0: "segment", 1: "vector", 2: "window"}
+KERNEL_NAMES = {0: "segment", 1: "vector", 2: "window", 3: "window_partial"}
 KIND_CODE = {"f32": F32, "bf16": BF16, "f16": F16}
 
 
@@ -58,7 +58,8 @@ class PlanDump(C.Structure):
                 ("vitem_ptr", C.c_void_p), ("vitem_seg", C.c_void_p),
                 ("n_segments", C.c_int64), ("seg_row", C.c_void_p), ("seg_begin", C.c_void_p),
                 ("seg_end", C.c_void_p), ("win_seg", C.c_void_p), ("win_order", C.c_void_p),
-                ("rem_col_dev", C.c_void_p)]
+                ("rem_col_dev", C.c_void_p), ("n_wparts", C.c_int64), ("win_part", C.c_void_p),
+                ("wpart_win", C.c_void_p), ("wpart_t0", C.c_void_p), ("wpart_t1", C.c_void_p)]
 
 
 class TuneReport(C.Structure):

@@ -160,6 +160,10 @@ class Plan:
             "win_seg": arr(d.win_seg, W, np.int32),
             "win_order": arr(d.win_order, W, np.int32),
             "rem_col_dev": arr(d.rem_col_dev, int(rp[-1]), np.int32),
+            "win_part": arr(d.win_part, W + 1, np.int32),
+            "wpart_win": arr(d.wpart_win, d.n_wparts, np.int32),
+            "wpart_t0": arr(d.wpart_t0, d.n_wparts, np.int32),
+            "wpart_t1": arr(d.wpart_t1, d.n_wparts, np.int32),
         }
 
     def run(self, B, Cout, stream=None):

@@ -29,6 +29,11 @@ struct DevPlan {
     const uint32_t *tile_bitmap;  // [T*H]
     const int32_t *tile_val_ptr;  // [T+1]
     const uint16_t *tile_vals;
+    int32_t n_wpart, win_tmax;  // window partial items; tiles an owner item computes itself
+    const int32_t *win_part;    // [n_win+1]
+    const int32_t *wpart_win;   // [n_wpart]
+    const int32_t *wpart_t0;    // [n_wpart]
+    const int32_t *wpart_t1;    // [n_wpart]
 };
 
 // Launch geometry and operand description of one execution.
@@ -37,7 +42,8 @@ struct RunArgs {
     int64_t ldb;
     float *C;
     int64_t ldc;
-    float *work;        // segment partial sums, [n_seg * work_ld]
+    float *work;        // segment partial sums [n_seg * work_ld], then window partials
+                        // [n_wpart * H * work_ld]
     int32_t work_ld;    // row stride of `work` (N rounded up to 4)
     int32_t vec_ok;     // 16-byte chunks usable for B and C
     int32_t np;         // columns per panel of the vector / segment kernels
@@ -56,11 +62,11 @@ struct RunArgs {
 struct BatchEntry {
     DevPlan P;
     RunArgs a;
-    int32_t seg_end, vec_end, win_end, pad;
+    int32_t seg_end, vec_end, win_end, wpart_end;
 };
 
 struct BatchHeader {
-    int32_t count, total_seg, total_vec, total_win;
+    int32_t count, total_seg, total_vec, total_win, total_wpart, pad[3];
 };
 
 // Persistent batched launches over a device table (header + entries).
@@ -79,6 +85,8 @@ hipError_t launch_vector(const DevPlan &P, int32_t val_t, int32_t b_t, const Run
                          hipStream_t s);
 hipError_t launch_window(const DevPlan &P, int32_t val_t, int32_t b_t, int32_t tile_t,
                          const RunArgs &a, hipStream_t s);
+hipError_t launch_window_partial(const DevPlan &P, int32_t val_t, int32_t b_t, int32_t tile_t,
+                                 const RunArgs &a, hipStream_t s);
 hipError_t launch_copy(const float4 *src, float4 *dst, int64_t n4, hipStream_t s);
 
 // chunk width (elements per 16-byte load) of a B type

@@ -598,7 +598,7 @@ __device__ __forceinline__ void stage_b8(const void *B, int64_t off, int valid, 
 // remainder and is written once.
 template <int VT, int BT, int TT, int MB, int E, int CPL, int SMB>
 __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, int item,
-                                            WinSmem<SMB> &sm) {
+                                            WinSmem<SMB> &sm, bool partial) {
     constexpr int H = MB * 16;
     using S = WinSmem<SMB>;
     constexpr int NPW = S::NPW, TC = S::TC, BSTR = S::BSTR, KROWS = S::KROWS;
@@ -606,14 +606,19 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
     static_assert(H * NPW * 4 <= KROWS * BSTR * 2, "C tile must fit in the B stage");
     unsigned short *Bs = sm.Bs;
 
-    const int panel = item / P.n_win;
-    const int wi = P.win_order[item - panel * P.n_win];
+    // owner items: (panel, window in heaviest-first order), tiles [t0, t0 + win_tmax);
+    // partial items: (panel, partial slot), tiles [wpart_t0, wpart_t1)
+    const int nitems = partial ? P.n_wpart : P.n_win;
+    const int panel = item / nitems, j_item = item - panel * nitems;
+    const int wi = partial ? P.wpart_win[j_item] : P.win_order[j_item];
     const int ncol0 = panel * NPW, ncols = min(NPW, P.n - ncol0);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane >> 4, l16 = lane & 15;
-    const int t0 = P.win_tile_ptr[wi], t1 = P.win_tile_ptr[wi + 1];
+    const int t0 = partial ? P.wpart_t0[j_item] : P.win_tile_ptr[wi];
+    const int t1 = partial ? P.wpart_t1[j_item] : min(P.win_tile_ptr[wi + 1], t0 + P.win_tmax);
+    float *wpart = a.work + (int64_t)P.n_seg * a.work_ld;  // window partials follow the segments
 
-    if (wave == 0) {
+    if (wave == 0 && !partial) {
         const int r = lane < H ? P.windows[(int64_t)wi * H + lane] : -1;
         const int b = r >= 0 ? P.rem_ptr[r] : 0;
         const int e = r >= 0 ? P.rem_ptr[r + 1] : 0;
@@ -695,6 +700,22 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
             }
         }
     }
+    if (partial) {
+        // the MFMA result of these tiles, for the owner item to add
+        float *dst = wpart + (int64_t)j_item * H * a.work_ld + ncol0;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nbi = 0; nbi < 2; ++nbi) {
+                const int col = (wave + 4 * nbi) * 16 + l16;
+                if (col < ncols) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        dst[(int64_t)(mb * 16 + 4 * g + i) * a.work_ld + col] = acc[mb][nbi][i];
+                }
+            }
+        return;
+    }
     __syncthreads();
     float *Cs = reinterpret_cast<float *>(Bs);
 #pragma unroll
@@ -704,6 +725,20 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
 #pragma unroll
             for (int i = 0; i < 4; ++i)
                 Cs[(mb * 16 + 4 * g + i) * NPW + (wave + 4 * nbi) * 16 + l16] = acc[mb][nbi][i];
+    // add the partial results of the window's other tiles, in tile order
+    const int pa = P.win_part[wi], pb = P.win_part[wi + 1];
+    if (pb > pa) {
+        __syncthreads();
+        for (int x = tid; x < H * NPW; x += 256) {
+            const int srow = x / NPW, col = x - srow * NPW;
+            if (col < ncols) {
+                float v = Cs[x];
+                for (int k = pa; k < pb; ++k)
+                    v += wpart[((int64_t)k * H + srow) * a.work_ld + ncol0 + col];
+                Cs[x] = v;
+            }
+        }
+    }
     __syncthreads();
 
     const Lanes L(a.win_lpr_log2);
@@ -743,7 +778,14 @@ template <int VT, int BT, int TT, int MB, int E, int CPL>
 __global__ __launch_bounds__(256) void window_kernel(DevPlan P, RunArgs a) {
     __shared__ WinSmem<MB> sm;
     const int item = logical_block(a.xcd);
-    if (item < P.n_win * a.win_panels) window_item<VT, BT, TT, MB, E, CPL, MB>(P, a, item, sm);
+    if (item < P.n_win * a.win_panels) window_item<VT, BT, TT, MB, E, CPL, MB>(P, a, item, sm, false);
+}
+
+template <int VT, int BT, int TT, int MB, int E, int CPL>
+__global__ __launch_bounds__(256) void window_partial_kernel(DevPlan P, RunArgs a) {
+    __shared__ WinSmem<MB> sm;
+    const int item = logical_block(a.xcd);
+    if (item < P.n_wpart * a.win_panels) window_item<VT, BT, TT, MB, E, CPL, MB>(P, a, item, sm, true);
 }
 
 
@@ -778,19 +820,19 @@ __global__ __launch_bounds__(256) void batch_vector_kernel(const BatchHeader *__
     }
 }
 
-template <int VT, int BT, int TT, int E, int CPL>
+template <int VT, int BT, int TT, int E, int CPL, bool PARTIAL>
 __global__ __launch_bounds__(256) void batch_window_kernel(const BatchHeader *__restrict__ hdr,
                                                            const BatchEntry *__restrict__ tab) {
     __shared__ WinSmem<4> sm;
-    const int total = hdr->total_win;
+    const int total = PARTIAL ? hdr->total_wpart : hdr->total_win;
     int d = 0;
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
-        while (g >= tab[d].win_end) ++d;
-        const int item = g - (d ? tab[d - 1].win_end : 0);
+        while (g >= (PARTIAL ? tab[d].wpart_end : tab[d].win_end)) ++d;
+        const int item = g - (d ? (PARTIAL ? tab[d - 1].wpart_end : tab[d - 1].win_end) : 0);
         switch (tab[d].P.H) {
-        case 16: window_item<VT, BT, TT, 1, E, CPL, 4>(tab[d].P, tab[d].a, item, sm); break;
-        case 32: window_item<VT, BT, TT, 2, E, CPL, 4>(tab[d].P, tab[d].a, item, sm); break;
-        default: window_item<VT, BT, TT, 4, E, CPL, 4>(tab[d].P, tab[d].a, item, sm); break;
+        case 16: window_item<VT, BT, TT, 1, E, CPL, 4>(tab[d].P, tab[d].a, item, sm, PARTIAL); break;
+        case 32: window_item<VT, BT, TT, 2, E, CPL, 4>(tab[d].P, tab[d].a, item, sm, PARTIAL); break;
+        default: window_item<VT, BT, TT, 4, E, CPL, 4>(tab[d].P, tab[d].a, item, sm, PARTIAL); break;
         }
         __syncthreads();  // the next item reuses the LDS
     }
@@ -840,17 +882,21 @@ static hipError_t vec_dispatch(const DevPlan &P, const RunArgs &a, hipStream_t s
 }
 
 template <int VT, int BT, int TT>
-static hipError_t win_dispatch(const DevPlan &P, const RunArgs &a, hipStream_t s) {
-    const int64_t wgs = (int64_t)P.n_win * a.win_panels;
+static hipError_t win_dispatch(const DevPlan &P, const RunArgs &a, hipStream_t s, bool partial) {
+    const int64_t wgs = (int64_t)(partial ? P.n_wpart : P.n_win) * a.win_panels;
     if (wgs == 0) return hipSuccess;
     constexpr int EV = BT == DT_F32 ? 4 : 8;
     dim3 grid((unsigned)wgs), block(256);
-#define SPMM_WIN(MB)                                                                              \
-    do {                                                                                          \
-        if (a.vec_ok)                                                                             \
-            hipLaunchKernelGGL((window_kernel<VT, BT, TT, MB, EV, 1>), grid, block, 0, s, P, a);  \
-        else                                                                                      \
-            hipLaunchKernelGGL((window_kernel<VT, BT, TT, MB, 1, 2>), grid, block, 0, s, P, a);   \
+#define SPMM_WIN(MB)                                                                                 \
+    do {                                                                                             \
+        if (partial && a.vec_ok)                                                                     \
+            hipLaunchKernelGGL((window_partial_kernel<VT, BT, TT, MB, EV, 1>), grid, block, 0, s, P, a); \
+        else if (partial)                                                                            \
+            hipLaunchKernelGGL((window_partial_kernel<VT, BT, TT, MB, 1, 2>), grid, block, 0, s, P, a);  \
+        else if (a.vec_ok)                                                                           \
+            hipLaunchKernelGGL((window_kernel<VT, BT, TT, MB, EV, 1>), grid, block, 0, s, P, a);     \
+        else                                                                                         \
+            hipLaunchKernelGGL((window_kernel<VT, BT, TT, MB, 1, 2>), grid, block, 0, s, P, a);      \
     } while (0)
     switch (P.H) {
     case 16: SPMM_WIN(1); break;
@@ -878,13 +924,23 @@ hipError_t launch_vector(const DevPlan &P, int32_t vt, int32_t bt, const RunArgs
     return hipErrorInvalidValue;
 }
 
+static hipError_t window_any(const DevPlan &P, int32_t vt, int32_t bt, int32_t tt, const RunArgs &a,
+                             hipStream_t s, bool partial) {
+    if (vt == DT_F32 && bt == DT_F32 && tt == DT_BF16) return win_dispatch<DT_F32, DT_F32, DT_BF16>(P, a, s, partial);
+    if (vt == DT_F32 && bt == DT_BF16 && tt == DT_BF16) return win_dispatch<DT_F32, DT_BF16, DT_BF16>(P, a, s, partial);
+    if (vt == DT_BF16 && bt == DT_BF16 && tt == DT_BF16) return win_dispatch<DT_BF16, DT_BF16, DT_BF16>(P, a, s, partial);
+    if (vt == DT_F16 && bt == DT_F16 && tt == DT_F16) return win_dispatch<DT_F16, DT_F16, DT_F16>(P, a, s, partial);
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_window(const DevPlan &P, int32_t vt, int32_t bt, int32_t tt, const RunArgs &a,
                          hipStream_t s) {
-    if (vt == DT_F32 && bt == DT_F32 && tt == DT_BF16) return win_dispatch<DT_F32, DT_F32, DT_BF16>(P, a, s);
-    if (vt == DT_F32 && bt == DT_BF16 && tt == DT_BF16) return win_dispatch<DT_F32, DT_BF16, DT_BF16>(P, a, s);
-    if (vt == DT_BF16 && bt == DT_BF16 && tt == DT_BF16) return win_dispatch<DT_BF16, DT_BF16, DT_BF16>(P, a, s);
-    if (vt == DT_F16 && bt == DT_F16 && tt == DT_F16) return win_dispatch<DT_F16, DT_F16, DT_F16>(P, a, s);
-    return hipErrorInvalidValue;
+    return window_any(P, vt, bt, tt, a, s, false);
+}
+
+hipError_t launch_window_partial(const DevPlan &P, int32_t vt, int32_t bt, int32_t tt,
+                                 const RunArgs &a, hipStream_t s) {
+    return window_any(P, vt, bt, tt, a, s, true);
 }
 
 template <int VT, int BT, int TT, int E, int CPL>
@@ -895,12 +951,15 @@ static hipError_t batch_variant(const BatchHeader *hdr, const BatchEntry *tab, u
             occ_wave, batch_vector_kernel<VT, BT, E, CPL>, 256, 0);
         if (e != hipSuccess) return e;
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            occ_win, batch_window_kernel<VT, BT, TT, E, CPL>, 256, 0);
+            occ_win, batch_window_kernel<VT, BT, TT, E, CPL, false>, 256, 0);
     }
+    // phase 1: partial sums (segments, window tile chunks); phase 2: owners
     hipLaunchKernelGGL((batch_segment_kernel<VT, BT, E, CPL>), dim3(gw), dim3(256), 0, s, hdr, tab);
+    hipLaunchKernelGGL((batch_window_kernel<VT, BT, TT, E, CPL, true>), dim3(gwin), dim3(256), 0, s,
+                       hdr, tab);
     hipLaunchKernelGGL((batch_vector_kernel<VT, BT, E, CPL>), dim3(gw), dim3(256), 0, s, hdr, tab);
-    hipLaunchKernelGGL((batch_window_kernel<VT, BT, TT, E, CPL>), dim3(gwin), dim3(256), 0, s, hdr,
-                       tab);
+    hipLaunchKernelGGL((batch_window_kernel<VT, BT, TT, E, CPL, false>), dim3(gwin), dim3(256), 0,
+                       s, hdr, tab);
     return hipGetLastError();
 }
 

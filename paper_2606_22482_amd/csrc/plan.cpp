@@ -350,9 +350,19 @@ spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_
     }
     // windows: segment ids in slot order, heaviest windows first
     std::vector<int64_t> wcost(W, 0);
+    P.win_part.push_back(0);
     for (int64_t w = 0; w < W; ++w) {
         P.win_seg.push_back((int32_t)P.seg_row.size());
-        wcost[w] = (int64_t)(P.win_tile_ptr[w + 1] - P.win_tile_ptr[w]) * kt;
+        const int32_t ta = P.win_tile_ptr[w], tb = P.win_tile_ptr[w + 1];
+        // tiles beyond the first kWinTiles become partial items of kWinTiles each
+        for (int32_t t = ta + kWinTiles; t < tb; t += kWinTiles) {
+            P.wpart_win.push_back((int32_t)w);
+            P.wpart_t0.push_back(t);
+            P.wpart_t1.push_back(std::min(t + kWinTiles, tb));
+        }
+        P.win_part.push_back((int32_t)P.wpart_win.size());
+        wcost[w] = (int64_t)std::min(tb - ta, kWinTiles) * kt +
+                   (int64_t)(P.win_part[w + 1] - P.win_part[w]) * H;
         for (int s = 0; s < H; ++s) {
             int32_t r = P.windows[w * H + s];
             if (r < 0) continue;

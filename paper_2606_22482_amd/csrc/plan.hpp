@@ -14,6 +14,7 @@ namespace spmm {
 
 constexpr int kWave = 64;
 constexpr int kRowCost = 4;  // per-row overhead of a vector item, in entry units
+constexpr int kWinTiles = 16;  // tiles a window item computes itself; the rest go to partial items
 
 struct HostPlan {
     // ---- problem and resolved options ----
@@ -42,6 +43,8 @@ struct HostPlan {
     std::vector<int32_t> win_tile_ptr;  // [W+1]
     std::vector<int32_t> win_seg;       // [W]
     std::vector<int32_t> win_order;     // [W]
+    std::vector<int32_t> win_part;      // [W+1]: partial items of window w are [win_part[w], win_part[w+1])
+    std::vector<int32_t> wpart_win, wpart_t0, wpart_t1;  // [n_wparts]
     bool identity_rows = false;         // vector_rows == 0..m-1
 
     // ---- device-facing copies of the remainder ----

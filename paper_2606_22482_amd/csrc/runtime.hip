@@ -169,6 +169,10 @@ extern "C" spmm_status spmm_plan_upload(spmm_plan_t *p) {
         const size_t i_tile_bitmap = add_vec(a, h.tile_bitmap);
         const size_t i_tile_val_ptr = add_vec(a, tile_val_ptr32);
         const size_t i_tile_vals = add_vec(a, h.tile_vals);
+        const size_t i_win_part = add_vec(a, h.win_part);
+        const size_t i_wpart_win = add_vec(a, h.wpart_win);
+        const size_t i_wpart_t0 = add_vec(a, h.wpart_t0);
+        const size_t i_wpart_t1 = add_vec(a, h.wpart_t1);
         const size_t total = std::max<size_t>(a.total, 256);
 
         std::vector<uint8_t> image(total, 0);
@@ -211,6 +215,12 @@ extern "C" spmm_status spmm_plan_upload(spmm_plan_t *p) {
         dp.tile_bitmap = reinterpret_cast<const uint32_t *>(at(i_tile_bitmap));
         dp.tile_val_ptr = reinterpret_cast<const int32_t *>(at(i_tile_val_ptr));
         dp.tile_vals = reinterpret_cast<const uint16_t *>(at(i_tile_vals));
+        dp.n_wpart = (int32_t)h.wpart_win.size();
+        dp.win_tmax = kWinTiles;
+        dp.win_part = reinterpret_cast<const int32_t *>(at(i_win_part));
+        dp.wpart_win = reinterpret_cast<const int32_t *>(at(i_wpart_win));
+        dp.wpart_t0 = reinterpret_cast<const int32_t *>(at(i_wpart_t0));
+        dp.wpart_t1 = reinterpret_cast<const int32_t *>(at(i_wpart_t1));
         p->dev = d;
         p->dev_bytes = total;
         p->device = dev;
@@ -241,6 +251,11 @@ extern "C" spmm_status spmm_plan_destroy(spmm_plan_t *p) {
 }
 
 namespace spmm {
+size_t workspace_floats(const HostPlan &h) {
+    const size_t ld = (size_t)(h.n + 3) / 4 * 4;
+    return ((size_t)h.seg_row.size() + (size_t)h.wpart_win.size() * h.opts.window_h) * ld;
+}
+
 double algorithmic_bytes(const HostPlan &h) {
     const double sa = dtype_size(h.val_type), sb = dtype_size(h.b_type), sc = 4.0;
     return 4.0 * (double)(h.m + 1) + (double)h.nnz * (4.0 + sa) + (double)h.k_ref * h.n * sb +
@@ -269,7 +284,7 @@ extern "C" spmm_status spmm_plan_stats(const spmm_plan_t *p, spmm_plan_stats_t *
     out->mean_tile_density = slots > 0 ? (double)out->nnz_tiles / slots : 0.0;
     out->zero_fraction_tiles = slots > 0 ? 1.0 - out->mean_tile_density : 0.0;
     out->device_bytes = (int64_t)p->dev_bytes;
-    out->workspace_bytes = (int64_t)h.seg_row.size() * ((h.n + 3) / 4 * 4) * 4;
+    out->workspace_bytes = (int64_t)workspace_floats(h) * 4;
     out->algorithmic_bytes = algorithmic_bytes(h);
     out->flops = 2.0 * (double)h.nnz * (double)h.n;
     out->plan_ms = h.plan_ms;
@@ -309,6 +324,11 @@ extern "C" spmm_status spmm_plan_export(const spmm_plan_t *p, spmm_plan_dump_t *
     out->win_seg = h.win_seg.data();
     out->win_order = h.win_order.data();
     out->rem_col_dev = h.rem_col.data();
+    out->n_wparts = (int64_t)h.wpart_win.size();
+    out->win_part = h.win_part.data();
+    out->wpart_win = h.wpart_win.data();
+    out->wpart_t0 = h.wpart_t0.data();
+    out->wpart_t1 = h.wpart_t1.data();
     return SPMM_OK;
 }
 
@@ -484,6 +504,11 @@ spmm_status launch_plan(const spmm_plan_t *p, const RunArgs &a, hipStream_t s, s
         st = timed(SPMM_KERNEL_SEGMENT, [&] { return launch_segment(P, h.val_type, h.b_type, a, s); });
         if (st != SPMM_OK) return st;
     }
+    if (P.n_wpart > 0) {
+        st = timed(SPMM_KERNEL_WINDOW_PARTIAL,
+                   [&] { return launch_window_partial(P, h.val_type, h.b_type, h.tile_type, a, s); });
+        if (st != SPMM_OK) return st;
+    }
     if (P.n_vitems > 0) {
         st = timed(SPMM_KERNEL_VECTOR, [&] { return launch_vector(P, h.val_type, h.b_type, a, s); });
         if (st != SPMM_OK) return st;
@@ -505,8 +530,7 @@ static spmm_status run_impl(const spmm_plan_t *p, const void *B, int64_t ldb, vo
     hipStream_t s = static_cast<hipStream_t>(stream);
     RunArgs a;
     make_run_args(p, B, ldb, C, ldc, a);
-    const size_t ws = (size_t)p->dp.n_seg * (size_t)a.work_ld * sizeof(float);
-    st = workspace_for(s, ws, &a.work);
+    st = workspace_for(s, workspace_floats(p->hp) * sizeof(float), &a.work);
     if (st != SPMM_OK) return st;
     return launch_plan(p, a, s, t);
 }

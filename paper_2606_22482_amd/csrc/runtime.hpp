@@ -27,6 +27,7 @@ spmm_status make_run_args(const spmm_plan_t *p, const void *B, int64_t ldb, void
 spmm_status check_run(const spmm_plan_t *p, const void *B, int64_t ldb, void *C, int64_t ldc);
 spmm_status launch_plan(const spmm_plan_t *p, const RunArgs &a, hipStream_t s, spmm_timer_t *t);
 double algorithmic_bytes(const HostPlan &h);
+size_t workspace_floats(const HostPlan &h);
 std::string profile_key(const spmm_csr *A, int32_t n, int32_t b_type);
 bool cache_lookup(const std::string &key, spmm_opts *o);
 }  // namespace spmm

@@ -116,7 +116,7 @@ extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *
         const spmm_plan_t *p = items[i].plan;
         if (p->hp.m == 0) continue;
         make_run_args(p, items[i].B, items[i].ldb, items[i].C, items[i].ldc, args[i]);
-        ws_floats += (size_t)p->dp.n_seg * (size_t)args[i].work_ld;
+        ws_floats += workspace_floats(p->hp);
         const int E = args[i].vec_ok ? chunk_elems(p->hp.b_type) : 1;
         const int chunks = args[i].vec_ok ? args[i].np / E : args[i].np;
         const int cpl = chunks > 64 ? 2 : 1;
@@ -141,7 +141,7 @@ extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *
             const spmm_plan_t *p = items[i].plan;
             if (p->hp.m == 0) continue;
             args[i].work = static_cast<float *>(ctx.ws) + off;
-            off += (size_t)p->dp.n_seg * (size_t)args[i].work_ld;
+            off += workspace_floats(p->hp);
         }
     }
 
@@ -169,7 +169,7 @@ extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *
             SPMM_TRY_HIP(hipEventCreateWithFlags(&c.pinned_ev[slot], hipEventDisableTiming), "hipEventCreate");
         auto *hdr = static_cast<BatchHeader *>(c.pinned[slot]);
         auto *tab = reinterpret_cast<BatchEntry *>(static_cast<uint8_t *>(c.pinned[slot]) + kHeaderBytes);
-        int64_t ns = 0, nv = 0, nw = 0;
+        int64_t ns = 0, nv = 0, nw = 0, np_ = 0;
         for (size_t j = 0; j < idx.size(); ++j) {
             const spmm_plan_t *p = items[idx[j]].plan;
             const RunArgs &a = args[idx[j]];
@@ -179,17 +179,19 @@ extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *
             ns += (int64_t)p->dp.n_seg * a.n_panels;
             nv += (int64_t)p->dp.n_vitems * a.n_panels;
             nw += (int64_t)p->dp.n_win * a.win_panels;
-            if (ns > INT32_MAX || nv > INT32_MAX || nw > INT32_MAX)
+            np_ += (int64_t)p->dp.n_wpart * a.win_panels;
+            if (ns > INT32_MAX || nv > INT32_MAX || nw > INT32_MAX || np_ > INT32_MAX)
                 return set_error(SPMM_ERR_UNSUPPORTED, "batch has more than 2^31 items");
             e.seg_end = (int32_t)ns;
             e.vec_end = (int32_t)nv;
             e.win_end = (int32_t)nw;
-            e.pad = 0;
+            e.wpart_end = (int32_t)np_;
         }
         hdr->count = (int32_t)idx.size();
         hdr->total_seg = (int32_t)ns;
         hdr->total_vec = (int32_t)nv;
         hdr->total_win = (int32_t)nw;
+        hdr->total_wpart = (int32_t)np_;
 
         VariantGraph &vg = ctx.variants[key];
         if (vg.dcap < bytes) {

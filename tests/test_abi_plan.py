@@ -130,6 +130,17 @@ def _check_schedule(A, d, seg_len):
                 sid += d["nseg"][r]
     assert sid == d["seg_row"].size
     assert np.array_equal(np.sort(d["win_order"]), np.arange(d["windows"].shape[0]))
+    # window partial items: tiles beyond a window's first 16, in chunks of 16, in order
+    wt = np.bincount(d["tile_window"], minlength=d["windows"].shape[0])
+    tstart = np.concatenate([[0], np.cumsum(wt)])
+    k = 0
+    for w in range(d["windows"].shape[0]):
+        assert d["win_part"][w] == k
+        for t in range(tstart[w] + 16, tstart[w + 1], 16):
+            assert d["wpart_win"][k] == w and d["wpart_t0"][k] == t
+            assert d["wpart_t1"][k] == min(t + 16, tstart[w + 1])
+            k += 1
+    assert d["win_part"][-1] == k == d["wpart_win"].size
     # every row is owned exactly once
     owners = np.concatenate([vr, d["windows"][d["windows"] >= 0]])
     assert np.array_equal(np.sort(owners), np.arange(m))
@@ -179,6 +190,14 @@ def test_plan_bit_exact_vs_reference(lib, case):
     if mode == L.MODE_MIXED and kw.get("alpha", 0) <= 1.0:
         assert st["tiles"] > 0
     assert st["nnz_tiles"] + st["nnz_remainder"] == A.nnz
+
+
+def test_many_tiles_make_window_partials(lib):
+    A = synth.random_csr(64, 8192, 0.3, 6)
+    p = api.Plan(A, 32, "f32", api.default_opts(mode="mfma_only", window_h=16), upload=False)
+    d = p.export()
+    assert d["wpart_win"].size > 0
+    _check_schedule(A, d, p.stats()["opts"]["seg_len"])
 
 
 def test_mixed_without_tiles_equals_plain(lib):

@@ -71,6 +71,24 @@ def test_window_heights_and_orders_exact(H, order):
     exact(C, A, B, "bf16")
 
 
+@pytest.mark.parametrize("H", [16, 64])
+def test_windows_with_many_tiles_exact(H):
+    # wide dense-ish rows: hundreds of tiles per window, split into partial items
+    A = synth.random_csr(200, 9000, 0.25, 17 + H, val_kind="bf16", int_values=(-2, 2))
+    B = synth.int_dense(3, (9000, 160), -8, 8, kind="bf16")
+    p, C = run(A, B, "bf16", api.default_opts(mode="mfma_only", window_h=H, seg_len=40))
+    d = p.export()
+    assert d["wpart_win"].size > 10
+    exact(C, A, B, "bf16")
+    # the same through a batched submission
+    import torch
+    Bd = device_B(B, "bf16")
+    C2 = device_C(A.m, 160)
+    api.spmm_wait(api.spmm_submit([api.WorkItem(p, Bd, C2)]))
+    torch.cuda.synchronize()
+    assert torch.equal(C, C2)
+
+
 def test_identity_returns_B_bitwise():
     import torch
     n = 2048
