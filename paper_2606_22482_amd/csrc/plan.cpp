@@ -22,6 +22,29 @@ namespace spmm {
 
 int dtype_size(int32_t t) { return t == SPMM_F32 ? 4 : 2; }
 
+}  // namespace spmm
+
+extern "C" void spmm_opts_default(spmm_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->mode = SPMM_MODE_AUTO;
+    o->window_h = 0;
+    o->t_row = SPMM_AUTO_INT;
+    o->kt = 0;
+    o->n_panel = 0;
+    o->row_order = SPMM_ORDER_AUTO;
+    o->seg_len = 0;
+    o->item_cost = 0;
+    o->xcd_remap = -1;
+    o->hot_cols = -1;
+    o->cold_policy = -1;
+    o->pipeline = -1;
+    o->alpha_c = -1.0f;
+    o->alpha = -1.0f;
+}
+
+namespace spmm {
+
 uint16_t f32_to_bf16_rne(float f) {
     uint32_t u;
     std::memcpy(&u, &f, 4);

@@ -68,25 +68,6 @@ extern "C" const char *spmm_status_string(spmm_status s) {
 
 extern "C" const char *spmm_last_error(void) { return g_last_error.c_str(); }
 
-extern "C" void spmm_opts_default(spmm_opts *o) {
-    if (!o) return;
-    std::memset(o, 0, sizeof(*o));
-    o->mode = SPMM_MODE_AUTO;
-    o->window_h = 0;
-    o->t_row = SPMM_AUTO_INT;
-    o->kt = 0;
-    o->n_panel = 0;
-    o->row_order = SPMM_ORDER_AUTO;
-    o->seg_len = 0;
-    o->item_cost = 0;
-    o->xcd_remap = -1;
-    o->hot_cols = -1;
-    o->cold_policy = -1;
-    o->pipeline = -1;
-    o->alpha_c = -1.0f;
-    o->alpha = -1.0f;
-}
-
 // ------------------------------------------------------------------------------------------
 // plans
 
