@@ -208,6 +208,7 @@ __device__ __forceinline__ int logical_block(int xcd) {
 // panel.
 struct Lanes {
     int lpr_log2, lpr, groups, group, li;
+    __device__ __forceinline__ Lanes() = default;
     __device__ __forceinline__ explicit Lanes(int lg) {
         const int lane = threadIdx.x & 63;
         lpr_log2 = lg;
@@ -215,6 +216,12 @@ struct Lanes {
         groups = 64 >> lg;
         group = lane >> lg;
         li = lane & (lpr - 1);
+    }
+    // the same lane position with entry stride 1: the group walks a row alone
+    __device__ __forceinline__ Lanes single() const {
+        Lanes o = *this;
+        o.groups = 1;
+        return o;
     }
 };
 
@@ -298,6 +305,27 @@ __device__ __forceinline__ void seg_accumulate(const int32_t *__restrict__ rcol,
         float v[U];
         load_entries<VT, U>(rcol, rval, p, p1, L, col, v);
         gather_fma<BT, E, CPL, U>(col, v, p, p1, B, rs, ldb, cok, coff, L, cold_aux, acc);
+    }
+}
+
+// acc += sum over entries [p0, p1) of one row, all taken by this lane's group
+// in increasing order (each group works on its own row).
+template <int VT, int BT, int E, int CPL, int U>
+__device__ __forceinline__ void row_accumulate_group(const int32_t *__restrict__ rcol,
+                                                     const void *__restrict__ rval, int p0, int p1,
+                                                     const void *__restrict__ B, int64_t ldb,
+                                                     int ncol0, int ncols, const Lanes &L,
+                                                     int cold_aux, float (&acc)[CPL][E]) {
+    const __amdgpu_buffer_rsrc_t rs = b_resource(B);
+    bool cok[CPL];
+    int64_t coff[CPL];
+    chunk_layout<E, CPL>(ncol0, ncols, L, cok, coff);
+    const Lanes one = L.single();
+    for (int p = p0; p < p1; p += U) {
+        int col[U];
+        float v[U];
+        load_entries<VT, U>(rcol, rval, p, p1, one, col, v);
+        gather_fma<BT, E, CPL, U>(col, v, p, p1, B, rs, ldb, cok, coff, one, cold_aux, acc);
     }
 }
 
@@ -741,36 +769,37 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
     }
     __syncthreads();
 
+    // Remainders: every lane group takes its own row of the window, so up to
+    // 4 * G rows progress at once; a row's entries are summed in order by its
+    // group.  Rows then add the tile result and are written once.
     const Lanes L(a.win_lpr_log2);
-    for (int s = wave; s < H; s += 4) {
-        const int r = sm.rows[s];
-        if (r < 0) continue;
-        const int b = sm.rb[s], e = sm.re[s];
+    for (int s0 = 0; s0 < H; s0 += 4 * L.groups) {
+        const int s = s0 + wave * L.groups + L.group;
+        const int r = s < H ? sm.rows[s] : -1;
         float v[CPL][E];
 #pragma unroll
         for (int c = 0; c < CPL; ++c)
 #pragma unroll
             for (int x = 0; x < E; ++x) v[c][x] = 0.0f;
-        if (e - b <= P.seg_len) {
-            if (e > b) {
-                seg_accumulate<VT, BT, E, CPL, unroll_of<E, CPL>()>(P.rem_col, P.rem_val, b, e, a.B,
-                                                                    a.ldb, ncol0, ncols, L,
-                                                                    a.cold_aux, v);
-                group_reduce<E, CPL>(v, L);
+        if (r >= 0) {
+            const int b = sm.rb[s], e = sm.re[s];
+            if (e - b <= P.seg_len) {
+                row_accumulate_group<VT, BT, E, CPL, unroll_of<E, CPL>()>(
+                    P.rem_col, P.rem_val, b, e, a.B, a.ldb, ncol0, ncols, L, a.cold_aux, v);
+            } else {
+                const int ns = (e - b + P.seg_len - 1) / P.seg_len;
+                sum_partials<E, CPL>(a.work, a.work_ld, sm.sid[s], ns, ncol0, ncols, L, v);
             }
-        } else {
-            const int ns = (e - b + P.seg_len - 1) / P.seg_len;
-            sum_partials<E, CPL>(a.work, a.work_ld, sm.sid[s], ns, ncol0, ncols, L, v);
-        }
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            const int q = c * L.lpr + L.li;
-            if (q * E < ncols) {
+            for (int c = 0; c < CPL; ++c) {
+                const int q = c * L.lpr + L.li;
+                if (q * E < ncols) {
 #pragma unroll
-                for (int x = 0; x < E; ++x) v[c][x] = Cs[s * NPW + q * E + x] + v[c][x];
+                    for (int x = 0; x < E; ++x) v[c][x] = Cs[s * NPW + q * E + x] + v[c][x];
+                    store_chunk<E>(a.C, (int64_t)r * a.ldc + ncol0 + (int64_t)q * E, v[c]);
+                }
             }
         }
-        store_row<E, CPL>(a.C, (int64_t)r * a.ldc, ncol0, ncols, L, v);
     }
 }
 
