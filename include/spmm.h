@@ -89,14 +89,15 @@ typedef struct {
     int32_t seg_len;   /* remainder entries per segment; longer rows are split; <= 0: auto */
     int32_t item_cost; /* target work per vector work item, in entries; <= 0: auto */
     int32_t xcd_remap; /* 1: consecutive items on one XCD, 0: dispatch order, < 0: auto */
-    int32_t hot_cols;  /* B rows gathered with the default (cacheable) policy: the most-gathered
-                          columns, at most this many; the rest are gathered non-temporally
-                          (Sec. 6.2.1, hot B rows cached, the rest bypassing).  < 0: auto (80% of
-                          one XCD's 4 MiB L2 in B-panel rows); 0: none */
+    int32_t hot_cols;  /* with cold_policy != 0: the most-gathered columns (at most this many)
+                          keep the default cache policy, the others use cold_policy (Sec. 6.2.1,
+                          hot B rows cached, the rest bypassing).  < 0: auto (80% of one XCD's
+                          4 MiB L2 in B-panel rows, or 0 when cold_policy is 0); 0: none */
     float alpha_c;     /* column stage: a window column is a tile column iff its count > floor(alpha_c*H); < 0: auto */
     float alpha;       /* a K-tile is kept iff nnz / (H*kt) >= alpha (Sec. 5.2.1); < 0: auto */
     int32_t cold_policy; /* cache-policy bits of gathers of non-hot B rows (gfx950 buffer-load aux:
-                            2 = nt, 16 = sc1, 18 = nt|sc1, 0 = default); < 0: auto */
+                            2 = nt, 16 = sc1, 18 = nt|sc1, 0 = default); < 0: auto (0: measured
+                            fastest on gfx950) */
     int32_t pipeline;  /* vector kernel: 1 = prefetch the next row during the current row's gathers,
                           0 = row by row (identical results); < 0: auto */
 } spmm_opts;

@@ -248,6 +248,8 @@ def test_hot_columns_are_most_gathered(lib):
         want = np.sort(np.array(order[:min(hot, used.size)], dtype=np.int64))
         assert np.array_equal(flagged, want)
         assert p.stats()["hot_cols"] == want.size
-    # auto: 80% of a 4 MiB L2 in rows of N * 4 bytes
-    p = api.Plan(A, 64, "f32", api.default_opts(mode="plain"), upload=False)
+    # auto: 80% of a 4 MiB L2 in rows of N * 4 bytes when cold rows get their own policy
+    p = api.Plan(A, 64, "f32", api.default_opts(mode="plain", cold_policy=2), upload=False)
     assert p.stats()["opts"]["hot_cols"] == int(0.8 * 4 * 1024 * 1024 / (64 * 4))
+    q = api.Plan(A, 64, "f32", api.default_opts(mode="plain"), upload=False)
+    assert q.stats()["opts"]["cold_policy"] == 0 and q.stats()["opts"]["hot_cols"] == 0

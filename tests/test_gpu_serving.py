@@ -44,8 +44,10 @@ def test_mix_equals_solo_and_oracle(pool):
 def test_budget_rejects_and_keeps_serving(pool):
     reqs = synth.serving_requests(30, len(pool), 4, seed=8, rate=None)
     sizes = [pool[d["matrix"]]["A"].m for d in reqs]
-    # a budget that the largest requests can never fit
-    budget = 64 * 1024 * 1024
+    # a budget that the largest requests can never fit: the median B + C footprint
+    foot = sorted(pool[d["matrix"]]["A"].m * d["n"] * (8 if d["b_kind"] == "f32" else 6)
+                  for d in reqs)
+    budget = foot[len(foot) // 2]
     srv = serve.Server(pool, budget_bytes=budget, n_streams=2, max_batch=4)
     s = srv.run(reqs, realtime=False).summary()
     assert s["rejected"] > 0 and s["completed"] > 0
