@@ -98,8 +98,10 @@ typedef struct {
     int32_t cold_policy; /* cache-policy bits of gathers of non-hot B rows (gfx950 buffer-load aux:
                             2 = nt, 16 = sc1, 18 = nt|sc1, 0 = default); < 0: auto (0: measured
                             fastest on gfx950) */
-    int32_t pipeline;  /* vector kernel: 1 = prefetch the next row during the current row's gathers,
-                          0 = row by row (identical results); < 0: auto */
+    int32_t pipeline;  /* vector kernel variant: 0 = row by row; 1 = prefetch the next row during
+                          the current row's gathers (bitwise identical to 0); 2 = short rows (at
+                          most two unrolled batches) packed one per lane group, each summed in
+                          entry order (a different, equally fixed order); < 0: auto */
 } spmm_opts;
 
 typedef struct spmm_plan_s spmm_plan_t;

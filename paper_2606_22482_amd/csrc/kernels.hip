@@ -534,6 +534,77 @@ __device__ __forceinline__ void vector_item_pipelined(const DevPlan &P, const Ru
     }
 }
 
+// Vector work item with short rows packed one per lane group: a row whose
+// remainder has at most 2U entries is summed in entry order by one group, and
+// up to G such consecutive rows are gathered at once; longer rows take the
+// whole wavefront as in vector_item.  The rule depends only on a row's length.
+template <int VT, int BT, int E, int CPL>
+__device__ __forceinline__ void vector_item_packed(const DevPlan &P, const RunArgs &a, int wid) {
+    constexpr int U = unroll_of<E, CPL>();
+    constexpr int SHORT = 2 * U;
+    const int panel = wid / P.n_vitems, item = wid - panel * P.n_vitems;
+    const int ncol0 = panel * a.np, ncols = min(a.np, P.n - ncol0);
+    const Lanes L(a.lpr_log2);
+    const int lane = threadIdx.x & 63;
+    int sid = P.vitem_seg[item];
+    const int i0 = P.vitem_ptr[item], i1 = P.vitem_ptr[item + 1];
+    int i = i0;
+    while (i < i1) {
+        // lengths of the next (up to 64) rows, one per lane
+        const int li_row = i + lane;
+        int len = 0x7FFFFFFF;
+        if (lane < 64 && li_row < i1) {
+            const int rr = P.vec_rows ? P.vec_rows[li_row] : li_row;
+            len = P.rem_ptr[rr + 1] - P.rem_ptr[rr];
+        }
+        // k = consecutive short rows from i, at most G
+        const uint64_t longmask = __ballot(len > SHORT || len > P.seg_len || li_row >= i1);
+        int k = longmask ? __builtin_ctzll(longmask) : 64;
+        k = min(k, L.groups);
+        if (k > 0) {
+            const int my = i + L.group;
+            float acc[CPL][E];
+#pragma unroll
+            for (int c = 0; c < CPL; ++c)
+#pragma unroll
+                for (int x = 0; x < E; ++x) acc[c][x] = 0.0f;
+            int r = -1;
+            if (L.group < k) {
+                r = P.vec_rows ? P.vec_rows[my] : my;
+                row_accumulate_group<VT, BT, E, CPL, U>(P.rem_col, P.rem_val, P.rem_ptr[r],
+                                                        P.rem_ptr[r + 1], a.B, a.ldb, ncol0, ncols,
+                                                        L, a.cold_aux, acc);
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    const int q = c * L.lpr + L.li;
+                    if (q * E < ncols) store_chunk<E>(a.C, (int64_t)r * a.ldc + ncol0 + (int64_t)q * E, acc[c]);
+                }
+            }
+            i += k;
+            continue;
+        }
+        // a long row: the whole wavefront, as in vector_item
+        const int r = P.vec_rows ? P.vec_rows[i] : i;
+        const int b = P.rem_ptr[r], e = P.rem_ptr[r + 1];
+        float acc[CPL][E];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c)
+#pragma unroll
+            for (int x = 0; x < E; ++x) acc[c][x] = 0.0f;
+        if (e - b <= P.seg_len) {
+            seg_accumulate<VT, BT, E, CPL, U>(P.rem_col, P.rem_val, b, e, a.B, a.ldb, ncol0, ncols,
+                                              L, a.cold_aux, acc);
+            group_reduce<E, CPL>(acc, L);
+        } else {
+            const int ns = (e - b + P.seg_len - 1) / P.seg_len;
+            sum_partials<E, CPL>(a.work, a.work_ld, sid, ns, ncol0, ncols, L, acc);
+            sid += ns;
+        }
+        store_row<E, CPL>(a.C, (int64_t)r * a.ldc, ncol0, ncols, L, acc);
+        ++i;
+    }
+}
+
 template <int VT, int BT, int E, int CPL>
 __global__ __launch_bounds__(256) void segment_kernel(DevPlan P, RunArgs a) {
     const int wid = logical_block(a.xcd) * 4 + (threadIdx.x >> 6);
@@ -544,7 +615,8 @@ template <int VT, int BT, int E, int CPL>
 __global__ __launch_bounds__(256) void vector_kernel(DevPlan P, RunArgs a) {
     const int wid = logical_block(a.xcd) * 4 + (threadIdx.x >> 6);
     if (wid >= P.n_vitems * a.n_panels) return;
-    if (a.pipeline) vector_item_pipelined<VT, BT, E, CPL>(P, a, wid);
+    if (a.pipeline == 2) vector_item_packed<VT, BT, E, CPL>(P, a, wid);
+    else if (a.pipeline == 1) vector_item_pipelined<VT, BT, E, CPL>(P, a, wid);
     else vector_item<VT, BT, E, CPL>(P, a, wid);
 }
 
@@ -844,7 +916,8 @@ __global__ __launch_bounds__(256) void batch_vector_kernel(const BatchHeader *__
     for (int g = blockIdx.x * 4 + (threadIdx.x >> 6); g < total; g += gridDim.x * 4) {
         while (g >= tab[d].vec_end) ++d;
         const int base = d ? tab[d - 1].vec_end : 0;
-        if (tab[d].a.pipeline) vector_item_pipelined<VT, BT, E, CPL>(tab[d].P, tab[d].a, g - base);
+        if (tab[d].a.pipeline == 2) vector_item_packed<VT, BT, E, CPL>(tab[d].P, tab[d].a, g - base);
+        else if (tab[d].a.pipeline == 1) vector_item_pipelined<VT, BT, E, CPL>(tab[d].P, tab[d].a, g - base);
         else vector_item<VT, BT, E, CPL>(tab[d].P, tab[d].a, g - base);
     }
 }

@@ -139,6 +139,7 @@ static spmm_status validate_opts(const spmm_opts &o, std::string &err) {
     if (o.item_cost < 1) { err = "item_cost"; return SPMM_ERR_UNSUPPORTED; }
     if (o.n_panel < 0) { err = "n_panel"; return SPMM_ERR_UNSUPPORTED; }
     if (o.hot_cols < 0) { err = "hot_cols"; return SPMM_ERR_UNSUPPORTED; }
+    if (o.pipeline < 0 || o.pipeline > 2) { err = "pipeline must be 0, 1 or 2"; return SPMM_ERR_UNSUPPORTED; }
     if (o.cold_policy != 0 && o.cold_policy != 2 && o.cold_policy != 16 && o.cold_policy != 18) {
         err = "cold_policy must be 0, 2, 16 or 18";
         return SPMM_ERR_UNSUPPORTED;

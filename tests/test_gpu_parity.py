@@ -163,6 +163,24 @@ def test_pipelined_vector_kernel_bitwise_equals_row_by_row(n, kind):
     for C in outs[1:]:
         assert torch.equal(outs[0], C)
     parity(outs[0], A, B, kind, TOL_F32)
+    # packed short rows: a different fixed order, same tolerance, same result in mixed(no tiles)
+    _, P1 = run(A, B, kind, api.default_opts(mode="plain", seg_len=50, pipeline=2))
+    _, P2 = run(A, B, kind, api.default_opts(mode="mixed", alpha=1.5, seg_len=50, pipeline=2))
+    assert torch.equal(P1, P2)
+    parity(P1, A, B, kind, TOL_F32)
+
+
+@pytest.mark.parametrize("n,kinds", [(32, ("f16", "f16")), (128, ("f32", "f32")),
+                                     (7, ("bf16", "bf16"))])
+def test_packed_rows_integer_exact(n, kinds):
+    vk, bk = kinds
+    A = synth.random_csr(3000, 1500, 0.006, 31 + n, val_kind=vk, int_values=(-2, 2),
+                         empty_rows=0.1)
+    # a few long rows (segments) between the short ones
+    B = synth.int_dense(n + 1, (1500, n), -8, 8, kind=bk)
+    for seg in (5, 300):
+        _, C = run(A, B, bk, api.default_opts(mode="plain", pipeline=2, seg_len=seg))
+        exact(C, A, B, bk)
 
 
 def test_deterministic_and_nan_prefill():
