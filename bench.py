@@ -105,6 +105,15 @@ def cpu_baseline(A, B, b_kind, n, budget_s=12.0):
                       % (rows, m, 100.0 * nnz / max(1, A.nnz), n, dt)}
 
 
+def parse_opts(text):
+    """"k=v,k=v" plan options (alpha* floats, mode/row_order names, others ints)."""
+    out = {}
+    for kv in filter(None, text.split(",")):
+        k, v = kv.split("=")
+        out[k] = float(v) if k.startswith("alpha") else (v if k in ("mode", "row_order") else int(v))
+    return out
+
+
 def serve_bench(args):
     """Serving stream: Poisson arrivals at 0.7x the closed-loop saturation rate
     measured on the same request list; plans pre-built (resident)."""
@@ -152,7 +161,7 @@ def batch_bench(args):
     plans, items, flops = [], [], 0.0
     for i, sp in enumerate(specs):
         A, B = synth.batch_matrix(i, sp, seed=4)
-        p = api.Plan(A, B.shape[1], "f16", api.default_opts(mode="auto"))
+        p = api.Plan(A, B.shape[1], "f16", api.default_opts(**dict({"mode": "auto"}, **parse_opts(args.opts))))
         Bd = api.device_tensor(B, "f16")
         Cd = torch.empty((A.m, B.shape[1]), dtype=torch.float32, device="cuda")
         plans.append(p)
@@ -242,10 +251,7 @@ def main():
     A, B, b_kind, wname = workload(args.workload)
     n = B.shape[1]
     log("workload %s: m=%d nnz=%d n=%d (%.1f s)" % (wname, A.m, A.nnz, n, time.perf_counter() - t0))
-    extra = {}
-    for kv in filter(None, args.opts.split(",")):
-        k, v = kv.split("=")
-        extra[k] = float(v) if k.startswith("alpha") else (v if k in ("mode", "row_order") else int(v))
+    extra = parse_opts(args.opts)
 
     Bd = api.device_tensor(B, b_kind)
     Cd = torch.empty((A.m, n), dtype=torch.float32, device="cuda")
