@@ -72,11 +72,11 @@ struct BatchHeader {
 // Persistent batched launches over a device table (header + entries).
 // `grid_*` are the workgroup counts of the three kernels.
 hipError_t launch_batch(const BatchHeader *hdr, const BatchEntry *tab, int32_t val_t, int32_t b_t,
-                        int32_t tile_t, int vec_ok, int cpl, unsigned grid_wave,
+                        int32_t tile_t, int vec_ok, int cpl, int var, unsigned grid_wave,
                         unsigned grid_win, hipStream_t s);
 // Resident workgroups per CU of the batched kernels of this variant.
 hipError_t batch_occupancy(int32_t val_t, int32_t b_t, int32_t tile_t, int vec_ok, int cpl,
-                           int *wave_kernels, int *win_kernel);
+                           int var, int *wave_kernels, int *win_kernel);
 
 // dtype codes as in spmm.h
 hipError_t launch_segment(const DevPlan &P, int32_t val_t, int32_t b_t, const RunArgs &a,

@@ -22,6 +22,8 @@
 // segment is accumulated by group i mod G with fmaf, in increasing i; the
 // groups are then combined by an xor butterfly.  Segments of a split row are
 // added in segment order.  No floating-point atomics are used anywhere.
+#include <type_traits>
+
 #include "devplan.hpp"
 
 namespace spmm {
@@ -94,6 +96,63 @@ __device__ __forceinline__ void load_chunk(const void *B, int64_t off, float (&v
     }
 }
 
+// A gathered chunk kept in its stored form until it is consumed, so that 16-bit
+// B rows hold 4 registers per 8 elements while loads are in flight.
+template <int BT, int E>
+struct Raw {
+    using T = typename std::conditional<E == 1, uint32_t,
+                                        typename std::conditional<BT == DT_F32, f32x4, u32x4>::type>::type;
+    T x;
+};
+
+template <int BT, int E, bool NT>
+__device__ __forceinline__ void load_raw(const void *B, int64_t off, Raw<BT, E> &r) {
+    if constexpr (E == 1) {
+        if constexpr (BT == DT_F32)
+            r.x = __float_as_uint(ld<NT>(static_cast<const float *>(B) + off));
+        else
+            r.x = ld<NT>(static_cast<const unsigned short *>(B) + off);
+    } else if constexpr (BT == DT_F32) {
+        r.x = ld<NT>(reinterpret_cast<const f32x4 *>(static_cast<const float *>(B) + off));
+    } else {
+        r.x = ld<NT>(reinterpret_cast<const u32x4 *>(static_cast<const unsigned short *>(B) + off));
+    }
+}
+
+template <int BT, int E>
+__device__ __forceinline__ void zero_raw(Raw<BT, E> &r) {
+    if constexpr (E == 1) r.x = 0u;
+    else if constexpr (BT == DT_F32) r.x = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    else r.x = u32x4{0u, 0u, 0u, 0u};
+}
+
+// acc[e] = fma(v, chunk[e], acc[e]) for the E elements of a raw chunk.
+template <int BT, int E>
+__device__ __forceinline__ void fma_raw(float v, const Raw<BT, E> &r, float (&acc)[E]) {
+    if constexpr (E == 1) {
+        const float b = BT == DT_F32 ? __uint_as_float(r.x)
+                                     : (BT == DT_BF16 ? bf16_to_f32(r.x) : f16_to_f32(r.x));
+        acc[0] = __builtin_fmaf(v, b, acc[0]);
+    } else if constexpr (BT == DT_F32) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] = __builtin_fmaf(v, r.x[e], acc[e]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float lo, hi;
+            if constexpr (BT == DT_BF16) {
+                lo = __uint_as_float(r.x[i] << 16);
+                hi = __uint_as_float(r.x[i] & 0xFFFF0000u);
+            } else {
+                lo = f16_to_f32(r.x[i] & 0xFFFFu);
+                hi = f16_to_f32(r.x[i] >> 16);
+            }
+            acc[2 * i] = __builtin_fmaf(v, lo, acc[2 * i]);
+            acc[2 * i + 1] = __builtin_fmaf(v, hi, acc[2 * i + 1]);
+        }
+    }
+}
+
 // The same chunk through a raw buffer load whose cache-policy bits are `aux`
 // (gfx950: bit 0 sc0, bit 1 nt, bit 4 sc1).  A distinct intrinsic, so the
 // compiler never merges it with the default-policy load of a hot row.
@@ -157,6 +216,40 @@ __device__ __forceinline__ void load_chunk_policy(__amdgpu_buffer_rsrc_t rs, int
                 }
             }
         }
+    }
+}
+
+template <int BT, int E>
+__device__ __forceinline__ void load_raw_policy(__amdgpu_buffer_rsrc_t rs, int64_t off, int aux,
+                                                Raw<BT, E> &r) {
+    constexpr int SB = BT == DT_F32 ? 4 : 2;
+    const uint32_t boff = (uint32_t)(off * SB);
+    if constexpr (E == 1) {
+        if constexpr (SB == 4) {
+            switch (aux) {
+            case 2: r.x = buf4<2>(rs, boff); break;
+            case 16: r.x = buf4<16>(rs, boff); break;
+            case 18: r.x = buf4<18>(rs, boff); break;
+            default: r.x = buf4<0>(rs, boff); break;
+            }
+        } else {
+            switch (aux) {
+            case 2: r.x = buf2<2>(rs, boff); break;
+            case 16: r.x = buf2<16>(rs, boff); break;
+            case 18: r.x = buf2<18>(rs, boff); break;
+            default: r.x = buf2<0>(rs, boff); break;
+            }
+        }
+    } else {
+        u32x4 x;
+        switch (aux) {
+        case 2: x = buf16<2>(rs, boff); break;
+        case 16: x = buf16<16>(rs, boff); break;
+        case 18: x = buf16<18>(rs, boff); break;
+        default: x = buf16<0>(rs, boff); break;
+        }
+        if constexpr (BT == DT_F32) r.x = __builtin_bit_cast(f32x4, x);
+        else r.x = x;
     }
 }
 
@@ -247,7 +340,7 @@ __device__ __forceinline__ void gather_fma(const int (&col)[U], const float (&v)
                                            __amdgpu_buffer_rsrc_t rs, int64_t ldb,
                                            const bool (&cok)[CPL], const int64_t (&coff)[CPL],
                                            const Lanes &L, int cold_aux, float (&acc)[CPL][E]) {
-    float b[U][CPL][E];
+    Raw<BT, E> b[U][CPL];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const bool ok = p + u * L.groups < p1;
@@ -256,12 +349,11 @@ __device__ __forceinline__ void gather_fma(const int (&col)[U], const float (&v)
             // bit 31 of a column marks a hot B row (cacheable gather)
             const int64_t boff = (int64_t)(col[u] & 0x7FFFFFFF) * ldb + coff[c];
             if (ok && cok[c] && (col[u] < 0 || cold_aux < 0)) {
-                load_chunk<BT, E, false>(B, boff, b[u][c]);
+                load_raw<BT, E, false>(B, boff, b[u][c]);
             } else if (ok && cok[c]) {
-                load_chunk_policy<BT, E>(rs, boff, cold_aux, b[u][c]);
+                load_raw_policy<BT, E>(rs, boff, cold_aux, b[u][c]);
             } else {
-#pragma unroll
-                for (int e = 0; e < E; ++e) b[u][c][e] = 0.0f;
+                zero_raw<BT, E>(b[u][c]);
             }
         }
     }
@@ -269,9 +361,7 @@ __device__ __forceinline__ void gather_fma(const int (&col)[U], const float (&v)
     for (int u = 0; u < U; ++u) {
         if (p + u * L.groups < p1) {
 #pragma unroll
-            for (int c = 0; c < CPL; ++c)
-#pragma unroll
-                for (int e = 0; e < E; ++e) acc[c][e] = __builtin_fmaf(v[u], b[u][c][e], acc[c][e]);
+            for (int c = 0; c < CPL; ++c) fma_raw<BT, E>(v[u], b[u][c], acc[c]);
         }
     }
 }
@@ -475,7 +565,7 @@ __device__ __forceinline__ void vector_item_pipelined(const DevPlan &P, const Ru
         int ncl[U];
         float nv[U];
         if (e - b <= P.seg_len) {
-            float bv[U][CPL][E];
+            Raw<BT, E> bv[U][CPL];
             // gathers of this row's first batch
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -484,12 +574,11 @@ __device__ __forceinline__ void vector_item_pipelined(const DevPlan &P, const Ru
                 for (int c = 0; c < CPL; ++c) {
                     const int64_t boff = (int64_t)(col[u] & 0x7FFFFFFF) * a.ldb + coff[c];
                     if (ok && cok[c] && (col[u] < 0 || a.cold_aux < 0)) {
-                        load_chunk<BT, E, false>(a.B, boff, bv[u][c]);
+                        load_raw<BT, E, false>(a.B, boff, bv[u][c]);
                     } else if (ok && cok[c]) {
-                        load_chunk_policy<BT, E>(rs, boff, a.cold_aux, bv[u][c]);
+                        load_raw_policy<BT, E>(rs, boff, a.cold_aux, bv[u][c]);
                     } else {
-#pragma unroll
-                        for (int x = 0; x < E; ++x) bv[u][c][x] = 0.0f;
+                        zero_raw<BT, E>(bv[u][c]);
                     }
                 }
             }
@@ -500,10 +589,7 @@ __device__ __forceinline__ void vector_item_pipelined(const DevPlan &P, const Ru
             for (int u = 0; u < U; ++u) {
                 if (b + L.group + u * L.groups < e) {
 #pragma unroll
-                    for (int c = 0; c < CPL; ++c)
-#pragma unroll
-                        for (int x = 0; x < E; ++x)
-                            acc[c][x] = __builtin_fmaf(v[u], bv[u][c][x], acc[c][x]);
+                    for (int c = 0; c < CPL; ++c) fma_raw<BT, E>(v[u], bv[u][c], acc[c]);
                 }
             }
             // the rest of a row longer than one batch, continuing the same order
@@ -611,13 +697,17 @@ __global__ __launch_bounds__(256) void segment_kernel(DevPlan P, RunArgs a) {
     if (wid < P.n_seg * a.n_panels) segment_item<VT, BT, E, CPL>(P, a, wid);
 }
 
-template <int VT, int BT, int E, int CPL>
+template <int VT, int BT, int E, int CPL, int VAR>
+__device__ __forceinline__ void vector_item_var(const DevPlan &P, const RunArgs &a, int wid) {
+    if constexpr (VAR == 2) vector_item_packed<VT, BT, E, CPL>(P, a, wid);
+    else if constexpr (VAR == 1) vector_item_pipelined<VT, BT, E, CPL>(P, a, wid);
+    else vector_item<VT, BT, E, CPL>(P, a, wid);
+}
+
+template <int VT, int BT, int E, int CPL, int VAR>
 __global__ __launch_bounds__(256) void vector_kernel(DevPlan P, RunArgs a) {
     const int wid = logical_block(a.xcd) * 4 + (threadIdx.x >> 6);
-    if (wid >= P.n_vitems * a.n_panels) return;
-    if (a.pipeline == 2) vector_item_packed<VT, BT, E, CPL>(P, a, wid);
-    else if (a.pipeline == 1) vector_item_pipelined<VT, BT, E, CPL>(P, a, wid);
-    else vector_item<VT, BT, E, CPL>(P, a, wid);
+    if (wid < P.n_vitems * a.n_panels) vector_item_var<VT, BT, E, CPL, VAR>(P, a, wid);
 }
 
 // Inclusive prefix sum over the 64 lanes of a wavefront.
@@ -908,7 +998,7 @@ __global__ __launch_bounds__(256) void batch_segment_kernel(const BatchHeader *_
     }
 }
 
-template <int VT, int BT, int E, int CPL>
+template <int VT, int BT, int E, int CPL, int VAR>
 __global__ __launch_bounds__(256) void batch_vector_kernel(const BatchHeader *__restrict__ hdr,
                                                            const BatchEntry *__restrict__ tab) {
     const int total = hdr->total_vec;
@@ -916,9 +1006,7 @@ __global__ __launch_bounds__(256) void batch_vector_kernel(const BatchHeader *__
     for (int g = blockIdx.x * 4 + (threadIdx.x >> 6); g < total; g += gridDim.x * 4) {
         while (g >= tab[d].vec_end) ++d;
         const int base = d ? tab[d - 1].vec_end : 0;
-        if (tab[d].a.pipeline == 2) vector_item_packed<VT, BT, E, CPL>(tab[d].P, tab[d].a, g - base);
-        else if (tab[d].a.pipeline == 1) vector_item_pipelined<VT, BT, E, CPL>(tab[d].P, tab[d].a, g - base);
-        else vector_item<VT, BT, E, CPL>(tab[d].P, tab[d].a, g - base);
+        vector_item_var<VT, BT, E, CPL, VAR>(tab[d].P, tab[d].a, g - base);
     }
 }
 
@@ -967,20 +1055,27 @@ static hipError_t seg_dispatch(const DevPlan &P, const RunArgs &a, hipStream_t s
     return hipGetLastError();
 }
 
-template <int VT, int BT>
-static hipError_t vec_dispatch(const DevPlan &P, const RunArgs &a, hipStream_t s) {
+template <int VT, int BT, int VAR>
+static hipError_t vec_dispatch_var(const DevPlan &P, const RunArgs &a, hipStream_t s) {
     const int64_t waves = (int64_t)P.n_vitems * a.n_panels;
     if (waves == 0) return hipSuccess;
     constexpr int EV = BT == DT_F32 ? 4 : 8;
     const int chunks = a.vec_ok ? (a.np + EV - 1) / EV : a.np;
     dim3 grid(grid_for_waves(waves)), block(256);
     if (a.vec_ok) {
-        if (chunks <= 64) hipLaunchKernelGGL((vector_kernel<VT, BT, EV, 1>), grid, block, 0, s, P, a);
-        else hipLaunchKernelGGL((vector_kernel<VT, BT, EV, 2>), grid, block, 0, s, P, a);
+        if (chunks <= 64) hipLaunchKernelGGL((vector_kernel<VT, BT, EV, 1, VAR>), grid, block, 0, s, P, a);
+        else hipLaunchKernelGGL((vector_kernel<VT, BT, EV, 2, VAR>), grid, block, 0, s, P, a);
     } else {
-        hipLaunchKernelGGL((vector_kernel<VT, BT, 1, 2>), grid, block, 0, s, P, a);
+        hipLaunchKernelGGL((vector_kernel<VT, BT, 1, 2, VAR>), grid, block, 0, s, P, a);
     }
     return hipGetLastError();
+}
+
+template <int VT, int BT>
+static hipError_t vec_dispatch(const DevPlan &P, const RunArgs &a, hipStream_t s) {
+    if (a.pipeline == 2) return vec_dispatch_var<VT, BT, 2>(P, a, s);
+    if (a.pipeline == 1) return vec_dispatch_var<VT, BT, 1>(P, a, s);
+    return vec_dispatch_var<VT, BT, 0>(P, a, s);
 }
 
 template <int VT, int BT, int TT>
@@ -1045,12 +1140,12 @@ hipError_t launch_window_partial(const DevPlan &P, int32_t vt, int32_t bt, int32
     return window_any(P, vt, bt, tt, a, s, true);
 }
 
-template <int VT, int BT, int TT, int E, int CPL>
+template <int VT, int BT, int TT, int E, int CPL, int VAR>
 static hipError_t batch_variant(const BatchHeader *hdr, const BatchEntry *tab, unsigned gw,
                                 unsigned gwin, hipStream_t s, int *occ_wave, int *occ_win) {
     if (occ_wave) {
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            occ_wave, batch_vector_kernel<VT, BT, E, CPL>, 256, 0);
+            occ_wave, batch_vector_kernel<VT, BT, E, CPL, VAR>, 256, 0);
         if (e != hipSuccess) return e;
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(
             occ_win, batch_window_kernel<VT, BT, TT, E, CPL, false>, 256, 0);
@@ -1059,24 +1154,36 @@ static hipError_t batch_variant(const BatchHeader *hdr, const BatchEntry *tab, u
     hipLaunchKernelGGL((batch_segment_kernel<VT, BT, E, CPL>), dim3(gw), dim3(256), 0, s, hdr, tab);
     hipLaunchKernelGGL((batch_window_kernel<VT, BT, TT, E, CPL, true>), dim3(gwin), dim3(256), 0, s,
                        hdr, tab);
-    hipLaunchKernelGGL((batch_vector_kernel<VT, BT, E, CPL>), dim3(gw), dim3(256), 0, s, hdr, tab);
+    hipLaunchKernelGGL((batch_vector_kernel<VT, BT, E, CPL, VAR>), dim3(gw), dim3(256), 0, s, hdr, tab);
     hipLaunchKernelGGL((batch_window_kernel<VT, BT, TT, E, CPL, false>), dim3(gwin), dim3(256), 0,
                        s, hdr, tab);
     return hipGetLastError();
 }
 
+template <int VT, int BT, int TT, int VAR>
+static hipError_t batch_types_var(const BatchHeader *hdr, const BatchEntry *tab, int vec_ok,
+                                  int cpl, unsigned gw, unsigned gwin, hipStream_t s, int *ow,
+                                  int *oc) {
+    constexpr int EV = BT == DT_F32 ? 4 : 8;
+    if (!vec_ok) return batch_variant<VT, BT, TT, 1, 2, VAR>(hdr, tab, gw, gwin, s, ow, oc);
+    if (cpl == 1) return batch_variant<VT, BT, TT, EV, 1, VAR>(hdr, tab, gw, gwin, s, ow, oc);
+    return batch_variant<VT, BT, TT, EV, 2, VAR>(hdr, tab, gw, gwin, s, ow, oc);
+}
+
+static int g_batch_var = 0;  // vector variant of the batch being launched (set by batch_any)
+
 template <int VT, int BT, int TT>
 static hipError_t batch_types(const BatchHeader *hdr, const BatchEntry *tab, int vec_ok, int cpl,
                               unsigned gw, unsigned gwin, hipStream_t s, int *ow, int *oc) {
-    constexpr int EV = BT == DT_F32 ? 4 : 8;
-    if (!vec_ok) return batch_variant<VT, BT, TT, 1, 2>(hdr, tab, gw, gwin, s, ow, oc);
-    if (cpl == 1) return batch_variant<VT, BT, TT, EV, 1>(hdr, tab, gw, gwin, s, ow, oc);
-    return batch_variant<VT, BT, TT, EV, 2>(hdr, tab, gw, gwin, s, ow, oc);
+    if (g_batch_var == 2) return batch_types_var<VT, BT, TT, 2>(hdr, tab, vec_ok, cpl, gw, gwin, s, ow, oc);
+    if (g_batch_var == 1) return batch_types_var<VT, BT, TT, 1>(hdr, tab, vec_ok, cpl, gw, gwin, s, ow, oc);
+    return batch_types_var<VT, BT, TT, 0>(hdr, tab, vec_ok, cpl, gw, gwin, s, ow, oc);
 }
 
 static hipError_t batch_any(const BatchHeader *hdr, const BatchEntry *tab, int32_t vt, int32_t bt,
-                            int32_t tt, int vec_ok, int cpl, unsigned gw, unsigned gwin,
+                            int32_t tt, int vec_ok, int cpl, int var, unsigned gw, unsigned gwin,
                             hipStream_t s, int *ow, int *oc) {
+    g_batch_var = var;
     if (vt == DT_F32 && bt == DT_F32 && tt == DT_BF16)
         return batch_types<DT_F32, DT_F32, DT_BF16>(hdr, tab, vec_ok, cpl, gw, gwin, s, ow, oc);
     if (vt == DT_F32 && bt == DT_BF16 && tt == DT_BF16)
@@ -1089,14 +1196,15 @@ static hipError_t batch_any(const BatchHeader *hdr, const BatchEntry *tab, int32
 }
 
 hipError_t launch_batch(const BatchHeader *hdr, const BatchEntry *tab, int32_t vt, int32_t bt,
-                        int32_t tt, int vec_ok, int cpl, unsigned grid_wave, unsigned grid_win,
-                        hipStream_t s) {
-    return batch_any(hdr, tab, vt, bt, tt, vec_ok, cpl, grid_wave, grid_win, s, nullptr, nullptr);
+                        int32_t tt, int vec_ok, int cpl, int var, unsigned grid_wave,
+                        unsigned grid_win, hipStream_t s) {
+    return batch_any(hdr, tab, vt, bt, tt, vec_ok, cpl, var, grid_wave, grid_win, s, nullptr,
+                     nullptr);
 }
 
-hipError_t batch_occupancy(int32_t vt, int32_t bt, int32_t tt, int vec_ok, int cpl,
+hipError_t batch_occupancy(int32_t vt, int32_t bt, int32_t tt, int vec_ok, int cpl, int var,
                            int *wave_kernels, int *win_kernel) {
-    return batch_any(nullptr, nullptr, vt, bt, tt, vec_ok, cpl, 0, 0, nullptr, wave_kernels,
+    return batch_any(nullptr, nullptr, vt, bt, tt, vec_ok, cpl, var, 0, 0, nullptr, wave_kernels,
                      win_kernel);
 }
 

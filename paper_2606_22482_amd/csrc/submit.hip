@@ -122,7 +122,7 @@ extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *
         const int cpl = chunks > 64 ? 2 : 1;
         const uint64_t key = (uint64_t)p->hp.val_type | ((uint64_t)p->hp.b_type << 4) |
                              ((uint64_t)p->hp.tile_type << 8) | ((uint64_t)args[i].vec_ok << 12) |
-                             ((uint64_t)cpl << 16);
+                             ((uint64_t)cpl << 16) | ((uint64_t)args[i].pipeline << 20);
         groups[key].push_back(i);
     }
     if (ws_floats * sizeof(float) > ctx.ws_bytes) {
@@ -149,7 +149,7 @@ extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *
         const uint64_t key = kv.first;
         const std::vector<int32_t> &idx = kv.second;
         const int32_t vt = key & 0xF, bt = (key >> 4) & 0xF, tt = (key >> 8) & 0xF;
-        const int vec_ok = (key >> 12) & 0xF, cpl = (key >> 16) & 0xF;
+        const int vec_ok = (key >> 12) & 0xF, cpl = (key >> 16) & 0xF, var = (key >> 20) & 0xF;
         // host table
         const size_t bytes = kHeaderBytes + idx.size() * sizeof(BatchEntry);
         BatchCtx &c = ctx;
@@ -205,7 +205,7 @@ extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *
         }
         if (!vg.exec) {
             int ow = 0, oc = 0;
-            SPMM_TRY_HIP(batch_occupancy(vt, bt, tt, vec_ok, cpl, &ow, &oc), "occupancy");
+            SPMM_TRY_HIP(batch_occupancy(vt, bt, tt, vec_ok, cpl, var, &ow, &oc), "occupancy");
             vg.grid_wave = (unsigned)std::max(1, ow) * (unsigned)ncu;
             vg.grid_win = (unsigned)std::max(1, oc) * (unsigned)ncu;
             if (!ctx.capture)
@@ -213,7 +213,7 @@ extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *
             const auto *dh = static_cast<const BatchHeader *>(vg.dtab);
             const auto *dt = reinterpret_cast<const BatchEntry *>(static_cast<uint8_t *>(vg.dtab) + kHeaderBytes);
             SPMM_TRY_HIP(hipStreamBeginCapture(ctx.capture, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-            hipError_t le = launch_batch(dh, dt, vt, bt, tt, vec_ok, cpl, vg.grid_wave, vg.grid_win, ctx.capture);
+            hipError_t le = launch_batch(dh, dt, vt, bt, tt, vec_ok, cpl, var, vg.grid_wave, vg.grid_win, ctx.capture);
             hipGraph_t graph = nullptr;
             hipError_t ce = hipStreamEndCapture(ctx.capture, &graph);
             if (le != hipSuccess) return hip_error(le, "batched launch (capture)");
