@@ -82,6 +82,28 @@ def kernel_bytes(A, d, n, s_a, s_b):
     return out
 
 
+def kernels_sha1():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2606_22482_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()
+
+
+def measured_traffic(workload, mode, kernel):
+    """HBM traffic per launch of a kernel from the committed counter summary
+    (profiles/traffic.json: FETCH_SIZE x2 + WRITE_SIZE x1, see the copy-kernel
+    calibration), only when it was taken with the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernels_sha1") != kernels_sha1():
+        return None
+    e = t.get("entries", {}).get("%s/%s/%s" % (workload, mode, kernel))
+    return None if e is None else int(e["fetch_bytes"] + e["write_bytes"])
+
+
 def cpu_baseline(A, B, b_kind, n, budget_s=12.0):
     """Time the FP64 oracle on a bounded leading block of rows, all host threads
     of this process's share (at most 16)."""
@@ -319,7 +341,8 @@ def main():
                    "b_dtype": b_kind, "mode": best},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "bytes_per_launch": int(kb[dom]),
+                     "traffic": measured_traffic(wname, best, dom),
+                     "bytes_per_launch": int(kb[dom]),
                      "avg_launch_ms": round(R["kavg"][dom], 5)},
         "path_hbm_roofline_frac": round(path_gbs / HBM_PEAK_GBS, 4),
         "path_algorithmic_bytes": int(st["algorithmic_bytes"]),
