@@ -65,8 +65,13 @@ struct BatchEntry {
     int32_t seg_end, vec_end, win_end, wpart_end;
 };
 
+// Entries are grouped by the XCD they are assigned to; x_* hold, per XCD x,
+// the first entry and the first item of each kind (exclusive prefix sums, 9
+// values each).  Workgroup b of a persistent kernel runs on XCD b % 8 and walks
+// only its XCD's items, so one XCD's L2 serves one matrix's B at a time.
 struct BatchHeader {
     int32_t count, total_seg, total_vec, total_win, total_wpart, pad[3];
+    int32_t x_entry[9], x_seg[9], x_vec[9], x_win[9], x_wpart[9];
 };
 
 // Persistent batched launches over a device table (header + entries).

@@ -986,45 +986,57 @@ __global__ __launch_bounds__(256) void window_partial_kernel(DevPlan P, RunArgs 
 // moves forward.  Each matrix's items run exactly the code of a single run, so
 // a matrix's result is bitwise the same alone and in a batch.
 
+// Persistent walk over one XCD's items of one kind: item ids g of XCD x are
+// [xb[x], xb[x+1]); entries of XCD x start at x_entry[x]; `end` gives an
+// entry's exclusive item prefix (global over the table).
+#define SPMM_XCD_WALK(XB, END, PER_WG, BODY)                                           \
+    do {                                                                               \
+        const int x = blockIdx.x & 7, local = blockIdx.x >> 3, nloc = gridDim.x >> 3;   \
+        const int lo = hdr->XB[x], hi = hdr->XB[x + 1];                                \
+        int d = hdr->x_entry[x];                                                       \
+        for (int g = lo + local * PER_WG + sub; g < hi; g += nloc * PER_WG) {          \
+            while (g >= tab[d].END) ++d;                                               \
+            const int item = g - (d ? tab[d - 1].END : 0);                             \
+            BODY;                                                                      \
+        }                                                                              \
+    } while (0)
+
 template <int VT, int BT, int E, int CPL>
 __global__ __launch_bounds__(256) void batch_segment_kernel(const BatchHeader *__restrict__ hdr,
                                                             const BatchEntry *__restrict__ tab) {
-    const int total = hdr->total_seg;
-    int d = 0;
-    for (int g = blockIdx.x * 4 + (threadIdx.x >> 6); g < total; g += gridDim.x * 4) {
-        while (g >= tab[d].seg_end) ++d;
-        const int base = d ? tab[d - 1].seg_end : 0;
-        segment_item<VT, BT, E, CPL>(tab[d].P, tab[d].a, g - base);
-    }
+    const int sub = threadIdx.x >> 6;
+    SPMM_XCD_WALK(x_seg, seg_end, 4, (segment_item<VT, BT, E, CPL>(tab[d].P, tab[d].a, item)));
 }
 
 template <int VT, int BT, int E, int CPL, int VAR>
 __global__ __launch_bounds__(256) void batch_vector_kernel(const BatchHeader *__restrict__ hdr,
                                                            const BatchEntry *__restrict__ tab) {
-    const int total = hdr->total_vec;
-    int d = 0;
-    for (int g = blockIdx.x * 4 + (threadIdx.x >> 6); g < total; g += gridDim.x * 4) {
-        while (g >= tab[d].vec_end) ++d;
-        const int base = d ? tab[d - 1].vec_end : 0;
-        vector_item_var<VT, BT, E, CPL, VAR>(tab[d].P, tab[d].a, g - base);
-    }
+    const int sub = threadIdx.x >> 6;
+    SPMM_XCD_WALK(x_vec, vec_end, 4, (vector_item_var<VT, BT, E, CPL, VAR>(tab[d].P, tab[d].a, item)));
+}
+
+template <int VT, int BT, int TT, int E, int CPL, int MB>
+__device__ __forceinline__ void window_item_h(const BatchEntry &e, int item, WinSmem<4> &sm,
+                                              bool partial) {
+    window_item<VT, BT, TT, MB, E, CPL, 4>(e.P, e.a, item, sm, partial);
+    __syncthreads();  // the next item reuses the LDS
 }
 
 template <int VT, int BT, int TT, int E, int CPL, bool PARTIAL>
 __global__ __launch_bounds__(256) void batch_window_kernel(const BatchHeader *__restrict__ hdr,
                                                            const BatchEntry *__restrict__ tab) {
     __shared__ WinSmem<4> sm;
-    const int total = PARTIAL ? hdr->total_wpart : hdr->total_win;
-    int d = 0;
-    for (int g = blockIdx.x; g < total; g += gridDim.x) {
-        while (g >= (PARTIAL ? tab[d].wpart_end : tab[d].win_end)) ++d;
-        const int item = g - (d ? (PARTIAL ? tab[d - 1].wpart_end : tab[d - 1].win_end) : 0);
-        switch (tab[d].P.H) {
-        case 16: window_item<VT, BT, TT, 1, E, CPL, 4>(tab[d].P, tab[d].a, item, sm, PARTIAL); break;
-        case 32: window_item<VT, BT, TT, 2, E, CPL, 4>(tab[d].P, tab[d].a, item, sm, PARTIAL); break;
-        default: window_item<VT, BT, TT, 4, E, CPL, 4>(tab[d].P, tab[d].a, item, sm, PARTIAL); break;
-        }
-        __syncthreads();  // the next item reuses the LDS
+    const int sub = 0;
+    if (PARTIAL) {
+        SPMM_XCD_WALK(x_wpart, wpart_end, 1,
+                      (tab[d].P.H == 16 ? window_item_h<VT, BT, TT, E, CPL, 1>(tab[d], item, sm, true)
+                       : tab[d].P.H == 32 ? window_item_h<VT, BT, TT, E, CPL, 2>(tab[d], item, sm, true)
+                                          : window_item_h<VT, BT, TT, E, CPL, 4>(tab[d], item, sm, true)));
+    } else {
+        SPMM_XCD_WALK(x_win, win_end, 1,
+                      (tab[d].P.H == 16 ? window_item_h<VT, BT, TT, E, CPL, 1>(tab[d], item, sm, false)
+                       : tab[d].P.H == 32 ? window_item_h<VT, BT, TT, E, CPL, 2>(tab[d], item, sm, false)
+                                          : window_item_h<VT, BT, TT, E, CPL, 4>(tab[d], item, sm, false)));
     }
 }
 

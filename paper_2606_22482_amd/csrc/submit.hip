@@ -72,6 +72,7 @@ std::mutex g_batch_mu;
 std::map<std::pair<int, hipStream_t>, BatchCtx> g_batch;
 
 constexpr size_t kHeaderBytes = 256;
+static_assert(sizeof(BatchHeader) <= kHeaderBytes, "batch header grew");
 
 spmm_status ensure_device(void **p, size_t *cap, size_t bytes) {
     if (*cap >= bytes) return SPMM_OK;
@@ -169,11 +170,46 @@ extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *
             SPMM_TRY_HIP(hipEventCreateWithFlags(&c.pinned_ev[slot], hipEventDisableTiming), "hipEventCreate");
         auto *hdr = static_cast<BatchHeader *>(c.pinned[slot]);
         auto *tab = reinterpret_cast<BatchEntry *>(static_cast<uint8_t *>(c.pinned[slot]) + kHeaderBytes);
+        // Longest-processing-time assignment of whole matrices to the 8 XCDs
+        // (cost ~ entries * N plus rows * N), entries then grouped by XCD.
+        std::vector<int32_t> order(idx.size());
+        for (size_t j = 0; j < idx.size(); ++j) order[j] = (int32_t)j;
+        auto cost = [&](int32_t j) {
+            const spmm_plan_t *p = items[idx[j]].plan;
+            return ((double)p->hp.nnz + (double)p->hp.m) * (double)p->hp.n;
+        };
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t x, int32_t y) { return cost(x) > cost(y); });
+        std::vector<int32_t> xcd_of(idx.size(), 0);
+        double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int32_t j : order) {
+            int best = 0;
+            for (int x = 1; x < 8; ++x)
+                if (load[x] < load[best]) best = x;
+            xcd_of[j] = best;
+            load[best] += cost(j);
+        }
+        std::vector<int32_t> seq;
+        seq.reserve(idx.size());
+        for (int x = 0; x < 8; ++x) {
+            hdr->x_entry[x] = (int32_t)seq.size();
+            for (int32_t j : order)
+                if (xcd_of[j] == x) seq.push_back(j);
+        }
+        hdr->x_entry[8] = (int32_t)seq.size();
         int64_t ns = 0, nv = 0, nw = 0, np_ = 0;
-        for (size_t j = 0; j < idx.size(); ++j) {
+        for (size_t jj = 0; jj < seq.size(); ++jj) {
+            const size_t j = (size_t)seq[jj];
+            for (int x = 0; x < 8; ++x)
+                if (hdr->x_entry[x] == (int32_t)jj) {
+                    hdr->x_seg[x] = (int32_t)ns;
+                    hdr->x_vec[x] = (int32_t)nv;
+                    hdr->x_win[x] = (int32_t)nw;
+                    hdr->x_wpart[x] = (int32_t)np_;
+                }
             const spmm_plan_t *p = items[idx[j]].plan;
             const RunArgs &a = args[idx[j]];
-            BatchEntry &e = tab[j];
+            BatchEntry &e = tab[jj];
             e.P = p->dp;
             e.a = a;
             ns += (int64_t)p->dp.n_seg * a.n_panels;
@@ -187,6 +223,18 @@ extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *
             e.win_end = (int32_t)nw;
             e.wpart_end = (int32_t)np_;
         }
+        // XCDs with no entry start where the next one does
+        for (int x = 7; x >= 0; --x)
+            if (hdr->x_entry[x] == hdr->x_entry[x + 1]) {
+                hdr->x_seg[x] = x < 7 ? hdr->x_seg[x + 1] : (int32_t)ns;
+                hdr->x_vec[x] = x < 7 ? hdr->x_vec[x + 1] : (int32_t)nv;
+                hdr->x_win[x] = x < 7 ? hdr->x_win[x + 1] : (int32_t)nw;
+                hdr->x_wpart[x] = x < 7 ? hdr->x_wpart[x + 1] : (int32_t)np_;
+            }
+        hdr->x_seg[8] = (int32_t)ns;
+        hdr->x_vec[8] = (int32_t)nv;
+        hdr->x_win[8] = (int32_t)nw;
+        hdr->x_wpart[8] = (int32_t)np_;
         hdr->count = (int32_t)idx.size();
         hdr->total_seg = (int32_t)ns;
         hdr->total_vec = (int32_t)nv;
@@ -206,8 +254,9 @@ extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *
         if (!vg.exec) {
             int ow = 0, oc = 0;
             SPMM_TRY_HIP(batch_occupancy(vt, bt, tt, vec_ok, cpl, var, &ow, &oc), "occupancy");
-            vg.grid_wave = (unsigned)std::max(1, ow) * (unsigned)ncu;
-            vg.grid_win = (unsigned)std::max(1, oc) * (unsigned)ncu;
+            // a multiple of 8 so that every XCD gets the same number of workgroups
+            vg.grid_wave = std::max(8u, ((unsigned)std::max(1, ow) * (unsigned)ncu) & ~7u);
+            vg.grid_win = std::max(8u, ((unsigned)std::max(1, oc) * (unsigned)ncu) & ~7u);
             if (!ctx.capture)
                 SPMM_TRY_HIP(hipStreamCreateWithFlags(&ctx.capture, hipStreamNonBlocking), "hipStreamCreate");
             const auto *dh = static_cast<const BatchHeader *>(vg.dtab);
