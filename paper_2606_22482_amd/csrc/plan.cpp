@@ -67,7 +67,10 @@ void resolve_options(const spmm_opts *in, const spmm_csr *A, int32_t n, int32_t 
     if (d.seg_len <= 0) d.seg_len = 256;
     if (d.item_cost <= 0) {
         double total = (double)(A ? A->nnz : 0) + (double)kRowCost * (double)(A ? A->m : 0);
-        double c = total / 32768.0;
+        // about 512 entries per item for small and medium matrices (whole lane
+        // groups of packed short rows), total/32768 for large ones, so that a
+        // large matrix still gives tens of thousands of items
+        double c = std::max(total / 32768.0, std::min(512.0, total / 512.0));
         d.item_cost = (int32_t)std::min(2048.0, std::max(32.0, c));
     }
     if (d.xcd_remap < 0) d.xcd_remap = 1;

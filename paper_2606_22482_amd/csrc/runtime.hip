@@ -110,9 +110,11 @@ extern "C" spmm_status spmm_plan_build(const spmm_csr *A, int32_t n, int32_t b_t
         st = build_host_plan(A, n, b_type, c_type, o, p->hp, err);
         if (st != SPMM_OK) return set_error(st, err);
         // AUTO without a tuned profile: keep the mixed partition only when the
-        // tiles take a useful share of the entries, else plan the plain path.
+        // tiles hold most of the entries, else plan the plain path.  Measured on
+        // gfx950: power-law graphs with 1-30% of the entries in tiles run faster
+        // plain; block-community matrices with 95% in tiles run 2x faster mixed.
         if (auto_mode && !have_tuned && A->nnz > 0 &&
-            (double)p->hp.tile_src.size() < 0.10 * (double)A->nnz) {
+            (double)p->hp.tile_src.size() < 0.5 * (double)A->nnz) {
             o.mode = SPMM_MODE_PLAIN_F32;
             st = build_host_plan(A, n, b_type, c_type, o, p->hp, err);
             if (st != SPMM_OK) return set_error(st, err);
