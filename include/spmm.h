@@ -102,6 +102,9 @@ typedef struct {
                           the current row's gathers (bitwise identical to 0); 2 = short rows (at
                           most two unrolled batches) packed one per lane group, each summed in
                           entry order (a different, equally fixed order); < 0: auto */
+    int32_t win_sched; /* launch order of windows: 0 = by window id (neighbouring windows, which
+                          tend to gather the same B rows, run together on one XCD); 1 = heaviest
+                          first (LPT, Sec. 6.3); < 0: auto */
 } spmm_opts;
 
 typedef struct spmm_plan_s spmm_plan_t;
@@ -158,7 +161,7 @@ typedef struct {
     const int32_t *seg_begin;   /* int32 [n_segments]: first remainder index (into rem arrays) */
     const int32_t *seg_end;     /* int32 [n_segments] */
     const int32_t *win_seg;     /* int32 [n_windows]: first segment id used by the window */
-    const int32_t *win_order;   /* int32 [n_windows]: execution order of windows (heaviest first) */
+    const int32_t *win_order;   /* int32 [n_windows]: launch order of windows (see win_sched) */
     const int32_t *rem_col_dev; /* int32 [nnz_remainder]: device column array, bit 31 set for hot columns */
     int64_t n_wparts;           /* window partial items: tiles of a window beyond its first 16 */
     const int32_t *win_part;    /* int32 [n_windows + 1]: partial items of window w */

@@ -30,7 +30,8 @@ class Opts(C.Structure):
                 ("kt", C.c_int32), ("n_panel", C.c_int32), ("row_order", C.c_int32),
                 ("seg_len", C.c_int32), ("item_cost", C.c_int32), ("xcd_remap", C.c_int32),
                 ("hot_cols", C.c_int32), ("alpha_c", C.c_float), ("alpha", C.c_float),
-                ("cold_policy", C.c_int32), ("pipeline", C.c_int32)]
+                ("cold_policy", C.c_int32), ("pipeline", C.c_int32),
+                ("win_sched", C.c_int32)]
 
 
 class PlanStats(C.Structure):

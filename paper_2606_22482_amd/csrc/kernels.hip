@@ -779,7 +779,9 @@ __device__ __forceinline__ void stage_b8(const void *B, int64_t off, int valid, 
     for (int i = 0; i < 4; ++i) w[i] = h[2 * i] | (h[2 * i + 1] << 16);
 }
 
-// One (window, 128-column panel) per workgroup: item in [0, n_win * win_panels).
+// One (window, 128-column panel) per workgroup: item in [0, n_win * win_panels),
+// panel innermost, so a window's panels run side by side on one XCD and share
+// its tile data in that XCD's L2.
 // Every thread of the workgroup calls it with the same item.  Per round of up
 // to TC tiles: (1) the tiles' columns, bitmaps and packed values and the
 // window's row metadata are loaded together; (2) the B rows of the tile
@@ -796,10 +798,9 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
     static_assert(H * NPW * 4 <= KROWS * BSTR * 2, "C tile must fit in the B stage");
     unsigned short *Bs = sm.Bs;
 
-    // owner items: (panel, window in heaviest-first order), tiles [t0, t0 + win_tmax);
-    // partial items: (panel, partial slot), tiles [wpart_t0, wpart_t1)
-    const int nitems = partial ? P.n_wpart : P.n_win;
-    const int panel = item / nitems, j_item = item - panel * nitems;
+    // owner items: (window in launch order, panel), tiles [t0, t0 + win_tmax);
+    // partial items: (partial slot, panel), tiles [wpart_t0, wpart_t1)
+    const int j_item = item / a.win_panels, panel = item - j_item * a.win_panels;
     const int wi = partial ? P.wpart_win[j_item] : P.win_order[j_item];
     const int ncol0 = panel * NPW, ncols = min(NPW, P.n - ncol0);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;

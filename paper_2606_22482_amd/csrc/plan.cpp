@@ -39,6 +39,7 @@ extern "C" void spmm_opts_default(spmm_opts *o) {
     o->hot_cols = -1;
     o->cold_policy = -1;
     o->pipeline = -1;
+    o->win_sched = -1;
     o->alpha_c = -1.0f;
     o->alpha = -1.0f;
 }
@@ -86,6 +87,7 @@ void resolve_options(const spmm_opts *in, const spmm_csr *A, int32_t n, int32_t 
                          : (int32_t)(kHotFraction * kL2BytesPerXcd / ((double)np * dtype_size(b_type)));
     }
     if (d.pipeline < 0) d.pipeline = 2;  // short rows packed: measured fastest
+    if (d.win_sched < 0) d.win_sched = 0;  // window id order: B rows reused in L2
     if (!(d.alpha_c >= 0.0f)) d.alpha_c = 1.0f / (float)d.window_h;
     if (!(d.alpha >= 0.0f)) d.alpha = 1.0f / (float)d.window_h;
     if (d.mode == SPMM_MODE_MFMA_ONLY) {
@@ -143,6 +145,7 @@ static spmm_status validate_opts(const spmm_opts &o, std::string &err) {
     if (o.n_panel < 0) { err = "n_panel"; return SPMM_ERR_UNSUPPORTED; }
     if (o.hot_cols < 0) { err = "hot_cols"; return SPMM_ERR_UNSUPPORTED; }
     if (o.pipeline < 0 || o.pipeline > 2) { err = "pipeline must be 0, 1 or 2"; return SPMM_ERR_UNSUPPORTED; }
+    if (o.win_sched < 0 || o.win_sched > 1) { err = "win_sched must be 0 or 1"; return SPMM_ERR_UNSUPPORTED; }
     if (o.cold_policy != 0 && o.cold_policy != 2 && o.cold_policy != 16 && o.cold_policy != 18) {
         err = "cold_policy must be 0, 2, 16 or 18";
         return SPMM_ERR_UNSUPPORTED;
@@ -380,7 +383,7 @@ spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_
         (void)first;
         if (nv == 0) P.vitem_seg.clear();
     }
-    // windows: segment ids in slot order, heaviest windows first
+    // windows: segment ids in slot order; launch order by window id or heaviest first
     std::vector<int64_t> wcost(W, 0);
     P.win_part.push_back(0);
     for (int64_t w = 0; w < W; ++w) {
@@ -405,8 +408,9 @@ spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_
     }
     P.win_order.resize(W);
     for (int64_t w = 0; w < W; ++w) P.win_order[w] = (int32_t)w;
-    std::stable_sort(P.win_order.begin(), P.win_order.end(),
-                     [&](int32_t a, int32_t b) { return wcost[a] > wcost[b]; });
+    if (o.win_sched == 1)
+        std::stable_sort(P.win_order.begin(), P.win_order.end(),
+                         [&](int32_t a, int32_t b) { return wcost[a] > wcost[b]; });
 
     auto t_end = std::chrono::steady_clock::now();
     P.plan_ms = std::chrono::duration<double, std::milli>(t_end - t_start).count();

@@ -75,6 +75,7 @@ def test_validation_codes(lib):
     assert _status(lib, A, ct=L.BF16) == L.SPMM_ERR_UNSUPPORTED
     assert _status(lib, A, opts=api.default_opts(window_h=24)) == L.SPMM_ERR_UNSUPPORTED
     assert _status(lib, A, opts=api.default_opts(kt=16)) == L.SPMM_ERR_UNSUPPORTED
+    assert _status(lib, A, opts=api.default_opts(win_sched=2)) == L.SPMM_ERR_UNSUPPORTED
     assert _status(lib, A, opts=api.default_opts(alpha=float("nan"), mode="mixed")) in (
         L.SPMM_OK, L.SPMM_ERR_UNSUPPORTED)
     h = C.c_void_p()
@@ -198,6 +199,47 @@ def test_many_tiles_make_window_partials(lib):
     d = p.export()
     assert d["wpart_win"].size > 0
     _check_schedule(A, d, p.stats()["opts"]["seg_len"])
+
+
+def _window_costs(d, kt, h):
+    """Per-window work estimate of the schedule: the owner's tiles (at most 16)
+    times kt, H per partial item, and 4 + entries (or segments) per row."""
+    nw = d["windows"].shape[0]
+    wt = np.bincount(d["tile_window"], minlength=nw)
+    rem_len = np.diff(d["rem_ptr"])
+    cost = np.minimum(wt, 16) * kt + np.diff(d["win_part"]) * h
+    for w in range(nw):
+        for r in d["windows"][w]:
+            if r >= 0:
+                cost[w] += 4 + (d["nseg"][r] if d["nseg"][r] else rem_len[r])
+    return cost
+
+
+@pytest.mark.parametrize("sched", [0, 1])
+def test_window_launch_order(lib, sched):
+    A, _ = synth.block_community(n=8192, band=8, n_cols=8, seed=4)
+    p = api.Plan(A, 64, "bf16", api.default_opts(mode="mixed", win_sched=sched, seg_len=8),
+                 upload=False)
+    d = p.export()
+    ro = p.stats()["opts"]
+    nw = d["windows"].shape[0]
+    assert nw > 100 and ro["win_sched"] == sched
+    if sched == 0:
+        assert np.array_equal(d["win_order"], np.arange(nw))
+    else:
+        cost = _window_costs(d, ro["kt"], ro["window_h"])
+        c = cost[d["win_order"]]
+        assert np.all(np.diff(c) <= 0) and np.unique(c).size > 1
+        # stable: equal costs keep window id order
+        same = np.diff(c) == 0
+        assert np.all(np.diff(d["win_order"])[same] > 0)
+    _check_schedule(A, d, ro["seg_len"])
+
+
+def test_default_window_order_is_by_id(lib):
+    A, _ = synth.block_community(n=2048, band=4, n_cols=8, seed=5)
+    p = api.Plan(A, 8, "bf16", api.default_opts(mode="mixed"), upload=False)
+    assert p.stats()["opts"]["win_sched"] == 0
 
 
 def test_mixed_without_tiles_equals_plain(lib):
