@@ -101,7 +101,11 @@ typedef struct {
     int32_t pipeline;  /* vector kernel variant: 0 = row by row; 1 = prefetch the next row during
                           the current row's gathers (bitwise identical to 0); 2 = short rows (at
                           most two unrolled batches) packed one per lane group, each summed in
-                          entry order (a different, equally fixed order); < 0: auto */
+                          entry order (a different, equally fixed order); 3 = rows packed by size
+                          class: a row of remainder length len is summed by S lane groups, S the
+                          least power of two with len <= 2*U*S (at most all groups), entry p of
+                          the row by group p mod S in entry order, then the groups' sums by an
+                          xor butterfly (classes 1 and all-groups sum as in variant 2); < 0: auto */
     int32_t win_sched; /* launch order of windows: 0 = by window id (neighbouring windows, which
                           tend to gather the same B rows, run together on one XCD); 1 = heaviest
                           first (LPT, Sec. 6.3); < 0: auto */
@@ -154,7 +158,7 @@ typedef struct {
     const int32_t *vector_rows; /* rows not in a window, ascending */
     const int32_t *nseg;        /* int32 [m]: segments of the row's remainder (0: not split) */
     int64_t n_vitems;
-    const int32_t *vitem_ptr;   /* int32 [n_vitems + 1]: item i covers vector_rows[ptr[i] .. ptr[i+1]) */
+    const int32_t *vitem_ptr;   /* int32 [n_vitems + 1]: item i covers vexec_rows[ptr[i] .. ptr[i+1]) */
     const int32_t *vitem_seg;   /* int32 [n_vitems]: first segment id used by the item */
     int64_t n_segments;
     const int32_t *seg_row;     /* int32 [n_segments]: row of each segment */
@@ -168,6 +172,10 @@ typedef struct {
     const int32_t *wpart_win;   /* int32 [n_wparts] */
     const int32_t *wpart_t0;    /* int32 [n_wparts]: first tile */
     const int32_t *wpart_t1;    /* int32 [n_wparts]: end tile */
+    const int32_t *vexec_rows;  /* int32 [n_vector_rows]: the vector rows in the order the vector
+                                   kernel takes them, item by item (equal to vector_rows except
+                                   with pipeline 3, which orders each item's rows by remainder
+                                   length, longest first, and split rows last) */
 } spmm_plan_dump_t;
 
 /* One matrix of a batched submission (device pointers). */

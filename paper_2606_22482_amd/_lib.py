@@ -60,7 +60,8 @@ class PlanDump(C.Structure):
                 ("n_segments", C.c_int64), ("seg_row", C.c_void_p), ("seg_begin", C.c_void_p),
                 ("seg_end", C.c_void_p), ("win_seg", C.c_void_p), ("win_order", C.c_void_p),
                 ("rem_col_dev", C.c_void_p), ("n_wparts", C.c_int64), ("win_part", C.c_void_p),
-                ("wpart_win", C.c_void_p), ("wpart_t0", C.c_void_p), ("wpart_t1", C.c_void_p)]
+                ("wpart_win", C.c_void_p), ("wpart_t0", C.c_void_p), ("wpart_t1", C.c_void_p),
+                ("vexec_rows", C.c_void_p)]
 
 
 class TuneReport(C.Structure):

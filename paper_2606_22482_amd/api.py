@@ -164,6 +164,7 @@ class Plan:
             "wpart_win": arr(d.wpart_win, d.n_wparts, np.int32),
             "wpart_t0": arr(d.wpart_t0, d.n_wparts, np.int32),
             "wpart_t1": arr(d.wpart_t1, d.n_wparts, np.int32),
+            "vexec_rows": arr(d.vexec_rows, d.n_vector_rows, np.int32),
         }
 
     def run(self, B, Cout, stream=None):

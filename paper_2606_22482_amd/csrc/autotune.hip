@@ -326,6 +326,22 @@ extern "C" spmm_status spmm_autotune(const spmm_csr *A, int32_t n, int32_t b_typ
             SPMM_TRY(try_opts(o));
         }
     }
+    // stage 4: vector kernel variant (packed short rows or size classes) and,
+    // for a mixed plan, the window launch order
+    {
+        const spmm_opts b3 = best;
+        spmm_opts r;
+        resolve_options(&b3, A, n, b_type, &r);
+        spmm_opts o = b3;
+        o.pipeline = r.pipeline == 3 ? 2 : 3;
+        SPMM_TRY(try_opts(o));
+        if (best.mode == SPMM_MODE_MIXED) {
+            spmm_opts w = best;
+            resolve_options(&w, A, n, b_type, &r);
+            w.win_sched = r.win_sched == 0 ? 1 : 0;
+            SPMM_TRY(try_opts(w));
+        }
+    }
 #undef SPMM_TRY
     rep.best_ms = best_ms;
     rep.search_ms = elapsed();

@@ -620,6 +620,17 @@ __device__ __forceinline__ void vector_item_pipelined(const DevPlan &P, const Ru
     }
 }
 
+// Inclusive prefix sum over the 64 lanes of a wavefront.
+__device__ __forceinline__ int wave_inclusive_scan(int x) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int t = __shfl_up(x, d, 64);
+        if (lane >= d) x += t;
+    }
+    return x;
+}
+
 // Vector work item with short rows packed one per lane group: a row whose
 // remainder has at most 2U entries is summed in entry order by one group, and
 // up to G such consecutive rows are gathered at once; longer rows take the
@@ -691,6 +702,124 @@ __device__ __forceinline__ void vector_item_packed(const DevPlan &P, const RunAr
     }
 }
 
+// Size class of a row: the least power of two S of lane groups with
+// len <= u2 * S, at most every group of the wavefront.
+__device__ __forceinline__ int size_class(int len, int u2, int groups) {
+    int s = 1;
+    while (s < groups && len > u2 * s) s <<= 1;
+    return s;
+}
+
+__device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
+    uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        lo |= __shfl_xor(lo, off, 64);
+        hi |= __shfl_xor(hi, off, 64);
+    }
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Vector work item with rows packed by size class: a row of class S is summed
+// by an aligned block of S lane groups (entry p of the row by group p mod S,
+// each group in entry order, then the groups' sums by an xor butterfly inside
+// the block), so the order depends only on the row's length.  One pass takes
+// consecutive rows while their classes do not grow and the blocks fit in the
+// wavefront; with rows ordered longest first every block is aligned.  Split
+// rows (class 1) sum their segment partials in segment order.
+template <int VT, int BT, int E, int CPL>
+__device__ __forceinline__ void vector_item_classed(const DevPlan &P, const RunArgs &a, int wid) {
+    constexpr int U = unroll_of<E, CPL>();
+    const int panel = wid / P.n_vitems, item = wid - panel * P.n_vitems;
+    const int ncol0 = panel * a.np, ncols = min(a.np, P.n - ncol0);
+    const Lanes L(a.lpr_log2);
+    const int lane = threadIdx.x & 63;
+    const __amdgpu_buffer_rsrc_t rs = b_resource(a.B);
+    bool cok[CPL];
+    int64_t coff[CPL];
+    chunk_layout<E, CPL>(ncol0, ncols, L, cok, coff);
+    int sid = P.vitem_seg[item];
+    const int i0 = P.vitem_ptr[item], i1 = P.vitem_ptr[item + 1];
+    for (int i = i0; i < i1;) {
+        // row i + lane: id, remainder range, class, segments
+        const int j_row = i + lane;
+        int r = -1, b = 0, e = 0, cls = 1, ns = 0;
+        if (j_row < i1) {
+            r = P.vec_rows ? P.vec_rows[j_row] : j_row;
+            b = P.rem_ptr[r];
+            e = P.rem_ptr[r + 1];
+            if (e - b > P.seg_len) {
+                ns = (e - b + P.seg_len - 1) / P.seg_len;
+                e = b;  // the entries were summed by the segment kernel
+            } else {
+                cls = size_class(e - b, 2 * U, L.groups);
+            }
+        }
+        // the pass: rows before the first class increase whose blocks fit
+        const int prev = __shfl_up(cls, 1, 64);
+        const uint64_t cut = __ballot(j_row >= i1 || (lane > 0 && cls > prev));
+        const int kmax = cut ? __builtin_ctzll(cut) : 64;
+        const int cin = lane < kmax ? cls : 0;
+        const int incl = wave_inclusive_scan(cin);
+        const uint64_t fits = __ballot(lane < kmax && incl <= L.groups);
+        const int k = __popcll(fits);  // >= 1: row i always fits
+        const int excl = incl - cin;
+        // this lane group's row: the last block start at or below the group
+        const uint64_t starts = wave_or64(lane < k ? (1ull << excl) : 0ull);
+        const int g = L.group;
+        const uint64_t upto = g >= 63 ? ~0ull : ((2ull << g) - 1ull);
+        const int jr = (g < __shfl(incl, k - 1, 64)) ? __popcll(starts & upto) - 1 : -1;
+        const int src = jr < 0 ? 0 : jr;
+        int my_r = __shfl(r, src, 64), my_b = __shfl(b, src, 64), my_e = __shfl(e, src, 64);
+        const int my_s = __shfl(cls, src, 64), my_ns = __shfl(ns, src, 64);
+        const int local = g - __shfl(excl, src, 64);
+        int my_sid = sid;
+        if (__ballot(lane < k && ns > 0)) {
+            const int nin = lane < k ? ns : 0;
+            const int nincl = wave_inclusive_scan(nin);
+            my_sid = sid + __shfl(nincl - nin, src, 64);
+            sid += __shfl(nincl, k - 1, 64);
+        }
+        if (jr < 0) my_b = my_e = 0;
+        const int smax = __shfl(cls, 0, 64);  // the pass's largest class
+
+        float acc[CPL][E];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c)
+#pragma unroll
+            for (int x = 0; x < E; ++x) acc[c][x] = 0.0f;
+        Lanes Ls = L;
+        Ls.groups = my_s;
+        for (int p = my_b + local; p < my_e; p += my_s * U) {
+            int col[U];
+            float v[U];
+            load_entries<VT, U>(P.rem_col, P.rem_val, p, my_e, Ls, col, v);
+            gather_fma<BT, E, CPL, U>(col, v, p, my_e, a.B, rs, a.ldb, cok, coff, Ls, a.cold_aux,
+                                      acc);
+        }
+        if (jr >= 0 && my_ns > 0) sum_partials<E, CPL>(a.work, a.work_ld, my_sid, my_ns, ncol0, ncols, L, acc);
+        // butterfly inside each block, from the pass's largest class down
+        for (int off = (smax * L.lpr) >> 1; off >= L.lpr; off >>= 1) {
+            const bool take = off < my_s * L.lpr;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c)
+#pragma unroll
+                for (int x = 0; x < E; ++x) {
+                    const float t = __shfl_xor(acc[c][x], off, 64);
+                    if (take) acc[c][x] += t;
+                }
+        }
+        if (jr >= 0 && local == 0) {
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int q = c * L.lpr + L.li;
+                if (q * E < ncols) store_chunk<E>(a.C, (int64_t)my_r * a.ldc + ncol0 + (int64_t)q * E, acc[c]);
+            }
+        }
+        i += k;
+    }
+}
+
 template <int VT, int BT, int E, int CPL>
 __global__ __launch_bounds__(256) void segment_kernel(DevPlan P, RunArgs a) {
     const int wid = logical_block(a.xcd) * 4 + (threadIdx.x >> 6);
@@ -699,7 +828,8 @@ __global__ __launch_bounds__(256) void segment_kernel(DevPlan P, RunArgs a) {
 
 template <int VT, int BT, int E, int CPL, int VAR>
 __device__ __forceinline__ void vector_item_var(const DevPlan &P, const RunArgs &a, int wid) {
-    if constexpr (VAR == 2) vector_item_packed<VT, BT, E, CPL>(P, a, wid);
+    if constexpr (VAR == 3) vector_item_classed<VT, BT, E, CPL>(P, a, wid);
+    else if constexpr (VAR == 2) vector_item_packed<VT, BT, E, CPL>(P, a, wid);
     else if constexpr (VAR == 1) vector_item_pipelined<VT, BT, E, CPL>(P, a, wid);
     else vector_item<VT, BT, E, CPL>(P, a, wid);
 }
@@ -708,17 +838,6 @@ template <int VT, int BT, int E, int CPL, int VAR>
 __global__ __launch_bounds__(256) void vector_kernel(DevPlan P, RunArgs a) {
     const int wid = logical_block(a.xcd) * 4 + (threadIdx.x >> 6);
     if (wid < P.n_vitems * a.n_panels) vector_item_var<VT, BT, E, CPL, VAR>(P, a, wid);
-}
-
-// Inclusive prefix sum over the 64 lanes of a wavefront.
-__device__ __forceinline__ int wave_inclusive_scan(int x) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        int t = __shfl_up(x, d, 64);
-        if (lane >= d) x += t;
-    }
-    return x;
 }
 
 // LDS of a window item: the staged B rows (reused for the f32 C tile), the
@@ -1086,6 +1205,7 @@ static hipError_t vec_dispatch_var(const DevPlan &P, const RunArgs &a, hipStream
 
 template <int VT, int BT>
 static hipError_t vec_dispatch(const DevPlan &P, const RunArgs &a, hipStream_t s) {
+    if (a.pipeline == 3) return vec_dispatch_var<VT, BT, 3>(P, a, s);
     if (a.pipeline == 2) return vec_dispatch_var<VT, BT, 2>(P, a, s);
     if (a.pipeline == 1) return vec_dispatch_var<VT, BT, 1>(P, a, s);
     return vec_dispatch_var<VT, BT, 0>(P, a, s);
@@ -1183,28 +1303,26 @@ static hipError_t batch_types_var(const BatchHeader *hdr, const BatchEntry *tab,
     return batch_variant<VT, BT, TT, EV, 2, VAR>(hdr, tab, gw, gwin, s, ow, oc);
 }
 
-static int g_batch_var = 0;  // vector variant of the batch being launched (set by batch_any)
-
 template <int VT, int BT, int TT>
 static hipError_t batch_types(const BatchHeader *hdr, const BatchEntry *tab, int vec_ok, int cpl,
-                              unsigned gw, unsigned gwin, hipStream_t s, int *ow, int *oc) {
-    if (g_batch_var == 2) return batch_types_var<VT, BT, TT, 2>(hdr, tab, vec_ok, cpl, gw, gwin, s, ow, oc);
-    if (g_batch_var == 1) return batch_types_var<VT, BT, TT, 1>(hdr, tab, vec_ok, cpl, gw, gwin, s, ow, oc);
+                              int var, unsigned gw, unsigned gwin, hipStream_t s, int *ow, int *oc) {
+    if (var == 3) return batch_types_var<VT, BT, TT, 3>(hdr, tab, vec_ok, cpl, gw, gwin, s, ow, oc);
+    if (var == 2) return batch_types_var<VT, BT, TT, 2>(hdr, tab, vec_ok, cpl, gw, gwin, s, ow, oc);
+    if (var == 1) return batch_types_var<VT, BT, TT, 1>(hdr, tab, vec_ok, cpl, gw, gwin, s, ow, oc);
     return batch_types_var<VT, BT, TT, 0>(hdr, tab, vec_ok, cpl, gw, gwin, s, ow, oc);
 }
 
 static hipError_t batch_any(const BatchHeader *hdr, const BatchEntry *tab, int32_t vt, int32_t bt,
                             int32_t tt, int vec_ok, int cpl, int var, unsigned gw, unsigned gwin,
                             hipStream_t s, int *ow, int *oc) {
-    g_batch_var = var;
     if (vt == DT_F32 && bt == DT_F32 && tt == DT_BF16)
-        return batch_types<DT_F32, DT_F32, DT_BF16>(hdr, tab, vec_ok, cpl, gw, gwin, s, ow, oc);
+        return batch_types<DT_F32, DT_F32, DT_BF16>(hdr, tab, vec_ok, cpl, var, gw, gwin, s, ow, oc);
     if (vt == DT_F32 && bt == DT_BF16 && tt == DT_BF16)
-        return batch_types<DT_F32, DT_BF16, DT_BF16>(hdr, tab, vec_ok, cpl, gw, gwin, s, ow, oc);
+        return batch_types<DT_F32, DT_BF16, DT_BF16>(hdr, tab, vec_ok, cpl, var, gw, gwin, s, ow, oc);
     if (vt == DT_BF16 && bt == DT_BF16 && tt == DT_BF16)
-        return batch_types<DT_BF16, DT_BF16, DT_BF16>(hdr, tab, vec_ok, cpl, gw, gwin, s, ow, oc);
+        return batch_types<DT_BF16, DT_BF16, DT_BF16>(hdr, tab, vec_ok, cpl, var, gw, gwin, s, ow, oc);
     if (vt == DT_F16 && bt == DT_F16 && tt == DT_F16)
-        return batch_types<DT_F16, DT_F16, DT_F16>(hdr, tab, vec_ok, cpl, gw, gwin, s, ow, oc);
+        return batch_types<DT_F16, DT_F16, DT_F16>(hdr, tab, vec_ok, cpl, var, gw, gwin, s, ow, oc);
     return hipErrorInvalidValue;
 }
 

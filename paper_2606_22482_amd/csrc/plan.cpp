@@ -86,7 +86,16 @@ void resolve_options(const spmm_opts *in, const spmm_csr *A, int32_t n, int32_t 
                          ? 0
                          : (int32_t)(kHotFraction * kL2BytesPerXcd / ((double)np * dtype_size(b_type)));
     }
-    if (d.pipeline < 0) d.pipeline = 2;  // short rows packed: measured fastest
+    if (d.pipeline < 0) {
+        // Measured on gfx950: packing rows by size class pays for 16-bit B rows
+        // spanning at most 16 chunk lanes (4 or more lane groups per wavefront:
+        // f16 N <= 128 power-law matrices 23% faster).  With 1-2 groups it
+        // gains little, and on f32 B (N = 32, 64) it ran 6-15% slower: those
+        // gathers are bandwidth-bound and its extra registers cost occupancy.
+        const int np = d.n_panel > 0 ? std::min(d.n_panel, std::max(n, 1)) : std::max(n, 1);
+        const int chunks = std::min((np + 7) / 8, 128);
+        d.pipeline = (b_type != SPMM_F32 && chunks <= 16) ? 3 : 2;
+    }
     if (d.win_sched < 0) d.win_sched = 0;  // window id order: B rows reused in L2
     if (!(d.alpha_c >= 0.0f)) d.alpha_c = 1.0f / (float)d.window_h;
     if (!(d.alpha >= 0.0f)) d.alpha = 1.0f / (float)d.window_h;
@@ -144,7 +153,7 @@ static spmm_status validate_opts(const spmm_opts &o, std::string &err) {
     if (o.item_cost < 1) { err = "item_cost"; return SPMM_ERR_UNSUPPORTED; }
     if (o.n_panel < 0) { err = "n_panel"; return SPMM_ERR_UNSUPPORTED; }
     if (o.hot_cols < 0) { err = "hot_cols"; return SPMM_ERR_UNSUPPORTED; }
-    if (o.pipeline < 0 || o.pipeline > 2) { err = "pipeline must be 0, 1 or 2"; return SPMM_ERR_UNSUPPORTED; }
+    if (o.pipeline < 0 || o.pipeline > 3) { err = "pipeline must be 0, 1, 2 or 3"; return SPMM_ERR_UNSUPPORTED; }
     if (o.win_sched < 0 || o.win_sched > 1) { err = "win_sched must be 0 or 1"; return SPMM_ERR_UNSUPPORTED; }
     if (o.cold_policy != 0 && o.cold_policy != 2 && o.cold_policy != 16 && o.cold_policy != 18) {
         err = "cold_policy must be 0, 2, 16 or 18";
@@ -365,23 +374,32 @@ spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_
     P.vitem_ptr.push_back(0);
     {
         int64_t acc = 0;
-        int32_t first = 0;
         const int64_t nv = (int64_t)P.vector_rows.size();
-        P.vitem_seg.push_back((int32_t)P.seg_row.size());
         for (int64_t i = 0; i < nv; ++i) {
             int32_t r = P.vector_rows[i];
             int64_t L = P.rem_ptr[r + 1] - P.rem_ptr[r];
             acc += kRowCost + (P.nseg[r] ? P.nseg[r] : L);
-            add_segments(r);
             if (acc >= o.item_cost || i + 1 == nv) {
                 P.vitem_ptr.push_back((int32_t)(i + 1));
-                if (i + 1 < nv) P.vitem_seg.push_back((int32_t)P.seg_row.size());
                 acc = 0;
-                first = (int32_t)(i + 1);
             }
         }
-        (void)first;
-        if (nv == 0) P.vitem_seg.clear();
+        // the size-class variant takes each item's rows longest first, so that
+        // rows of one size class are packed side by side; split rows go last
+        if (o.pipeline == 3 && nv > 0) {
+            P.vexec = P.vector_rows;
+            auto key = [&](int32_t r) -> int64_t {
+                return P.nseg[r] ? -1 : P.rem_ptr[r + 1] - P.rem_ptr[r];
+            };
+            for (size_t it = 0; it + 1 < P.vitem_ptr.size(); ++it)
+                std::stable_sort(P.vexec.begin() + P.vitem_ptr[it], P.vexec.begin() + P.vitem_ptr[it + 1],
+                                 [&](int32_t a, int32_t b) { return key(a) > key(b); });
+        }
+        const std::vector<int32_t> &order = P.vexec.empty() ? P.vector_rows : P.vexec;
+        for (size_t it = 0; it + 1 < P.vitem_ptr.size(); ++it) {
+            P.vitem_seg.push_back((int32_t)P.seg_row.size());
+            for (int32_t i = P.vitem_ptr[it]; i < P.vitem_ptr[it + 1]; ++i) add_segments(order[i]);
+        }
     }
     // windows: segment ids in slot order; launch order by window id or heaviest first
     std::vector<int64_t> wcost(W, 0);

@@ -37,7 +37,8 @@ struct HostPlan {
     std::vector<int32_t> nseg;          // [m]
 
     // ---- schedule ----
-    std::vector<int32_t> vitem_ptr;     // [V+1] into vector_rows
+    std::vector<int32_t> vexec;         // launch order of vector rows (item by item); empty: vector_rows
+    std::vector<int32_t> vitem_ptr;     // [V+1] into the launch order
     std::vector<int32_t> vitem_seg;     // [V]
     std::vector<int32_t> seg_row, seg_begin, seg_end;  // [S]
     std::vector<int32_t> win_tile_ptr;  // [W+1]

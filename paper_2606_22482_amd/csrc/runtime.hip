@@ -139,7 +139,7 @@ extern "C" spmm_status spmm_plan_upload(spmm_plan_t *p) {
         const size_t i_rem_ptr = add_vec(a, h.rem_ptr32);
         const size_t i_rem_col = add_vec(a, h.rem_col);
         const size_t i_rem_val = add_vec(a, h.rem_val);
-        const size_t i_vec_rows = add_vec(a, h.vector_rows);
+        const size_t i_vec_rows = add_vec(a, h.vexec.empty() ? h.vector_rows : h.vexec);
         const size_t i_vitem_ptr = add_vec(a, h.vitem_ptr);
         const size_t i_vitem_seg = add_vec(a, h.vitem_seg);
         const size_t i_seg_begin = add_vec(a, h.seg_begin);
@@ -185,7 +185,8 @@ extern "C" spmm_status spmm_plan_upload(spmm_plan_t *p) {
         dp.rem_ptr = reinterpret_cast<const int32_t *>(at(i_rem_ptr));
         dp.rem_col = reinterpret_cast<const int32_t *>(at(i_rem_col));
         dp.rem_val = at(i_rem_val);
-        dp.vec_rows = h.identity_rows ? nullptr : reinterpret_cast<const int32_t *>(at(i_vec_rows));
+        dp.vec_rows = h.identity_rows && h.vexec.empty() ? nullptr
+                                                         : reinterpret_cast<const int32_t *>(at(i_vec_rows));
         dp.vitem_ptr = reinterpret_cast<const int32_t *>(at(i_vitem_ptr));
         dp.vitem_seg = reinterpret_cast<const int32_t *>(at(i_vitem_seg));
         dp.seg_begin = reinterpret_cast<const int32_t *>(at(i_seg_begin));
@@ -312,6 +313,7 @@ extern "C" spmm_status spmm_plan_export(const spmm_plan_t *p, spmm_plan_dump_t *
     out->wpart_win = h.wpart_win.data();
     out->wpart_t0 = h.wpart_t0.data();
     out->wpart_t1 = h.wpart_t1.data();
+    out->vexec_rows = h.vexec.empty() ? h.vector_rows.data() : h.vexec.data();
     return SPMM_OK;
 }
 

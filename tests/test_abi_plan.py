@@ -107,9 +107,10 @@ def _cmp_plan(A, dump, ref):
     assert np.array_equal(dump["nseg"], ref.nseg)
 
 
-def _check_schedule(A, d, seg_len):
+def _check_schedule(A, d, seg_len, pipeline=2):
     m = A.m
     vr = d["vector_rows"]
+    ve = d["vexec_rows"]
     vp = d["vitem_ptr"]
     assert vp[0] == 0 and vp[-1] == vr.size and np.all(np.diff(vp) > 0)
     # segments: walk items then windows in order, ids must be consecutive
@@ -117,7 +118,18 @@ def _check_schedule(A, d, seg_len):
     sid = 0
     for i in range(vp.size - 1):
         assert d["vitem_seg"][i] == sid
-        for r in vr[vp[i]:vp[i + 1]]:
+        part = ve[vp[i]:vp[i + 1]]
+        # an item's launch order is a permutation of its vector rows: the same
+        # rows for every variant; variant 3 takes them longest first (split
+        # rows last), ties in row order
+        assert np.array_equal(np.sort(part), vr[vp[i]:vp[i + 1]])
+        if pipeline == 3:
+            key = np.where(d["nseg"][part] > 0, -1, rem_len[part])
+            assert np.all(np.diff(key) <= 0)
+            assert np.all(np.diff(part)[np.diff(key) == 0] > 0)
+        else:
+            assert np.array_equal(part, vr[vp[i]:vp[i + 1]])
+        for r in part:
             for j in range(d["nseg"][r]):
                 assert d["seg_row"][sid] == r
                 assert d["seg_begin"][sid] == d["rem_ptr"][r] + j * seg_len
@@ -186,7 +198,7 @@ def test_plan_bit_exact_vs_reference(lib, case):
                         tile_kind="f16" if bk == "f16" else "bf16", val_kind=vk)
     d = p.export()
     _cmp_plan(A, d, ref)
-    _check_schedule(A, d, ro["seg_len"])
+    _check_schedule(A, d, ro["seg_len"], ro["pipeline"])
     assert np.all(pr.coverage(ref) == 1)
     if mode == L.MODE_MIXED and kw.get("alpha", 0) <= 1.0:
         assert st["tiles"] > 0
@@ -198,7 +210,7 @@ def test_many_tiles_make_window_partials(lib):
     p = api.Plan(A, 32, "f32", api.default_opts(mode="mfma_only", window_h=16), upload=False)
     d = p.export()
     assert d["wpart_win"].size > 0
-    _check_schedule(A, d, p.stats()["opts"]["seg_len"])
+    _check_schedule(A, d, p.stats()["opts"]["seg_len"], p.stats()["opts"]["pipeline"])
 
 
 def _window_costs(d, kt, h):
@@ -233,7 +245,29 @@ def test_window_launch_order(lib, sched):
         # stable: equal costs keep window id order
         same = np.diff(c) == 0
         assert np.all(np.diff(d["win_order"])[same] > 0)
-    _check_schedule(A, d, ro["seg_len"])
+    _check_schedule(A, d, ro["seg_len"], ro["pipeline"])
+
+
+@pytest.mark.parametrize("pipeline", [2, 3])
+def test_vector_launch_order(lib, pipeline):
+    A = synth.chung_lu_graph(6000, 2.2, 12.0, 700.0, 8, val_kind="f16")
+    p = api.Plan(A, 32, "f16", api.default_opts(mode="plain", pipeline=pipeline, seg_len=40,
+                                                item_cost=300), upload=False)
+    d = p.export()
+    assert d["vitem_ptr"].size > 10 and d["seg_row"].size > 0
+    _check_schedule(A, d, 40, pipeline)
+    if pipeline == 3:
+        assert not np.array_equal(d["vexec_rows"], d["vector_rows"])
+
+
+def test_auto_vector_variant(lib):
+    A = synth.random_csr(200, 200, 0.05, 2, val_kind="f16")
+    pick = lambda n, bk: api.Plan(A, n, bk, api.default_opts(mode="plain"),
+                                  upload=False).stats()["opts"]["pipeline"]
+    assert pick(32, "f16") == 3 and pick(128, "f16") == 3 and pick(256, "f16") == 2
+    Af = synth.random_csr(200, 200, 0.05, 2)
+    assert api.Plan(Af, 64, "f32", None, upload=False).stats()["opts"]["pipeline"] == 2
+    assert api.Plan(Af, 64, "bf16", None, upload=False).stats()["opts"]["pipeline"] == 3
 
 
 def test_default_window_order_is_by_id(lib):

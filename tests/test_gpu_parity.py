@@ -183,6 +183,79 @@ def test_packed_rows_integer_exact(n, kinds):
         exact(C, A, B, bk)
 
 
+def _lane_shape(n, kind):
+    """(lane groups G, unroll U) of the vector kernel for N = n: 16-byte chunks
+    of 4 f32 or 8 16-bit values (one value per lane when N is not a multiple),
+    chunk lanes per row the power of two >= the chunk count (at most 64)."""
+    e = 4 if kind == "f32" else 8
+    if n % e:
+        e = 1
+    chunks = n // e
+    lpr = 1
+    while lpr < min(chunks, 64):
+        lpr *= 2
+    u = 4 if e == 1 else (8 if chunks <= 64 else 4)
+    return 64 // lpr, u
+
+
+@pytest.mark.parametrize("n,kinds", [(32, ("f16", "f16")), (64, ("f16", "f16")),
+                                     (128, ("f16", "f16")), (128, ("f32", "f32")),
+                                     (256, ("bf16", "bf16")), (33, ("f32", "f32")),
+                                     (8, ("f32", "bf16"))])
+def test_class_packed_variant(n, kinds):
+    """Rows packed by size class: within the FP32 bound of the oracle, and bit
+    for bit equal to the packed-short-row variant on every row whose class is
+    1 (at most 2U entries) or all groups (more than U*G entries), which both
+    variants sum in the same order."""
+    import torch
+    vk, bk = kinds
+    A = synth.chung_lu_graph(20000, 2.2, 20.0, 1500.0, 40 + n, val_kind=vk, values="uniform")
+    B = synth.dense_values(np.random.default_rng(n), (20000, n), bk)
+    print("case", n, kinds, flush=True)
+    p3, C3 = run(A, B, bk, api.default_opts(mode="plain", pipeline=3, seg_len=300))
+    parity(C3, A, B, bk, TOL_F32)
+    _, C2 = run(A, B, bk, api.default_opts(mode="plain", pipeline=2, seg_len=300))
+    G, U = _lane_shape(n, bk)
+    L = np.diff(A.rowptr)
+    same = torch.from_numpy((L <= 2 * U) | (L > U * G)).cuda()
+    if G > 2:
+        assert int((~same).sum()) > 100
+    assert torch.equal(C2[same], C3[same])
+    assert p3.stats()["segments"] > 0
+
+
+@pytest.mark.parametrize("n,kinds", [(32, ("f16", "f16")), (7, ("bf16", "bf16"))])
+def test_class_packed_integer_exact(n, kinds):
+    vk, bk = kinds
+    A = synth.random_csr(3000, 1500, 0.02, 57 + n, val_kind=vk, int_values=(-2, 2),
+                         empty_rows=0.1)
+    B = synth.int_dense(n + 3, (1500, n), -8, 8, kind=bk)
+    for seg in (5, 40, 300):
+        _, C = run(A, B, bk, api.default_opts(mode="plain", pipeline=3, seg_len=seg,
+                                              item_cost=200))
+        exact(C, A, B, bk)
+
+
+def test_submit_class_packed_matches_solo_bitwise():
+    import torch
+    specs = synth.batch_specs(count=6, seed=9, rows_lo=2000, rows_hi=40000)
+    items, solos = [], []
+    for i, sp in enumerate(specs):
+        A, B = synth.batch_matrix(i, sp, seed=9)
+        p = api.Plan(A, B.shape[1], "f16", api.default_opts(mode="plain", pipeline=3, seg_len=64))
+        Bd = device_B(B, "f16")
+        Cs = device_C(A.m, B.shape[1])
+        p.run(Bd, Cs)
+        items.append(api.WorkItem(p, Bd, device_C(A.m, B.shape[1])))
+        solos.append((Cs, A, B))
+    for _ in range(2):
+        api.spmm_wait(api.spmm_submit(items))
+    torch.cuda.synchronize()
+    for it, (Cs, A, B) in zip(items, solos):
+        assert torch.equal(it.C, Cs)
+    parity(items[0].C, solos[0][1], solos[0][2], "f16", TOL_F32)
+
+
 def test_deterministic_and_nan_prefill():
     import torch
     A, B = synth.block_community(n=16384, band=8, n_cols=256, seed=8)
