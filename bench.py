@@ -235,6 +235,9 @@ def main():
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--max-batch", type=int, default=64)
     ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--adapt-from", type=float, default=0.0,
+                    help="mixed mode: start from this tile threshold and run the epoch-level "
+                         "re-partition (spmm_adapt_epoch) until it stops, before timing")
     ap.add_argument("--copy-plain", action="store_true",
                     help="with --copy-probe: use torch's plain copy kernel instead")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -296,6 +299,24 @@ def main():
             "vector items=%d" % (mode, (time.perf_counter() - t0) * 1e3, st["tiles"],
                                  100.0 * st["nnz_tiles"] / max(1, A.nnz),
                                  st["mean_tile_density"], st["segments"], st["vector_items"]))
+        adapt = None
+        if mode == "mixed" and args.adapt_from > 0:
+            plan = api.Plan(A, n, b_kind, api.default_opts(**dict(kw, alpha=args.adapt_from)))
+            for _ in range(2):
+                plan.run(Bd, Cd)
+            ast = api.adapt_state()
+            adapt = []
+            for epoch in range(10):
+                a_used = plan.stats()["opts"]["alpha"]
+                plan.adapt_epoch(A, Bd, Cd, ast)
+                adapt.append({"alpha": round(a_used, 5), "alpha_star": round(ast.alpha_star, 5),
+                              "skew": round(ast.skew, 3),
+                              "epoch_ms": round(ast.t_vec_ms + ast.t_mfma_ms, 4)})
+                log("adapt epoch %d: alpha %.4f -> alpha* %.4f (skew %.2f), paths %.4f + %.4f ms"
+                    % (epoch, a_used, ast.alpha_star, ast.skew, ast.t_vec_ms, ast.t_mfma_ms))
+                if not ast.replanned:
+                    break
+            st = plan.stats()
         for _ in range(args.warmup):
             plan.run(Bd, Cd)
         torch.cuda.synchronize()
@@ -314,7 +335,7 @@ def main():
             per.setdefault(name, []).append(kms)
         kavg = {k: float(np.mean(v)) for k, v in per.items()}
         log("mode %s: %.4f ms/step, kernels %s" % (mode, ms, {k: round(v, 4) for k, v in kavg.items()}))
-        results[mode] = dict(plan=plan, stats=st, ms=ms, kavg=kavg)
+        results[mode] = dict(plan=plan, stats=st, ms=ms, kavg=kavg, adapt=adapt)
 
     best = min(results, key=lambda k: results[k]["ms"])
     R = results[best]
@@ -352,6 +373,9 @@ def main():
                       "nnz_tiles_frac": round(v["stats"]["nnz_tiles"] / max(1, A.nnz), 4)}
                   for k, v in results.items()},
     }
+    for k, v in results.items():
+        if v["adapt"] is not None:
+            out["modes"][k]["adapt"] = v["adapt"]
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(A, B, b_kind, n)

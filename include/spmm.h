@@ -136,6 +136,9 @@ typedef struct {
     double plan_ms;             /* host time spent building the plan */
     int32_t uploaded;           /* 1 after spmm_plan_upload */
     int32_t reserved;
+    double work_vec;            /* entries gathered by the segment and vector kernels */
+    double work_tile;           /* tile slots: tiles * H * kt */
+    double work_winrem;         /* remainder entries of window rows (gathered in the window kernels) */
 } spmm_plan_stats_t;
 
 /* Host views of the plan's arrays (valid until spmm_plan_destroy).  Used by
@@ -192,7 +195,8 @@ typedef struct spmm_timer_s spmm_timer_t;
 
 int32_t spmm_abi_version(void);
 /* sizeof of the ABI structs, for bindings to check their mirrors:
- * 0 spmm_csr, 1 spmm_opts, 2 spmm_plan_stats_t, 3 spmm_plan_dump_t, 4 spmm_work;
+ * 0 spmm_csr, 1 spmm_opts, 2 spmm_plan_stats_t, 3 spmm_plan_dump_t, 4 spmm_work,
+ * 5 spmm_adapt_state;
  * -1 for any other value. */
 int64_t spmm_sizeof(int32_t which);
 const char *spmm_status_string(spmm_status s);
@@ -284,6 +288,56 @@ spmm_status spmm_tune_cache_get(const char *key, spmm_opts *o, int32_t *found);
 spmm_status spmm_tune_cache_save(const char *path);
 spmm_status spmm_tune_cache_load(const char *path);
 void spmm_tune_cache_clear(void);
+
+/* Epoch-level adaptive re-partition (Sec. 5.3, Eq. 6-7), read for one pool of
+ * compute units: the vector path (segment and vector kernels) and the MFMA
+ * path (window kernels) run one after the other on the same CUs, so the split
+ * that minimises an epoch is the cost crossover of Eq. 3 with r = 1.  Each
+ * epoch measures both paths and derives their throughputs (Eq. 1 inverted;
+ * the window kernels' remainder entries are charged at the vector rate), the
+ * crossover alpha* = P_vec / P_mfma, and Eq. 6's skew between the two paths'
+ * times for a tile of the current threshold density, which is
+ * max(alpha, alpha*) / min(alpha, alpha*).  Above 1 + eps the plan is rebuilt
+ * with the threshold moved towards alpha* (sparser tiles move to the vector
+ * path when alpha* > alpha, denser rows are packed into tiles when
+ * alpha* < alpha): to the secant estimate of log(alpha*) = log(alpha) from
+ * this epoch and the previous one when it lies strictly inside the bracket of
+ * earlier thresholds, else to alpha* but at most to the geometric midpoint
+ * towards a known bracket end; at most 7 rounds.
+ *
+ * Zero the state before the first epoch; alpha <= 0 starts from the plan's
+ * own threshold.  All throughputs are entries (or tile slots) * N per second. */
+typedef struct {
+    double alpha;       /* threshold of the current plan (next plan's after a re-partition) */
+    double alpha_star;  /* crossover measured in the last epoch, at most 1 */
+    double lo, hi;      /* bracket of the threshold; 0 = open */
+    int32_t rounds;     /* re-partitions so far */
+    int32_t converged;  /* 1 once skew <= 1 + eps */
+    int32_t replanned;  /* 1 if the last epoch rebuilt the plan */
+    int32_t reserved;
+    double skew;        /* Eq. 6 of the last epoch */
+    double p_vec, p_mfma;       /* throughputs used for alpha_star */
+    double t_vec_ms, t_mfma_ms; /* the last epoch's path times */
+    double prev_alpha, prev_alpha_star; /* the epoch before: threshold and crossover (0 = none) */
+} spmm_adapt_state;
+
+/* The host part of one epoch: from the two paths' times (ms) and work
+ * (w_vec entries*N gathered by the vector path, w_tile tile slots*N, w_winrem
+ * remainder entries*N of window rows gathered inside the window kernels) and
+ * the dry-run throughputs used for a path without work, update *st (alpha,
+ * bracket, rounds, skew, converged, replanned).  INVALID for a null state,
+ * negative times or work, or eps < 0. */
+spmm_status spmm_adapt_next(spmm_adapt_state *st, double t_vec_ms, double t_mfma_ms,
+                            double w_vec, double w_tile, double w_winrem, double p_vec_dry,
+                            double p_mfma_dry, float eps);
+/* One epoch on the device: C = A*B with *plan (timed on `stream`, which is
+ * synchronised), then spmm_adapt_next, and when it asks for a re-partition,
+ * a new mixed plan of A with the same options except the threshold replaces
+ * *plan (the old plan is destroyed; BUSY, with *plan kept, if it still has
+ * outstanding tickets).  A must be the matrix *plan was built from. */
+spmm_status spmm_adapt_epoch(const spmm_csr *A, spmm_plan_t **plan, const void *B, int64_t ldb,
+                             void *C, int64_t ldc, void *stream, float eps,
+                             spmm_adapt_state *st);
 
 /* Device copy bandwidth (read + write bytes per second) over `bytes` bytes. */
 spmm_status spmm_copy_bandwidth(int64_t bytes, void *stream, double *bytes_per_s);

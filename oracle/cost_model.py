@@ -7,11 +7,21 @@
 * Eq. 5: Thres = alpha * K (a density turned into a length).
 * Eq. 6: Skew = max(dt_a, dt_b) / min(dt_a, dt_b) >= 1; rebalancing triggers
   only when Skew > 1 + eps (Sec. 5.3, eps = 0.05).
+* Sec. 5.3 (Eq. 6-7) read for one engine pool: an epoch measures the two
+  paths' times, turns them into throughputs (Eq. 1 inverted), takes the
+  crossover alpha* = P_vec / P_mat (Eq. 3 and Eq. 7 with r = 1), and applies
+  Eq. 6 to the two paths' times for a tile of the current threshold density
+  (which reduces to max(alpha, alpha*) / min(alpha, alpha*)).  Above 1 + eps
+  the threshold moves towards alpha* inside a bracket of earlier thresholds
+  (a secant step on log(alpha*/alpha) over two epochs when it falls inside,
+  else at most the geometric midpoint to the bracket end), at most 7 rounds.
 * Eq. 8: double-buffered residency limits for an (M, N, K) tile:
   2*M*K <= C_A/2, 2*N*K <= C_B/2, 4*M*N <= C_C/2; fp16 input traffic of a
   tile is 2*(M*K + N*K) bytes (Sec. 6.2.2).
 """
 from __future__ import annotations
+
+import math
 
 
 def cost_vec(nnz, p_vec):
@@ -71,3 +81,67 @@ def tile_feasible(m, n, k, cap_a, cap_b, cap_c, in_bytes=2, acc_bytes=4, multipl
 def tile_input_bytes(m, n, k, in_bytes=2):
     """Input traffic of one tile: the A tile plus the B tile (Sec. 6.2.2)."""
     return in_bytes * (m * k + n * k)
+
+
+def path_throughputs(t_vec, t_mat, w_vec, w_tile, w_winrem, p_vec_dry, p_mat_dry):
+    """Eq. 1 inverted on one epoch.  t_vec: time of the vector path (segment
+    and vector kernels), which gathered w_vec entries; t_mat: time of the
+    window kernels, which computed w_tile tile slots and also gathered
+    w_winrem remainder entries of window rows (charged at P_vec).  A path
+    with no work, or a time that leaves nothing for the tiles, falls back to
+    the dry-run throughput."""
+    if w_vec > 0 and t_vec > 0:
+        p_vec = w_vec / t_vec
+    else:
+        p_vec = p_vec_dry
+    if w_tile > 0 and t_mat > 0:
+        t_tiles = t_mat - w_winrem / p_vec
+        if t_tiles < 0.1 * t_mat:
+            t_tiles = 0.1 * t_mat
+        p_mat = w_tile / t_tiles
+    else:
+        p_mat = p_mat_dry
+    return p_vec, p_mat
+
+
+def adapt_next(alpha, lo, hi, rounds, prev_alpha, prev_star, p_vec, p_mat, eps=0.05, r=1.0,
+               max_rounds=7):
+    """One epoch of the adaptive re-partition.  (lo, hi) bracket the
+    threshold (0 = open); (prev_alpha, prev_star) is the previous epoch's
+    threshold and measured crossover (0 = none).  Returns (next alpha, lo,
+    hi, rounds, alpha*, skew, replan).
+
+    The next threshold is the secant estimate of where the measured
+    crossover meets the threshold (in logarithms, from this epoch and the
+    previous one) when it lies strictly inside the updated bracket; else
+    alpha* itself, but never more than the geometric midpoint towards a
+    known bracket end."""
+    a_star = min(1.0, alpha_closed_form(p_vec, p_mat, r))
+    s = skew(alpha, a_star)
+    if s <= 1.0 + eps or rounds >= max_rounds:
+        return alpha, lo, hi, rounds, a_star, s, False
+    raise_it = a_star > alpha
+    # bracket: the threshold must rise above alpha, or fall below it
+    if raise_it:
+        lo = alpha
+    else:
+        hi = alpha
+    nxt = None
+    if prev_alpha > 0 and prev_star > 0 and prev_alpha != alpha:
+        f = math.log(a_star / alpha)
+        f_prev = math.log(prev_star / prev_alpha)
+        if f != f_prev:
+            x = math.log(alpha) - f * (math.log(alpha) - math.log(prev_alpha)) / (f - f_prev)
+            cand = math.exp(x)
+            if (lo <= 0 or cand > lo) and (hi <= 0 or cand < hi):
+                nxt = cand
+    if nxt is None:
+        if raise_it:
+            # the tiles at the threshold cost more on the matrix path: move
+            # the sparser tiles to the vector path
+            nxt = a_star if hi <= 0 else min(a_star, math.sqrt(alpha * hi))
+        else:
+            # rows just below the threshold cost more on the vector path:
+            # pack them into tiles
+            nxt = a_star if lo <= 0 else max(a_star, math.sqrt(alpha * lo))
+    return nxt, lo, hi, rounds + 1, a_star, s, True

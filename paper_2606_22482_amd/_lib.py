@@ -45,7 +45,8 @@ class PlanStats(C.Structure):
                 ("mean_tile_density", C.c_double), ("zero_fraction_tiles", C.c_double),
                 ("device_bytes", C.c_int64), ("workspace_bytes", C.c_int64),
                 ("algorithmic_bytes", C.c_double), ("flops", C.c_double),
-                ("plan_ms", C.c_double), ("uploaded", C.c_int32), ("reserved", C.c_int32)]
+                ("plan_ms", C.c_double), ("uploaded", C.c_int32), ("reserved", C.c_int32),
+                ("work_vec", C.c_double), ("work_tile", C.c_double), ("work_winrem", C.c_double)]
 
 
 class PlanDump(C.Structure):
@@ -68,6 +69,15 @@ class TuneReport(C.Structure):
     _fields_ = [("candidates", C.c_int32), ("reserved", C.c_int32), ("default_ms", C.c_double),
                 ("best_ms", C.c_double), ("alpha_cost", C.c_double), ("p_vec", C.c_double),
                 ("p_mfma", C.c_double), ("search_ms", C.c_double)]
+
+
+class AdaptState(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("alpha_star", C.c_double), ("lo", C.c_double),
+                ("hi", C.c_double), ("rounds", C.c_int32), ("converged", C.c_int32),
+                ("replanned", C.c_int32), ("reserved", C.c_int32), ("skew", C.c_double),
+                ("p_vec", C.c_double), ("p_mfma", C.c_double), ("t_vec_ms", C.c_double),
+                ("t_mfma_ms", C.c_double), ("prev_alpha", C.c_double),
+                ("prev_alpha_star", C.c_double)]
 
 
 class Work(C.Structure):
@@ -104,6 +114,10 @@ SIGNATURES = {
     "spmm_dryrun": (_S, [C.c_int32, C.c_int32, _P, C.POINTER(C.c_double),
                          C.POINTER(C.c_double)]),
     "spmm_copy_bandwidth": (_S, [C.c_int64, _P, C.POINTER(C.c_double)]),
+    "spmm_adapt_next": (_S, [C.POINTER(AdaptState), C.c_double, C.c_double, C.c_double,
+                             C.c_double, C.c_double, C.c_double, C.c_double, C.c_float]),
+    "spmm_adapt_epoch": (_S, [C.POINTER(Csr), C.POINTER(_P), _P, C.c_int64, _P, C.c_int64, _P,
+                              C.c_float, C.POINTER(AdaptState)]),
     "spmm_autotune": (_S, [C.POINTER(Csr), C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64, _P,
                            C.c_int64, _P, C.c_double, C.POINTER(Opts), C.POINTER(TuneReport)]),
     "spmm_profile_key": (_S, [C.POINTER(Csr), C.c_int32, C.c_int32, C.c_char_p, C.c_int32]),
@@ -114,7 +128,7 @@ SIGNATURES = {
     "spmm_tune_cache_clear": (None, []),
 }
 
-STRUCTS = {0: Csr, 1: Opts, 2: PlanStats, 3: PlanDump, 4: Work}
+STRUCTS = {0: Csr, 1: Opts, 2: PlanStats, 3: PlanDump, 4: Work, 5: AdaptState}
 
 _lib = None
 

@@ -179,6 +179,19 @@ class Plan:
         L.check(self._lib.spmm_run_timed(self._h, bp, ldb, cp, ldc, _stream_handle(stream),
                                          timer.handle))
 
+    def adapt_epoch(self, A, B, Cout, state: "L.AdaptState", eps: float = 0.05, stream=None):
+        """spmm_adapt_epoch: one timed run (Cout = A @ B, the stream is
+        synchronised), then the adaptive re-partition step; when it rebuilds
+        the plan, this object takes the new plan's handle.  A must be the
+        matrix this plan was built from.  Returns ``state``."""
+        csr, keep = _csr_struct(A)
+        bp, ldb = _dev2d(B, "B")
+        cp, ldc = _dev2d(Cout, "C")
+        L.check(self._lib.spmm_adapt_epoch(C.byref(csr), C.byref(self._h), bp, ldb, cp, ldc,
+                                           _stream_handle(stream), float(eps), C.byref(state)))
+        del keep
+        return state
+
     def destroy(self):
         if self._h:
             L.check(self._lib.spmm_plan_destroy(self._h))
@@ -319,3 +332,20 @@ def spmm_copy_bandwidth(nbytes: int, stream=None) -> float:
     out = C.c_double()
     L.check(lib.spmm_copy_bandwidth(int(nbytes), _stream_handle(stream), C.byref(out)))
     return out.value
+
+
+def adapt_state(alpha: float = 0.0) -> L.AdaptState:
+    """A zeroed adaptive re-partition state (alpha <= 0: start from the plan's
+    own threshold)."""
+    st = L.AdaptState()
+    st.alpha = alpha
+    return st
+
+
+def adapt_next(state: L.AdaptState, t_vec_ms, t_mfma_ms, w_vec, w_tile, w_winrem,
+               p_vec_dry=0.0, p_mfma_dry=0.0, eps=0.05) -> L.AdaptState:
+    """spmm_adapt_next: the host update of one epoch (see include/spmm.h)."""
+    lib = L.load()
+    L.check(lib.spmm_adapt_next(C.byref(state), t_vec_ms, t_mfma_ms, w_vec, w_tile, w_winrem,
+                                p_vec_dry, p_mfma_dry, eps))
+    return state

@@ -352,3 +352,132 @@ extern "C" spmm_status spmm_autotune(const spmm_csr *A, int32_t n, int32_t b_typ
     g_cache[key] = best;
     return SPMM_OK;
 }
+
+// ------------------------------------------------------------------------------------------
+// Epoch-level adaptive re-partition (Sec. 5.3, Eq. 6-7; one pool of CUs, r = 1)
+
+extern "C" spmm_status spmm_adapt_next(spmm_adapt_state *st, double t_vec_ms, double t_mfma_ms,
+                                       double w_vec, double w_tile, double w_winrem,
+                                       double p_vec_dry, double p_mfma_dry, float eps) {
+    if (!st) return set_error(SPMM_ERR_INVALID, "state is null");
+    if (!(t_vec_ms >= 0) || !(t_mfma_ms >= 0) || !(w_vec >= 0) || !(w_tile >= 0) ||
+        !(w_winrem >= 0) || !(eps >= 0))
+        return set_error(SPMM_ERR_INVALID, "times, work and eps must be >= 0");
+    if (!(st->alpha > 0)) return set_error(SPMM_ERR_INVALID, "state alpha must be > 0");
+    // Eq. 1 inverted on the epoch; the window kernels' remainder entries are
+    // charged at the vector rate, the rest of their time is the tiles'
+    double pv = (w_vec > 0 && t_vec_ms > 0) ? w_vec / (t_vec_ms * 1e-3) : p_vec_dry;
+    double pm = p_mfma_dry;
+    if (w_tile > 0 && t_mfma_ms > 0) {
+        if (!(pv > 0)) return set_error(SPMM_ERR_INVALID, "no vector throughput");
+        double t_tiles = t_mfma_ms * 1e-3 - w_winrem / pv;
+        t_tiles = std::max(t_tiles, 0.1 * t_mfma_ms * 1e-3);
+        pm = w_tile / t_tiles;
+    }
+    if (!(pv > 0) || !(pm > 0)) return set_error(SPMM_ERR_INVALID, "no throughput for a path");
+    const double a = st->alpha;
+    const double as = std::min(1.0, pv / pm);  // Eq. 3 / Eq. 7, r = 1
+    const double sk = std::max(a, as) / std::min(a, as);  // Eq. 6 on a threshold-density tile
+    st->alpha_star = as;
+    st->skew = sk;
+    st->p_vec = pv;
+    st->p_mfma = pm;
+    st->t_vec_ms = t_vec_ms;
+    st->t_mfma_ms = t_mfma_ms;
+    st->replanned = 0;
+    st->converged = sk <= 1.0 + eps ? 1 : 0;
+    if (st->converged || st->rounds >= 7) return SPMM_OK;
+    const bool raise = as > a;
+    if (raise) st->lo = a;
+    else st->hi = a;
+    // secant step on log(alpha*/alpha) over this epoch and the previous one,
+    // taken when it falls strictly inside the bracket
+    double next = -1.0;
+    if (st->prev_alpha > 0 && st->prev_alpha_star > 0 && st->prev_alpha != a) {
+        const double f = std::log(as / a), fp = std::log(st->prev_alpha_star / st->prev_alpha);
+        if (f != fp) {
+            const double x = std::log(a) - f * (std::log(a) - std::log(st->prev_alpha)) / (f - fp);
+            const double cand = std::exp(x);
+            if ((st->lo <= 0 || cand > st->lo) && (st->hi <= 0 || cand < st->hi)) next = cand;
+        }
+    }
+    if (next < 0) {
+        if (raise)  // tiles at the threshold cost more on the matrix path: sparser tiles to vector
+            next = st->hi <= 0 ? as : std::min(as, std::sqrt(a * st->hi));
+        else  // rows just below the threshold cost more on the vector path: pack them into tiles
+            next = st->lo <= 0 ? as : std::max(as, std::sqrt(a * st->lo));
+    }
+    st->prev_alpha = a;
+    st->prev_alpha_star = as;
+    st->alpha = next;
+    st->rounds += 1;
+    st->replanned = 1;
+    return SPMM_OK;
+}
+
+extern "C" spmm_status spmm_adapt_epoch(const spmm_csr *A, spmm_plan_t **plan, const void *B,
+                                        int64_t ldb, void *C, int64_t ldc, void *stream,
+                                        float eps, spmm_adapt_state *st) {
+    if (!A || !plan || !*plan || !st) return set_error(SPMM_ERR_INVALID, "null argument");
+    spmm_plan_t *p = *plan;
+    const HostPlan &h = p->hp;
+    if (A->m != h.m || A->k != h.k || A->nnz != h.nnz)
+        return set_error(SPMM_ERR_INVALID, "A is not the matrix of the plan");
+    spmm_timer_t *t = nullptr;
+    spmm_status st0 = spmm_timer_create(16, &t);
+    if (st0 != SPMM_OK) return st0;
+    st0 = spmm_run_timed(p, B, ldb, C, ldc, stream, t);
+    int32_t ids[16], cnt = 0;
+    float ms[16];
+    if (st0 == SPMM_OK) st0 = spmm_timer_read(t, ids, ms, 16, &cnt);
+    (void)spmm_timer_destroy(t);
+    if (st0 != SPMM_OK) return st0;
+    double tv = 0, tm = 0;
+    for (int32_t i = 0; i < cnt; ++i) {
+        if (ids[i] == SPMM_KERNEL_SEGMENT || ids[i] == SPMM_KERNEL_VECTOR) tv += ms[i];
+        else tm += ms[i];
+    }
+    double wv = 0, wt = 0, wr = 0;
+    plan_path_work(h, &wv, &wt, &wr);
+    const double n = (double)h.n;
+    if (!(st->alpha > 0)) st->alpha = h.opts.alpha;
+    // a path without work takes the dry-run throughput (cached per N and B type)
+    double pvd = 0, pmd = 0;
+    if (wv == 0 || wt == 0) {
+        std::pair<double, double> cached{0, 0};
+        bool have = false;
+        {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            auto it = g_dryrun.find({h.n, h.b_type});
+            if (it != g_dryrun.end()) { cached = it->second; have = true; }
+        }
+        if (!have) {
+            st0 = spmm_dryrun(h.n, h.b_type, stream, &cached.first, &cached.second);
+            if (st0 != SPMM_OK) return st0;
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            g_dryrun[{h.n, h.b_type}] = cached;
+        }
+        pvd = cached.first;
+        pmd = cached.second;
+    }
+    const spmm_adapt_state before = *st;
+    st0 = spmm_adapt_next(st, tv, tm, wv * n, wt * n, wr * n, pvd, pmd, eps);
+    if (st0 != SPMM_OK || !st->replanned) return st0;
+    spmm_opts o = h.opts;
+    o.mode = SPMM_MODE_MIXED;
+    o.alpha = (float)st->alpha;
+    spmm_plan_t *np = nullptr;
+    st0 = spmm_plan(A, h.n, h.b_type, h.c_type, &o, &np);
+    if (st0 != SPMM_OK) {
+        *st = before;  // the epoch's result stands; the plan and state are unchanged
+        return st0;
+    }
+    st0 = spmm_plan_destroy(p);
+    if (st0 != SPMM_OK) {
+        (void)spmm_plan_destroy(np);
+        *st = before;
+        return st0;
+    }
+    *plan = np;
+    return SPMM_OK;
+}

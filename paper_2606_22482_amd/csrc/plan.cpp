@@ -435,4 +435,16 @@ spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_
     return SPMM_OK;
 }
 
+void plan_path_work(const HostPlan &P, double *w_vec, double *w_tile, double *w_winrem) {
+    double v = 0, wr = 0;
+    for (size_t i = 0; i < P.seg_row.size(); ++i) v += (double)(P.seg_end[i] - P.seg_begin[i]);
+    for (int32_t r : P.vector_rows)
+        if (!P.nseg[r]) v += (double)(P.rem_ptr[r + 1] - P.rem_ptr[r]);
+    for (int32_t r : P.windows)
+        if (r >= 0 && !P.nseg[r]) wr += (double)(P.rem_ptr[r + 1] - P.rem_ptr[r]);
+    *w_vec = v;
+    *w_tile = (double)P.tile_window.size() * P.opts.window_h * P.opts.kt;
+    *w_winrem = wr;
+}
+
 }  // namespace spmm

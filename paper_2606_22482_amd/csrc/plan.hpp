@@ -73,6 +73,11 @@ void resolve_options(const spmm_opts *in, const spmm_csr *A, int32_t n, int32_t 
 spmm_status validate_problem(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
                              std::string &err);
 
+// Work of the two paths of a plan: entries gathered by the segment and vector
+// kernels, tile slots (tiles * H * kt), and remainder entries of window rows
+// gathered inside the window kernels.
+void plan_path_work(const HostPlan &P, double *w_vec, double *w_tile, double *w_winrem);
+
 // Build the full host plan for already-resolved options.
 spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
                             const spmm_opts &o, HostPlan &P, std::string &err);

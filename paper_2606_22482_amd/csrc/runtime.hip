@@ -49,6 +49,7 @@ extern "C" int64_t spmm_sizeof(int32_t which) {
     case 2: return (int64_t)sizeof(spmm_plan_stats_t);
     case 3: return (int64_t)sizeof(spmm_plan_dump_t);
     case 4: return (int64_t)sizeof(spmm_work);
+    case 5: return (int64_t)sizeof(spmm_adapt_state);
     default: return -1;
     }
 }
@@ -273,6 +274,7 @@ extern "C" spmm_status spmm_plan_stats(const spmm_plan_t *p, spmm_plan_stats_t *
     out->flops = 2.0 * (double)h.nnz * (double)h.n;
     out->plan_ms = h.plan_ms;
     out->uploaded = p->dev != nullptr;
+    plan_path_work(h, &out->work_vec, &out->work_tile, &out->work_winrem);
     return SPMM_OK;
 }
 

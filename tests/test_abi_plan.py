@@ -329,3 +329,86 @@ def test_hot_columns_are_most_gathered(lib):
     assert p.stats()["opts"]["hot_cols"] == int(0.8 * 4 * 1024 * 1024 / (64 * 4))
     q = api.Plan(A, 64, "f32", api.default_opts(mode="plain"), upload=False)
     assert q.stats()["opts"]["cold_policy"] == 0 and q.stats()["opts"]["hot_cols"] == 0
+
+
+def _path_work(d, h, kt):
+    """Entries of the vector path (all segments, unsplit vector rows), tile
+    slots, and unsplit window rows' remainder entries, from the export."""
+    rem_len = np.diff(d["rem_ptr"])
+    wv = float(np.sum(d["seg_end"] - d["seg_begin"]))
+    vr = d["vector_rows"]
+    wv += float(rem_len[vr][d["nseg"][vr] == 0].sum())
+    wr_rows = d["windows"][d["windows"] >= 0]
+    wr = float(rem_len[wr_rows][d["nseg"][wr_rows] == 0].sum())
+    return wv, float(d["tile_window"].size * h * kt), wr
+
+
+def test_plan_path_work(lib):
+    A, _ = synth.block_community(n=4096, band=8, n_cols=8, seed=3)
+    for alpha in (0.05, 0.3, 2.0):
+        p = api.Plan(A, 64, "bf16", api.default_opts(mode="mixed", alpha=alpha, seg_len=24),
+                     upload=False)
+        st, d = p.stats(), p.export()
+        wv, wt, wr = _path_work(d, st["opts"]["window_h"], st["opts"]["kt"])
+        assert (st["work_vec"], st["work_tile"], st["work_winrem"]) == (wv, wt, wr)
+        assert wv + wr + st["nnz_tiles"] == A.nnz
+
+
+def test_adapt_next_matches_reference(lib):
+    from oracle import cost_model as cm
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        g = rng.uniform(0, 2)
+        a0 = float(np.exp(rng.uniform(np.log(0.002), 0)))
+        at = float(np.exp(rng.uniform(np.log(0.01), np.log(0.8))))
+        st = api.adapt_state(a0)
+        lo = hi = pa = ps = 0.0
+        rounds = 0
+        for _ in range(9):
+            alpha = st.alpha
+            a_meas = min(1.0, at * (at / alpha) ** g)
+            # epoch times that measure P_vec = a_meas, P_mat = 1 (per second)
+            t_vec, t_mat, wr = 2.0, 3.0, 0.5e-3 * a_meas
+            w_vec = a_meas * t_vec * 1e-3
+            w_tile = (t_mat * 1e-3 - wr / a_meas) * 1.0
+            api.adapt_next(st, t_vec, t_mat, w_vec, w_tile, wr, 0.0, 0.0, 0.05)
+            p_vec, p_mat = cm.path_throughputs(t_vec * 1e-3, t_mat * 1e-3, w_vec, w_tile, wr,
+                                               0.0, 0.0)
+            nxt, lo, hi, rounds, a_s, s, replan = cm.adapt_next(alpha, lo, hi, rounds, pa, ps,
+                                                                p_vec, p_mat, 0.05)
+            assert st.alpha_star == pytest.approx(a_s, rel=1e-12)
+            assert st.skew == pytest.approx(s, rel=1e-12)
+            assert bool(st.replanned) == replan
+            if not replan:
+                assert st.converged == int(s <= 1.05)
+                break
+            assert st.alpha == pytest.approx(nxt, rel=1e-12)
+            assert (st.lo, st.hi, st.rounds) == (lo, hi, rounds)
+            pa, ps = alpha, a_s
+        assert st.converged
+
+
+def test_adapt_loop_on_plans(lib):
+    """The host loop on real plans with a model device whose per-path rates
+    are fixed: one re-partition reaches the crossover, and the plan's split
+    follows the threshold."""
+    A, _ = synth.block_community(n=4096, band=8, n_cols=8, seed=3)
+    n, pv, pm = 64, 3.0e11, 2.0e12
+    for a0 in (0.9, 0.01):
+        st = api.adapt_state(a0)
+        tiles = []
+        for epoch in range(9):
+            p = api.Plan(A, n, "bf16", api.default_opts(mode="mixed", alpha=st.alpha),
+                         upload=False)
+            s = p.stats()
+            tiles.append(s["tiles"])
+            t_vec = s["work_vec"] * n / pv * 1e3
+            t_mat = (s["work_tile"] * n / pm + s["work_winrem"] * n / pv) * 1e3
+            api.adapt_next(st, t_vec, t_mat, s["work_vec"] * n, s["work_tile"] * n,
+                           s["work_winrem"] * n, pv, pm, 0.05)
+            if not st.replanned:
+                break
+        assert st.converged and epoch <= 7
+        assert abs(np.log(st.alpha / (pv / pm))) <= np.log(1.05) + 1e-12
+        if a0 == 0.9:  # no tile is that dense; at the crossover most are kept
+            assert tiles[0] == 0 and tiles[-1] > 0

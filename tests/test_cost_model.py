@@ -101,3 +101,84 @@ def test_table1_measure(t):
     Af = synth.csr_from_coo(32, 32, *np.nonzero(F), np.ones(1024, np.float32), "f32")
     assert stats.active_tile_zero_fraction(Af.rowptr, Af.colidx, 32, 32, t) == 0.0
     assert stats.empty_tile_fraction(D.rowptr, D.colidx, n, n, 16) == pytest.approx(1 - 4 / 16)
+
+
+# ---- Sec. 5.3 adaptive re-partition (Eq. 6-7, one pool of CUs) -------------------------
+
+def _plant(alpha, a_true, gamma):
+    """Model device: the crossover measured at threshold alpha drifts from the
+    true one as the split moves (log-linear, slope -gamma)."""
+    return min(1.0, a_true * (a_true / alpha) ** gamma)
+
+
+def _run_ref(a0, a_true, gamma, eps=0.05, max_epochs=9):
+    alpha, lo, hi, rounds, pa, ps = a0, 0.0, 0.0, 0, 0.0, 0.0
+    trace = []
+    for _ in range(max_epochs):
+        a_star = _plant(alpha, a_true, gamma)
+        nxt, lo, hi, rounds2, a_s, s, replan = cm.adapt_next(alpha, lo, hi, rounds, pa, ps,
+                                                             a_star, 1.0, eps)
+        trace.append((alpha, a_s, s, replan, lo, hi))
+        if not replan:
+            break
+        pa, ps = alpha, a_s
+        alpha, rounds = nxt, rounds2
+    return trace
+
+
+def test_adapt_fixed_point_trigger_and_direction():
+    # alpha = alpha*: Eq. 6 skew 1, nothing moves
+    nxt, lo, hi, rounds, a_s, s, replan = cm.adapt_next(0.2, 0, 0, 0, 0, 0, 2.0, 10.0)
+    assert a_s == pytest.approx(0.2) and s == pytest.approx(1.0) and not replan
+    # the trigger is Eq. 6's: Skew > 1 + eps
+    for ratio in (1.04, 1.0499, 1.0501, 1.2, 1 / 1.2, 1 / 1.0501):
+        a_star = 0.1 * ratio
+        out = cm.adapt_next(0.1, 0, 0, 0, 0, 0, a_star, 1.0)
+        assert out[6] == cm.should_migrate(0.1, a_star)
+    # direction: alpha* above -> threshold rises, lower bracket end set
+    nxt, lo, hi, *_ = cm.adapt_next(0.05, 0, 0, 0, 0, 0, 0.3, 1.0)
+    assert nxt == pytest.approx(0.3) and lo == 0.05 and hi == 0
+    nxt, lo, hi, *_ = cm.adapt_next(0.5, 0, 0, 0, 0, 0, 0.1, 1.0)
+    assert nxt == pytest.approx(0.1) and hi == 0.5 and lo == 0
+    # never past the geometric midpoint towards a known bracket end
+    nxt, lo, hi, *_ = cm.adapt_next(0.05, 0.0, 0.2, 1, 0, 0, 0.9, 1.0)
+    assert nxt == pytest.approx((0.05 * 0.2) ** 0.5)
+    # at most 7 re-partitions
+    assert not cm.adapt_next(0.05, 0, 0, 7, 0, 0, 0.9, 1.0)[6]
+
+
+def test_adapt_balance_at_the_crossover():
+    """Eq. 7 with r = 1: at alpha = P_vec / P_mat a tile of threshold density
+    costs the same on both paths (Eq. 1)."""
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        pv, pm = rng.uniform(1, 100, size=2)
+        if pv >= pm:
+            continue
+        a = cm.adapt_next(0.5, 0, 0, 0, 0, 0, pv, pm)[4]
+        m, k = 16, 32
+        assert cm.cost_vec(a * m * k, pv) == pytest.approx(cm.cost_mat(m, k, pm), rel=1e-12)
+
+
+@pytest.mark.parametrize("gamma", [0.0, 0.3, 0.6, 0.9, 1.2, 1.5, 1.9, 3.0])
+def test_adapt_converges_on_a_model_device(gamma):
+    for a0 in (0.002, 0.01, 0.05, 0.3, 1.0):
+        for a_true in (0.02, 0.1, 0.5):
+            tr = _run_ref(a0, a_true, gamma)
+            last = tr[-1]
+            assert not last[3] and last[2] <= 1.05, (gamma, a0, a_true, tr)
+            assert len(tr) - 1 <= 7
+            for alpha, _, _, replan, lo, hi in tr[:-1]:
+                # the bracket always contains the next threshold
+                assert (lo == 0 or lo <= alpha) and (hi == 0 or alpha <= hi)
+
+
+def test_path_throughputs():
+    # window kernels: tiles plus window-row remainders charged at the vector rate
+    pv, pm = cm.path_throughputs(2.0, 3.0, 100.0, 400.0, 50.0, 1.0, 1.0)
+    assert pv == 50.0 and pm == pytest.approx(400.0 / (3.0 - 1.0))
+    # a path without work takes the dry run
+    assert cm.path_throughputs(0.0, 3.0, 0.0, 400.0, 0.0, 7.0, 9.0)[0] == 7.0
+    assert cm.path_throughputs(2.0, 0.0, 100.0, 0.0, 0.0, 7.0, 9.0)[1] == 9.0
+    # the tiles keep at least a tenth of the window time
+    assert cm.path_throughputs(1.0, 1.0, 100.0, 10.0, 1000.0, 1, 1)[1] == pytest.approx(100.0)

@@ -327,6 +327,36 @@ def test_submit_matches_solo_bitwise():
         parity(Cs, A, B, kind, TOL_16 if kind == "f16" else TOL_F32)
 
 
+@pytest.mark.parametrize("a0", [0.9, 0.004])
+def test_adapt_epochs(a0):
+    """Epoch-level re-partition from a threshold that keeps no tile (0.9) and
+    from one that keeps very sparse tiles (0.004): every epoch's C matches the
+    oracle, the state's bookkeeping holds, and it stops within 7 rounds."""
+    import torch
+    A, B = synth.block_community(n=32768, band=16, n_cols=128, seed=6)
+    Bd = device_B(B, "bf16")
+    p = api.Plan(A, 128, "bf16", api.default_opts(mode="mixed", alpha=a0))
+    st = api.adapt_state()
+    rows = np.sort(np.random.default_rng(0).choice(A.m, 3000, replace=False))
+    alphas = []
+    for epoch in range(9):
+        C = device_C(A.m, 128)
+        alphas.append(p.stats()["opts"]["alpha"])
+        p.adapt_epoch(A, Bd, C, st)
+        print("epoch", epoch, alphas[-1], st.alpha_star, st.skew, st.t_vec_ms, st.t_mfma_ms,
+              flush=True)
+        parity(C, A, B, "bf16", TOL_16, rows=rows)
+        if not st.replanned:
+            break
+        assert p.stats()["opts"]["alpha"] == pytest.approx(st.alpha, rel=1e-6)
+    assert st.rounds <= 7 and (st.converged or st.rounds == 7)
+    assert st.p_vec > 0 and st.p_mfma > 0 and 0 < st.alpha_star <= 1
+    C = device_C(A.m, 128)
+    p.run(Bd, C)
+    torch.cuda.synchronize()
+    parity(C, A, B, "bf16", TOL_16)
+
+
 def test_destroy_busy_plan_rejected():
     import torch
     A = synth.random_csr(2000, 2000, 0.01, 3)
