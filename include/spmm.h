@@ -302,8 +302,10 @@ void spmm_tune_cache_clear(void);
  * path when alpha* > alpha, denser rows are packed into tiles when
  * alpha* < alpha): to the secant estimate of log(alpha*) = log(alpha) from
  * this epoch and the previous one when it lies strictly inside the bracket of
- * earlier thresholds, else to alpha* but at most to the geometric midpoint
- * towards a known bracket end; at most 7 rounds.
+ * earlier thresholds, on alpha*'s side and at most twice as far (in
+ * logarithms) as alpha*, else to alpha* but at most to the geometric midpoint
+ * towards a known bracket end; at most 7 rounds.  A path without work in an
+ * epoch keeps the throughput measured last (the dry run's before any).
  *
  * Zero the state before the first epoch; alpha <= 0 starts from the plan's
  * own threshold.  All throughputs are entries (or tile slots) * N per second. */
@@ -324,7 +326,8 @@ typedef struct {
 /* The host part of one epoch: from the two paths' times (ms) and work
  * (w_vec entries*N gathered by the vector path, w_tile tile slots*N, w_winrem
  * remainder entries*N of window rows gathered inside the window kernels) and
- * the dry-run throughputs used for a path without work, update *st (alpha,
+ * the dry-run throughputs used for a path without work when *st holds no
+ * measured one, update *st (alpha,
  * bracket, rounds, skew, converged, replanned).  INVALID for a null state,
  * negative times or work, or eps < 0. */
 spmm_status spmm_adapt_next(spmm_adapt_state *st, double t_vec_ms, double t_mfma_ms,

@@ -88,8 +88,8 @@ def path_throughputs(t_vec, t_mat, w_vec, w_tile, w_winrem, p_vec_dry, p_mat_dry
     and vector kernels), which gathered w_vec entries; t_mat: time of the
     window kernels, which computed w_tile tile slots and also gathered
     w_winrem remainder entries of window rows (charged at P_vec).  A path
-    with no work, or a time that leaves nothing for the tiles, falls back to
-    the dry-run throughput."""
+    with no work takes the fallback throughput (the last one measured, else
+    the dry run's)."""
     if w_vec > 0 and t_vec > 0:
         p_vec = w_vec / t_vec
     else:
@@ -113,9 +113,10 @@ def adapt_next(alpha, lo, hi, rounds, prev_alpha, prev_star, p_vec, p_mat, eps=0
 
     The next threshold is the secant estimate of where the measured
     crossover meets the threshold (in logarithms, from this epoch and the
-    previous one) when it lies strictly inside the updated bracket; else
-    alpha* itself, but never more than the geometric midpoint towards a
-    known bracket end."""
+    previous one) when it lies strictly inside the updated bracket, on
+    alpha*'s side of alpha and at most twice as far (in logarithms) as
+    alpha*; else alpha* itself, but never more than the geometric midpoint
+    towards a known bracket end."""
     a_star = min(1.0, alpha_closed_form(p_vec, p_mat, r))
     s = skew(alpha, a_star)
     if s <= 1.0 + eps or rounds >= max_rounds:
@@ -133,7 +134,9 @@ def adapt_next(alpha, lo, hi, rounds, prev_alpha, prev_star, p_vec, p_mat, eps=0
         if f != f_prev:
             x = math.log(alpha) - f * (math.log(alpha) - math.log(prev_alpha)) / (f - f_prev)
             cand = math.exp(x)
-            if (lo <= 0 or cand > lo) and (hi <= 0 or cand < hi):
+            d = x - math.log(alpha)
+            inside = (lo <= 0 or cand > lo) and (hi <= 0 or cand < hi)
+            if inside and d * f > 0 and abs(d) <= 2.0 * abs(f):
                 nxt = cand
     if nxt is None:
         if raise_it:

@@ -365,9 +365,12 @@ extern "C" spmm_status spmm_adapt_next(spmm_adapt_state *st, double t_vec_ms, do
         return set_error(SPMM_ERR_INVALID, "times, work and eps must be >= 0");
     if (!(st->alpha > 0)) return set_error(SPMM_ERR_INVALID, "state alpha must be > 0");
     // Eq. 1 inverted on the epoch; the window kernels' remainder entries are
-    // charged at the vector rate, the rest of their time is the tiles'
-    double pv = (w_vec > 0 && t_vec_ms > 0) ? w_vec / (t_vec_ms * 1e-3) : p_vec_dry;
-    double pm = p_mfma_dry;
+    // charged at the vector rate, the rest of their time is the tiles'.  A
+    // path without work keeps the throughput measured last, else the dry run's.
+    const double pv_fb = st->p_vec > 0 ? st->p_vec : p_vec_dry;
+    const double pm_fb = st->p_mfma > 0 ? st->p_mfma : p_mfma_dry;
+    double pv = (w_vec > 0 && t_vec_ms > 0) ? w_vec / (t_vec_ms * 1e-3) : pv_fb;
+    double pm = pm_fb;
     if (w_tile > 0 && t_mfma_ms > 0) {
         if (!(pv > 0)) return set_error(SPMM_ERR_INVALID, "no vector throughput");
         double t_tiles = t_mfma_ms * 1e-3 - w_winrem / pv;
@@ -397,8 +400,10 @@ extern "C" spmm_status spmm_adapt_next(spmm_adapt_state *st, double t_vec_ms, do
         const double f = std::log(as / a), fp = std::log(st->prev_alpha_star / st->prev_alpha);
         if (f != fp) {
             const double x = std::log(a) - f * (std::log(a) - std::log(st->prev_alpha)) / (f - fp);
-            const double cand = std::exp(x);
-            if ((st->lo <= 0 || cand > st->lo) && (st->hi <= 0 || cand < st->hi)) next = cand;
+            const double cand = std::exp(x), d = x - std::log(a);
+            const bool inside = (st->lo <= 0 || cand > st->lo) && (st->hi <= 0 || cand < st->hi);
+            // on alpha*'s side, at most twice its distance: no wild extrapolation
+            if (inside && d * f > 0 && std::fabs(d) <= 2.0 * std::fabs(f)) next = cand;
         }
     }
     if (next < 0) {

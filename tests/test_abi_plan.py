@@ -412,3 +412,17 @@ def test_adapt_loop_on_plans(lib):
         assert abs(np.log(st.alpha / (pv / pm))) <= np.log(1.05) + 1e-12
         if a0 == 0.9:  # no tile is that dense; at the crossover most are kept
             assert tiles[0] == 0 and tiles[-1] > 0
+
+
+def test_adapt_next_keeps_the_last_measured_rate(lib):
+    st = api.adapt_state(0.3)
+    # both paths measured: P_vec = 1e9, P_mfma = 4e9 per second -> alpha* = 0.25
+    api.adapt_next(st, 1.0, 1.0, 1e6, 4e6, 0.0, 5e8, 1e12, 0.05)
+    assert st.alpha_star == pytest.approx(0.25) and st.p_mfma == pytest.approx(4e9)
+    # no tiles in this epoch: the last measured P_mfma, not the dry run's
+    api.adapt_next(st, 1.0, 0.0, 1e6, 0.0, 0.0, 5e8, 1e12, 0.05)
+    assert st.alpha_star == pytest.approx(0.25) and st.converged
+    # a fresh state without measurements takes the dry run
+    st2 = api.adapt_state(0.3)
+    api.adapt_next(st2, 1.0, 0.0, 1e6, 0.0, 0.0, 5e8, 1e12, 0.05)
+    assert st2.p_mfma == 1e12 and st2.alpha_star == pytest.approx(1e9 / 1e12)

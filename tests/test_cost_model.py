@@ -182,3 +182,16 @@ def test_path_throughputs():
     assert cm.path_throughputs(2.0, 0.0, 100.0, 0.0, 0.0, 7.0, 9.0)[1] == 9.0
     # the tiles keep at least a tenth of the window time
     assert cm.path_throughputs(1.0, 1.0, 100.0, 10.0, 1000.0, 1, 1)[1] == pytest.approx(100.0)
+
+
+def test_adapt_secant_never_extrapolates_wildly():
+    # two epochs whose crossovers barely differ put the secant root far away
+    # (about 4e-6 here); the step falls back to alpha* itself
+    nxt, lo, hi, rounds, a_s, s, replan = cm.adapt_next(0.2596, 0.0, 0.9, 1, 0.9, 0.2596,
+                                                        0.085, 1.0)
+    assert replan and nxt == pytest.approx(0.085) and hi == 0.2596
+    # a secant root on alpha*'s side within twice its distance is taken: on a
+    # log-linear device (crossover 0.1 * (0.1 / alpha) ** 0.5) it is exact
+    plant = lambda a: 0.1 * (0.1 / a) ** 0.5
+    nxt, lo, hi, *_ = cm.adapt_next(0.2, 0.0, 0.4, 1, 0.4, plant(0.4), plant(0.2), 1.0)
+    assert nxt == pytest.approx(0.1, rel=1e-12) and hi == 0.2
