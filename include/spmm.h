@@ -304,7 +304,8 @@ void spmm_tune_cache_clear(void);
  * this epoch and the previous one when it lies strictly inside the bracket of
  * earlier thresholds, on alpha*'s side and at most twice as far (in
  * logarithms) as alpha*, else to alpha* but at most to the geometric midpoint
- * towards a known bracket end; at most 7 rounds.  A path without work in an
+ * towards a known bracket end (after two such cut steps in one direction that
+ * bracket end is dropped and the step goes to alpha*); at most 7 rounds.  A path without work in an
  * epoch keeps the throughput measured last (the dry run's before any).
  *
  * Zero the state before the first epoch; alpha <= 0 starts from the plan's
@@ -316,7 +317,7 @@ typedef struct {
     int32_t rounds;     /* re-partitions so far */
     int32_t converged;  /* 1 once skew <= 1 + eps */
     int32_t replanned;  /* 1 if the last epoch rebuilt the plan */
-    int32_t reserved;
+    int32_t capped;     /* +1 / -1: the last step was cut at the bracket midpoint going up / down */
     double skew;        /* Eq. 6 of the last epoch */
     double p_vec, p_mfma;       /* throughputs used for alpha_star */
     double t_vec_ms, t_mfma_ms; /* the last epoch's path times */

@@ -14,7 +14,8 @@
   (which reduces to max(alpha, alpha*) / min(alpha, alpha*)).  Above 1 + eps
   the threshold moves towards alpha* inside a bracket of earlier thresholds
   (a secant step on log(alpha*/alpha) over two epochs when it falls inside,
-  else at most the geometric midpoint to the bracket end), at most 7 rounds.
+  else at most the geometric midpoint to the bracket end, and a bracket end
+  contradicted by two capped steps is dropped), at most 7 rounds.
 * Eq. 8: double-buffered residency limits for an (M, N, K) tile:
   2*M*K <= C_A/2, 2*N*K <= C_B/2, 4*M*N <= C_C/2; fp16 input traffic of a
   tile is 2*(M*K + N*K) bytes (Sec. 6.2.2).
@@ -104,30 +105,32 @@ def path_throughputs(t_vec, t_mat, w_vec, w_tile, w_winrem, p_vec_dry, p_mat_dry
     return p_vec, p_mat
 
 
-def adapt_next(alpha, lo, hi, rounds, prev_alpha, prev_star, p_vec, p_mat, eps=0.05, r=1.0,
-               max_rounds=7):
+def adapt_next(alpha, lo, hi, rounds, prev_alpha, prev_star, capped, p_vec, p_mat, eps=0.05,
+               r=1.0, max_rounds=7):
     """One epoch of the adaptive re-partition.  (lo, hi) bracket the
     threshold (0 = open); (prev_alpha, prev_star) is the previous epoch's
-    threshold and measured crossover (0 = none).  Returns (next alpha, lo,
-    hi, rounds, alpha*, skew, replan).
+    threshold and measured crossover (0 = none); capped is +1 / -1 when the
+    previous step was cut at the bracket midpoint going up / down, else 0.
+    Returns (next alpha, lo, hi, rounds, alpha*, skew, replan, capped).
 
     The next threshold is the secant estimate of where the measured
     crossover meets the threshold (in logarithms, from this epoch and the
     previous one) when it lies strictly inside the updated bracket, on
     alpha*'s side of alpha and at most twice as far (in logarithms) as
     alpha*; else alpha* itself, but never more than the geometric midpoint
-    towards a known bracket end."""
+    towards a known bracket end -- unless the previous step was cut the same
+    way, in which case that bracket end is dropped (two newer measurements
+    outvote the one that set it) and the step goes to alpha*."""
     a_star = min(1.0, alpha_closed_form(p_vec, p_mat, r))
     s = skew(alpha, a_star)
     if s <= 1.0 + eps or rounds >= max_rounds:
-        return alpha, lo, hi, rounds, a_star, s, False
+        return alpha, lo, hi, rounds, a_star, s, False, capped
     raise_it = a_star > alpha
     # bracket: the threshold must rise above alpha, or fall below it
     if raise_it:
         lo = alpha
     else:
         hi = alpha
-    nxt = None
     if prev_alpha > 0 and prev_star > 0 and prev_alpha != alpha:
         f = math.log(a_star / alpha)
         f_prev = math.log(prev_star / prev_alpha)
@@ -137,14 +140,19 @@ def adapt_next(alpha, lo, hi, rounds, prev_alpha, prev_star, p_vec, p_mat, eps=0
             d = x - math.log(alpha)
             inside = (lo <= 0 or cand > lo) and (hi <= 0 or cand < hi)
             if inside and d * f > 0 and abs(d) <= 2.0 * abs(f):
-                nxt = cand
-    if nxt is None:
-        if raise_it:
-            # the tiles at the threshold cost more on the matrix path: move
-            # the sparser tiles to the vector path
-            nxt = a_star if hi <= 0 else min(a_star, math.sqrt(alpha * hi))
-        else:
-            # rows just below the threshold cost more on the vector path:
-            # pack them into tiles
-            nxt = a_star if lo <= 0 else max(a_star, math.sqrt(alpha * lo))
-    return nxt, lo, hi, rounds + 1, a_star, s, True
+                return cand, lo, hi, rounds + 1, a_star, s, True, 0
+    if raise_it:
+        # the tiles at the threshold cost more on the matrix path: move the
+        # sparser tiles to the vector path
+        if hi > 0 and a_star >= math.sqrt(alpha * hi):
+            if capped == 1:
+                return a_star, lo, 0.0, rounds + 1, a_star, s, True, 0
+            return math.sqrt(alpha * hi), lo, hi, rounds + 1, a_star, s, True, 1
+    else:
+        # rows just below the threshold cost more on the vector path: pack
+        # them into tiles
+        if lo > 0 and a_star <= math.sqrt(alpha * lo):
+            if capped == -1:
+                return a_star, 0.0, hi, rounds + 1, a_star, s, True, 0
+            return math.sqrt(alpha * lo), lo, hi, rounds + 1, a_star, s, True, -1
+    return a_star, lo, hi, rounds + 1, a_star, s, True, 0

@@ -74,7 +74,7 @@ class TuneReport(C.Structure):
 class AdaptState(C.Structure):
     _fields_ = [("alpha", C.c_double), ("alpha_star", C.c_double), ("lo", C.c_double),
                 ("hi", C.c_double), ("rounds", C.c_int32), ("converged", C.c_int32),
-                ("replanned", C.c_int32), ("reserved", C.c_int32), ("skew", C.c_double),
+                ("replanned", C.c_int32), ("capped", C.c_int32), ("skew", C.c_double),
                 ("p_vec", C.c_double), ("p_mfma", C.c_double), ("t_vec_ms", C.c_double),
                 ("t_mfma_ms", C.c_double), ("prev_alpha", C.c_double),
                 ("prev_alpha_star", C.c_double)]

@@ -403,14 +403,27 @@ extern "C" spmm_status spmm_adapt_next(spmm_adapt_state *st, double t_vec_ms, do
             const double cand = std::exp(x), d = x - std::log(a);
             const bool inside = (st->lo <= 0 || cand > st->lo) && (st->hi <= 0 || cand < st->hi);
             // on alpha*'s side, at most twice its distance: no wild extrapolation
-            if (inside && d * f > 0 && std::fabs(d) <= 2.0 * std::fabs(f)) next = cand;
+            if (inside && d * f > 0 && std::fabs(d) <= 2.0 * std::fabs(f)) {
+                next = cand;
+                st->capped = 0;
+            }
         }
     }
     if (next < 0) {
-        if (raise)  // tiles at the threshold cost more on the matrix path: sparser tiles to vector
-            next = st->hi <= 0 ? as : std::min(as, std::sqrt(a * st->hi));
-        else  // rows just below the threshold cost more on the vector path: pack them into tiles
-            next = st->lo <= 0 ? as : std::max(as, std::sqrt(a * st->lo));
+        next = as;
+        int capped = 0;
+        if (raise) {  // tiles at the threshold cost more on the matrix path: sparser tiles to vector
+            if (st->hi > 0 && as >= std::sqrt(a * st->hi)) {
+                if (st->capped == 1) st->hi = 0;  // a second cut step: drop that bracket end
+                else { next = std::sqrt(a * st->hi); capped = 1; }
+            }
+        } else {  // rows just below the threshold cost more on the vector path: pack them into tiles
+            if (st->lo > 0 && as <= std::sqrt(a * st->lo)) {
+                if (st->capped == -1) st->lo = 0;
+                else { next = std::sqrt(a * st->lo); capped = -1; }
+            }
+        }
+        st->capped = capped;
     }
     st->prev_alpha = a;
     st->prev_alpha_star = as;

@@ -363,10 +363,10 @@ def test_adapt_next_matches_reference(lib):
         at = float(np.exp(rng.uniform(np.log(0.01), np.log(0.8))))
         st = api.adapt_state(a0)
         lo = hi = pa = ps = 0.0
-        rounds = 0
+        rounds = capped = 0
         for _ in range(9):
             alpha = st.alpha
-            a_meas = min(1.0, at * (at / alpha) ** g)
+            a_meas = min(1.0, at * (at / alpha) ** g * float(np.exp(rng.uniform(-0.05, 0.05))))
             # epoch times that measure P_vec = a_meas, P_mat = 1 (per second)
             t_vec, t_mat, wr = 2.0, 3.0, 0.5e-3 * a_meas
             w_vec = a_meas * t_vec * 1e-3
@@ -374,8 +374,8 @@ def test_adapt_next_matches_reference(lib):
             api.adapt_next(st, t_vec, t_mat, w_vec, w_tile, wr, 0.0, 0.0, 0.05)
             p_vec, p_mat = cm.path_throughputs(t_vec * 1e-3, t_mat * 1e-3, w_vec, w_tile, wr,
                                                0.0, 0.0)
-            nxt, lo, hi, rounds, a_s, s, replan = cm.adapt_next(alpha, lo, hi, rounds, pa, ps,
-                                                                p_vec, p_mat, 0.05)
+            nxt, lo, hi, rounds, a_s, s, replan, capped = cm.adapt_next(
+                alpha, lo, hi, rounds, pa, ps, capped, p_vec, p_mat, 0.05)
             assert st.alpha_star == pytest.approx(a_s, rel=1e-12)
             assert st.skew == pytest.approx(s, rel=1e-12)
             assert bool(st.replanned) == replan
@@ -383,7 +383,7 @@ def test_adapt_next_matches_reference(lib):
                 assert st.converged == int(s <= 1.05)
                 break
             assert st.alpha == pytest.approx(nxt, rel=1e-12)
-            assert (st.lo, st.hi, st.rounds) == (lo, hi, rounds)
+            assert (st.lo, st.hi, st.rounds, st.capped) == (lo, hi, rounds, capped)
             pa, ps = alpha, a_s
         assert st.converged
 

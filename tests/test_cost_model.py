@@ -112,12 +112,13 @@ def _plant(alpha, a_true, gamma):
 
 
 def _run_ref(a0, a_true, gamma, eps=0.05, max_epochs=9):
-    alpha, lo, hi, rounds, pa, ps = a0, 0.0, 0.0, 0, 0.0, 0.0
+    alpha, lo, hi, rounds, pa, ps, capped = a0, 0.0, 0.0, 0, 0.0, 0.0, 0
     trace = []
     for _ in range(max_epochs):
         a_star = _plant(alpha, a_true, gamma)
-        nxt, lo, hi, rounds2, a_s, s, replan = cm.adapt_next(alpha, lo, hi, rounds, pa, ps,
-                                                             a_star, 1.0, eps)
+        nxt, lo, hi, rounds2, a_s, s, replan, capped = cm.adapt_next(alpha, lo, hi, rounds, pa,
+                                                                     ps, capped, a_star, 1.0,
+                                                                     eps)
         trace.append((alpha, a_s, s, replan, lo, hi))
         if not replan:
             break
@@ -128,23 +129,23 @@ def _run_ref(a0, a_true, gamma, eps=0.05, max_epochs=9):
 
 def test_adapt_fixed_point_trigger_and_direction():
     # alpha = alpha*: Eq. 6 skew 1, nothing moves
-    nxt, lo, hi, rounds, a_s, s, replan = cm.adapt_next(0.2, 0, 0, 0, 0, 0, 2.0, 10.0)
+    nxt, lo, hi, rounds, a_s, s, replan, _ = cm.adapt_next(0.2, 0, 0, 0, 0, 0, 0, 2.0, 10.0)
     assert a_s == pytest.approx(0.2) and s == pytest.approx(1.0) and not replan
     # the trigger is Eq. 6's: Skew > 1 + eps
     for ratio in (1.04, 1.0499, 1.0501, 1.2, 1 / 1.2, 1 / 1.0501):
         a_star = 0.1 * ratio
-        out = cm.adapt_next(0.1, 0, 0, 0, 0, 0, a_star, 1.0)
+        out = cm.adapt_next(0.1, 0, 0, 0, 0, 0, 0, a_star, 1.0)
         assert out[6] == cm.should_migrate(0.1, a_star)
     # direction: alpha* above -> threshold rises, lower bracket end set
-    nxt, lo, hi, *_ = cm.adapt_next(0.05, 0, 0, 0, 0, 0, 0.3, 1.0)
+    nxt, lo, hi, *_ = cm.adapt_next(0.05, 0, 0, 0, 0, 0, 0, 0.3, 1.0)
     assert nxt == pytest.approx(0.3) and lo == 0.05 and hi == 0
-    nxt, lo, hi, *_ = cm.adapt_next(0.5, 0, 0, 0, 0, 0, 0.1, 1.0)
+    nxt, lo, hi, *_ = cm.adapt_next(0.5, 0, 0, 0, 0, 0, 0, 0.1, 1.0)
     assert nxt == pytest.approx(0.1) and hi == 0.5 and lo == 0
     # never past the geometric midpoint towards a known bracket end
-    nxt, lo, hi, *_ = cm.adapt_next(0.05, 0.0, 0.2, 1, 0, 0, 0.9, 1.0)
+    nxt, lo, hi, *_ = cm.adapt_next(0.05, 0.0, 0.2, 1, 0, 0, 0, 0.9, 1.0)
     assert nxt == pytest.approx((0.05 * 0.2) ** 0.5)
     # at most 7 re-partitions
-    assert not cm.adapt_next(0.05, 0, 0, 7, 0, 0, 0.9, 1.0)[6]
+    assert not cm.adapt_next(0.05, 0, 0, 7, 0, 0, 0, 0.9, 1.0)[6]
 
 
 def test_adapt_balance_at_the_crossover():
@@ -155,7 +156,7 @@ def test_adapt_balance_at_the_crossover():
         pv, pm = rng.uniform(1, 100, size=2)
         if pv >= pm:
             continue
-        a = cm.adapt_next(0.5, 0, 0, 0, 0, 0, pv, pm)[4]
+        a = cm.adapt_next(0.5, 0, 0, 0, 0, 0, 0, pv, pm)[4]
         m, k = 16, 32
         assert cm.cost_vec(a * m * k, pv) == pytest.approx(cm.cost_mat(m, k, pm), rel=1e-12)
 
@@ -187,11 +188,37 @@ def test_path_throughputs():
 def test_adapt_secant_never_extrapolates_wildly():
     # two epochs whose crossovers barely differ put the secant root far away
     # (about 4e-6 here); the step falls back to alpha* itself
-    nxt, lo, hi, rounds, a_s, s, replan = cm.adapt_next(0.2596, 0.0, 0.9, 1, 0.9, 0.2596,
-                                                        0.085, 1.0)
+    nxt, lo, hi, rounds, a_s, s, replan, _ = cm.adapt_next(0.2596, 0.0, 0.9, 1, 0.9, 0.2596, 0,
+                                                           0.085, 1.0)
     assert replan and nxt == pytest.approx(0.085) and hi == 0.2596
     # a secant root on alpha*'s side within twice its distance is taken: on a
     # log-linear device (crossover 0.1 * (0.1 / alpha) ** 0.5) it is exact
     plant = lambda a: 0.1 * (0.1 / a) ** 0.5
-    nxt, lo, hi, *_ = cm.adapt_next(0.2, 0.0, 0.4, 1, 0.4, plant(0.4), plant(0.2), 1.0)
+    nxt, lo, hi, *_ = cm.adapt_next(0.2, 0.0, 0.4, 1, 0.4, plant(0.4), 0, plant(0.2), 1.0)
     assert nxt == pytest.approx(0.1, rel=1e-12) and hi == 0.2
+
+
+def test_adapt_drops_a_contradicted_bracket_end():
+    # an early outlier set lo = 0.12; later epochs keep measuring 0.10 below it
+    nxt, lo, hi, _, _, _, replan, capped = cm.adapt_next(0.15, 0.12, 0.2, 2, 0, 0, 0, 0.10, 1.0)
+    assert replan and nxt == pytest.approx((0.15 * 0.12) ** 0.5) and capped == -1
+    nxt, lo, hi, _, _, _, replan, capped = cm.adapt_next(nxt, lo, hi, 3, 0, 0, capped, 0.10, 1.0)
+    assert replan and nxt == pytest.approx(0.10) and lo == 0.0 and capped == 0
+
+
+@pytest.mark.parametrize("outlier", [1.6, 0.6])
+def test_adapt_converges_after_an_outlier(outlier):
+    rng = np.random.default_rng(5)
+    for _ in range(100):
+        g = rng.uniform(0, 2)
+        a0 = float(np.exp(rng.uniform(np.log(0.002), 0)))
+        at = float(np.exp(rng.uniform(np.log(0.01), np.log(0.8))))
+        alpha, lo, hi, rounds, pa, ps, capped = a0, 0.0, 0.0, 0, 0.0, 0.0, 0
+        for epoch in range(9):
+            a_star = _plant(alpha, at, g) * (outlier if epoch == 1 else 1.0)
+            nxt, lo, hi, rounds, a_s, s, replan, capped = cm.adapt_next(
+                alpha, lo, hi, rounds, pa, ps, capped, min(a_star, 1.0), 1.0)
+            if not replan:
+                break
+            pa, ps, alpha = alpha, a_s, nxt
+        assert s <= 1.05 and rounds <= 7
