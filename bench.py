@@ -46,6 +46,9 @@ def workload(name):
     if name == "block":
         A, B = synth.block_community()
         return A, B, "bf16", "block_community_262144_n256_bf16"
+    if name == "block_shuffled":
+        A, B = synth.block_community()
+        return synth.permute_rows(A, 9), B, "bf16", "block_community_262144_n256_bf16_rows_shuffled"
     if name == "uniform":
         A, B = synth.uniform_rows()
         return A, B, "f32", "uniform_4096_16perrow_n32"
@@ -291,6 +294,8 @@ def main():
             kw.update(row_order="length_sorted", t_row=16)
         if mode == "mixed" and args.workload == "block":
             kw.update(row_order="original_ranges")
+        if mode == "mixed" and args.workload == "block_shuffled":
+            kw.update(row_order="compacted")
         kw.update(extra)
         t0 = time.perf_counter()
         plan = api.Plan(A, n, b_kind, api.default_opts(**kw))
@@ -370,7 +375,8 @@ def main():
         "modes": {k: {"ms_per_step": round(v["ms"], 5),
                       "gflops": round(2.0 * A.nnz * n / (v["ms"] * 1e-3) / 1e9, 1),
                       "kernels_ms": {a: round(b, 5) for a, b in v["kavg"].items()},
-                      "nnz_tiles_frac": round(v["stats"]["nnz_tiles"] / max(1, A.nnz), 4)}
+                      "nnz_tiles_frac": round(v["stats"]["nnz_tiles"] / max(1, A.nnz), 4),
+                      "mean_tile_density": round(v["stats"]["mean_tile_density"], 4)}
                   for k, v in results.items()},
     }
     for k, v in results.items():

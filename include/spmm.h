@@ -109,6 +109,14 @@ typedef struct {
     int32_t win_sched; /* launch order of windows: 0 = by window id (neighbouring windows, which
                           tend to gather the same B rows, run together on one XCD); 1 = heaviest
                           first (LPT, Sec. 6.3); < 0: auto */
+    int32_t local_reorder; /* Sec. 6.1 local reordering: > 0 = rows per cluster (rounded up to a
+                              multiple of H) of the compacted or length-sorted row list, inside
+                              which windows are rebuilt: the longest unassigned row of each
+                              current window becomes an anchor and takes the H-1 unassigned rows
+                              of the cluster most similar to it (Jaccard over distinct column
+                              sets, ties: earlier row in the list), leftover rows form windows in
+                              list order; 0 = off; < 0: auto (off).  UNSUPPORTED with the
+                              original-ranges order. */
 } spmm_opts;
 
 typedef struct spmm_plan_s spmm_plan_t;

@@ -31,11 +31,22 @@ rows failing the row stage leave holes), ``compacted`` (rows passing the row
 stage, in their original order) and ``length_sorted`` (by Len descending,
 ties by row id), the last being the degree-grouping the local reordering of
 Sec. 6.1 starts from.
+
+Local reordering (Sec. 6.1, ``local_reorder`` = rows per cluster, rounded up
+to a multiple of H): the row list is cut into clusters of consecutive rows;
+inside a cluster the current windows are visited in order, one
+representative row of each -- read as its longest unassigned row, ties to the
+earlier one -- becomes an anchor, and the anchor takes the H-1 unassigned
+rows of the cluster most similar to it by Jaccard similarity of their
+distinct column sets (ties to the earlier row; an empty union counts as 0).
+Rows left unassigned after all windows were visited form windows in list
+order.
 """
 from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
+from fractions import Fraction
 
 import numpy as np
 
@@ -96,10 +107,45 @@ class PlanRef:
     stats: dict = field(default_factory=dict)
 
 
+def jaccard(a: set, b: set) -> Fraction:
+    """|a & b| / |a | b| as an exact fraction (0 when both are empty)."""
+    union = len(a | b)
+    return Fraction(len(a & b), union) if union else Fraction(0)
+
+
+def local_reorder(D, H, cluster_rows, rowptr, colidx):
+    """Windows (lists of H slots, -1 padded) of the rows in D after the local
+    reordering of Sec. 6.1 (see the module docstring)."""
+    out = []
+    for c0 in range(0, len(D), cluster_rows):
+        cluster = list(D[c0:c0 + cluster_rows])
+        colsets = [set(int(c) for c in colidx[rowptr[r]:rowptr[r + 1]]) for r in cluster]
+        length = [int(rowptr[r + 1] - rowptr[r]) for r in cluster]
+        unassigned = set(range(len(cluster)))
+        for w0 in range(0, len(cluster), H):
+            members = [i for i in range(w0, min(w0 + H, len(cluster))) if i in unassigned]
+            if not members:
+                continue
+            anchor = min(members, key=lambda i: (-length[i], i))
+            unassigned.discard(anchor)
+            ranked = sorted(unassigned, key=lambda i: (-jaccard(colsets[anchor], colsets[i]), i))
+            picked = ranked[:H - 1]
+            for i in picked:
+                unassigned.discard(i)
+            window = [cluster[anchor]] + [cluster[i] for i in picked]
+            out.append(window + [-1] * (H - len(window)))
+        rest = [cluster[i] for i in sorted(unassigned)]
+        for w in range(0, len(rest), H):
+            chunk = rest[w:w + H]
+            out.append(chunk + [-1] * (H - len(chunk)))
+    return out
+
+
 def build_plan(rowptr, colidx, vals, *, k: int, mode: int, window_h: int = 16, t_row: int = 0,
                alpha_c: float = 1.0 / 16, alpha: float = 0.0, kt: int = 32,
                row_order: int = ORDER_LENGTH_SORTED, seg: int = 256,
-               tile_kind: str = "bf16", val_kind: str = "f32") -> PlanRef:
+               tile_kind: str = "bf16", val_kind: str = "f32",
+               local_reorder_rows: int = 0) -> PlanRef:
     """Build the partition of A for the given options (see module docstring).
 
     ``vals`` holds the stored values: float32, or uint16 bit patterns for
@@ -130,9 +176,13 @@ def build_plan(rowptr, colidx, vals, *, k: int, mode: int, window_h: int = 16, t
                 D.sort(key=lambda r: (-int(lens[r]), r))
             elif row_order != ORDER_COMPACTED:
                 raise ValueError("unknown row order")
-            for w in range(0, len(D), H):
-                chunk = D[w:w + H]
-                windows.append(chunk + [-1] * (H - len(chunk)))
+            if local_reorder_rows > 0:
+                crows = (local_reorder_rows + H - 1) // H * H
+                windows = local_reorder(D, H, crows, rowptr, colidx)
+            else:
+                for w in range(0, len(D), H):
+                    chunk = D[w:w + H]
+                    windows.append(chunk + [-1] * (H - len(chunk)))
 
     # ---- column stage, K-tiles, density test, packing -----------------------
     col_thr = math.floor(float(np.float32(alpha_c)) * H)

@@ -31,7 +31,7 @@ class Opts(C.Structure):
                 ("seg_len", C.c_int32), ("item_cost", C.c_int32), ("xcd_remap", C.c_int32),
                 ("hot_cols", C.c_int32), ("alpha_c", C.c_float), ("alpha", C.c_float),
                 ("cold_policy", C.c_int32), ("pipeline", C.c_int32),
-                ("win_sched", C.c_int32)]
+                ("win_sched", C.c_int32), ("local_reorder", C.c_int32)]
 
 
 class PlanStats(C.Structure):

@@ -36,23 +36,23 @@ std::map<std::pair<int32_t, int32_t>, std::pair<double, double>> g_dryrun;  // (
 
 std::string opts_to_text(const spmm_opts &o) {
     char buf[256];
-    std::snprintf(buf, sizeof buf, "%d %d %d %d %d %d %d %d %d %d %.9g %.9g %d %d %d", o.mode,
+    std::snprintf(buf, sizeof buf, "%d %d %d %d %d %d %d %d %d %d %.9g %.9g %d %d %d %d", o.mode,
                   o.window_h, o.t_row, o.kt, o.n_panel, o.row_order, o.seg_len, o.item_cost,
                   o.xcd_remap, o.hot_cols, (double)o.alpha_c, (double)o.alpha, o.cold_policy,
-                  o.pipeline, o.win_sched);
+                  o.pipeline, o.win_sched, o.local_reorder);
     return buf;
 }
 
 bool opts_from_text(const std::string &t, spmm_opts *o) {
     spmm_opts_default(o);
     double ac = 0, al = 0;
-    int n = std::sscanf(t.c_str(), "%d %d %d %d %d %d %d %d %d %d %lg %lg %d %d %d", &o->mode,
+    int n = std::sscanf(t.c_str(), "%d %d %d %d %d %d %d %d %d %d %lg %lg %d %d %d %d", &o->mode,
                         &o->window_h, &o->t_row, &o->kt, &o->n_panel, &o->row_order, &o->seg_len,
                         &o->item_cost, &o->xcd_remap, &o->hot_cols, &ac, &al, &o->cold_policy,
-                        &o->pipeline, &o->win_sched);
+                        &o->pipeline, &o->win_sched, &o->local_reorder);
     o->alpha_c = (float)ac;
     o->alpha = (float)al;
-    return n == 15;
+    return n == 16;
 }
 
 int ilog2_floor(int64_t x) {

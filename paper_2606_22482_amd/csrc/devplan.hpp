@@ -63,13 +63,15 @@ struct RunArgs {
 struct BatchEntry {
     DevPlan P;
     RunArgs a;
-    int32_t seg_end, vec_end, win_end, wpart_end;
+    int32_t seg_end, vec_end, win_end, wpart_end;      // exclusive prefix over the table
+    int32_t seg_base, vec_base, win_base, wpart_base;  // matrix item index of the first item
 };
 
-// Entries are grouped by the XCD they are assigned to; x_* hold, per XCD x,
-// the first entry and the first item of each kind (exclusive prefix sums, 9
-// values each).  Workgroup b of a persistent kernel runs on XCD b % 8 and walks
-// only its XCD's items, so one XCD's L2 serves one matrix's B at a time.
+// An entry is a contiguous range of one matrix's items of each kind, either
+// the whole matrix or one of 8 chunks of it.  Entries are grouped by the XCD
+// they are assigned to; x_* hold, per XCD x, the first entry and the first
+// item of each kind (exclusive prefix sums, 9 values each).  Workgroup b of a
+// persistent kernel runs on XCD b % 8 and walks only its XCD's items.
 struct BatchHeader {
     int32_t count, total_seg, total_vec, total_win, total_wpart, pad[3];
     int32_t x_entry[9], x_seg[9], x_vec[9], x_win[9], x_wpart[9];

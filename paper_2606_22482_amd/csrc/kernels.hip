@@ -1108,15 +1108,16 @@ __global__ __launch_bounds__(256) void window_partial_kernel(DevPlan P, RunArgs 
 
 // Persistent walk over one XCD's items of one kind: item ids g of XCD x are
 // [xb[x], xb[x+1]); entries of XCD x start at x_entry[x]; `end` gives an
-// entry's exclusive item prefix (global over the table).
-#define SPMM_XCD_WALK(XB, END, PER_WG, BODY)                                           \
+// entry's exclusive item prefix (global over the table), `base` the matrix
+// item index of its first item.
+#define SPMM_XCD_WALK(XB, END, BASE, PER_WG, BODY)                                     \
     do {                                                                               \
         const int x = blockIdx.x & 7, local = blockIdx.x >> 3, nloc = gridDim.x >> 3;   \
         const int lo = hdr->XB[x], hi = hdr->XB[x + 1];                                \
         int d = hdr->x_entry[x];                                                       \
         for (int g = lo + local * PER_WG + sub; g < hi; g += nloc * PER_WG) {          \
             while (g >= tab[d].END) ++d;                                               \
-            const int item = g - (d ? tab[d - 1].END : 0);                             \
+            const int item = g - (d ? tab[d - 1].END : 0) + tab[d].BASE;               \
             BODY;                                                                      \
         }                                                                              \
     } while (0)
@@ -1125,14 +1126,14 @@ template <int VT, int BT, int E, int CPL>
 __global__ __launch_bounds__(256) void batch_segment_kernel(const BatchHeader *__restrict__ hdr,
                                                             const BatchEntry *__restrict__ tab) {
     const int sub = threadIdx.x >> 6;
-    SPMM_XCD_WALK(x_seg, seg_end, 4, (segment_item<VT, BT, E, CPL>(tab[d].P, tab[d].a, item)));
+    SPMM_XCD_WALK(x_seg, seg_end, seg_base, 4, (segment_item<VT, BT, E, CPL>(tab[d].P, tab[d].a, item)));
 }
 
 template <int VT, int BT, int E, int CPL, int VAR>
 __global__ __launch_bounds__(256) void batch_vector_kernel(const BatchHeader *__restrict__ hdr,
                                                            const BatchEntry *__restrict__ tab) {
     const int sub = threadIdx.x >> 6;
-    SPMM_XCD_WALK(x_vec, vec_end, 4, (vector_item_var<VT, BT, E, CPL, VAR>(tab[d].P, tab[d].a, item)));
+    SPMM_XCD_WALK(x_vec, vec_end, vec_base, 4, (vector_item_var<VT, BT, E, CPL, VAR>(tab[d].P, tab[d].a, item)));
 }
 
 template <int VT, int BT, int TT, int E, int CPL, int MB>
@@ -1148,12 +1149,12 @@ __global__ __launch_bounds__(256) void batch_window_kernel(const BatchHeader *__
     __shared__ WinSmem<4> sm;
     const int sub = 0;
     if (PARTIAL) {
-        SPMM_XCD_WALK(x_wpart, wpart_end, 1,
+        SPMM_XCD_WALK(x_wpart, wpart_end, wpart_base, 1,
                       (tab[d].P.H == 16 ? window_item_h<VT, BT, TT, E, CPL, 1>(tab[d], item, sm, true)
                        : tab[d].P.H == 32 ? window_item_h<VT, BT, TT, E, CPL, 2>(tab[d], item, sm, true)
                                           : window_item_h<VT, BT, TT, E, CPL, 4>(tab[d], item, sm, true)));
     } else {
-        SPMM_XCD_WALK(x_win, win_end, 1,
+        SPMM_XCD_WALK(x_win, win_end, win_base, 1,
                       (tab[d].P.H == 16 ? window_item_h<VT, BT, TT, E, CPL, 1>(tab[d], item, sm, false)
                        : tab[d].P.H == 32 ? window_item_h<VT, BT, TT, E, CPL, 2>(tab[d], item, sm, false)
                                           : window_item_h<VT, BT, TT, E, CPL, 4>(tab[d], item, sm, false)));

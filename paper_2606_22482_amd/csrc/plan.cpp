@@ -40,6 +40,7 @@ extern "C" void spmm_opts_default(spmm_opts *o) {
     o->cold_policy = -1;
     o->pipeline = -1;
     o->win_sched = -1;
+    o->local_reorder = -1;
     o->alpha_c = -1.0f;
     o->alpha = -1.0f;
 }
@@ -68,11 +69,11 @@ void resolve_options(const spmm_opts *in, const spmm_csr *A, int32_t n, int32_t 
     if (d.seg_len <= 0) d.seg_len = 256;
     if (d.item_cost <= 0) {
         double total = (double)(A ? A->nnz : 0) + (double)kRowCost * (double)(A ? A->m : 0);
-        // about 512 entries per item for small and medium matrices (whole lane
-        // groups of packed short rows), total/32768 for large ones, so that a
-        // large matrix still gives tens of thousands of items
-        double c = std::max(total / 32768.0, std::min(512.0, total / 512.0));
-        d.item_cost = (int32_t)std::min(2048.0, std::max(32.0, c));
+        // about 2048 items per matrix, so that a matrix run alone (or in a
+        // small batch) still fills the device, with items of 32 to 512
+        // entries (measured on gfx950: larger items lose on the GNN graph and
+        // on the uneven batch, smaller ones lose on both as well)
+        d.item_cost = (int32_t)std::min(512.0, std::max(32.0, total / 2048.0));
     }
     if (d.xcd_remap < 0) d.xcd_remap = 1;
     // Measured on gfx950: streaming (non-temporal) gathers of cold rows raise the
@@ -97,6 +98,7 @@ void resolve_options(const spmm_opts *in, const spmm_csr *A, int32_t n, int32_t 
         d.pipeline = (b_type != SPMM_F32 && chunks <= 16) ? 3 : 2;
     }
     if (d.win_sched < 0) d.win_sched = 0;  // window id order: B rows reused in L2
+    if (d.local_reorder < 0) d.local_reorder = 0;
     if (!(d.alpha_c >= 0.0f)) d.alpha_c = 1.0f / (float)d.window_h;
     if (!(d.alpha >= 0.0f)) d.alpha = 1.0f / (float)d.window_h;
     if (d.mode == SPMM_MODE_MFMA_ONLY) {
@@ -144,6 +146,87 @@ spmm_status validate_problem(const spmm_csr *A, int32_t n, int32_t b_type, int32
     return SPMM_OK;
 }
 
+// Sec. 6.1 local reordering.  D is cut into clusters of crows consecutive
+// rows; inside a cluster the current windows (groups of H in D's order) are
+// visited in order, and the longest unassigned row of each (ties: earlier)
+// becomes an anchor that takes the H-1 unassigned rows of the cluster with
+// the highest Jaccard similarity of distinct column sets (compared exactly as
+// fractions; ties: earlier in D; an empty union counts as 0).  The rows left
+// when every window has been visited form windows in D's order.
+static void local_reorder(const std::vector<int32_t> &D, int H, int64_t crows,
+                          const int64_t *rowptr, const int32_t *colidx,
+                          const std::vector<int64_t> &len, int64_t k,
+                          std::vector<std::vector<int32_t>> &out) {
+    std::vector<int64_t> stamp(std::max<int64_t>(k, 1), 0);
+    int64_t now = 0;
+    struct Cand {
+        int64_t inter, uni;
+        int32_t pos;
+    };
+    auto better = [](const Cand &a, const Cand &b) {
+        const int64_t l = a.inter * b.uni, r = b.inter * a.uni;
+        return l != r ? l > r : a.pos < b.pos;
+    };
+    const int64_t nD = (int64_t)D.size();
+    for (int64_t c0 = 0; c0 < nD; c0 += crows) {
+        const int32_t n = (int32_t)std::min(crows, nD - c0);
+        // distinct columns of each row of the cluster
+        std::vector<int64_t> cptr(n + 1, 0);
+        std::vector<int32_t> cols;
+        for (int32_t i = 0; i < n; ++i) {
+            const int32_t r = D[c0 + i];
+            const size_t b = cols.size();
+            cols.insert(cols.end(), colidx + rowptr[r], colidx + rowptr[r + 1]);
+            std::sort(cols.begin() + b, cols.end());
+            cols.erase(std::unique(cols.begin() + b, cols.end()), cols.end());
+            cptr[i + 1] = (int64_t)cols.size();
+        }
+        std::vector<uint8_t> used(n, 0);
+        std::vector<Cand> cs;
+        for (int32_t w0 = 0; w0 < n; w0 += H) {
+            int32_t a = -1;
+            for (int32_t i = w0; i < std::min(w0 + H, n); ++i)
+                if (!used[i] && (a < 0 || len[D[c0 + i]] > len[D[c0 + a]])) a = i;
+            if (a < 0) continue;
+            used[a] = 1;
+            ++now;
+            for (int64_t q = cptr[a]; q < cptr[a + 1]; ++q) stamp[cols[q]] = now;
+            const int64_t na = cptr[a + 1] - cptr[a];
+            cs.clear();
+            for (int32_t i = 0; i < n; ++i) {
+                if (used[i]) continue;
+                int64_t inter = 0;
+                for (int64_t q = cptr[i]; q < cptr[i + 1]; ++q) inter += stamp[cols[q]] == now;
+                int64_t uni = na + (cptr[i + 1] - cptr[i]) - inter;
+                if (uni == 0) { inter = 0; uni = 1; }
+                cs.push_back({inter, uni, i});
+            }
+            const size_t take = std::min<size_t>((size_t)(H - 1), cs.size());
+            std::partial_sort(cs.begin(), cs.begin() + take, cs.end(), better);
+            std::vector<int32_t> slots(H, -1);
+            slots[0] = D[c0 + a];
+            for (size_t j = 0; j < take; ++j) {
+                slots[j + 1] = D[c0 + cs[j].pos];
+                used[cs[j].pos] = 1;
+            }
+            out.push_back(std::move(slots));
+        }
+        std::vector<int32_t> slots;
+        for (int32_t i = 0; i < n; ++i) {
+            if (used[i]) continue;
+            slots.push_back(D[c0 + i]);
+            if ((int)slots.size() == H) {
+                out.push_back(slots);
+                slots.clear();
+            }
+        }
+        if (!slots.empty()) {
+            slots.resize(H, -1);
+            out.push_back(slots);
+        }
+    }
+}
+
 static spmm_status validate_opts(const spmm_opts &o, std::string &err) {
     if (o.mode < SPMM_MODE_PLAIN_F32 || o.mode > SPMM_MODE_MFMA_ONLY) { err = "mode"; return SPMM_ERR_UNSUPPORTED; }
     if (o.window_h != 16 && o.window_h != 32 && o.window_h != 64) { err = "window_h must be 16, 32 or 64"; return SPMM_ERR_UNSUPPORTED; }
@@ -155,6 +238,11 @@ static spmm_status validate_opts(const spmm_opts &o, std::string &err) {
     if (o.hot_cols < 0) { err = "hot_cols"; return SPMM_ERR_UNSUPPORTED; }
     if (o.pipeline < 0 || o.pipeline > 3) { err = "pipeline must be 0, 1, 2 or 3"; return SPMM_ERR_UNSUPPORTED; }
     if (o.win_sched < 0 || o.win_sched > 1) { err = "win_sched must be 0 or 1"; return SPMM_ERR_UNSUPPORTED; }
+    if (o.local_reorder < 0) { err = "local_reorder"; return SPMM_ERR_UNSUPPORTED; }
+    if (o.local_reorder > 0 && o.row_order == SPMM_ORDER_ORIGINAL_RANGES) {
+        err = "local_reorder needs the compacted or length-sorted row order";
+        return SPMM_ERR_UNSUPPORTED;
+    }
     if (o.cold_policy != 0 && o.cold_policy != 2 && o.cold_policy != 16 && o.cold_policy != 18) {
         err = "cold_policy must be 0, 2, 16 or 18";
         return SPMM_ERR_UNSUPPORTED;
@@ -212,10 +300,15 @@ spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_
             if (o.row_order == SPMM_ORDER_LENGTH_SORTED)
                 std::stable_sort(D.begin(), D.end(),
                                  [&](int32_t a, int32_t b) { return len[a] > len[b]; });
-            for (size_t w0 = 0; w0 < D.size(); w0 += H) {
-                std::vector<int32_t> slots(H, -1);
-                for (int s = 0; s < H && w0 + s < D.size(); ++s) slots[s] = D[w0 + s];
-                cand.push_back(std::move(slots));
+            if (o.local_reorder > 0) {
+                const int64_t crows = ((int64_t)o.local_reorder + H - 1) / H * H;
+                local_reorder(D, H, crows, rowptr, colidx, len, k, cand);
+            } else {
+                for (size_t w0 = 0; w0 < D.size(); w0 += H) {
+                    std::vector<int32_t> slots(H, -1);
+                    for (int s = 0; s < H && w0 + s < D.size(); ++s) slots[s] = D[w0 + s];
+                    cand.push_back(std::move(slots));
+                }
             }
         }
     }

@@ -151,8 +151,62 @@ extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *
         const std::vector<int32_t> &idx = kv.second;
         const int32_t vt = key & 0xF, bt = (key >> 4) & 0xF, tt = (key >> 8) & 0xF;
         const int vec_ok = (key >> 12) & 0xF, cpl = (key >> 16) & 0xF, var = (key >> 20) & 0xF;
+        // Work of each matrix (~ entries * N plus rows * N).  Whole matrices go
+        // to the 8 XCDs by longest processing time when that keeps the XCDs
+        // within 20% of an even share (each XCD's L2 then serves one matrix's
+        // B at a time); otherwise, as for a batch of a few matrices, each
+        // matrix's items of every kind are cut into 8 contiguous chunks, one
+        // per XCD, so that no XCD idles.
+        std::vector<int32_t> order(idx.size());
+        for (size_t j = 0; j < idx.size(); ++j) order[j] = (int32_t)j;
+        auto cost = [&](int32_t j) {
+            const spmm_plan_t *p = items[idx[j]].plan;
+            return ((double)p->hp.nnz + (double)p->hp.m) * (double)p->hp.n;
+        };
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t x, int32_t y) { return cost(x) > cost(y); });
+        std::vector<int32_t> xcd_of(idx.size(), 0);
+        double load[8] = {0, 0, 0, 0, 0, 0, 0, 0}, total = 0;
+        for (int32_t j : order) {
+            int best = 0;
+            for (int x = 1; x < 8; ++x)
+                if (load[x] < load[best]) best = x;
+            xcd_of[j] = best;
+            load[best] += cost(j);
+            total += cost(j);
+        }
+        const bool whole = *std::max_element(load, load + 8) <= 1.2 * total / 8.0;
+        struct Ent {
+            int32_t j;
+            int64_t base[4], cnt[4];
+        };
+        std::vector<Ent> ents;
+        int32_t x_first[9];
+        for (int x = 0; x < 8; ++x) {
+            x_first[x] = (int32_t)ents.size();
+            for (int32_t j : order) {
+                const spmm_plan_t *p = items[idx[j]].plan;
+                const RunArgs &a = args[idx[j]];
+                const int64_t n4[4] = {(int64_t)p->dp.n_seg * a.n_panels,
+                                       (int64_t)p->dp.n_vitems * a.n_panels,
+                                       (int64_t)p->dp.n_win * a.win_panels,
+                                       (int64_t)p->dp.n_wpart * a.win_panels};
+                Ent e{j, {0, 0, 0, 0}, {0, 0, 0, 0}};
+                if (whole) {
+                    if (xcd_of[j] != x) continue;
+                    for (int q = 0; q < 4; ++q) e.cnt[q] = n4[q];
+                } else {
+                    for (int q = 0; q < 4; ++q) {
+                        e.base[q] = n4[q] * x / 8;
+                        e.cnt[q] = n4[q] * (x + 1) / 8 - e.base[q];
+                    }
+                }
+                ents.push_back(e);
+            }
+        }
+        x_first[8] = (int32_t)ents.size();
         // host table
-        const size_t bytes = kHeaderBytes + idx.size() * sizeof(BatchEntry);
+        const size_t bytes = kHeaderBytes + std::max<size_t>(ents.size(), 1) * sizeof(BatchEntry);
         BatchCtx &c = ctx;
         const int slot = c.next;
         c.next = (c.next + 1) % BatchCtx::kSlots;
@@ -170,58 +224,35 @@ extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *
             SPMM_TRY_HIP(hipEventCreateWithFlags(&c.pinned_ev[slot], hipEventDisableTiming), "hipEventCreate");
         auto *hdr = static_cast<BatchHeader *>(c.pinned[slot]);
         auto *tab = reinterpret_cast<BatchEntry *>(static_cast<uint8_t *>(c.pinned[slot]) + kHeaderBytes);
-        // Longest-processing-time assignment of whole matrices to the 8 XCDs
-        // (cost ~ entries * N plus rows * N), entries then grouped by XCD.
-        std::vector<int32_t> order(idx.size());
-        for (size_t j = 0; j < idx.size(); ++j) order[j] = (int32_t)j;
-        auto cost = [&](int32_t j) {
-            const spmm_plan_t *p = items[idx[j]].plan;
-            return ((double)p->hp.nnz + (double)p->hp.m) * (double)p->hp.n;
-        };
-        std::stable_sort(order.begin(), order.end(),
-                         [&](int32_t x, int32_t y) { return cost(x) > cost(y); });
-        std::vector<int32_t> xcd_of(idx.size(), 0);
-        double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int32_t j : order) {
-            int best = 0;
-            for (int x = 1; x < 8; ++x)
-                if (load[x] < load[best]) best = x;
-            xcd_of[j] = best;
-            load[best] += cost(j);
-        }
-        std::vector<int32_t> seq;
-        seq.reserve(idx.size());
-        for (int x = 0; x < 8; ++x) {
-            hdr->x_entry[x] = (int32_t)seq.size();
-            for (int32_t j : order)
-                if (xcd_of[j] == x) seq.push_back(j);
-        }
-        hdr->x_entry[8] = (int32_t)seq.size();
         int64_t ns = 0, nv = 0, nw = 0, np_ = 0;
-        for (size_t jj = 0; jj < seq.size(); ++jj) {
-            const size_t j = (size_t)seq[jj];
+        for (int x = 0; x <= 8; ++x) hdr->x_entry[x] = x_first[x];
+        for (size_t jj = 0; jj < ents.size(); ++jj) {
+            const Ent &en = ents[jj];
             for (int x = 0; x < 8; ++x)
-                if (hdr->x_entry[x] == (int32_t)jj) {
+                if (x_first[x] == (int32_t)jj) {
                     hdr->x_seg[x] = (int32_t)ns;
                     hdr->x_vec[x] = (int32_t)nv;
                     hdr->x_win[x] = (int32_t)nw;
                     hdr->x_wpart[x] = (int32_t)np_;
                 }
-            const spmm_plan_t *p = items[idx[j]].plan;
-            const RunArgs &a = args[idx[j]];
+            const spmm_plan_t *p = items[idx[en.j]].plan;
             BatchEntry &e = tab[jj];
             e.P = p->dp;
-            e.a = a;
-            ns += (int64_t)p->dp.n_seg * a.n_panels;
-            nv += (int64_t)p->dp.n_vitems * a.n_panels;
-            nw += (int64_t)p->dp.n_win * a.win_panels;
-            np_ += (int64_t)p->dp.n_wpart * a.win_panels;
+            e.a = args[idx[en.j]];
+            ns += en.cnt[0];
+            nv += en.cnt[1];
+            nw += en.cnt[2];
+            np_ += en.cnt[3];
             if (ns > INT32_MAX || nv > INT32_MAX || nw > INT32_MAX || np_ > INT32_MAX)
                 return set_error(SPMM_ERR_UNSUPPORTED, "batch has more than 2^31 items");
             e.seg_end = (int32_t)ns;
             e.vec_end = (int32_t)nv;
             e.win_end = (int32_t)nw;
             e.wpart_end = (int32_t)np_;
+            e.seg_base = (int32_t)en.base[0];
+            e.vec_base = (int32_t)en.base[1];
+            e.win_base = (int32_t)en.base[2];
+            e.wpart_base = (int32_t)en.base[3];
         }
         // XCDs with no entry start where the next one does
         for (int x = 7; x >= 0; --x)
@@ -235,7 +266,7 @@ extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *
         hdr->x_vec[8] = (int32_t)nv;
         hdr->x_win[8] = (int32_t)nw;
         hdr->x_wpart[8] = (int32_t)np_;
-        hdr->count = (int32_t)idx.size();
+        hdr->count = (int32_t)ents.size();
         hdr->total_seg = (int32_t)ns;
         hdr->total_vec = (int32_t)nv;
         hdr->total_win = (int32_t)nw;

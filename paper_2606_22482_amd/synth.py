@@ -233,6 +233,19 @@ def block_community(n=262144, block=16, blocks_per_row=8, band=32, fill=0.3, off
 # --------------------------------------------------------------------------------------------
 # Batched uneven matrices.
 # --------------------------------------------------------------------------------------------
+def permute_rows(A: "CSR", seed: int) -> "CSR":
+    """A with its rows in a seeded random order (each row keeps its columns
+    and values): community structure that the row order no longer shows."""
+    (r,) = _rngs(seed, 1)
+    perm = r.permutation(A.m)
+    lens = np.diff(A.rowptr)[perm]
+    rowptr = np.zeros(A.m + 1, dtype=np.int64)
+    np.cumsum(lens, out=rowptr[1:])
+    idx = np.concatenate([np.arange(A.rowptr[q], A.rowptr[q + 1]) for q in perm]) \
+        if A.nnz else np.zeros(0, dtype=np.int64)
+    return CSR(A.m, A.k, rowptr, A.colidx[idx], A.vals[idx], A.val_kind)
+
+
 def batch_specs(count=512, seed=4, rows_lo=1000, rows_hi=200000):
     """Per-matrix (rows, mean degree, wmax, N) for the batched workload."""
     (r,) = _rngs(seed, 1)

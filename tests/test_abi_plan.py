@@ -76,6 +76,10 @@ def test_validation_codes(lib):
     assert _status(lib, A, opts=api.default_opts(window_h=24)) == L.SPMM_ERR_UNSUPPORTED
     assert _status(lib, A, opts=api.default_opts(kt=16)) == L.SPMM_ERR_UNSUPPORTED
     assert _status(lib, A, opts=api.default_opts(win_sched=2)) == L.SPMM_ERR_UNSUPPORTED
+    assert _status(lib, A, opts=api.default_opts(mode="mixed", row_order="original_ranges",
+                                                  local_reorder=32)) == L.SPMM_ERR_UNSUPPORTED
+    assert _status(lib, A, opts=api.default_opts(mode="mixed", row_order="compacted",
+                                                  local_reorder=32)) == L.SPMM_OK
     assert _status(lib, A, opts=api.default_opts(alpha=float("nan"), mode="mixed")) in (
         L.SPMM_OK, L.SPMM_ERR_UNSUPPORTED)
     h = C.c_void_p()
@@ -173,6 +177,13 @@ CASES = [
     ("random", "f32", "f32", dict(mode="mixed", t_row=-1, alpha_c=0.0, alpha=1.5, seg_len=6)),
     ("block", "f32", "bf16", dict(mode="mixed", window_h=16, t_row=1, alpha_c=1 / 16,
                                   alpha=1 / 16, row_order="original_ranges", seg_len=16)),
+    ("random", "f32", "f32", dict(mode="mixed", window_h=16, t_row=3, alpha_c=1 / 16, alpha=0.02,
+                                  row_order="compacted", seg_len=7, local_reorder=40)),
+    ("random", "f16", "f16", dict(mode="mixed", window_h=32, t_row=2, alpha_c=1 / 32, alpha=0.0,
+                                  row_order="length_sorted", seg_len=9, local_reorder=96)),
+    ("block", "f32", "bf16", dict(mode="mixed", window_h=16, t_row=1, alpha_c=1 / 16,
+                                  alpha=1 / 16, row_order="compacted", seg_len=16,
+                                  local_reorder=256)),
 ]
 
 
@@ -195,7 +206,8 @@ def test_plan_bit_exact_vs_reference(lib, case):
     ref = pr.build_plan(A.rowptr, A.colidx, A.vals, k=A.k, mode=mode, window_h=ro["window_h"],
                         t_row=ro["t_row"], alpha_c=ro["alpha_c"], alpha=ro["alpha"],
                         kt=ro["kt"], row_order=ro["row_order"], seg=ro["seg_len"],
-                        tile_kind="f16" if bk == "f16" else "bf16", val_kind=vk)
+                        tile_kind="f16" if bk == "f16" else "bf16", val_kind=vk,
+                        local_reorder_rows=ro["local_reorder"])
     d = p.export()
     _cmp_plan(A, d, ref)
     _check_schedule(A, d, ro["seg_len"], ro["pipeline"])

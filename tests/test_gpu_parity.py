@@ -359,6 +359,60 @@ def test_adapt_epochs(a0):
     parity(C, A, B, "bf16", TOL_16)
 
 
+@pytest.mark.parametrize("order", ["compacted", "length_sorted"])
+def test_local_reorder_exact(order):
+    A = synth.random_csr(2000, 800, 0.02, 21, int_values=(-2, 2), dup_frac=0.02,
+                         empty_rows=0.05)
+    B = synth.int_dense(5, (800, 64), -8, 8, kind="bf16")
+    p, C = run(A, B, "bf16", api.default_opts(mode="mixed", window_h=16, t_row=2,
+                                              alpha_c=1 / 16, alpha=0.0, row_order=order,
+                                              local_reorder=64, seg_len=11))
+    assert p.stats()["tiles"] > 0
+    exact(C, A, B, "bf16")
+
+
+def test_local_reorder_shuffled_communities():
+    """Row-shuffled community matrix: the rebuilt windows put most entries
+    back into dense tiles, and the result stays within the 16-bit bound."""
+    A0, B = synth.block_community(n=16384, band=8, n_cols=64, seed=4)
+    A = synth.permute_rows(A0, 3)
+    kw = dict(mode="mixed", row_order="compacted", t_row=1, alpha=1 / 16)
+    p0 = api.Plan(A, 64, "bf16", api.default_opts(**kw), upload=False)
+    p1, C = run(A, B, "bf16", api.default_opts(local_reorder=256, **kw))
+    s0, s1 = p0.stats(), p1.stats()
+    assert s1["nnz_tiles"] > 3 * s0["nnz_tiles"]
+    assert s1["mean_tile_density"] > s0["mean_tile_density"]
+    parity(C, A, B, "bf16", TOL_16)
+
+
+@pytest.mark.parametrize("shape", ["equal16", "one_big"])
+def test_submit_xcd_assignment_bitwise(shape):
+    """16 matrices of equal work (whole matrices per XCD) and one large
+    matrix with three small ones (every matrix cut into 8 chunks, one per
+    XCD): both equal their solo runs bit for bit."""
+    import torch
+    if shape == "equal16":
+        mats = [synth.random_csr(3000, 3000, 0.004, 60 + i) for i in range(16)]
+    else:
+        mats = [synth.chung_lu_graph(60000, 2.1, 16.0, 3000.0, 61)] + \
+               [synth.random_csr(500, 500, 0.01, 62 + i) for i in range(3)]
+    items, solos = [], []
+    for i, A in enumerate(mats):
+        B = np.random.default_rng(i).standard_normal((A.k, 64)).astype(np.float32)
+        p = api.Plan(A, 64, "f32", api.default_opts(mode="plain", seg_len=40))
+        Bd = device_B(B, "f32")
+        Cs = device_C(A.m, 64)
+        p.run(Bd, Cs)
+        items.append(api.WorkItem(p, Bd, device_C(A.m, 64)))
+        solos.append((Cs, A, B))
+    for _ in range(2):
+        api.spmm_wait(api.spmm_submit(items))
+    torch.cuda.synchronize()
+    for it, (Cs, A, B) in zip(items, solos):
+        assert torch.equal(it.C, Cs)
+    parity(items[0].C, solos[0][1], solos[0][2], "f32", TOL_F32)
+
+
 def test_destroy_busy_plan_rejected():
     import torch
     A = synth.random_csr(2000, 2000, 0.01, 3)
