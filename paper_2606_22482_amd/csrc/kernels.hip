@@ -842,7 +842,7 @@ __global__ __launch_bounds__(256) void vector_kernel(DevPlan P, RunArgs a) {
 
 // LDS of a window item: the staged B rows (reused for the f32 C tile), the
 // window's rows, remainder ranges and segment ids, and the staged tiles'
-// columns, bitmaps, per-row value offsets and packed values.  MB = H / 16.
+// bitmaps, per-row value offsets and packed values.  MB = H / 16.
 template <int MB>
 struct WinSmem {
     static constexpr int NPW = 128;          // panel columns of a window item
@@ -852,7 +852,7 @@ struct WinSmem {
     static constexpr int H = MB * 16;
     __attribute__((aligned(16))) unsigned short Bs[KROWS * BSTR];
     unsigned short vals[TC * H * 32];
-    int32_t rows[H], rb[H], re[H], sid[H], cols[KROWS], off[TC * H];
+    int32_t rows[H], rb[H], re[H], sid[H], off[TC * H];
     uint32_t bm[TC * H];
 };
 
@@ -902,11 +902,12 @@ __device__ __forceinline__ void stage_b8(const void *B, int64_t off, int valid, 
 // panel innermost, so a window's panels run side by side on one XCD and share
 // its tile data in that XCD's L2.
 // Every thread of the workgroup calls it with the same item.  Per round of up
-// to TC tiles: (1) the tiles' columns, bitmaps and packed values and the
-// window's row metadata are loaded together; (2) the B rows of the tile
-// columns are loaded (all loads issued before any LDS write) and stored
-// converted to the tile type; (3) MFMA from LDS only.  Then each row adds its
-// remainder and is written once.
+// to TC tiles, with one barrier: each thread loads the columns of its own B
+// staging chunks and then those B rows (converted to the tile type), each wave
+// its tile's bitmap words and computes the rows' value offsets, and the
+// bitmaps, packed values and (first round) the window's row metadata go to
+// LDS; then MFMA from LDS only.  Then each row adds its remainder and is
+// written once.
 template <int VT, int BT, int TT, int MB, int E, int CPL, int SMB>
 __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, int item,
                                             WinSmem<SMB> &sm, bool partial) {
@@ -928,21 +929,6 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
     const int t1 = partial ? P.wpart_t1[j_item] : min(P.win_tile_ptr[wi + 1], t0 + P.win_tmax);
     float *wpart = a.work + (int64_t)P.n_seg * a.work_ld;  // window partials follow the segments
 
-    if (wave == 0 && !partial) {
-        const int r = lane < H ? P.windows[(int64_t)wi * H + lane] : -1;
-        const int b = r >= 0 ? P.rem_ptr[r] : 0;
-        const int e = r >= 0 ? P.rem_ptr[r + 1] : 0;
-        const int len = e - b;
-        const int ns = len > P.seg_len ? (len + P.seg_len - 1) / P.seg_len : 0;
-        const int x = wave_inclusive_scan(ns);
-        if (lane < H) {
-            sm.rows[lane] = r;
-            sm.rb[lane] = b;
-            sm.re[lane] = e;
-            sm.sid[lane] = P.win_seg[wi] + x - ns;
-        }
-    }
-
     f32x4 acc[MB][2];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
@@ -951,29 +937,52 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
 
     for (int tc0 = t0; tc0 < t1; tc0 += TC) {
         const int nt = min(TC, t1 - tc0);
-        __syncthreads();
-        const int v0 = P.tile_val_ptr[tc0], nv = P.tile_val_ptr[tc0 + nt] - v0;
-        for (int i = tid; i < nt * 32; i += 256) sm.cols[i] = P.tile_cols[(int64_t)tc0 * 32 + i];
-        for (int i = tid; i < nt * H; i += 256) sm.bm[i] = P.tile_bitmap[(int64_t)tc0 * H + i];
-        for (int i = tid; i < nv; i += 256) sm.vals[i] = P.tile_vals[v0 + i];
-        __syncthreads();
-        if (wave < nt) {
-            const uint32_t wd = lane < H ? sm.bm[wave * H + lane] : 0u;
-            const int c = __popc(wd);
-            const int x = wave_inclusive_scan(c);
-            // offset of the row's first value inside the staged round
-            if (lane < H) sm.off[wave * H + lane] = P.tile_val_ptr[tc0 + wave] - v0 + x - c;
-        }
+        if (tc0 != t0) __syncthreads();  // the previous round's LDS reads are done
+        // Everything a round needs is loaded from global memory in two
+        // dependent levels (tile columns -> B rows; value base -> values;
+        // window rows -> remainder ranges) before the round's one barrier.
         constexpr int PER = KROWS * (NPW / 8) / 256;  // 16-byte staging chunks per thread
+        int colr[PER];
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            const int kr = (tid + it * 256) >> 4;
+            colr[it] = kr < nt * 32 ? P.tile_cols[(int64_t)tc0 * 32 + kr] : -1;
+        }
+        const int v0 = P.tile_val_ptr[tc0], nv = P.tile_val_ptr[tc0 + nt] - v0;
+        // this wave's tile: bitmap word of row `lane` and the tile's first value
+        const uint32_t wd = (wave < nt && lane < H) ? P.tile_bitmap[(int64_t)(tc0 + wave) * H + lane] : 0u;
+        const int tv = wave < nt ? P.tile_val_ptr[tc0 + wave] : 0;
         uint32_t w[PER][4];
 #pragma unroll
         for (int it = 0; it < PER; ++it) {
-            const int i = tid + it * 256, kr = i >> 4, n = (i & 15) * 8;
+            const int n = ((tid + it * 256) & 15) * 8;
             w[it][0] = w[it][1] = w[it][2] = w[it][3] = 0u;
-            const int col = kr < nt * 32 ? sm.cols[kr] : -1;
             const int valid = min(8, ncols - n);
-            if (col >= 0 && valid > 0)
-                stage_b8<BT, TT>(a.B, (int64_t)col * a.ldb + ncol0 + n, valid, a.vec_ok, w[it]);
+            if (colr[it] >= 0 && valid > 0)
+                stage_b8<BT, TT>(a.B, (int64_t)colr[it] * a.ldb + ncol0 + n, valid, a.vec_ok, w[it]);
+        }
+        for (int i = tid; i < nt * H; i += 256) sm.bm[i] = P.tile_bitmap[(int64_t)tc0 * H + i];
+        for (int i = tid; i < nv; i += 256) sm.vals[i] = P.tile_vals[v0 + i];
+        if (tc0 == t0 && wave == 0 && !partial) {
+            // the window's rows, their remainder ranges and segment ids
+            const int r = lane < H ? P.windows[(int64_t)wi * H + lane] : -1;
+            const int b = r >= 0 ? P.rem_ptr[r] : 0;
+            const int e = r >= 0 ? P.rem_ptr[r + 1] : 0;
+            const int len = e - b;
+            const int ns = len > P.seg_len ? (len + P.seg_len - 1) / P.seg_len : 0;
+            const int x = wave_inclusive_scan(ns);
+            if (lane < H) {
+                sm.rows[lane] = r;
+                sm.rb[lane] = b;
+                sm.re[lane] = e;
+                sm.sid[lane] = P.win_seg[wi] + x - ns;
+            }
+        }
+        if (wave < nt) {
+            // offset of each row's first value inside the staged round
+            const int c = __popc(wd);
+            const int x = wave_inclusive_scan(c);
+            if (lane < H) sm.off[wave * H + lane] = tv - v0 + x - c;
         }
 #pragma unroll
         for (int it = 0; it < PER; ++it) {
