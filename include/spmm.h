@@ -61,6 +61,10 @@ typedef int32_t spmm_status;
 #define SPMM_ORDER_ORIGINAL_RANGES 1 /* fixed ranges [wH, wH+H); rows failing the row stage leave holes */
 #define SPMM_ORDER_COMPACTED 2       /* passing rows in original order, cut into groups of H */
 #define SPMM_ORDER_LENGTH_SORTED 3   /* passing rows by length descending (ties: row id), groups of H */
+#define SPMM_ORDER_CLUSTERED 4       /* passing rows in the global clustering order (Sec. 6.1 global
+                                        stage: Rabbit Order -- incremental modularity aggregation,
+                                        then a depth-first walk of the merge dendrogram -- on the
+                                        bipartite row-column graph of A), groups of H */
 
 #define SPMM_AUTO_INT (-2147483647 - 1) /* "choose for me" for integer options that accept -1 */
 

@@ -53,6 +53,7 @@ import numpy as np
 ORDER_ORIGINAL_RANGES = 1
 ORDER_COMPACTED = 2
 ORDER_LENGTH_SORTED = 3
+ORDER_CLUSTERED = 4
 
 MODE_PLAIN = 1
 MODE_MIXED = 2
@@ -105,6 +106,80 @@ class PlanRef:
     vector_rows: np.ndarray        # int32: rows not covered by a kept window (ascending)
     nseg: np.ndarray               # int32 [M]: segments of each row's remainder (0 if <= seg)
     stats: dict = field(default_factory=dict)
+
+
+def rabbit_order(rowptr, colidx, m, k):
+    """Global clustering order of the rows (Sec. 6.1, global stage), from the
+    published Rabbit Order algorithm (community detection by incremental
+    aggregation, then a depth-first walk of the merge dendrogram), applied
+    to the bipartite graph of A: vertices 0..m-1 are rows, m..m+k-1 columns,
+    one unit-weight edge per stored entry.
+
+    Vertices are visited once, in increasing degree (ties: lower id).  A
+    visited vertex u is the root of its community (whatever merged into it
+    so far); it joins the neighbouring community v with the largest
+    modularity gain, 2 * (w_uv / 2M - d_u * d_v / (2M)^2) > 0, compared
+    exactly as w_uv * 2M - d_u * d_v (ties: lower root id), where w_uv counts
+    the edges between the two communities, d the summed degrees and M the
+    edge count; otherwise it stays a root.  The order lists the roots in the
+    order they were visited, each followed depth first by what merged into
+    it, children in the order they merged.  Returns the rank of each row in
+    that order (rows only)."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    colidx = np.asarray(colidx, dtype=np.int64)
+    n = m + k
+    nnz = int(rowptr[-1])
+    adj = [[] for _ in range(n)]
+    for r in range(m):
+        for p in range(rowptr[r], rowptr[r + 1]):
+            c = m + int(colidx[p])
+            adj[r].append(c)
+            adj[c].append(r)
+    two_m = 2 * nnz
+    deg = [len(a) for a in adj]
+    parent = list(range(n))
+    members = [[v] for v in range(n)]
+    children = [[] for _ in range(n)]
+
+    def find(v):
+        while parent[v] != v:
+            v = parent[v]
+        return v
+
+    visited_roots = []
+    for u in sorted(range(n), key=lambda v: (deg[v], v)):
+        w = {}
+        for x in members[u]:
+            for y in adj[x]:
+                ry = find(y)
+                if ry != u:
+                    w[ry] = w.get(ry, 0) + 1
+        best, best_gain = -1, 0
+        for v in sorted(w):
+            gain = w[v] * two_m - deg[u] * deg[v]
+            if gain > best_gain:
+                best, best_gain = v, gain
+        if best < 0:
+            visited_roots.append(u)
+            continue
+        parent[u] = best
+        children[best].append(u)
+        members[best].extend(members[u])
+        deg[best] += deg[u]
+    order = []
+    for root in [v for v in visited_roots if parent[v] == v]:
+        stack = [root]
+        while stack:
+            v = stack.pop()
+            order.append(v)
+            stack.extend(reversed(children[v]))
+    rank = np.empty(m, dtype=np.int64)
+    pos = 0
+    for v in order:
+        if v < m:
+            rank[v] = pos
+            pos += 1
+    return rank
 
 
 def jaccard(a: set, b: set) -> Fraction:
@@ -174,6 +249,9 @@ def build_plan(rowptr, colidx, vals, *, k: int, mode: int, window_h: int = 16, t
             D = [r for r in range(m) if inD[r]]
             if row_order == ORDER_LENGTH_SORTED:
                 D.sort(key=lambda r: (-int(lens[r]), r))
+            elif row_order == ORDER_CLUSTERED:
+                rank = rabbit_order(rowptr, colidx, m, k)
+                D.sort(key=lambda r: int(rank[r]))
             elif row_order != ORDER_COMPACTED:
                 raise ValueError("unknown row order")
             if local_reorder_rows > 0:

@@ -13,6 +13,7 @@ SPMM_ERR_UNSUPPORTED, SPMM_ERR_BUDGET, SPMM_ERR_BUSY = 4, 5, 6
 F32, BF16, F16 = 0, 1, 2
 MODE_AUTO, MODE_PLAIN_F32, MODE_MIXED, MODE_MFMA_ONLY = 0, 1, 2, 3
 ORDER_AUTO, ORDER_ORIGINAL_RANGES, ORDER_COMPACTED, ORDER_LENGTH_SORTED = 0, 1, 2, 3
+ORDER_CLUSTERED = 4
 AUTO_INT = -(2 ** 31)
 KERNEL_SEGMENT, KERNEL_VECTOR, KERNEL_WINDOW = 0, 1, 2
 KERNEL_NAMES = {0: "segment", 1: "vector", 2: "window", 3: "window_partial"}

@@ -28,7 +28,8 @@ def default_opts(**kw) -> L.Opts:
     modes = {"auto": L.MODE_AUTO, "plain": L.MODE_PLAIN_F32, "plain_f32": L.MODE_PLAIN_F32,
              "mixed": L.MODE_MIXED, "mfma_only": L.MODE_MFMA_ONLY}
     orders = {"auto": L.ORDER_AUTO, "original_ranges": L.ORDER_ORIGINAL_RANGES,
-              "compacted": L.ORDER_COMPACTED, "length_sorted": L.ORDER_LENGTH_SORTED}
+              "compacted": L.ORDER_COMPACTED, "length_sorted": L.ORDER_LENGTH_SORTED,
+              "clustered": L.ORDER_CLUSTERED}
     for k, v in kw.items():
         if k == "mode" and isinstance(v, str):
             v = modes[v]

@@ -146,6 +146,98 @@ spmm_status validate_problem(const spmm_csr *A, int32_t n, int32_t b_type, int32
     return SPMM_OK;
 }
 
+// Sec. 6.1 global stage: the rank of every row in the Rabbit Order of the
+// bipartite graph of A (vertices 0..m-1 rows, m..m+k-1 columns, one unit edge
+// per stored entry).  Vertices are visited once in increasing degree (ties:
+// lower id); a visited vertex u is the root of its community and joins the
+// neighbouring community v with the largest modularity gain, compared exactly
+// as w_uv * 2M - d_u * d_v > 0 (ties: lower root id), else stays a root.  The
+// order lists the roots in visit order, each followed depth first by what
+// merged into it, children in merge order.
+static std::vector<int64_t> rabbit_rank(int64_t m, int64_t k, const int64_t *rowptr,
+                                        const int32_t *colidx) {
+    const int64_t n = m + k, nnz = rowptr[m];
+    // adjacency: rows -> columns (as m + c), columns -> rows
+    std::vector<int64_t> aptr(n + 1, 0);
+    for (int64_t r = 0; r < m; ++r) aptr[r + 1] = rowptr[r + 1] - rowptr[r];
+    for (int64_t p = 0; p < nnz; ++p) ++aptr[m + colidx[p] + 1];
+    for (int64_t v = 0; v < n; ++v) aptr[v + 1] += aptr[v];
+    std::vector<int64_t> adj(aptr[n]);
+    {
+        std::vector<int64_t> fill(aptr.begin(), aptr.end() - 1);
+        for (int64_t r = 0; r < m; ++r)
+            for (int64_t p = rowptr[r]; p < rowptr[r + 1]; ++p) {
+                const int64_t c = m + colidx[p];
+                adj[fill[r]++] = c;
+                adj[fill[c]++] = r;
+            }
+    }
+    const __int128 two_m = 2 * (__int128)nnz;
+    std::vector<int64_t> deg(n), parent(n), next(n, -1), tail(n);
+    std::vector<int64_t> acc(n, 0), touched;
+    std::vector<std::vector<int64_t>> children(n);
+    for (int64_t v = 0; v < n; ++v) {
+        deg[v] = aptr[v + 1] - aptr[v];
+        parent[v] = v;
+        tail[v] = v;
+    }
+    auto find = [&](int64_t v) {
+        int64_t r = v;
+        while (parent[r] != r) r = parent[r];
+        while (parent[v] != r) {  // path compression; roots are unchanged
+            const int64_t up = parent[v];
+            parent[v] = r;
+            v = up;
+        }
+        return r;
+    };
+    std::vector<int64_t> visit(n);
+    for (int64_t v = 0; v < n; ++v) visit[v] = v;
+    std::stable_sort(visit.begin(), visit.end(), [&](int64_t a, int64_t b) { return deg[a] < deg[b]; });
+    std::vector<int64_t> roots;
+    for (int64_t u : visit) {
+        touched.clear();
+        for (int64_t x = u; x >= 0; x = next[x])
+            for (int64_t q = aptr[x]; q < aptr[x + 1]; ++q) {
+                const int64_t ry = find(adj[q]);
+                if (ry == u) continue;
+                if (acc[ry]++ == 0) touched.push_back(ry);
+            }
+        int64_t best = -1;
+        __int128 best_gain = 0;
+        for (int64_t v : touched) {
+            const __int128 gain = (__int128)acc[v] * two_m - (__int128)deg[u] * deg[v];
+            if (gain > best_gain || (gain == best_gain && best >= 0 && v < best)) {
+                best = v;
+                best_gain = gain;
+            }
+            acc[v] = 0;
+        }
+        if (best < 0) {
+            roots.push_back(u);
+            continue;
+        }
+        parent[u] = best;
+        children[best].push_back(u);
+        next[tail[best]] = u;  // members of best, then of u
+        tail[best] = tail[u];
+        deg[best] += deg[u];
+    }
+    std::vector<int64_t> rank(m, 0), stack;
+    int64_t pos = 0;
+    for (int64_t root : roots) {
+        if (parent[root] != root) continue;
+        stack.push_back(root);
+        while (!stack.empty()) {
+            const int64_t v = stack.back();
+            stack.pop_back();
+            if (v < m) rank[v] = pos++;
+            for (auto it = children[v].rbegin(); it != children[v].rend(); ++it) stack.push_back(*it);
+        }
+    }
+    return rank;
+}
+
 // Sec. 6.1 local reordering.  D is cut into clusters of crows consecutive
 // rows; inside a cluster the current windows (groups of H in D's order) are
 // visited in order, and the longest unassigned row of each (ties: earlier)
@@ -231,7 +323,7 @@ static spmm_status validate_opts(const spmm_opts &o, std::string &err) {
     if (o.mode < SPMM_MODE_PLAIN_F32 || o.mode > SPMM_MODE_MFMA_ONLY) { err = "mode"; return SPMM_ERR_UNSUPPORTED; }
     if (o.window_h != 16 && o.window_h != 32 && o.window_h != 64) { err = "window_h must be 16, 32 or 64"; return SPMM_ERR_UNSUPPORTED; }
     if (o.kt != 32) { err = "kt must be 32"; return SPMM_ERR_UNSUPPORTED; }
-    if (o.row_order < SPMM_ORDER_ORIGINAL_RANGES || o.row_order > SPMM_ORDER_LENGTH_SORTED) { err = "row_order"; return SPMM_ERR_UNSUPPORTED; }
+    if (o.row_order < SPMM_ORDER_ORIGINAL_RANGES || o.row_order > SPMM_ORDER_CLUSTERED) { err = "row_order"; return SPMM_ERR_UNSUPPORTED; }
     if (o.seg_len < 1 || o.seg_len > (1 << 30)) { err = "seg_len"; return SPMM_ERR_UNSUPPORTED; }
     if (o.item_cost < 1) { err = "item_cost"; return SPMM_ERR_UNSUPPORTED; }
     if (o.n_panel < 0) { err = "n_panel"; return SPMM_ERR_UNSUPPORTED; }
@@ -300,6 +392,10 @@ spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_
             if (o.row_order == SPMM_ORDER_LENGTH_SORTED)
                 std::stable_sort(D.begin(), D.end(),
                                  [&](int32_t a, int32_t b) { return len[a] > len[b]; });
+            if (o.row_order == SPMM_ORDER_CLUSTERED) {
+                const std::vector<int64_t> rank = rabbit_rank(m, k, rowptr, colidx);
+                std::sort(D.begin(), D.end(), [&](int32_t a, int32_t b) { return rank[a] < rank[b]; });
+            }
             if (o.local_reorder > 0) {
                 const int64_t crows = ((int64_t)o.local_reorder + H - 1) / H * H;
                 local_reorder(D, H, crows, rowptr, colidx, len, k, cand);

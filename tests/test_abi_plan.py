@@ -184,6 +184,13 @@ CASES = [
     ("block", "f32", "bf16", dict(mode="mixed", window_h=16, t_row=1, alpha_c=1 / 16,
                                   alpha=1 / 16, row_order="compacted", seg_len=16,
                                   local_reorder=256)),
+    ("random", "f32", "f32", dict(mode="mixed", window_h=16, t_row=2, alpha_c=1 / 16, alpha=0.02,
+                                  row_order="clustered", seg_len=7)),
+    ("shuffled", "f32", "bf16", dict(mode="mixed", window_h=16, t_row=1, alpha_c=1 / 16,
+                                     alpha=1 / 16, row_order="clustered", seg_len=16,
+                                     local_reorder=64)),
+    ("shuffled", "bf16", "bf16", dict(mode="mixed", window_h=32, t_row=1, alpha_c=1 / 32,
+                                      alpha=0.03, row_order="clustered", seg_len=16)),
 ]
 
 
@@ -191,7 +198,7 @@ def _matrix(kind, vk):
     if kind == "random":
         return synth.random_csr(400, 300, 0.04, 7, val_kind=vk, dup_frac=0.05, empty_rows=0.05)
     A, _ = synth.block_community(n=2048, band=4, n_cols=8, seed=5, val_kind=vk)
-    return A
+    return synth.permute_rows(A, 2) if kind == "shuffled" else A
 
 
 @pytest.mark.parametrize("case", range(len(CASES)))

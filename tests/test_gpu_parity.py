@@ -359,7 +359,7 @@ def test_adapt_epochs(a0):
     parity(C, A, B, "bf16", TOL_16)
 
 
-@pytest.mark.parametrize("order", ["compacted", "length_sorted"])
+@pytest.mark.parametrize("order", ["compacted", "length_sorted", "clustered"])
 def test_local_reorder_exact(order):
     A = synth.random_csr(2000, 800, 0.02, 21, int_values=(-2, 2), dup_frac=0.02,
                          empty_rows=0.05)

@@ -243,3 +243,73 @@ def test_local_reorder_raises_tile_density():
     after = pr.build_plan(rp, ci, vals, local_reorder_rows=256, **kw)
     assert after.stats["nnz_tiles"] > 2 * before.stats["nnz_tiles"]
     assert after.stats["mean_tile_density"] > before.stats["mean_tile_density"]
+
+
+# ---- Sec. 6.1 global stage (Rabbit Order on the bipartite row-column graph) ------------------
+
+def _modularity(edges, n, comm):
+    """Q from its definition: (1/2M) sum_ij [A_ij - d_i d_j / 2M] [c_i == c_j],
+    A the symmetric adjacency (multi-edges counted)."""
+    A = np.zeros((n, n))
+    for a, b in edges:
+        A[a, b] += 1
+        A[b, a] += 1
+    d = A.sum(axis=1)
+    two_m = A.sum()
+    same = np.equal.outer(comm, comm)
+    return float(((A - np.outer(d, d) / two_m) * same).sum() / two_m)
+
+
+def test_rabbit_gain_is_the_modularity_gain():
+    """The integer gain w_uv * 2M - d_u * d_v is (Q_after - Q_before) * (2M)^2 / 2
+    for merging two communities, Q computed by brute force."""
+    rng = np.random.default_rng(4)
+    m, k = 7, 6
+    edges = [(int(r), m + int(c)) for r, c in zip(rng.integers(0, m, 30), rng.integers(0, k, 30))]
+    n = m + k
+    comm = np.arange(n)
+    comm[[0, 3]] = 0          # a few communities already merged
+    comm[[m + 1, m + 4]] = m + 1
+    d = np.zeros(n)
+    for a, b in edges:
+        d[a] += 1
+        d[b] += 1
+    two_m = 2 * len(edges)
+    for cu, cv in [(0, m + 1), (2, m + 1), (0, 5)]:
+        before = _modularity(edges, n, comm)
+        merged = np.where(comm == cu, cv, comm)
+        after = _modularity(edges, n, merged)
+        w = sum(1 for a, b in edges if (comm[a], comm[b]) in ((cu, cv), (cv, cu)))
+        du, dv = d[comm == cu].sum(), d[comm == cv].sum()
+        assert (after - before) * two_m ** 2 / 2 == pytest.approx(w * two_m - du * dv, abs=1e-9)
+
+
+def test_rabbit_order_keeps_components_together():
+    """Two disconnected groups of rows (each a dense biclique on its own
+    columns), interleaved: each group occupies a contiguous rank range."""
+    rows = []
+    for r in range(20):
+        g = r % 2
+        rows.append(list(range(10 * g, 10 * g + 6)))
+    rp, ci = _csr_rows(rows)
+    rank = pr.rabbit_order(rp, ci, 20, 20)
+    assert sorted(rank.tolist()) == list(range(20))
+    for g in range(2):
+        rk = sorted(rank[g::2].tolist())
+        assert rk[-1] - rk[0] == 9
+
+
+def test_rabbit_order_recovers_shuffled_communities():
+    A0, _ = synth.block_community(n=4096, band=8, n_cols=8, seed=5)
+    A = synth.permute_rows(A0, 3)
+    rank = pr.rabbit_order(A.rowptr, A.colidx, A.m, A.k)
+    assert sorted(rank.tolist()) == list(range(A.m))
+    kw = dict(k=A.k, mode=pr.MODE_MIXED, window_h=16, t_row=1, alpha_c=1 / 16, alpha=1 / 16)
+    v = np.ones(A.nnz, dtype=np.float32)
+    shuffled = pr.build_plan(A.rowptr, A.colidx, v, row_order=pr.ORDER_COMPACTED, **kw)
+    clustered = pr.build_plan(A.rowptr, A.colidx, v, row_order=pr.ORDER_CLUSTERED, **kw)
+    both = pr.build_plan(A.rowptr, A.colidx, v, row_order=pr.ORDER_CLUSTERED,
+                         local_reorder_rows=256, **kw)
+    assert clustered.stats["nnz_tiles"] > 4 * shuffled.stats["nnz_tiles"]
+    assert both.stats["nnz_tiles"] > clustered.stats["nnz_tiles"]
+    assert both.stats["mean_tile_density"] > shuffled.stats["mean_tile_density"]
