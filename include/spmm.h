@@ -230,6 +230,19 @@ spmm_status spmm_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_ty
                       const spmm_opts *opts, spmm_plan_t **out);
 /* Release a plan.  BUSY while batched submissions that use it are unfinished. */
 spmm_status spmm_plan_destroy(spmm_plan_t *p);
+/* Plan images, so that a plan is built once and loaded by later processes
+ * (Sec. 5.2.2 preprocessing is amortised over many runs).  serialize writes a
+ * versioned, checksummed image of the host plan into buf (cap bytes) and its
+ * size into *size; with buf = NULL only *size is set; INVALID if cap is too
+ * small.  deserialize reads an image written by the same library version,
+ * checks the checksum and every index invariant the kernels rely on (row,
+ * column, tile, segment and item ranges), and returns a new plan, uploaded
+ * when `upload` is non-zero.  INVALID for a malformed or corrupted image,
+ * UNSUPPORTED for another format version.  The image holds the plan's host
+ * arrays, including the packed values: the caller's copy of A is not needed. */
+spmm_status spmm_plan_serialize(const spmm_plan_t *p, void *buf, int64_t cap, int64_t *size);
+spmm_status spmm_plan_deserialize(const void *buf, int64_t size, int32_t upload,
+                                  spmm_plan_t **out);
 spmm_status spmm_plan_stats(const spmm_plan_t *p, spmm_plan_stats_t *out);
 spmm_status spmm_plan_export(const spmm_plan_t *p, spmm_plan_dump_t *out);
 

@@ -115,6 +115,27 @@ class Plan:
     def handle(self):
         return self._h
 
+    def serialize(self) -> bytes:
+        """spmm_plan_serialize: the plan image as bytes."""
+        size = C.c_int64()
+        L.check(self._lib.spmm_plan_serialize(self._h, None, 0, C.byref(size)))
+        buf = C.create_string_buffer(size.value)
+        L.check(self._lib.spmm_plan_serialize(self._h, buf, size.value, C.byref(size)))
+        return buf.raw[: size.value]
+
+    @classmethod
+    def deserialize(cls, image: bytes, upload=True) -> "Plan":
+        """spmm_plan_deserialize: a plan from an image written by serialize."""
+        lib = L.load()
+        h = C.c_void_p()
+        L.check(lib.spmm_plan_deserialize(image, len(image), 1 if upload else 0, C.byref(h)))
+        p = cls.__new__(cls)
+        p._lib, p._h, p._keep = lib, h, None
+        st = p.stats()
+        p.n, p.m, p.k = int(st["n"]), int(st["m"]), int(st["k"])
+        p.b_kind = {0: "f32", 1: "bf16", 2: "f16"}[int(st["b_type"])]
+        return p
+
     def upload(self):
         L.check(self._lib.spmm_plan_upload(self._h))
 

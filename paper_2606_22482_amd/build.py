@@ -28,7 +28,7 @@ CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC,
              "-I", "/opt/rocm/include"]
 
 HIP_SOURCES = ["kernels.hip", "runtime.hip", "submit.hip", "autotune.hip"]
-CXX_SOURCES = ["plan.cpp"]
+CXX_SOURCES = ["plan.cpp", "serialize.cpp"]
 
 
 def _run(cmd):

@@ -319,7 +319,7 @@ static void local_reorder(const std::vector<int32_t> &D, int H, int64_t crows,
     }
 }
 
-static spmm_status validate_opts(const spmm_opts &o, std::string &err) {
+spmm_status validate_opts(const spmm_opts &o, std::string &err) {
     if (o.mode < SPMM_MODE_PLAIN_F32 || o.mode > SPMM_MODE_MFMA_ONLY) { err = "mode"; return SPMM_ERR_UNSUPPORTED; }
     if (o.window_h != 16 && o.window_h != 32 && o.window_h != 64) { err = "window_h must be 16, 32 or 64"; return SPMM_ERR_UNSUPPORTED; }
     if (o.kt != 32) { err = "kt must be 32"; return SPMM_ERR_UNSUPPORTED; }

@@ -73,6 +73,15 @@ void resolve_options(const spmm_opts *in, const spmm_csr *A, int32_t n, int32_t 
 spmm_status validate_problem(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
                              std::string &err);
 
+// Range checks of resolved options (no "auto" left).
+spmm_status validate_opts(const spmm_opts &o, std::string &err);
+
+// Plan serialisation: a versioned, checksummed image of every HostPlan array.
+void serialize_host_plan(const HostPlan &P, std::vector<uint8_t> &out);
+// Parses an image and checks every index invariant the kernels rely on, so
+// that a plan that loads cannot make a kernel read or write out of bounds.
+spmm_status deserialize_host_plan(const uint8_t *buf, size_t size, HostPlan &P, std::string &err);
+
 // Work of the two paths of a plan: entries gathered by the segment and vector
 // kernels, tile slots (tiles * H * kt), and remainder entries of window rows
 // gathered inside the window kernels.

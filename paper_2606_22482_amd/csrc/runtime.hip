@@ -227,6 +227,44 @@ extern "C" spmm_status spmm_plan(const spmm_csr *A, int32_t n, int32_t b_type, i
     return st;
 }
 
+extern "C" spmm_status spmm_plan_serialize(const spmm_plan_t *p, void *buf, int64_t cap,
+                                           int64_t *size) {
+    if (!p || !size) return set_error(SPMM_ERR_INVALID, "null argument");
+    try {
+        std::vector<uint8_t> img;
+        serialize_host_plan(p->hp, img);
+        *size = (int64_t)img.size();
+        if (!buf) return SPMM_OK;
+        if (cap < (int64_t)img.size()) return set_error(SPMM_ERR_INVALID, "buffer too small");
+        std::memcpy(buf, img.data(), img.size());
+        return SPMM_OK;
+    } catch (const std::bad_alloc &) {
+        return set_error(SPMM_ERR_OOM, "host allocation failed while serialising");
+    }
+}
+
+extern "C" spmm_status spmm_plan_deserialize(const void *buf, int64_t size, int32_t upload,
+                                             spmm_plan_t **out) {
+    if (!out) return set_error(SPMM_ERR_INVALID, "out is null");
+    *out = nullptr;
+    if (!buf || size <= 0) return set_error(SPMM_ERR_INVALID, "empty plan image");
+    try {
+        std::unique_ptr<spmm_plan_s> p(new spmm_plan_s());
+        std::string err;
+        spmm_status st = deserialize_host_plan(static_cast<const uint8_t *>(buf), (size_t)size,
+                                               p->hp, err);
+        if (st != SPMM_OK) return set_error(st, err);
+        if (upload) {
+            st = spmm_plan_upload(p.get());
+            if (st != SPMM_OK) return st;
+        }
+        *out = p.release();
+        return SPMM_OK;
+    } catch (const std::bad_alloc &) {
+        return set_error(SPMM_ERR_OOM, "host allocation failed while loading a plan image");
+    }
+}
+
 extern "C" spmm_status spmm_plan_destroy(spmm_plan_t *p) {
     if (!p) return SPMM_OK;
     if (p->busy.load() > 0) return set_error(SPMM_ERR_BUSY, "plan has unfinished submissions");

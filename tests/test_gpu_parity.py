@@ -413,6 +413,22 @@ def test_submit_xcd_assignment_bitwise(shape):
     parity(items[0].C, solos[0][1], solos[0][2], "f32", TOL_F32)
 
 
+def test_plan_image_runs_bitwise():
+    """A plan loaded from its image (uploaded anew) gives the same C bit for
+    bit as the plan it was written from."""
+    import torch
+    A, B = synth.block_community(n=8192, band=8, n_cols=64, seed=2)
+    p = api.Plan(A, 64, "bf16", api.default_opts(mode="mixed", seg_len=20))
+    q = api.Plan.deserialize(p.serialize())
+    Bd = device_B(B, "bf16")
+    C1, C2 = device_C(A.m, 64), device_C(A.m, 64)
+    p.run(Bd, C1)
+    q.run(Bd, C2)
+    torch.cuda.synchronize()
+    assert torch.equal(C1, C2)
+    parity(C2, A, B, "bf16", TOL_16)
+
+
 def test_destroy_busy_plan_rejected():
     import torch
     A = synth.random_csr(2000, 2000, 0.01, 3)
