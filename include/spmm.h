@@ -101,7 +101,9 @@ typedef struct {
     float alpha;       /* a K-tile is kept iff nnz / (H*kt) >= alpha (Sec. 5.2.1); < 0: auto */
     int32_t cold_policy; /* cache-policy bits of gathers of non-hot B rows (gfx950 buffer-load aux:
                             2 = nt, 16 = sc1, 18 = nt|sc1, 0 = default); < 0: auto (0: measured
-                            fastest on gfx950) */
+                            fastest on gfx950).  Non-zero needs pipeline 0 (auto picks it) and
+                            applies to the segment and vector kernels; window rows' remainders
+                            gather with the default policy. */
     int32_t pipeline;  /* vector kernel variant: 0 = row by row; 1 = prefetch the next row during
                           the current row's gathers (bitwise identical to 0); 2 = short rows (at
                           most two unrolled batches) packed one per lane group, each summed in

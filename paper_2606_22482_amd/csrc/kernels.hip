@@ -334,7 +334,10 @@ __device__ __forceinline__ void load_entries(const int32_t *__restrict__ rcol,
 
 // Gathers the B rows of U loaded entries (hot rows cacheable, the others with
 // the cold policy) and accumulates them in entry order.
-template <int BT, int E, int CPL, int U>
+// POL: the per-entry cache-policy choice is compiled in (row-by-row variant
+// and segments of plans with a cold policy); without it every gather uses the
+// default policy and the loop carries no per-entry branches.
+template <int BT, int E, int CPL, int U, bool POL = false>
 __device__ __forceinline__ void gather_fma(const int (&col)[U], const float (&v)[U], int p, int p1,
                                            const void *__restrict__ B,
                                            __amdgpu_buffer_rsrc_t rs, int64_t ldb,
@@ -348,12 +351,19 @@ __device__ __forceinline__ void gather_fma(const int (&col)[U], const float (&v)
         for (int c = 0; c < CPL; ++c) {
             // bit 31 of a column marks a hot B row (cacheable gather)
             const int64_t boff = (int64_t)(col[u] & 0x7FFFFFFF) * ldb + coff[c];
-            if (ok && cok[c] && (col[u] < 0 || cold_aux < 0)) {
-                load_raw<BT, E, false>(B, boff, b[u][c]);
-            } else if (ok && cok[c]) {
-                load_raw_policy<BT, E>(rs, boff, cold_aux, b[u][c]);
+            if constexpr (POL) {
+                if (ok && cok[c] && (col[u] < 0 || cold_aux < 0)) {
+                    load_raw<BT, E, false>(B, boff, b[u][c]);
+                } else if (ok && cok[c]) {
+                    load_raw_policy<BT, E>(rs, boff, cold_aux, b[u][c]);
+                } else {
+                    zero_raw<BT, E>(b[u][c]);
+                }
             } else {
-                zero_raw<BT, E>(b[u][c]);
+                (void)rs;
+                (void)cold_aux;
+                if (ok && cok[c]) load_raw<BT, E, false>(B, boff, b[u][c]);
+                else zero_raw<BT, E>(b[u][c]);
             }
         }
     }
@@ -379,7 +389,7 @@ __device__ __forceinline__ void chunk_layout(int ncol0, int ncols, const Lanes &
 
 // acc += sum over entries [p0, p1) of v_p * B[col_p][panel columns], entry
 // p0 + i taken by group i % G in increasing i (see the file comment).
-template <int VT, int BT, int E, int CPL, int U>
+template <int VT, int BT, int E, int CPL, int U, bool POL = false>
 __device__ __forceinline__ void seg_accumulate(const int32_t *__restrict__ rcol,
                                                const void *__restrict__ rval, int p0, int p1,
                                                const void *__restrict__ B, int64_t ldb,
@@ -394,13 +404,13 @@ __device__ __forceinline__ void seg_accumulate(const int32_t *__restrict__ rcol,
         int col[U];
         float v[U];
         load_entries<VT, U>(rcol, rval, p, p1, L, col, v);
-        gather_fma<BT, E, CPL, U>(col, v, p, p1, B, rs, ldb, cok, coff, L, cold_aux, acc);
+        gather_fma<BT, E, CPL, U, POL>(col, v, p, p1, B, rs, ldb, cok, coff, L, cold_aux, acc);
     }
 }
 
 // acc += sum over entries [p0, p1) of one row, all taken by this lane's group
 // in increasing order (each group works on its own row).
-template <int VT, int BT, int E, int CPL, int U>
+template <int VT, int BT, int E, int CPL, int U, bool POL = false>
 __device__ __forceinline__ void row_accumulate_group(const int32_t *__restrict__ rcol,
                                                      const void *__restrict__ rval, int p0, int p1,
                                                      const void *__restrict__ B, int64_t ldb,
@@ -415,7 +425,7 @@ __device__ __forceinline__ void row_accumulate_group(const int32_t *__restrict__
         int col[U];
         float v[U];
         load_entries<VT, U>(rcol, rval, p, p1, one, col, v);
-        gather_fma<BT, E, CPL, U>(col, v, p, p1, B, rs, ldb, cok, coff, one, cold_aux, acc);
+        gather_fma<BT, E, CPL, U, POL>(col, v, p, p1, B, rs, ldb, cok, coff, one, cold_aux, acc);
     }
 }
 
@@ -465,7 +475,7 @@ constexpr int unroll_of() { return E == 1 ? 4 : (CPL == 1 ? 8 : 4); }
 
 // ------------------------------------------------------------------------------------------
 // One segment (of one panel) per wavefront: wid in [0, n_seg * n_panels).
-template <int VT, int BT, int E, int CPL>
+template <int VT, int BT, int E, int CPL, bool POL>
 __device__ __forceinline__ void segment_item(const DevPlan &P, const RunArgs &a, int wid) {
     const int panel = wid / P.n_seg, sid = wid - panel * P.n_seg;
     const int ncol0 = panel * a.np, ncols = min(a.np, P.n - ncol0);
@@ -475,7 +485,7 @@ __device__ __forceinline__ void segment_item(const DevPlan &P, const RunArgs &a,
     for (int c = 0; c < CPL; ++c)
 #pragma unroll
         for (int e = 0; e < E; ++e) acc[c][e] = 0.0f;
-    seg_accumulate<VT, BT, E, CPL, unroll_of<E, CPL>()>(P.rem_col, P.rem_val, P.seg_begin[sid],
+    seg_accumulate<VT, BT, E, CPL, unroll_of<E, CPL>(), POL>(P.rem_col, P.rem_val, P.seg_begin[sid],
                                                         P.seg_end[sid], a.B, a.ldb, ncol0, ncols,
                                                         L, a.cold_aux, acc);
     group_reduce<E, CPL>(acc, L);
@@ -514,7 +524,7 @@ __device__ __forceinline__ void vector_item(const DevPlan &P, const RunArgs &a, 
 #pragma unroll
             for (int x = 0; x < E; ++x) acc[c][x] = 0.0f;
         if (e - b <= P.seg_len) {
-            seg_accumulate<VT, BT, E, CPL, unroll_of<E, CPL>()>(P.rem_col, P.rem_val, b, e, a.B,
+            seg_accumulate<VT, BT, E, CPL, unroll_of<E, CPL>(), true>(P.rem_col, P.rem_val, b, e, a.B,
                                                                 a.ldb, ncol0, ncols, L, a.cold_aux,
                                                                 acc);
             group_reduce<E, CPL>(acc, L);
@@ -573,13 +583,8 @@ __device__ __forceinline__ void vector_item_pipelined(const DevPlan &P, const Ru
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) {
                     const int64_t boff = (int64_t)(col[u] & 0x7FFFFFFF) * a.ldb + coff[c];
-                    if (ok && cok[c] && (col[u] < 0 || a.cold_aux < 0)) {
-                        load_raw<BT, E, false>(a.B, boff, bv[u][c]);
-                    } else if (ok && cok[c]) {
-                        load_raw_policy<BT, E>(rs, boff, a.cold_aux, bv[u][c]);
-                    } else {
-                        zero_raw<BT, E>(bv[u][c]);
-                    }
+                    if (ok && cok[c]) load_raw<BT, E, false>(a.B, boff, bv[u][c]);
+                    else zero_raw<BT, E>(bv[u][c]);
                 }
             }
             // the next row's first batch, in flight behind the gathers
@@ -820,10 +825,10 @@ __device__ __forceinline__ void vector_item_classed(const DevPlan &P, const RunA
     }
 }
 
-template <int VT, int BT, int E, int CPL>
+template <int VT, int BT, int E, int CPL, bool POL>
 __global__ __launch_bounds__(256) void segment_kernel(DevPlan P, RunArgs a) {
     const int wid = logical_block(a.xcd) * 4 + (threadIdx.x >> 6);
-    if (wid < P.n_seg * a.n_panels) segment_item<VT, BT, E, CPL>(P, a, wid);
+    if (wid < P.n_seg * a.n_panels) segment_item<VT, BT, E, CPL, POL>(P, a, wid);
 }
 
 template <int VT, int BT, int E, int CPL, int VAR>
@@ -1131,11 +1136,11 @@ __global__ __launch_bounds__(256) void window_partial_kernel(DevPlan P, RunArgs 
         }                                                                              \
     } while (0)
 
-template <int VT, int BT, int E, int CPL>
+template <int VT, int BT, int E, int CPL, bool POL>
 __global__ __launch_bounds__(256) void batch_segment_kernel(const BatchHeader *__restrict__ hdr,
                                                             const BatchEntry *__restrict__ tab) {
     const int sub = threadIdx.x >> 6;
-    SPMM_XCD_WALK(x_seg, seg_end, seg_base, 4, (segment_item<VT, BT, E, CPL>(tab[d].P, tab[d].a, item)));
+    SPMM_XCD_WALK(x_seg, seg_end, seg_base, 4, (segment_item<VT, BT, E, CPL, POL>(tab[d].P, tab[d].a, item)));
 }
 
 template <int VT, int BT, int E, int CPL, int VAR>
@@ -1181,20 +1186,27 @@ __global__ __launch_bounds__(256) void copy_kernel(const f32x4 *__restrict__ src
 
 static inline unsigned grid_for_waves(int64_t waves) { return (unsigned)((waves + 3) / 4); }
 
-template <int VT, int BT>
-static hipError_t seg_dispatch(const DevPlan &P, const RunArgs &a, hipStream_t s) {
+template <int VT, int BT, bool POL>
+static hipError_t seg_dispatch_pol(const DevPlan &P, const RunArgs &a, hipStream_t s) {
     const int64_t waves = (int64_t)P.n_seg * a.n_panels;
     if (waves == 0) return hipSuccess;
     constexpr int EV = BT == DT_F32 ? 4 : 8;
     const int chunks = a.vec_ok ? (a.np + EV - 1) / EV : a.np;
     dim3 grid(grid_for_waves(waves)), block(256);
     if (a.vec_ok) {
-        if (chunks <= 64) hipLaunchKernelGGL((segment_kernel<VT, BT, EV, 1>), grid, block, 0, s, P, a);
-        else hipLaunchKernelGGL((segment_kernel<VT, BT, EV, 2>), grid, block, 0, s, P, a);
+        if (chunks <= 64) hipLaunchKernelGGL((segment_kernel<VT, BT, EV, 1, POL>), grid, block, 0, s, P, a);
+        else hipLaunchKernelGGL((segment_kernel<VT, BT, EV, 2, POL>), grid, block, 0, s, P, a);
     } else {
-        hipLaunchKernelGGL((segment_kernel<VT, BT, 1, 2>), grid, block, 0, s, P, a);
+        hipLaunchKernelGGL((segment_kernel<VT, BT, 1, 2, POL>), grid, block, 0, s, P, a);
     }
     return hipGetLastError();
+}
+
+template <int VT, int BT>
+static hipError_t seg_dispatch(const DevPlan &P, const RunArgs &a, hipStream_t s) {
+    // the per-entry cache-policy choice only for plans with a cold policy
+    return a.cold_aux >= 0 ? seg_dispatch_pol<VT, BT, true>(P, a, s)
+                           : seg_dispatch_pol<VT, BT, false>(P, a, s);
 }
 
 template <int VT, int BT, int VAR>
@@ -1294,7 +1306,7 @@ static hipError_t batch_variant(const BatchHeader *hdr, const BatchEntry *tab, u
             occ_win, batch_window_kernel<VT, BT, TT, E, CPL, false>, 256, 0);
     }
     // phase 1: partial sums (segments, window tile chunks); phase 2: owners
-    hipLaunchKernelGGL((batch_segment_kernel<VT, BT, E, CPL>), dim3(gw), dim3(256), 0, s, hdr, tab);
+    hipLaunchKernelGGL((batch_segment_kernel<VT, BT, E, CPL, VAR == 0>), dim3(gw), dim3(256), 0, s, hdr, tab);
     hipLaunchKernelGGL((batch_window_kernel<VT, BT, TT, E, CPL, true>), dim3(gwin), dim3(256), 0, s,
                        hdr, tab);
     hipLaunchKernelGGL((batch_vector_kernel<VT, BT, E, CPL, VAR>), dim3(gw), dim3(256), 0, s, hdr, tab);

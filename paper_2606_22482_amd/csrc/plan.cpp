@@ -96,6 +96,7 @@ void resolve_options(const spmm_opts *in, const spmm_csr *A, int32_t n, int32_t 
         const int np = d.n_panel > 0 ? std::min(d.n_panel, std::max(n, 1)) : std::max(n, 1);
         const int chunks = std::min((np + 7) / 8, 128);
         d.pipeline = (b_type != SPMM_F32 && chunks <= 16) ? 3 : 2;
+        if (d.cold_policy > 0) d.pipeline = 0;  // only the row-by-row variant selects policies
     }
     if (d.win_sched < 0) d.win_sched = 0;  // window id order: B rows reused in L2
     if (d.local_reorder < 0) d.local_reorder = 0;
@@ -337,6 +338,10 @@ spmm_status validate_opts(const spmm_opts &o, std::string &err) {
     }
     if (o.cold_policy != 0 && o.cold_policy != 2 && o.cold_policy != 16 && o.cold_policy != 18) {
         err = "cold_policy must be 0, 2, 16 or 18";
+        return SPMM_ERR_UNSUPPORTED;
+    }
+    if (o.cold_policy != 0 && o.pipeline != 0) {
+        err = "a cold policy needs the row-by-row vector variant (pipeline 0)";
         return SPMM_ERR_UNSUPPORTED;
     }
     if (!std::isfinite(o.alpha) || o.alpha < 0 || !std::isfinite(o.alpha_c) || o.alpha_c < 0) {

@@ -76,6 +76,8 @@ def test_validation_codes(lib):
     assert _status(lib, A, opts=api.default_opts(window_h=24)) == L.SPMM_ERR_UNSUPPORTED
     assert _status(lib, A, opts=api.default_opts(kt=16)) == L.SPMM_ERR_UNSUPPORTED
     assert _status(lib, A, opts=api.default_opts(win_sched=2)) == L.SPMM_ERR_UNSUPPORTED
+    assert _status(lib, A, opts=api.default_opts(cold_policy=2, pipeline=2)) == L.SPMM_ERR_UNSUPPORTED
+    assert _status(lib, A, opts=api.default_opts(cold_policy=2)) == L.SPMM_OK
     assert _status(lib, A, opts=api.default_opts(mode="mixed", row_order="original_ranges",
                                                   local_reorder=32)) == L.SPMM_ERR_UNSUPPORTED
     assert _status(lib, A, opts=api.default_opts(mode="mixed", row_order="compacted",

@@ -429,6 +429,22 @@ def test_plan_image_runs_bitwise():
     parity(C2, A, B, "bf16", TOL_16)
 
 
+@pytest.mark.parametrize("policy", [2, 16, 18])
+def test_cold_gather_policies_bitwise(policy):
+    """Gathers of cold B rows with non-temporal / sc1 cache policies (and the
+    hottest rows with the default one) change only where lines are cached:
+    C equals the default-policy run bit for bit, segments included."""
+    import torch
+    A = synth.chung_lu_graph(30000, 2.1, 16.0, 3000.0, 71)
+    B = np.random.default_rng(8).standard_normal((30000, 64)).astype(np.float32)
+    p0, C0 = run(A, B, "f32", api.default_opts(mode="plain", seg_len=60, pipeline=0))
+    p1, C1 = run(A, B, "f32", api.default_opts(mode="plain", seg_len=60, cold_policy=policy))
+    s1 = p1.stats()
+    assert s1["opts"]["pipeline"] == 0 and s1["hot_cols"] > 0 and s1["segments"] > 0
+    assert torch.equal(C0, C1)
+    parity(C1, A, B, "f32", TOL_F32)
+
+
 def test_destroy_busy_plan_rejected():
     import torch
     A = synth.random_csr(2000, 2000, 0.01, 3)
