@@ -786,13 +786,16 @@ __device__ __forceinline__ void vector_item_classed(const DevPlan &P, const RunA
             sid += __shfl(nincl, k - 1, 64);
         }
         if (jr < 0) my_b = my_e = 0;
-        const int smax = __shfl(cls, 0, 64);  // the pass's largest class
+        const int smax = __builtin_amdgcn_readfirstlane(cls);  // the pass's largest class (lane 0)
+        const bool writes = jr >= 0 && local == 0;  // the first group of a row's block stores it
 
         float acc[CPL][E];
 #pragma unroll
         for (int c = 0; c < CPL; ++c)
 #pragma unroll
             for (int x = 0; x < E; ++x) acc[c][x] = 0.0f;
+        // split rows (no entries left to gather) start from their segment sums
+        if (jr >= 0 && my_ns > 0) sum_partials<E, CPL>(a.work, a.work_ld, my_sid, my_ns, ncol0, ncols, L, acc);
         Lanes Ls = L;
         Ls.groups = my_s;
         for (int p = my_b + local; p < my_e; p += my_s * U) {
@@ -802,7 +805,6 @@ __device__ __forceinline__ void vector_item_classed(const DevPlan &P, const RunA
             gather_fma<BT, E, CPL, U>(col, v, p, my_e, a.B, rs, a.ldb, cok, coff, Ls, a.cold_aux,
                                       acc);
         }
-        if (jr >= 0 && my_ns > 0) sum_partials<E, CPL>(a.work, a.work_ld, my_sid, my_ns, ncol0, ncols, L, acc);
         // butterfly inside each block, from the pass's largest class down
         for (int off = (smax * L.lpr) >> 1; off >= L.lpr; off >>= 1) {
             const bool take = off < my_s * L.lpr;
@@ -814,7 +816,7 @@ __device__ __forceinline__ void vector_item_classed(const DevPlan &P, const RunA
                     if (take) acc[c][x] += t;
                 }
         }
-        if (jr >= 0 && local == 0) {
+        if (writes) {
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
                 const int q = c * L.lpr + L.li;
