@@ -232,6 +232,17 @@ spmm_status spmm_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_ty
                       const spmm_opts *opts, spmm_plan_t **out);
 /* Release a plan.  BUSY while batched submissions that use it are unfinished. */
 spmm_status spmm_plan_destroy(spmm_plan_t *p);
+/* A plain plan built on the device from a CSR whose rowptr, colidx and vals
+ * are device pointers (sizes as in spmm_csr), work enqueued on `stream`
+ * (which is synchronised): the CSR checks, row lengths (Eq. 4), the item cut,
+ * the launch order and the segments run as kernels, and A's entries are
+ * copied device to device; only O(m) schedule arrays are read back for
+ * statistics.  The result equals spmm_plan's plain plan of the same matrix
+ * and options array for array.  UNSUPPORTED for a mode other than AUTO or
+ * PLAIN_F32, a cold policy, or item_cost > 4096; INVALID for a malformed CSR
+ * (found on the device, before anything is indexed by it). */
+spmm_status spmm_plan_device(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
+                             const spmm_opts *opts, void *stream, spmm_plan_t **out);
 /* Plan images, so that a plan is built once and loaded by later processes
  * (Sec. 5.2.2 preprocessing is amortised over many runs).  serialize writes a
  * versioned, checksummed image of the host plan into buf (cap bytes) and its

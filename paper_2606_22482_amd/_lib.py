@@ -100,6 +100,8 @@ SIGNATURES = {
     "spmm_plan": (_S, [C.POINTER(Csr), C.c_int32, C.c_int32, C.c_int32, C.POINTER(Opts),
                        C.POINTER(_P)]),
     "spmm_plan_destroy": (_S, [_P]),
+    "spmm_plan_device": (_S, [C.POINTER(Csr), C.c_int32, C.c_int32, C.c_int32, C.POINTER(Opts), _P,
+                              C.POINTER(_P)]),
     "spmm_plan_serialize": (_S, [_P, _P, C.c_int64, C.POINTER(C.c_int64)]),
     "spmm_plan_deserialize": (_S, [_P, C.c_int64, C.c_int32, C.POINTER(_P)]),
     "spmm_plan_stats": (_S, [_P, C.POINTER(PlanStats)]),

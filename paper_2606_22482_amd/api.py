@@ -124,6 +124,30 @@ class Plan:
         return buf.raw[: size.value]
 
     @classmethod
+    def on_device(cls, rowptr, colidx, vals, m: int, k: int, n: int, b_kind: str,
+                  opts: "L.Opts | None" = None, stream=None) -> "Plan":
+        """spmm_plan_device: a plain plan built on the device from device
+        tensors rowptr (int64, m+1), colidx (int32, nnz) and vals (nnz)."""
+        import torch
+        lib = L.load()
+        for t, what in ((rowptr, "rowptr"), (colidx, "colidx"), (vals, "vals")):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("%s must be a contiguous device tensor" % what)
+        if rowptr.dtype != torch.int64 or colidx.dtype != torch.int32:
+            raise ValueError("rowptr must be int64 and colidx int32")
+        kind = _kind_of_tensor(vals)
+        csr = L.Csr(int(m), int(k), int(colidx.numel()), rowptr.data_ptr(), colidx.data_ptr(),
+                    vals.data_ptr(), L.KIND_CODE[kind], 0)
+        h = C.c_void_p()
+        L.check(lib.spmm_plan_device(C.byref(csr), int(n), L.KIND_CODE[b_kind], L.F32,
+                                     C.byref(opts) if opts is not None else None,
+                                     _stream_handle(stream), C.byref(h)))
+        p = cls.__new__(cls)
+        p._lib, p._h, p._keep = lib, h, None
+        p.n, p.m, p.k, p.b_kind = int(n), int(m), int(k), b_kind
+        return p
+
+    @classmethod
     def deserialize(cls, image: bytes, upload=True) -> "Plan":
         """spmm_plan_deserialize: a plan from an image written by serialize."""
         lib = L.load()

@@ -115,8 +115,8 @@ static bool dtype_pair_ok(int32_t v, int32_t b) {
            (v == SPMM_BF16 && b == SPMM_BF16) || (v == SPMM_F16 && b == SPMM_F16);
 }
 
-spmm_status validate_problem(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
-                             std::string &err) {
+spmm_status validate_shape(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
+                           std::string &err) {
     if (!A) { err = "A is null"; return SPMM_ERR_INVALID; }
     if (A->m < 0 || A->k < 0 || A->nnz < 0) { err = "negative size"; return SPMM_ERR_INVALID; }
     if (n < 1) { err = "n must be >= 1"; return SPMM_ERR_INVALID; }
@@ -135,6 +135,13 @@ spmm_status validate_problem(const spmm_csr *A, int32_t n, int32_t b_type, int32
     }
     if (!A->rowptr) { err = "rowptr is null"; return SPMM_ERR_INVALID; }
     if (A->nnz > 0 && (!A->colidx || !A->vals)) { err = "colidx/vals null"; return SPMM_ERR_INVALID; }
+    return SPMM_OK;
+}
+
+spmm_status validate_problem(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
+                             std::string &err) {
+    spmm_status st = validate_shape(A, n, b_type, c_type, err);
+    if (st != SPMM_OK) return st;
     if (A->rowptr[0] != 0) { err = "rowptr[0] != 0"; return SPMM_ERR_INVALID; }
     for (int64_t r = 0; r < A->m; ++r)
         if (A->rowptr[r + 1] < A->rowptr[r]) { err = "rowptr not monotone"; return SPMM_ERR_INVALID; }
@@ -564,20 +571,23 @@ spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_
         }
     };
 
-    // vector items: consecutive vector rows with balanced cost (Sec. 7)
+    // vector items: consecutive vector rows with balanced cost (Sec. 7).  Row i
+    // (in vector-row order) belongs to item floor(c_i / item_cost), c_i the
+    // summed cost of the rows before it (empty items dropped): a rule of prefix
+    // sums, so a device-side builder reproduces it exactly.
     P.vitem_ptr.push_back(0);
     {
-        int64_t acc = 0;
+        int64_t before = 0, bucket = -1;
         const int64_t nv = (int64_t)P.vector_rows.size();
         for (int64_t i = 0; i < nv; ++i) {
             int32_t r = P.vector_rows[i];
             int64_t L = P.rem_ptr[r + 1] - P.rem_ptr[r];
-            acc += kRowCost + (P.nseg[r] ? P.nseg[r] : L);
-            if (acc >= o.item_cost || i + 1 == nv) {
-                P.vitem_ptr.push_back((int32_t)(i + 1));
-                acc = 0;
-            }
+            const int64_t b = before / o.item_cost;
+            if (i > 0 && b != bucket) P.vitem_ptr.push_back((int32_t)i);
+            bucket = b;
+            before += kRowCost + (P.nseg[r] ? P.nseg[r] : L);
         }
+        if (nv > 0) P.vitem_ptr.push_back((int32_t)nv);
         // the size-class variant takes each item's rows longest first, so that
         // rows of one size class are packed side by side; split rows go last
         if (o.pipeline == 3 && nv > 0) {

@@ -69,6 +69,10 @@ constexpr double kHotFraction = 0.8;                   // cap of the cached B wo
 void resolve_options(const spmm_opts *in, const spmm_csr *A, int32_t n, int32_t b_type,
                      spmm_opts *o);
 
+// Sizes, dtypes and null pointers only (the arrays are not read).
+spmm_status validate_shape(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
+                           std::string &err);
+
 // Validate the CSR and sizes.  Returns SPMM_OK or an error with a message.
 spmm_status validate_problem(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
                              std::string &err);

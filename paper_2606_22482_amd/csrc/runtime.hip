@@ -230,6 +230,8 @@ extern "C" spmm_status spmm_plan(const spmm_csr *A, int32_t n, int32_t b_type, i
 extern "C" spmm_status spmm_plan_serialize(const spmm_plan_t *p, void *buf, int64_t cap,
                                            int64_t *size) {
     if (!p || !size) return set_error(SPMM_ERR_INVALID, "null argument");
+    spmm_status st0 = ensure_host_remainder(const_cast<spmm_plan_t *>(p));
+    if (st0 != SPMM_OK) return st0;
     try {
         std::vector<uint8_t> img;
         serialize_host_plan(p->hp, img);
@@ -286,6 +288,22 @@ double algorithmic_bytes(const HostPlan &h) {
 }
 }  // namespace spmm
 
+namespace spmm {
+spmm_status ensure_host_remainder(spmm_plan_t *p) {
+    std::lock_guard<std::mutex> lk(p->host_mu);
+    HostPlan &h = p->hp;
+    if (!p->rem_device_only || (int64_t)h.rem_col.size() == h.nnz) return SPMM_OK;
+    const size_t n = (size_t)h.nnz, sval = (size_t)dtype_size(h.val_type);
+    h.rem_col.resize(n);
+    h.rem_val.resize(n * sval);
+    SPMM_TRY_HIP(hipMemcpy(h.rem_col.data(), p->dp.rem_col, 4 * n, hipMemcpyDeviceToHost), "hipMemcpy(plan)");
+    SPMM_TRY_HIP(hipMemcpy(h.rem_val.data(), p->dp.rem_val, sval * n, hipMemcpyDeviceToHost), "hipMemcpy(plan)");
+    h.rem_src.resize(n);
+    for (size_t i = 0; i < n; ++i) h.rem_src[i] = (int64_t)i;  // plain: entry p is remainder entry p
+    return SPMM_OK;
+}
+}  // namespace spmm
+
 extern "C" spmm_status spmm_plan_stats(const spmm_plan_t *p, spmm_plan_stats_t *out) {
     if (!p || !out) return set_error(SPMM_ERR_INVALID, "null argument");
     const HostPlan &h = p->hp;
@@ -297,7 +315,7 @@ extern "C" spmm_status spmm_plan_stats(const spmm_plan_t *p, spmm_plan_stats_t *
     out->windows = (int64_t)h.win_order.size();
     out->tiles = (int64_t)h.tile_window.size();
     out->nnz_tiles = (int64_t)h.tile_src.size();
-    out->nnz_remainder = (int64_t)h.rem_src.size();
+    out->nnz_remainder = p->rem_device_only ? h.nnz : (int64_t)h.rem_src.size();
     out->vector_rows = (int64_t)h.vector_rows.size();
     out->segments = (int64_t)h.seg_row.size();
     out->vector_items = (int64_t)h.vitem_ptr.size() - 1;
@@ -318,6 +336,10 @@ extern "C" spmm_status spmm_plan_stats(const spmm_plan_t *p, spmm_plan_stats_t *
 
 extern "C" spmm_status spmm_plan_export(const spmm_plan_t *p, spmm_plan_dump_t *out) {
     if (!p || !out) return set_error(SPMM_ERR_INVALID, "null argument");
+    {
+        spmm_status st = ensure_host_remainder(const_cast<spmm_plan_t *>(p));
+        if (st != SPMM_OK) return st;
+    }
     const HostPlan &h = p->hp;
     std::memset(out, 0, sizeof(*out));
     out->m = h.m;

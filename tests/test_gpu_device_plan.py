@@ -1,0 +1,113 @@
+"""Plain plans built on the device (spmm_plan_device) from a CSR in device
+memory equal the host builder's plans array for array, run to the same C bit
+for bit, and a malformed device CSR is refused by the device-side checks."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from gpu_util import TOL_F32, device_B, device_C, parity
+from paper_2606_22482_amd import _lib as L
+from paper_2606_22482_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L.load()
+
+
+def device_csr(A):
+    import torch
+    rp = torch.from_numpy(np.ascontiguousarray(A.rowptr, dtype=np.int64)).cuda()
+    ci = torch.from_numpy(np.ascontiguousarray(A.colidx, dtype=np.int32)).cuda()
+    v = np.ascontiguousarray(A.vals)
+    if A.val_kind == "f32":
+        vt = torch.from_numpy(v.astype(np.float32)).cuda()
+    else:
+        vt = torch.from_numpy(v.view(np.int16)).view(
+            torch.bfloat16 if A.val_kind == "bf16" else torch.float16).cuda()
+    return rp, ci, vt
+
+
+CASES = [
+    ("graph", "f32", "f32", 64, dict(seg_len=40)),
+    ("graph", "f16", "f16", 32, dict(seg_len=50)),                      # size-class variant
+    ("graph", "bf16", "bf16", 128, dict(seg_len=7, item_cost=100)),
+    ("graph", "f32", "f32", 33, dict(seg_len=300, pipeline=0)),
+    ("random", "f32", "bf16", 16, dict(seg_len=5, item_cost=4096, pipeline=3)),
+    ("empty", "f32", "f32", 8, dict()),
+]
+
+
+def _matrix(kind, vk):
+    if kind == "graph":
+        return synth.chung_lu_graph(20000, 2.1, 14.0, 2500.0, 31, val_kind=vk, values="uniform")
+    if kind == "random":
+        return synth.random_csr(5000, 3000, 0.004, 9, val_kind=vk, dup_frac=0.05, empty_rows=0.2)
+    return synth.random_csr(0, 50, 0.1, 1, val_kind=vk)
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_device_plan_equals_host_plan(case):
+    import torch
+    kind, vk, bk, n, kw = CASES[case]
+    A = _matrix(kind, vk)
+    opts = api.default_opts(mode="plain", **kw)
+    host = api.Plan(A, n, bk, opts)
+    rp, ci, vt = device_csr(A)
+    dev = api.Plan.on_device(rp, ci, vt, A.m, A.k, n, bk, opts)
+    sh, sd = host.stats(), dev.stats()
+    for key in ("vector_items", "segments", "k_ref", "workspace_bytes", "nnz_remainder",
+                "vector_rows", "algorithmic_bytes"):
+        assert sh[key] == sd[key], key
+    assert sh["opts"] == sd["opts"]
+    dh, dd = host.export(), dev.export()
+    for key in ("rem_ptr", "rem_src", "vector_rows", "nseg", "vitem_ptr", "vitem_seg",
+                "vexec_rows", "seg_row", "seg_begin", "seg_end", "rem_col_dev"):
+        assert np.array_equal(dh[key], dd[key]), key
+    if A.m == 0:
+        return
+    B = synth.dense_values(np.random.default_rng(case), (A.k, n), bk)
+    Bd = device_B(B, bk)
+    C1, C2 = device_C(A.m, n), device_C(A.m, n)
+    host.run(Bd, C1)
+    dev.run(Bd, C2)
+    torch.cuda.synchronize()
+    assert torch.equal(C1, C2)
+    parity(C2, A, B, bk, TOL_F32)
+    # the device plan's image loads as an ordinary plan
+    q = api.Plan.deserialize(dev.serialize())
+    C3 = device_C(A.m, n)
+    q.run(Bd, C3)
+    torch.cuda.synchronize()
+    assert torch.equal(C1, C3)
+
+
+def _status(rp, ci, vt, m, k, opts=None):
+    lib = L.load()
+    csr = L.Csr(m, k, int(ci.numel()), rp.data_ptr(), ci.data_ptr(), vt.data_ptr(), L.F32, 0)
+    h = C.c_void_p()
+    st = lib.spmm_plan_device(C.byref(csr), 8, L.F32, L.F32,
+                              C.byref(opts) if opts is not None else None, None, C.byref(h))
+    if st == L.SPMM_OK:
+        lib.spmm_plan_destroy(h)
+    return st, lib.spmm_last_error().decode()
+
+
+def test_device_checks_refuse_a_bad_csr():
+    A = synth.random_csr(300, 200, 0.05, 4)
+    rp, ci, vt = device_csr(A)
+    assert _status(rp, ci, vt, A.m, A.k)[0] == L.SPMM_OK
+    bad_rp = rp.clone()
+    bad_rp[10], bad_rp[11] = rp[11] + 1, rp[10]          # not monotone
+    assert _status(bad_rp, ci, vt, A.m, A.k) == (L.SPMM_ERR_INVALID, "rowptr not monotone from 0 to nnz")
+    bad_ci = ci.clone()
+    bad_ci[7] = A.k                                    # column out of range
+    assert _status(rp, bad_ci, vt, A.m, A.k) == (L.SPMM_ERR_INVALID, "column index out of range")
+    st, _ = _status(rp, ci, vt, A.m, A.k, api.default_opts(mode="mixed"))
+    assert st == L.SPMM_ERR_UNSUPPORTED
