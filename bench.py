@@ -130,6 +130,48 @@ def cpu_baseline(A, B, b_kind, n, budget_s=12.0):
                       % (rows, m, 100.0 * nnz / max(1, A.nnz), n, dt)}
 
 
+def plan_time_bench(A, B, b_kind, wname, n, args):
+    """Plain-plan construction: host build + upload (A on the host) vs the
+    device builder (A already in device memory), median of several builds,
+    and both plans' run time."""
+    import torch
+    from paper_2606_22482_amd import api
+    opts = api.default_opts(mode="plain", **parse_opts(args.opts))
+    rp = torch.from_numpy(np.ascontiguousarray(A.rowptr, dtype=np.int64)).cuda()
+    ci = torch.from_numpy(np.ascontiguousarray(A.colidx, dtype=np.int32)).cuda()
+    vt = torch.from_numpy(np.ascontiguousarray(A.vals, dtype=np.float32)).cuda() \
+        if A.val_kind == "f32" else None
+    if vt is None:
+        raise SystemExit("--plan-time expects f32 values")
+    host_ms, dev_ms = [], []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ph = api.Plan(A, n, b_kind, opts)
+        torch.cuda.synchronize()
+        host_ms.append((time.perf_counter() - t0) * 1e3)
+        t0 = time.perf_counter()
+        pd = api.Plan.on_device(rp, ci, vt, A.m, A.k, n, b_kind, opts)
+        torch.cuda.synchronize()
+        dev_ms.append((time.perf_counter() - t0) * 1e3)
+    Bd = api.device_tensor(B, b_kind)
+    Cd = torch.empty((A.m, n), dtype=torch.float32, device="cuda")
+    runs = {}
+    for name, p in (("host", ph), ("device", pd)):
+        for _ in range(3):
+            p.run(Bd, Cd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            p.run(Bd, Cd)
+        torch.cuda.synchronize()
+        runs[name] = (time.perf_counter() - t0) * 1e3 / args.steps
+    out = {"workload": wname, "host_build_upload_ms": round(float(np.median(host_ms)), 2),
+           "device_build_ms": round(float(np.median(dev_ms)), 2),
+           "run_ms": {k: round(v, 4) for k, v in runs.items()}}
+    print(json.dumps(out), flush=True)
+
+
 def parse_opts(text):
     """"k=v,k=v" plan options (alpha* floats, mode/row_order names, others ints)."""
     out = {}
@@ -238,6 +280,8 @@ def main():
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--max-batch", type=int, default=64)
     ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--plan-time", action="store_true",
+                    help="time plan construction: host build + upload vs built on the device")
     ap.add_argument("--adapt-from", type=float, default=0.0,
                     help="mixed mode: start from this tile threshold and run the epoch-level "
                          "re-partition (spmm_adapt_epoch) until it stops, before timing")
@@ -279,6 +323,8 @@ def main():
     A, B, b_kind, wname = workload(args.workload)
     n = B.shape[1]
     log("workload %s: m=%d nnz=%d n=%d (%.1f s)" % (wname, A.m, A.nnz, n, time.perf_counter() - t0))
+    if args.plan_time:
+        return plan_time_bench(A, B, b_kind, wname, n, args)
     extra = parse_opts(args.opts)
 
     Bd = api.device_tensor(B, b_kind)
