@@ -400,6 +400,7 @@ spmm_status workspace_for(hipStream_t s, size_t bytes, float **out) {
     std::lock_guard<std::mutex> lk(g_ws_mu);
     Workspace &w = g_ws[{dev, s}];
     if (w.bytes < bytes) {
+        const size_t old = w.bytes;
         if (w.ptr) {
             // earlier work on this stream may still read the old buffer
             SPMM_TRY_HIP(hipStreamSynchronize(s), "hipStreamSynchronize(workspace)");
@@ -407,7 +408,7 @@ spmm_status workspace_for(hipStream_t s, size_t bytes, float **out) {
             w.ptr = nullptr;
             w.bytes = 0;
         }
-        size_t want = std::max(bytes, w.bytes * 2);
+        size_t want = std::max(bytes, old * 2);
         hipError_t e = hipMalloc(&w.ptr, want);
         if (e != hipSuccess) {
             w.ptr = nullptr;
