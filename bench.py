@@ -175,9 +175,27 @@ def plan_time_bench(A, B, b_kind, wname, n, args):
             p.run(Bd, Cd)
         torch.cuda.synchronize()
         runs[name] = (time.perf_counter() - t0) * 1e3 / args.steps
+    # B handed over in pinned host memory and C returned there: the rate a
+    # caller sees when its dense operands live on the host (PCIe included)
+    Bh = Bd.cpu().pin_memory()
+    Ch = torch.empty(Cd.shape, dtype=Cd.dtype).pin_memory()
+    pcie = []
+    for _ in range(max(3, min(args.steps, 10))):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Bd.copy_(Bh, non_blocking=True)
+        pd.run(Bd, Cd)
+        Ch.copy_(Cd, non_blocking=True)
+        torch.cuda.synchronize()
+        pcie.append((time.perf_counter() - t0) * 1e3)
+    pcie_ms = float(np.median(pcie))
     out = {"workload": wname, "host_build_upload_ms": round(float(np.median(host_ms)), 2),
            "device_build_ms": round(float(np.median(dev_ms)), 2),
-           "run_ms": {k: round(v, 4) for k, v in runs.items()}}
+           "run_ms": {k: round(v, 4) for k, v in runs.items()},
+           "pcie_inclusive_ms": round(pcie_ms, 3),
+           "pcie_inclusive_gflops": round(2.0 * A.nnz * n / (pcie_ms * 1e-3) / 1e9, 1),
+           "b_bytes": int(Bd.numel() * Bd.element_size()),
+           "c_bytes": int(Cd.numel() * Cd.element_size())}
     print(json.dumps(out), flush=True)
 
 

@@ -24,7 +24,7 @@ struct DevPlan {
     const int32_t *windows;    // [n_win*H]
     const int32_t *win_tile_ptr;  // [n_win+1]
     const int32_t *win_seg;    // [n_win]
-    const int32_t *win_order;  // [n_win]
+    const int32_t *win_order;  // [n_win], or null when windows run in id order
     const int32_t *tile_cols;  // [T*kt]
     const uint32_t *tile_bitmap;  // [T*H]
     const int32_t *tile_val_ptr;  // [T+1]
@@ -34,6 +34,7 @@ struct DevPlan {
     const int32_t *wpart_win;   // [n_wpart]
     const int32_t *wpart_t0;    // [n_wpart]
     const int32_t *wpart_t1;    // [n_wpart]
+    const uint16_t *zeros;      // 256 zero bytes (source of staged padding columns)
 };
 
 // Launch geometry and operand description of one execution.

@@ -376,6 +376,20 @@ __device__ __forceinline__ void gather_fma(const int (&col)[U], const float (&v)
     }
 }
 
+// acc += v_u * b_u over the entries below p1, in entry order (the FMA half of
+// gather_fma, for B chunks gathered earlier by the caller).
+template <int BT, int E, int CPL, int U>
+__device__ __forceinline__ void fma_rows(const float (&v)[U], const Raw<BT, E> (&b)[U][CPL], int p,
+                                         int p1, const Lanes &L, float (&acc)[CPL][E]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if (p + u * L.groups < p1) {
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) fma_raw<BT, E>(v[u], b[u][c], acc[c]);
+        }
+    }
+}
+
 template <int E, int CPL>
 __device__ __forceinline__ void chunk_layout(int ncol0, int ncols, const Lanes &L, bool (&cok)[CPL],
                                              int64_t (&coff)[CPL]) {
@@ -850,12 +864,17 @@ __global__ __launch_bounds__(256) void vector_kernel(DevPlan P, RunArgs a) {
 // LDS of a window item: the staged B rows (reused for the f32 C tile), the
 // window's rows, remainder ranges and segment ids, and the staged tiles'
 // bitmaps, per-row value offsets and packed values.  MB = H / 16.
+// Staged B row k occupies 256 bytes (16 chunks of 8 elements) with chunk c
+// stored in slot c ^ bswz(k): the four 8-row groups that one MFMA operand
+// read touches then fall in different banks without padding, so a wave's
+// 64 x 16-byte chunks are one contiguous kilobyte and can be written by one
+// direct global-to-LDS load.
 template <int MB>
 struct WinSmem {
     static constexpr int NPW = 128;          // panel columns of a window item
     static constexpr int TC = 4;             // tiles staged per round
     static constexpr int KROWS = TC * 32;    // B rows staged per round
-    static constexpr int BSTR = NPW + 2;     // LDS row stride (16-bit elements): odd dword stride
+    static constexpr int BSTR = NPW;         // LDS row stride (16-bit elements)
     static constexpr int H = MB * 16;
     __attribute__((aligned(16))) unsigned short Bs[KROWS * BSTR];
     unsigned short vals[TC * H * 32];
@@ -905,36 +924,71 @@ __device__ __forceinline__ void stage_b8(const void *B, int64_t off, int valid, 
     for (int i = 0; i < 4; ++i) w[i] = h[2 * i] | (h[2 * i + 1] << 16);
 }
 
+// Slot of a chunk in a staged B row (see WinSmem).
+__device__ __forceinline__ int bswz(int k) { return ((k >> 3) & 3) << 1; }
+
 // One (window, 128-column panel) per workgroup: item in [0, n_win * win_panels),
 // panel innermost, so a window's panels run side by side on one XCD and share
 // its tile data in that XCD's L2.
 // Every thread of the workgroup calls it with the same item.  Per round of up
 // to TC tiles, with one barrier: each thread loads the columns of its own B
-// staging chunks and then those B rows (converted to the tile type), each wave
-// its tile's bitmap words and computes the rows' value offsets, and the
-// bitmaps, packed values and (first round) the window's row metadata go to
-// LDS; then MFMA from LDS only.  Then each row adds its remainder and is
-// written once.
+// staging chunks and then those B rows (16-bit B straight into LDS, f32 B
+// through registers, converted to bf16), each wave its tile's bitmap words
+// and computes the rows' value offsets, and the bitmaps, packed values and
+// (first round) the window's row metadata go to LDS; then MFMA from LDS only.
+// Then each row adds its remainder and is written once.
+// A workgroup spends most of its life waiting on chains of dependent loads,
+// so the loads of a round are issued level by level (item -> tile range and
+// window rows -> tile columns, bitmaps, value base and row ranges -> B rows,
+// values and remainder entries -> their B rows) with no branch around a load
+// that would make the next one wait; the window order is skipped when it is
+// the identity; the first remainder pass (window rows 0 .. 4G-1, one per lane
+// group) gathers its rows' first U1 entries alongside the first round's tile
+// loads and consumes them after the MFMA rounds.
 template <int VT, int BT, int TT, int MB, int E, int CPL, int SMB>
 __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, int item,
                                             WinSmem<SMB> &sm, bool partial) {
     constexpr int H = MB * 16;
     using S = WinSmem<SMB>;
     constexpr int NPW = S::NPW, TC = S::TC, BSTR = S::BSTR, KROWS = S::KROWS;
+    constexpr int PER = KROWS * (NPW / 8) / 256;  // 16-byte staging chunks per thread
+    constexpr int U1 = MB == 1 ? 4 : 2;           // remainder entries per row gathered early
     static_assert(MB <= SMB, "LDS sized for a smaller window");
     static_assert(H * NPW * 4 <= KROWS * BSTR * 2, "C tile must fit in the B stage");
+    static_assert(TC * H <= 256, "one staged bitmap word per thread");
     unsigned short *Bs = sm.Bs;
 
     // owner items: (window in launch order, panel), tiles [t0, t0 + win_tmax);
     // partial items: (partial slot, panel), tiles [wpart_t0, wpart_t1)
     const int j_item = item / a.win_panels, panel = item - j_item * a.win_panels;
-    const int wi = partial ? P.wpart_win[j_item] : P.win_order[j_item];
+    const int wi = partial ? P.wpart_win[j_item] : (P.win_order ? P.win_order[j_item] : j_item);
     const int ncol0 = panel * NPW, ncols = min(NPW, P.n - ncol0);
+    const bool full = a.vec_ok && ncols == NPW;  // every staging chunk is whole
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane >> 4, l16 = lane & 15;
     const int t0 = partial ? P.wpart_t0[j_item] : P.win_tile_ptr[wi];
     const int t1 = partial ? P.wpart_t1[j_item] : min(P.win_tile_ptr[wi + 1], t0 + P.win_tmax);
+    const int pa = partial ? 0 : P.win_part[wi], pb = partial ? 0 : P.win_part[wi + 1];
+    const int seg0 = partial ? 0 : P.win_seg[wi];  // first segment id of the window's rows
     float *wpart = a.work + (int64_t)P.n_seg * a.work_ld;  // window partials follow the segments
+
+    // window rows: lane `lane` of every wave holds row lane % H (wave 0 puts
+    // them in LDS), lane group `group` of wave `wave` owns row s1 of the first
+    // remainder pass
+    const Lanes L(a.win_lpr_log2);
+    const Lanes one = L.single();
+    const int s1 = wave * L.groups + L.group;
+    const int64_t wrow0 = (int64_t)(partial ? 0 : wi) * H;
+    const int rm = P.windows[wrow0 + (lane & (H - 1))];
+    const int r1 = P.windows[wrow0 + min(s1, H - 1)];
+
+    bool cok[CPL];
+    int64_t coff[CPL];
+    chunk_layout<E, CPL>(ncol0, ncols, L, cok, coff);
+    int col1[U1];
+    float val1[U1];
+    Raw<BT, E> g1[U1][CPL];
+    int b1 = 0, e1 = 0;
 
     f32x4 acc[MB][2];
 #pragma unroll
@@ -942,64 +996,151 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[mb][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    for (int tc0 = t0; tc0 < t1; tc0 += TC) {
+    auto round = [&](auto first_tag, int tc0) {
+        constexpr bool FIRST = decltype(first_tag)::value;
         const int nt = min(TC, t1 - tc0);
-        if (tc0 != t0) __syncthreads();  // the previous round's LDS reads are done
-        // Everything a round needs is loaded from global memory in two
-        // dependent levels (tile columns -> B rows; value base -> values;
-        // window rows -> remainder ranges) before the round's one barrier.
-        constexpr int PER = KROWS * (NPW / 8) / 256;  // 16-byte staging chunks per thread
+        // level 2: tile columns, bitmap words, value offsets, row ranges
         int colr[PER];
 #pragma unroll
         for (int it = 0; it < PER; ++it) {
             const int kr = (tid + it * 256) >> 4;
-            colr[it] = kr < nt * 32 ? P.tile_cols[(int64_t)tc0 * 32 + kr] : -1;
+            const int c = P.tile_cols[(int64_t)tc0 * 32 + min(kr, nt * 32 - 1)];
+            colr[it] = kr < nt * 32 ? c : -1;
         }
         const int v0 = P.tile_val_ptr[tc0], nv = P.tile_val_ptr[tc0 + nt] - v0;
-        // this wave's tile: bitmap word of row `lane` and the tile's first value
-        const uint32_t wd = (wave < nt && lane < H) ? P.tile_bitmap[(int64_t)(tc0 + wave) * H + lane] : 0u;
-        const int tv = wave < nt ? P.tile_val_ptr[tc0 + wave] : 0;
-        uint32_t w[PER][4];
-#pragma unroll
-        for (int it = 0; it < PER; ++it) {
-            const int n = ((tid + it * 256) & 15) * 8;
-            w[it][0] = w[it][1] = w[it][2] = w[it][3] = 0u;
-            const int valid = min(8, ncols - n);
-            if (colr[it] >= 0 && valid > 0)
-                stage_b8<BT, TT>(a.B, (int64_t)colr[it] * a.ldb + ncol0 + n, valid, a.vec_ok, w[it]);
+        const int wv = min(wave, nt - 1);
+        const uint32_t wd0 = P.tile_bitmap[(int64_t)(tc0 + wv) * H + (lane & (H - 1))];
+        const int tv = P.tile_val_ptr[tc0 + wv];
+        const uint32_t bmw = P.tile_bitmap[(int64_t)tc0 * H + min(tid, nt * H - 1)];
+        int bm_ = 0, em_ = 0;
+        if constexpr (FIRST) {
+            bm_ = P.rem_ptr[max(rm, 0)];
+            em_ = P.rem_ptr[max(rm, 0) + 1];
+            b1 = P.rem_ptr[max(r1, 0)];
+            e1 = P.rem_ptr[max(r1, 0) + 1];
         }
-        for (int i = tid; i < nt * H; i += 256) sm.bm[i] = P.tile_bitmap[(int64_t)tc0 * H + i];
-        for (int i = tid; i < nv; i += 256) sm.vals[i] = P.tile_vals[v0 + i];
-        if (tc0 == t0 && wave == 0 && !partial) {
-            // the window's rows, their remainder ranges and segment ids
-            const int r = lane < H ? P.windows[(int64_t)wi * H + lane] : -1;
-            const int b = r >= 0 ? P.rem_ptr[r] : 0;
-            const int e = r >= 0 ? P.rem_ptr[r + 1] : 0;
-            const int len = e - b;
-            const int ns = len > P.seg_len ? (len + P.seg_len - 1) / P.seg_len : 0;
-            const int x = wave_inclusive_scan(ns);
-            if (lane < H) {
-                sm.rows[lane] = r;
-                sm.rb[lane] = b;
-                sm.re[lane] = e;
-                sm.sid[lane] = P.win_seg[wi] + x - ns;
+        // level 3: packed values, remainder entries, B rows of the staging chunks
+        unsigned short xv[4];
+        const int vlast = v0 + max(nv - 1, 0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) xv[k] = P.tile_vals[min(v0 + k * 256 + tid, vlast)];
+        bool live1 = false, split1 = false;
+        int q1 = 0;
+        if constexpr (FIRST) {
+            live1 = !partial && s1 < H && r1 >= 0;
+            split1 = e1 - b1 > P.seg_len;
+            q1 = live1 && !split1 ? e1 : b1;  // end of the entries gathered here
+            // indices clamped into [0, q1 - 1] (the plan arrays carry a zero
+            // tail for an empty range); entries at and beyond q1 are not used
+#pragma unroll
+            for (int u = 0; u < U1; ++u) {
+                const int pp = max(min(b1 + u, q1 - 1), 0);
+                col1[u] = __builtin_nontemporal_load(P.rem_col + pp);
+                val1[u] = load_val<VT>(P.rem_val, pp);
+            }
+        }
+        // B rows of the staging chunks: thread tid stages, in pass it, row
+        // kr = 16 it + tid / 16 into LDS bytes [4096 it + 16 tid, +16), i.e.
+        // slot tid % 16 of that row, which holds chunk (tid % 16) ^ bswz(kr)
+        if constexpr (BT != DT_F32) {
+            if (full) {
+                // one direct global-to-LDS load per pass and wave; chunks
+                // without a column (tile padding, rows beyond the round) read
+                // the plan's zero block
+#pragma unroll
+                for (int it = 0; it < PER; ++it) {
+                    const int kr = 16 * it + (tid >> 4), cg = (tid & 15) ^ bswz(kr);
+                    const unsigned short *src =
+                        colr[it] >= 0 ? static_cast<const unsigned short *>(a.B) +
+                                            (int64_t)colr[it] * a.ldb + ncol0 + cg * 8
+                                      : P.zeros;
+                    __builtin_amdgcn_global_load_lds(
+                        src, (__attribute__((address_space(3))) void *)(Bs + it * 2048 + wave * 512), 16, 0,
+                        0);
+                }
+            } else {
+#pragma unroll
+                for (int it = 0; it < PER; ++it) {
+                    const int kr = 16 * it + (tid >> 4), cg = (tid & 15) ^ bswz(kr);
+                    uint32_t w[4] = {0u, 0u, 0u, 0u};
+                    const int valid = min(8, ncols - cg * 8);
+                    if (colr[it] >= 0 && valid > 0)
+                        stage_b8<BT, TT>(a.B, (int64_t)colr[it] * a.ldb + ncol0 + cg * 8, valid, a.vec_ok, w);
+                    *reinterpret_cast<u32x4 *>(&Bs[it * 2048 + tid * 8]) = u32x4{w[0], w[1], w[2], w[3]};
+                }
+            }
+        } else {
+            // f32 B, converted to bf16: two passes' loads in flight at a time
+#pragma unroll
+            for (int h = 0; h < PER; h += 2) {
+                uint32_t w[2][4];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int it = h + q, kr = 16 * it + (tid >> 4), cg = (tid & 15) ^ bswz(kr);
+                    w[q][0] = w[q][1] = w[q][2] = w[q][3] = 0u;
+                    const int valid = min(8, ncols - cg * 8);
+                    if (full) {
+                        const float *b = static_cast<const float *>(a.B) +
+                                         (int64_t)max(colr[it], 0) * a.ldb + ncol0 + cg * 8;
+                        const f32x4 x0 = *reinterpret_cast<const f32x4 *>(b);
+                        const f32x4 x1 = *reinterpret_cast<const f32x4 *>(b + 4);
+                        const bool ok = colr[it] >= 0;
+                        w[q][0] = ok ? (f32_to_bf16_bits(x0[0]) | (f32_to_bf16_bits(x0[1]) << 16)) : 0u;
+                        w[q][1] = ok ? (f32_to_bf16_bits(x0[2]) | (f32_to_bf16_bits(x0[3]) << 16)) : 0u;
+                        w[q][2] = ok ? (f32_to_bf16_bits(x1[0]) | (f32_to_bf16_bits(x1[1]) << 16)) : 0u;
+                        w[q][3] = ok ? (f32_to_bf16_bits(x1[2]) | (f32_to_bf16_bits(x1[3]) << 16)) : 0u;
+                    } else if (colr[it] >= 0 && valid > 0) {
+                        stage_b8<BT, TT>(a.B, (int64_t)colr[it] * a.ldb + ncol0 + cg * 8, valid, a.vec_ok,
+                                         w[q]);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    *reinterpret_cast<u32x4 *>(&Bs[(h + q) * 2048 + tid * 8]) =
+                        u32x4{w[q][0], w[q][1], w[q][2], w[q][3]};
+            }
+        }
+        // LDS: values, bitmaps, row metadata, value offsets, staged B rows
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k * 256 + tid < nv) sm.vals[k * 256 + tid] = xv[k];
+        for (int i = 1024 + tid; i < nv; i += 256) sm.vals[i] = P.tile_vals[v0 + i];
+        if (tid < nt * H) sm.bm[tid] = bmw;
+        if constexpr (FIRST) {
+            if (wave == 0 && !partial) {
+                // the window's rows, their remainder ranges and segment ids
+                const bool own = lane < H && rm >= 0;
+                const int len = own ? em_ - bm_ : 0;
+                const int ns = len > P.seg_len ? (len + P.seg_len - 1) / P.seg_len : 0;
+                const int x = wave_inclusive_scan(ns);
+                if (lane < H) {
+                    sm.rows[lane] = rm;
+                    sm.rb[lane] = bm_;
+                    sm.re[lane] = em_;
+                    sm.sid[lane] = seg0 + x - ns;
+                }
             }
         }
         if (wave < nt) {
             // offset of each row's first value inside the staged round
+            const uint32_t wd = lane < H ? wd0 : 0u;
             const int c = __popc(wd);
             const int x = wave_inclusive_scan(c);
             if (lane < H) sm.off[wave * H + lane] = tv - v0 + x - c;
         }
-#pragma unroll
-        for (int it = 0; it < PER; ++it) {
-            const int i = tid + it * 256, kr = i >> 4, n = (i & 15) * 8;
-            if (kr < nt * 32) {
-                uint32_t *dst = reinterpret_cast<uint32_t *>(&Bs[kr * BSTR + n]);
-                dst[0] = w[it][0]; dst[1] = w[it][1]; dst[2] = w[it][2]; dst[3] = w[it][3];
-            }
-        }
         __syncthreads();
+        if constexpr (FIRST) {
+            // level 4: the early remainder entries' B rows (a valid row for
+            // unused entries and chunks outside the panel), issued after the
+            // barrier (which waits for the staging loads) and consumed after
+            // the MFMA rounds
+#pragma unroll
+            for (int u = 0; u < U1; ++u)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c)
+                    load_raw<BT, E, false>(a.B, (int64_t)(col1[u] & 0x7FFFFFFF) * a.ldb +
+                                                    (cok[c] ? coff[c] : (int64_t)ncol0), g1[u][c]);
+        }
         for (int j = 0; j < nt; ++j) {
             u16x8 af[MB];
 #pragma unroll
@@ -1020,11 +1161,21 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
                 const int nb = wave + 4 * nbi;
                 u16x8 bf;
 #pragma unroll
-                for (int i = 0; i < 8; ++i) bf[i] = Bs[(j * 32 + 8 * g + i) * BSTR + nb * 16 + l16];
+                for (int i = 0; i < 8; ++i) {
+                    const int k = j * 32 + 8 * g + i;
+                    bf[i] = Bs[k * BSTR + (((2 * nb + (l16 >> 3)) ^ bswz(k)) << 3) + (l16 & 7)];
+                }
 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb) acc[mb][nbi] = mfma_16x16x32<TT>(af[mb], bf, acc[mb][nbi]);
             }
         }
+        return q1;
+    };
+    // a valid plan gives every window and partial item at least one tile
+    const int q1 = round(std::true_type{}, t0);
+    for (int tc0 = t0 + TC; tc0 < t1; tc0 += TC) {
+        __syncthreads();  // the previous round's LDS reads are done
+        (void)round(std::false_type{}, tc0);
     }
     if (partial) {
         // the MFMA result of these tiles, for the owner item to add
@@ -1042,6 +1193,16 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
             }
         return;
     }
+    // the first pass's rows: their early entries, then the rest in order
+    float v1[CPL][E];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c)
+#pragma unroll
+        for (int x = 0; x < E; ++x) v1[c][x] = 0.0f;
+    fma_rows<BT, E, CPL, U1>(val1, g1, b1, q1, one, v1);
+    if (q1 > b1 + U1)
+        row_accumulate_group<VT, BT, E, CPL, unroll_of<E, CPL>()>(
+            P.rem_col, P.rem_val, b1 + U1, q1, a.B, a.ldb, ncol0, ncols, L, a.cold_aux, v1);
     __syncthreads();
     float *Cs = reinterpret_cast<float *>(Bs);
 #pragma unroll
@@ -1052,7 +1213,6 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
             for (int i = 0; i < 4; ++i)
                 Cs[(mb * 16 + 4 * g + i) * NPW + (wave + 4 * nbi) * 16 + l16] = acc[mb][nbi][i];
     // add the partial results of the window's other tiles, in tile order
-    const int pa = P.win_part[wi], pb = P.win_part[wi + 1];
     if (pb > pa) {
         __syncthreads();
         for (int x = tid; x < H * NPW; x += 256) {
@@ -1070,23 +1230,22 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
     // Remainders: every lane group takes its own row of the window, so up to
     // 4 * G rows progress at once; a row's entries are summed in order by its
     // group.  Rows then add the tile result and are written once.
-    const Lanes L(a.win_lpr_log2);
     for (int s0 = 0; s0 < H; s0 += 4 * L.groups) {
-        const int s = s0 + wave * L.groups + L.group;
+        const int s = s0 + s1;
         const int r = s < H ? sm.rows[s] : -1;
         float v[CPL][E];
 #pragma unroll
         for (int c = 0; c < CPL; ++c)
 #pragma unroll
-            for (int x = 0; x < E; ++x) v[c][x] = 0.0f;
+            for (int x = 0; x < E; ++x) v[c][x] = s0 == 0 ? v1[c][x] : 0.0f;
         if (r >= 0) {
             const int b = sm.rb[s], e = sm.re[s];
-            if (e - b <= P.seg_len) {
-                row_accumulate_group<VT, BT, E, CPL, unroll_of<E, CPL>()>(
-                    P.rem_col, P.rem_val, b, e, a.B, a.ldb, ncol0, ncols, L, a.cold_aux, v);
-            } else {
+            if (e - b > P.seg_len) {
                 const int ns = (e - b + P.seg_len - 1) / P.seg_len;
                 sum_partials<E, CPL>(a.work, a.work_ld, sm.sid[s], ns, ncol0, ncols, L, v);
+            } else if (s0 != 0) {
+                row_accumulate_group<VT, BT, E, CPL, unroll_of<E, CPL>()>(
+                    P.rem_col, P.rem_val, b, e, a.B, a.ldb, ncol0, ncols, L, a.cold_aux, v);
             }
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {

@@ -74,6 +74,9 @@ extern "C" const char *spmm_last_error(void) { return g_last_error.c_str(); }
 
 namespace {
 
+// Every sub-array is followed by at least 16 zero bytes, so a kernel that
+// clamps an index into [0, size] (an empty range included) stays inside the
+// allocation; the window kernel issues its predicated loads that way.
 struct Arena {
     std::vector<std::pair<const void *, size_t>> parts;
     std::vector<size_t> offs;
@@ -82,7 +85,7 @@ struct Arena {
         total = (total + 255) & ~size_t(255);
         offs.push_back(total);
         parts.push_back({p, bytes});
-        total += bytes;
+        total += bytes + 16;
         return parts.size() - 1;
     }
 };
@@ -157,6 +160,8 @@ extern "C" spmm_status spmm_plan_upload(spmm_plan_t *p) {
         const size_t i_wpart_win = add_vec(a, h.wpart_win);
         const size_t i_wpart_t0 = add_vec(a, h.wpart_t0);
         const size_t i_wpart_t1 = add_vec(a, h.wpart_t1);
+        static const uint8_t kZeros[256] = {};
+        const size_t i_zeros = a.add(kZeros, sizeof(kZeros));
         const size_t total = std::max<size_t>(a.total, 256);
 
         std::vector<uint8_t> image(total, 0);
@@ -195,7 +200,9 @@ extern "C" spmm_status spmm_plan_upload(spmm_plan_t *p) {
         dp.windows = reinterpret_cast<const int32_t *>(at(i_windows));
         dp.win_tile_ptr = reinterpret_cast<const int32_t *>(at(i_win_tile_ptr));
         dp.win_seg = reinterpret_cast<const int32_t *>(at(i_win_seg));
-        dp.win_order = reinterpret_cast<const int32_t *>(at(i_win_order));
+        bool order_id = true;
+        for (size_t w = 0; w < h.win_order.size() && order_id; ++w) order_id = h.win_order[w] == (int32_t)w;
+        dp.win_order = order_id ? nullptr : reinterpret_cast<const int32_t *>(at(i_win_order));
         dp.tile_cols = reinterpret_cast<const int32_t *>(at(i_tile_cols));
         dp.tile_bitmap = reinterpret_cast<const uint32_t *>(at(i_tile_bitmap));
         dp.tile_val_ptr = reinterpret_cast<const int32_t *>(at(i_tile_val_ptr));
@@ -206,6 +213,7 @@ extern "C" spmm_status spmm_plan_upload(spmm_plan_t *p) {
         dp.wpart_win = reinterpret_cast<const int32_t *>(at(i_wpart_win));
         dp.wpart_t0 = reinterpret_cast<const int32_t *>(at(i_wpart_t0));
         dp.wpart_t1 = reinterpret_cast<const int32_t *>(at(i_wpart_t1));
+        dp.zeros = reinterpret_cast<const uint16_t *>(at(i_zeros));
         p->dev = d;
         p->dev_bytes = total;
         p->device = dev;

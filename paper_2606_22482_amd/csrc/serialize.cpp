@@ -125,9 +125,12 @@ spmm_status check_plan(const HostPlan &P, std::string &err) {
     const int64_t T = (int64_t)P.tile_window.size();
     SPMM_CHECK((int64_t)P.win_tile_ptr.size() == W + 1 && monotone_from_zero(P.win_tile_ptr, T),
                "plan image: window tiles");
-    for (int64_t w = 0; w < W; ++w)
+    for (int64_t w = 0; w < W; ++w) {
+        // the window kernel takes its rows' metadata in its first tile round
+        SPMM_CHECK(P.win_tile_ptr[w + 1] > P.win_tile_ptr[w], "plan image: window without tiles");
         for (int32_t t = P.win_tile_ptr[w]; t < P.win_tile_ptr[w + 1]; ++t)
             SPMM_CHECK(P.tile_window[t] == w, "plan image: tile window");
+    }
     SPMM_CHECK((int64_t)P.tile_cols.size() == T * kt && (int64_t)P.tile_bitmap.size() == T * H,
                "plan image: tile arrays");
     for (int32_t c : P.tile_cols) SPMM_CHECK(c >= -1 && c < k, "plan image: tile column");
@@ -148,6 +151,8 @@ spmm_status check_plan(const HostPlan &P, std::string &err) {
             bits += __builtin_popcount(b);
         }
         SPMM_CHECK(bits == P.tile_val_ptr[t + 1] - P.tile_val_ptr[t], "plan image: tile value count");
+        // the window kernel reads a round's values at clamped indices
+        SPMM_CHECK(bits > 0, "plan image: tile without values");
     }
     // vector rows and items
     for (size_t i = 0; i < P.vector_rows.size(); ++i) {
