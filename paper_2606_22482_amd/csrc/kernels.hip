@@ -862,8 +862,8 @@ __global__ __launch_bounds__(256) void vector_kernel(DevPlan P, RunArgs a) {
 }
 
 // LDS of a window item: the staged B rows (reused for the f32 C tile), the
-// window's rows, remainder ranges and segment ids, and the staged tiles'
-// bitmaps, per-row value offsets and packed values.  MB = H / 16.
+// round's tiles expanded from bitmap + packed values to dense 16-bit rows, and
+// the window's rows, remainder ranges and segment ids.  MB = H / 16.
 // Staged B row k occupies 256 bytes (16 chunks of 8 elements) with chunk c
 // stored in slot c ^ bswz(k): the four 8-row groups that one MFMA operand
 // read touches then fall in different banks without padding, so a wave's
@@ -877,9 +877,8 @@ struct WinSmem {
     static constexpr int BSTR = NPW;         // LDS row stride (16-bit elements)
     static constexpr int H = MB * 16;
     __attribute__((aligned(16))) unsigned short Bs[KROWS * BSTR];
-    unsigned short vals[TC * H * 32];
-    int32_t rows[H], rb[H], re[H], sid[H], off[TC * H];
-    uint32_t bm[TC * H];
+    __attribute__((aligned(16))) unsigned short As[TC * H * 32];  // expanded tiles, row-major
+    int32_t rows[H], rb[H], re[H], sid[H];
 };
 
 template <int TT>
@@ -923,6 +922,8 @@ __device__ __forceinline__ void stage_b8(const void *B, int64_t off, int valid, 
 #pragma unroll
     for (int i = 0; i < 4; ++i) w[i] = h[2 * i] | (h[2 * i + 1] << 16);
 }
+
+typedef short v4i16 __attribute__((ext_vector_type(4)));
 
 // Slot of a chunk in a staged B row (see WinSmem).
 __device__ __forceinline__ int bswz(int k) { return ((k >> 3) & 3) << 1; }
@@ -1007,11 +1008,14 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
             const int c = P.tile_cols[(int64_t)tc0 * 32 + min(kr, nt * 32 - 1)];
             colr[it] = kr < nt * 32 ? c : -1;
         }
-        const int v0 = P.tile_val_ptr[tc0], nv = P.tile_val_ptr[tc0 + nt] - v0;
-        const int wv = min(wave, nt - 1);
-        const uint32_t wd0 = P.tile_bitmap[(int64_t)(tc0 + wv) * H + (lane & (H - 1))];
+        // wave w expands tile w of the round: lane (r, q) = (lane / 4, lane % 4)
+        // takes columns 8q .. 8q+7 of rows r, r + 16, .. of the tile
+        const int wv = min(wave, nt - 1), q4 = lane & 3;
+        const int vend = P.tile_val_ptr[tc0 + nt];
         const int tv = P.tile_val_ptr[tc0 + wv];
-        const uint32_t bmw = P.tile_bitmap[(int64_t)tc0 * H + min(tid, nt * H - 1)];
+        uint32_t wrd[MB];
+#pragma unroll
+        for (int rp = 0; rp < MB; ++rp) wrd[rp] = P.tile_bitmap[(int64_t)(tc0 + wv) * H + rp * 16 + (lane >> 2)];
         int bm_ = 0, em_ = 0;
         if constexpr (FIRST) {
             bm_ = P.rem_ptr[max(rm, 0)];
@@ -1019,11 +1023,31 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
             b1 = P.rem_ptr[max(r1, 0)];
             e1 = P.rem_ptr[max(r1, 0) + 1];
         }
-        // level 3: packed values, remainder entries, B rows of the staging chunks
-        unsigned short xv[4];
-        const int vlast = v0 + max(nv - 1, 0);
+        // level 3: tile values, remainder entries, B rows of the staging chunks.
+        // A row's values follow those of the tile's earlier rows (prefix over
+        // the 16-row passes by a wave scan) and, inside the row, the bitmap
+        // order; every load is issued at a clamped index and masked after.
+        uint32_t av[MB][4];
+        {
+            int carry = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) xv[k] = P.tile_vals[min(v0 + k * 256 + tid, vlast)];
+            for (int rp = 0; rp < MB; ++rp) {
+                const uint32_t word = wrd[rp], mine = (word >> (8 * q4)) & 0xFFu;
+                const int pc = __popc(word);
+                const int incl = wave_inclusive_scan(q4 == 0 ? pc : 0);
+                const int base = tv + carry + incl - pc + __popc(word & ((1u << (8 * q4)) - 1u));
+                carry += __shfl(incl, 63, 64);
+                unsigned short x[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int idx = base + __popc(mine & ((1u << i) - 1u));
+                    const unsigned short t = P.tile_vals[max(min(idx, vend - 1), 0)];
+                    x[i] = (mine >> i) & 1u ? t : (unsigned short)0;
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) av[rp][i] = (uint32_t)x[2 * i] | ((uint32_t)x[2 * i + 1] << 16);
+            }
+        }
         bool live1 = false, split1 = false;
         int q1 = 0;
         if constexpr (FIRST) {
@@ -1100,12 +1124,14 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
                         u32x4{w[q][0], w[q][1], w[q][2], w[q][3]};
             }
         }
-        // LDS: values, bitmaps, row metadata, value offsets, staged B rows
+        // LDS: expanded tiles (tile w, row r, columns 8q ..: 16 bytes at
+        // ((w H + r) 32 + 8q) elements), row metadata
+        if (wave < nt) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (k * 256 + tid < nv) sm.vals[k * 256 + tid] = xv[k];
-        for (int i = 1024 + tid; i < nv; i += 256) sm.vals[i] = P.tile_vals[v0 + i];
-        if (tid < nt * H) sm.bm[tid] = bmw;
+            for (int rp = 0; rp < MB; ++rp)
+                *reinterpret_cast<u32x4 *>(&sm.As[((wave * H + rp * 16 + (lane >> 2)) * 32) + 8 * q4]) =
+                    u32x4{av[rp][0], av[rp][1], av[rp][2], av[rp][3]};
+        }
         if constexpr (FIRST) {
             if (wave == 0 && !partial) {
                 // the window's rows, their remainder ranges and segment ids
@@ -1121,13 +1147,6 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
                 }
             }
         }
-        if (wave < nt) {
-            // offset of each row's first value inside the staged round
-            const uint32_t wd = lane < H ? wd0 : 0u;
-            const int c = __popc(wd);
-            const int x = wave_inclusive_scan(c);
-            if (lane < H) sm.off[wave * H + lane] = tv - v0 + x - c;
-        }
         __syncthreads();
         if constexpr (FIRST) {
             // level 4: the early remainder entries' B rows (a valid row for
@@ -1142,28 +1161,28 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
                                                     (cok[c] ? coff[c] : (int64_t)ncol0), g1[u][c]);
         }
         for (int j = 0; j < nt; ++j) {
+            // A operand: lane (g, m) takes row m, columns 8g .. 8g+7 of tile j
             u16x8 af[MB];
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                const int m = mb * 16 + l16;
-                const uint32_t wd = sm.bm[j * H + m];
-                const uint32_t mine = (wd >> (8 * g)) & 0xFFu;
-                int off = sm.off[j * H + m] + __popc(wd & ((1u << (8 * g)) - 1u));
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    unsigned short x = 0;
-                    if ((mine >> i) & 1u) x = sm.vals[off++];
-                    af[mb][i] = x;
-                }
-            }
+            for (int mb = 0; mb < MB; ++mb)
+                af[mb] = *reinterpret_cast<const u16x8 *>(&sm.As[((j * H + mb * 16 + l16) * 32) + 8 * g]);
 #pragma unroll
             for (int nbi = 0; nbi < 2; ++nbi) {
                 const int nb = wave + 4 * nbi;
+                // B operand: lane (g, n) needs rows 8g .. 8g+7 of column n.
+                // ds_read_b64_tr_b16 transposes within each 16-lane block:
+                // lane a of the block reads 4 consecutive columns of one row,
+                // and lane n receives element i from lane 4i + n/4, column
+                // n % 4; so lane a reads row 4h + a/4, columns 4(a % 4) ..
                 u16x8 bf;
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const int k = j * 32 + 8 * g + i;
-                    bf[i] = Bs[k * BSTR + (((2 * nb + (l16 >> 3)) ^ bswz(k)) << 3) + (l16 & 7)];
+                for (int h = 0; h < 2; ++h) {
+                    const int k = j * 32 + 8 * g + 4 * h + (l16 >> 2), n0 = nb * 16 + 4 * (l16 & 3);
+                    const v4i16 t = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+                        (__attribute__((address_space(3))) v4i16 *)(Bs + k * BSTR +
+                                                                    (((n0 >> 3) ^ bswz(k)) << 3) + (n0 & 7)));
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) bf[4 * h + i] = (unsigned short)t[i];
                 }
 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb) acc[mb][nbi] = mfma_16x16x32<TT>(af[mb], bf, acc[mb][nbi]);
