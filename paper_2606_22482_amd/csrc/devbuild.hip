@@ -352,10 +352,17 @@ extern "C" spmm_status spmm_plan_device(const spmm_csr *A, int32_t n, int32_t b_
             SPMM_TRY_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
         }
         if (V > INT32_MAX || S > INT32_MAX) return set_error(SPMM_ERR_UNSUPPORTED, "too many items");
-        // 3. the plan allocation (layout as an uploaded plan)
+        // 3. the plan allocation (layout as an uploaded plan: every array is
+        // followed by at least 16 zero bytes, which the kernels' clamped loads
+        // of an empty range may read)
         const bool sorted = o.pipeline == 3 && m > 0;
         size_t poff = 0;
-        auto pcarve = [&](size_t bytes) { poff = (poff + 255) & ~size_t(255); size_t a = poff; poff += bytes; return a; };
+        auto pcarve = [&](size_t bytes) {
+            poff = (poff + 255) & ~size_t(255);
+            size_t a = poff;
+            poff += bytes + 16;
+            return a;
+        };
         const size_t p_rem_ptr = pcarve(4 * (size_t)(m + 1)), p_rem_col = pcarve(4 * (size_t)nnz),
                      p_rem_val = pcarve((size_t)sval * (size_t)nnz),
                      p_vec = pcarve(sorted ? 4 * (size_t)m : 0), p_vptr = pcarve(4 * (size_t)(V + 1)),
@@ -376,6 +383,7 @@ extern "C" spmm_status spmm_plan_device(const spmm_csr *A, int32_t n, int32_t b_
         auto *seg_begin = reinterpret_cast<int32_t *>(pat(p_sb));
         auto *seg_end = reinterpret_cast<int32_t *>(pat(p_se));
         auto *seg_row = reinterpret_cast<int32_t *>(pat(p_sr));  // host bookkeeping only
+        SPMM_TRY_HIP(hipMemsetAsync(d, 0, ptotal, s), "hipMemsetAsync");
         SPMM_TRY_HIP(hipMemcpyAsync(pat(p_rem_ptr), rp32, 4 * (size_t)(m + 1), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
         if (nnz > 0) {
             SPMM_TRY_HIP(hipMemcpyAsync(pat(p_rem_col), A->colidx, 4 * (size_t)nnz, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");

@@ -54,6 +54,8 @@ struct RunArgs {
     int32_t win_panels; // panels of the window kernel (128 columns each)
     int32_t win_lpr_log2;
     int32_t cold_aux;   // buffer-load policy bits for non-hot B rows; -1: plain loads for all
+    uint32_t b_rec;     // bytes of B reachable through a buffer resource (its span);
+                        // 0 when B spans 4 GiB or more (predicated plain loads)
     int32_t pipeline;   // vector kernel variant: 0 row by row, 1 row-pipelined, 2 short rows packed,
                         // 3 rows packed by size class
 };

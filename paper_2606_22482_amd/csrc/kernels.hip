@@ -253,10 +253,24 @@ __device__ __forceinline__ void load_raw_policy(__amdgpu_buffer_rsrc_t rs, int64
     }
 }
 
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t b_resource(const void *B) {
-    // raw buffer over B: stride 0, 2^32-1 bytes addressable, gfx9 word-3 flags
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(B), (short)0, (int)0xFFFFFFFF,
-                                             0x00020000);
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t b_resource(const void *B, uint32_t rec) {
+    // raw buffer over B: stride 0, `rec` bytes addressable (all 2^32-1 when 0),
+    // gfx9 word-3 flags; a load at or beyond `rec` returns zeros and moves no data
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(B), (short)0,
+                                             rec ? (int)rec : (int)0xFFFFFFFF, 0x00020000);
+}
+
+// A raw chunk through the default-policy buffer load at byte offset `off`.
+template <int BT, int E>
+__device__ __forceinline__ void load_raw_buf(__amdgpu_buffer_rsrc_t rs, uint32_t off, Raw<BT, E> &r) {
+    if constexpr (E == 1) {
+        if constexpr (BT == DT_F32) r.x = buf4<0>(rs, off);
+        else r.x = buf2<0>(rs, off);
+    } else {
+        const u32x4 x = buf16<0>(rs, off);
+        if constexpr (BT == DT_F32) r.x = __builtin_bit_cast(f32x4, x);
+        else r.x = x;
+    }
 }
 
 template <int E>
@@ -319,16 +333,31 @@ struct Lanes {
 };
 
 // Entries p, p + G, ..., p + (U-1)G of a group (masked at p1): columns and values.
-template <int VT, int U>
+// CLAMP: every load is issued, at an index clamped into [0, p1 - 1], with no
+// branch around it (a branch can make the compiler wait for each load before
+// issuing the next); a masked entry gets value 0 and the column of the
+// clamped entry, which is a real column when p < p1 (the plan arrays carry a
+// zero tail for the empty case).  Otherwise masked entries are not loaded, so
+// a step whose entries are all masked issues nothing.  Measured: clamping
+// pays where gathers are small and latency-bound (16-bit B), predication
+// where they are large and bandwidth-bound (f32 B).
+template <int VT, int U, bool CLAMP>
 __device__ __forceinline__ void load_entries(const int32_t *__restrict__ rcol,
                                              const void *__restrict__ rval, int p, int p1,
                                              const Lanes &L, int (&col)[U], float (&v)[U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int pp = p + u * L.groups;
-        const bool ok = pp < p1;
-        col[u] = ok ? __builtin_nontemporal_load(rcol + pp) : 0;
-        v[u] = ok ? load_val<VT>(rval, pp) : 0.0f;
+        if constexpr (CLAMP) {
+            const int q = max(min(pp, p1 - 1), 0);
+            col[u] = __builtin_nontemporal_load(rcol + q);
+            const float x = load_val<VT>(rval, q);
+            v[u] = pp < p1 ? x : 0.0f;
+        } else {
+            const bool ok = pp < p1;
+            col[u] = ok ? __builtin_nontemporal_load(rcol + pp) : 0;
+            v[u] = ok ? load_val<VT>(rval, pp) : 0.0f;
+        }
     }
 }
 
@@ -340,9 +369,10 @@ __device__ __forceinline__ void load_entries(const int32_t *__restrict__ rcol,
 template <int BT, int E, int CPL, int U, bool POL = false>
 __device__ __forceinline__ void gather_fma(const int (&col)[U], const float (&v)[U], int p, int p1,
                                            const void *__restrict__ B,
-                                           __amdgpu_buffer_rsrc_t rs, int64_t ldb,
+                                           __amdgpu_buffer_rsrc_t rs, int64_t ldb, uint32_t brec,
                                            const bool (&cok)[CPL], const int64_t (&coff)[CPL],
                                            const Lanes &L, int cold_aux, float (&acc)[CPL][E]) {
+    constexpr int SB = BT == DT_F32 ? 4 : 2;
     Raw<BT, E> b[U][CPL];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -352,6 +382,7 @@ __device__ __forceinline__ void gather_fma(const int (&col)[U], const float (&v)
             // bit 31 of a column marks a hot B row (cacheable gather)
             const int64_t boff = (int64_t)(col[u] & 0x7FFFFFFF) * ldb + coff[c];
             if constexpr (POL) {
+                (void)brec;
                 if (ok && cok[c] && (col[u] < 0 || cold_aux < 0)) {
                     load_raw<BT, E, false>(B, boff, b[u][c]);
                 } else if (ok && cok[c]) {
@@ -360,10 +391,20 @@ __device__ __forceinline__ void gather_fma(const int (&col)[U], const float (&v)
                     zero_raw<BT, E>(b[u][c]);
                 }
             } else {
-                (void)rs;
+                // No branch around a load when B is addressable by a buffer
+                // resource (a branch makes the compiler wait for each load
+                // before issuing the next): a masked entry or a chunk outside
+                // the panel loads at offset brec, out of the buffer's range,
+                // which returns zeros without a memory access.  B spanning
+                // 4 GiB or more takes predicated plain loads.
                 (void)cold_aux;
-                if (ok && cok[c]) load_raw<BT, E, false>(B, boff, b[u][c]);
-                else zero_raw<BT, E>(b[u][c]);
+                if (brec != 0) {
+                    load_raw_buf<BT, E>(rs, ok && cok[c] ? (uint32_t)(boff * SB) : brec, b[u][c]);
+                } else if (ok && cok[c]) {
+                    load_raw<BT, E, false>(B, boff, b[u][c]);
+                } else {
+                    zero_raw<BT, E>(b[u][c]);
+                }
             }
         }
     }
@@ -397,7 +438,7 @@ __device__ __forceinline__ void chunk_layout(int ncol0, int ncols, const Lanes &
     for (int c = 0; c < CPL; ++c) {
         const int q = c * L.lpr + L.li;
         cok[c] = q * E < ncols;
-        coff[c] = ncol0 + (int64_t)q * E;
+        coff[c] = ncol0 + (cok[c] ? (int64_t)q * E : 0);  // a valid chunk when outside the panel
     }
 }
 
@@ -406,10 +447,10 @@ __device__ __forceinline__ void chunk_layout(int ncol0, int ncols, const Lanes &
 template <int VT, int BT, int E, int CPL, int U, bool POL = false>
 __device__ __forceinline__ void seg_accumulate(const int32_t *__restrict__ rcol,
                                                const void *__restrict__ rval, int p0, int p1,
-                                               const void *__restrict__ B, int64_t ldb,
+                                               const void *__restrict__ B, int64_t ldb, uint32_t brec,
                                                int ncol0, int ncols, const Lanes &L, int cold_aux,
                                                float (&acc)[CPL][E]) {
-    const __amdgpu_buffer_rsrc_t rs = b_resource(B);
+    const __amdgpu_buffer_rsrc_t rs = b_resource(B, brec);
     bool cok[CPL];
     int64_t coff[CPL];
     chunk_layout<E, CPL>(ncol0, ncols, L, cok, coff);
@@ -417,8 +458,8 @@ __device__ __forceinline__ void seg_accumulate(const int32_t *__restrict__ rcol,
     for (int p = p0 + L.group; p < p1; p += step) {
         int col[U];
         float v[U];
-        load_entries<VT, U>(rcol, rval, p, p1, L, col, v);
-        gather_fma<BT, E, CPL, U, POL>(col, v, p, p1, B, rs, ldb, cok, coff, L, cold_aux, acc);
+        load_entries<VT, U, BT != DT_F32>(rcol, rval, p, p1, L, col, v);
+        gather_fma<BT, E, CPL, U, POL>(col, v, p, p1, B, rs, ldb, brec, cok, coff, L, cold_aux, acc);
     }
 }
 
@@ -428,9 +469,10 @@ template <int VT, int BT, int E, int CPL, int U, bool POL = false>
 __device__ __forceinline__ void row_accumulate_group(const int32_t *__restrict__ rcol,
                                                      const void *__restrict__ rval, int p0, int p1,
                                                      const void *__restrict__ B, int64_t ldb,
-                                                     int ncol0, int ncols, const Lanes &L,
-                                                     int cold_aux, float (&acc)[CPL][E]) {
-    const __amdgpu_buffer_rsrc_t rs = b_resource(B);
+                                                     uint32_t brec, int ncol0, int ncols,
+                                                     const Lanes &L, int cold_aux,
+                                                     float (&acc)[CPL][E]) {
+    const __amdgpu_buffer_rsrc_t rs = b_resource(B, brec);
     bool cok[CPL];
     int64_t coff[CPL];
     chunk_layout<E, CPL>(ncol0, ncols, L, cok, coff);
@@ -438,8 +480,8 @@ __device__ __forceinline__ void row_accumulate_group(const int32_t *__restrict__
     for (int p = p0; p < p1; p += U) {
         int col[U];
         float v[U];
-        load_entries<VT, U>(rcol, rval, p, p1, one, col, v);
-        gather_fma<BT, E, CPL, U, POL>(col, v, p, p1, B, rs, ldb, cok, coff, one, cold_aux, acc);
+        load_entries<VT, U, BT != DT_F32>(rcol, rval, p, p1, one, col, v);
+        gather_fma<BT, E, CPL, U, POL>(col, v, p, p1, B, rs, ldb, brec, cok, coff, one, cold_aux, acc);
     }
 }
 
@@ -500,7 +542,7 @@ __device__ __forceinline__ void segment_item(const DevPlan &P, const RunArgs &a,
 #pragma unroll
         for (int e = 0; e < E; ++e) acc[c][e] = 0.0f;
     seg_accumulate<VT, BT, E, CPL, unroll_of<E, CPL>(), POL>(P.rem_col, P.rem_val, P.seg_begin[sid],
-                                                        P.seg_end[sid], a.B, a.ldb, ncol0, ncols,
+                                                        P.seg_end[sid], a.B, a.ldb, a.b_rec, ncol0, ncols,
                                                         L, a.cold_aux, acc);
     group_reduce<E, CPL>(acc, L);
     if (L.group != 0) return;
@@ -539,7 +581,7 @@ __device__ __forceinline__ void vector_item(const DevPlan &P, const RunArgs &a, 
             for (int x = 0; x < E; ++x) acc[c][x] = 0.0f;
         if (e - b <= P.seg_len) {
             seg_accumulate<VT, BT, E, CPL, unroll_of<E, CPL>(), true>(P.rem_col, P.rem_val, b, e, a.B,
-                                                                a.ldb, ncol0, ncols, L, a.cold_aux,
+                                                                a.ldb, a.b_rec, ncol0, ncols, L, a.cold_aux,
                                                                 acc);
             group_reduce<E, CPL>(acc, L);
         } else {
@@ -562,7 +604,7 @@ __device__ __forceinline__ void vector_item_pipelined(const DevPlan &P, const Ru
     const int ncol0 = panel * a.np, ncols = min(a.np, P.n - ncol0);
     const Lanes L(a.lpr_log2);
     const int step = L.groups * U;
-    const __amdgpu_buffer_rsrc_t rs = b_resource(a.B);
+    const __amdgpu_buffer_rsrc_t rs = b_resource(a.B, a.b_rec);
     bool cok[CPL];
     int64_t coff[CPL];
     chunk_layout<E, CPL>(ncol0, ncols, L, cok, coff);
@@ -573,7 +615,7 @@ __device__ __forceinline__ void vector_item_pipelined(const DevPlan &P, const Ru
     int b = P.rem_ptr[r], e = P.rem_ptr[r + 1];
     int col[U];
     float v[U];
-    load_entries<VT, U>(P.rem_col, P.rem_val, b + L.group, e - b <= P.seg_len ? e : b, L, col, v);
+    load_entries<VT, U, BT != DT_F32>(P.rem_col, P.rem_val, b + L.group, e - b <= P.seg_len ? e : b, L, col, v);
     for (int i = i0; i < i1; ++i) {
         int nr = r, nb = 0, ne = 0;
         if (i + 1 < i1) {
@@ -602,7 +644,7 @@ __device__ __forceinline__ void vector_item_pipelined(const DevPlan &P, const Ru
                 }
             }
             // the next row's first batch, in flight behind the gathers
-            load_entries<VT, U>(P.rem_col, P.rem_val, nb + L.group, ne - nb <= P.seg_len ? ne : nb,
+            load_entries<VT, U, BT != DT_F32>(P.rem_col, P.rem_val, nb + L.group, ne - nb <= P.seg_len ? ne : nb,
                                 L, ncl, nv);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -615,13 +657,13 @@ __device__ __forceinline__ void vector_item_pipelined(const DevPlan &P, const Ru
             for (int p = b + step + L.group; p < e; p += step) {
                 int c2[U];
                 float v2[U];
-                load_entries<VT, U>(P.rem_col, P.rem_val, p, e, L, c2, v2);
-                gather_fma<BT, E, CPL, U>(c2, v2, p, e, a.B, rs, a.ldb, cok, coff, L, a.cold_aux,
+                load_entries<VT, U, BT != DT_F32>(P.rem_col, P.rem_val, p, e, L, c2, v2);
+                gather_fma<BT, E, CPL, U>(c2, v2, p, e, a.B, rs, a.ldb, a.b_rec, cok, coff, L, a.cold_aux,
                                           acc);
             }
             group_reduce<E, CPL>(acc, L);
         } else {
-            load_entries<VT, U>(P.rem_col, P.rem_val, nb + L.group, ne - nb <= P.seg_len ? ne : nb,
+            load_entries<VT, U, BT != DT_F32>(P.rem_col, P.rem_val, nb + L.group, ne - nb <= P.seg_len ? ne : nb,
                                 L, ncl, nv);
             const int ns = (e - b + P.seg_len - 1) / P.seg_len;
             sum_partials<E, CPL>(a.work, a.work_ld, sid, ns, ncol0, ncols, L, acc);
@@ -688,7 +730,7 @@ __device__ __forceinline__ void vector_item_packed(const DevPlan &P, const RunAr
             if (L.group < k) {
                 r = P.vec_rows ? P.vec_rows[my] : my;
                 row_accumulate_group<VT, BT, E, CPL, U>(P.rem_col, P.rem_val, P.rem_ptr[r],
-                                                        P.rem_ptr[r + 1], a.B, a.ldb, ncol0, ncols,
+                                                        P.rem_ptr[r + 1], a.B, a.ldb, a.b_rec, ncol0, ncols,
                                                         L, a.cold_aux, acc);
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) {
@@ -708,7 +750,7 @@ __device__ __forceinline__ void vector_item_packed(const DevPlan &P, const RunAr
 #pragma unroll
             for (int x = 0; x < E; ++x) acc[c][x] = 0.0f;
         if (e - b <= P.seg_len) {
-            seg_accumulate<VT, BT, E, CPL, U>(P.rem_col, P.rem_val, b, e, a.B, a.ldb, ncol0, ncols,
+            seg_accumulate<VT, BT, E, CPL, U>(P.rem_col, P.rem_val, b, e, a.B, a.ldb, a.b_rec, ncol0, ncols,
                                               L, a.cold_aux, acc);
             group_reduce<E, CPL>(acc, L);
         } else {
@@ -753,7 +795,7 @@ __device__ __forceinline__ void vector_item_classed(const DevPlan &P, const RunA
     const int ncol0 = panel * a.np, ncols = min(a.np, P.n - ncol0);
     const Lanes L(a.lpr_log2);
     const int lane = threadIdx.x & 63;
-    const __amdgpu_buffer_rsrc_t rs = b_resource(a.B);
+    const __amdgpu_buffer_rsrc_t rs = b_resource(a.B, a.b_rec);
     bool cok[CPL];
     int64_t coff[CPL];
     chunk_layout<E, CPL>(ncol0, ncols, L, cok, coff);
@@ -815,8 +857,8 @@ __device__ __forceinline__ void vector_item_classed(const DevPlan &P, const RunA
         for (int p = my_b + local; p < my_e; p += my_s * U) {
             int col[U];
             float v[U];
-            load_entries<VT, U>(P.rem_col, P.rem_val, p, my_e, Ls, col, v);
-            gather_fma<BT, E, CPL, U>(col, v, p, my_e, a.B, rs, a.ldb, cok, coff, Ls, a.cold_aux,
+            load_entries<VT, U, BT != DT_F32>(P.rem_col, P.rem_val, p, my_e, Ls, col, v);
+            gather_fma<BT, E, CPL, U>(col, v, p, my_e, a.B, rs, a.ldb, a.b_rec, cok, coff, Ls, a.cold_aux,
                                       acc);
         }
         // butterfly inside each block, from the pass's largest class down
@@ -1157,8 +1199,7 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
             for (int u = 0; u < U1; ++u)
 #pragma unroll
                 for (int c = 0; c < CPL; ++c)
-                    load_raw<BT, E, false>(a.B, (int64_t)(col1[u] & 0x7FFFFFFF) * a.ldb +
-                                                    (cok[c] ? coff[c] : (int64_t)ncol0), g1[u][c]);
+                    load_raw<BT, E, false>(a.B, (int64_t)(col1[u] & 0x7FFFFFFF) * a.ldb + coff[c], g1[u][c]);
         }
         for (int j = 0; j < nt; ++j) {
             // A operand: lane (g, m) takes row m, columns 8g .. 8g+7 of tile j
@@ -1221,7 +1262,7 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
     fma_rows<BT, E, CPL, U1>(val1, g1, b1, q1, one, v1);
     if (q1 > b1 + U1)
         row_accumulate_group<VT, BT, E, CPL, unroll_of<E, CPL>()>(
-            P.rem_col, P.rem_val, b1 + U1, q1, a.B, a.ldb, ncol0, ncols, L, a.cold_aux, v1);
+            P.rem_col, P.rem_val, b1 + U1, q1, a.B, a.ldb, a.b_rec, ncol0, ncols, L, a.cold_aux, v1);
     __syncthreads();
     float *Cs = reinterpret_cast<float *>(Bs);
 #pragma unroll
@@ -1264,7 +1305,7 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
                 sum_partials<E, CPL>(a.work, a.work_ld, sm.sid[s], ns, ncol0, ncols, L, v);
             } else if (s0 != 0) {
                 row_accumulate_group<VT, BT, E, CPL, unroll_of<E, CPL>()>(
-                    P.rem_col, P.rem_val, b, e, a.B, a.ldb, ncol0, ncols, L, a.cold_aux, v);
+                    P.rem_col, P.rem_val, b, e, a.B, a.ldb, a.b_rec, ncol0, ncols, L, a.cold_aux, v);
             }
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {

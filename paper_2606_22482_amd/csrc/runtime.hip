@@ -460,6 +460,7 @@ spmm_status make_run_args(const spmm_plan_t *p, const void *B, int64_t ldb, void
     // cold B rows go through a raw buffer load (32-bit byte offsets from B)
     const double b_span = ((double)std::max<int64_t>(h.k, 1) - 1.0) * (double)ldb * sb + (double)N * sb;
     a.cold_aux = (b_span < 4294967295.0 && h.opts.cold_policy != 0) ? h.opts.cold_policy : -1;
+    a.b_rec = b_span < 4294967040.0 ? (uint32_t)b_span : 0u;
     a.pipeline = h.opts.pipeline;
     a.win_panels = (N + 127) / 128;
     const int wchunks = a.vec_ok ? 128 / E : 128;
