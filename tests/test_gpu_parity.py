@@ -57,6 +57,39 @@ def test_integer_exact_all_paths(mode, kinds, n):
     exact(C, A, B, bk)
 
 
+@pytest.mark.parametrize("mode", ["plain", "mixed"])
+@pytest.mark.parametrize("kinds,n", [(("f32", "f32"), 40), (("bf16", "bf16"), 128)])
+def test_b_spanning_4gib_exact(mode, kinds, n):
+    """B rows 2 GiB apart (a span beyond 4 GiB): the gathers cannot use a
+    32-bit buffer resource and take predicated plain loads, and the window
+    kernel stages B (direct to LDS for bf16 with whole 128-column panels)
+    with 64-bit addresses.  Integer-exact against the oracle."""
+    import torch
+    vk, bk = kinds
+    k = 3
+    A = synth.random_csr(300, k, 0.7, 21, val_kind=vk, int_values=(-2, 2), empty_rows=0.05)
+    B = synth.int_dense(5, (k, n), -8, 8, kind=bk)
+    esize = 4 if bk == "f32" else 2
+    ldb = (1 << 31) // esize + 64
+    Bt = device_B(B, bk)
+    big = torch.zeros((k - 1) * ldb + n, dtype=Bt.dtype, device="cuda")
+    Bv = big.as_strided((k, n), (ldb, 1))
+    Bv.copy_(Bt)
+    kw = dict(mode=mode, seg_len=13)
+    if mode == "mixed":
+        kw.update(window_h=16, t_row=2, alpha_c=1 / 16, alpha=0.0)
+    print("case", mode, kinds, n, ldb, flush=True)
+    p = api.Plan(A, n, bk, api.default_opts(**kw))
+    C = device_C(A.m, n)
+    p.run(Bv, C)
+    torch.cuda.synchronize()
+    if mode == "mixed":
+        assert p.stats()["tiles"] > 0
+    exact(C, A, B, bk)
+    del big, Bv
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("H", [16, 32, 64])
 @pytest.mark.parametrize("order", ["original_ranges", "compacted", "length_sorted"])
 def test_window_heights_and_orders_exact(H, order):

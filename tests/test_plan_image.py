@@ -136,6 +136,31 @@ def test_crafted_images_are_refused(name, index, value, msg):
     assert st == L.SPMM_ERR_INVALID and msg in err, err
 
 
+def test_windows_without_tiles_and_tiles_without_values_are_refused():
+    """The window kernel reads a round's tile data at clamped indices and takes
+    its rows' metadata in the first tile round, so an image with an empty
+    window or a tile without values is refused."""
+    A, bk = _matrix("block")
+    p = api.Plan(A, 8, bk, api.default_opts(mode="mixed", row_order="original_ranges"),
+                 upload=False)
+    img = p.serialize()
+    offs = array_offsets(img)
+    assert offs["win_tile_ptr"][1] > 2
+    # window 0 without tiles: its tiles moved to window 1 (win_tile_ptr[1] = 0)
+    st, err = load(_crafted(img, "win_tile_ptr", 1, 0))
+    assert st == L.SPMM_ERR_INVALID and "window without tiles" in err, err
+    # tile 0 without values: bitmap words and value count both zero
+    H = p.export()["window_h"]
+    b = bytearray(img)
+    off, _, _ = offs["tile_bitmap"]
+    for s in range(H):
+        struct.pack_into("<I", b, off + 4 * s, 0)
+    off, _, _ = offs["tile_val_ptr"]
+    struct.pack_into("<q", b, off + 8, 0)
+    st, err = load(reseal(b))
+    assert st == L.SPMM_ERR_INVALID and "tile without values" in err, err
+
+
 def test_size_query_and_small_buffer():
     lib = L.load()
     A, bk = _matrix("random")
