@@ -310,6 +310,10 @@ __device__ __forceinline__ int logical_block(int xcd) {
     return (x < rem ? x * (full + 1) : rem * (full + 1) + (x - rem) * full) + local;
 }
 
+// This wave's index in its workgroup, as a wave-uniform (scalar) value, so
+// that the item and descriptor loads that depend on it are scalar loads.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
 // Lane layout of the gather-FMA: lane = group * LPR + li; lane li of a group
 // owns chunks q = c * LPR + li (c < CPL), i.e. columns q*E .. q*E+E-1 of the
 // panel.
@@ -885,7 +889,7 @@ __device__ __forceinline__ void vector_item_classed(const DevPlan &P, const RunA
 
 template <int VT, int BT, int E, int CPL, bool POL>
 __global__ __launch_bounds__(256) void segment_kernel(DevPlan P, RunArgs a) {
-    const int wid = logical_block(a.xcd) * 4 + (threadIdx.x >> 6);
+    const int wid = logical_block(a.xcd) * 4 + wave_id();
     if (wid < P.n_seg * a.n_panels) segment_item<VT, BT, E, CPL, POL>(P, a, wid);
 }
 
@@ -899,7 +903,7 @@ __device__ __forceinline__ void vector_item_var(const DevPlan &P, const RunArgs 
 
 template <int VT, int BT, int E, int CPL, int VAR>
 __global__ __launch_bounds__(256) void vector_kernel(DevPlan P, RunArgs a) {
-    const int wid = logical_block(a.xcd) * 4 + (threadIdx.x >> 6);
+    const int wid = logical_block(a.xcd) * 4 + wave_id();
     if (wid < P.n_vitems * a.n_panels) vector_item_var<VT, BT, E, CPL, VAR>(P, a, wid);
 }
 
@@ -1360,14 +1364,14 @@ __global__ __launch_bounds__(256) void window_partial_kernel(DevPlan P, RunArgs 
 template <int VT, int BT, int E, int CPL, bool POL>
 __global__ __launch_bounds__(256) void batch_segment_kernel(const BatchHeader *__restrict__ hdr,
                                                             const BatchEntry *__restrict__ tab) {
-    const int sub = threadIdx.x >> 6;
+    const int sub = wave_id();
     SPMM_XCD_WALK(x_seg, seg_end, seg_base, 4, (segment_item<VT, BT, E, CPL, POL>(tab[d].P, tab[d].a, item)));
 }
 
 template <int VT, int BT, int E, int CPL, int VAR>
 __global__ __launch_bounds__(256) void batch_vector_kernel(const BatchHeader *__restrict__ hdr,
                                                            const BatchEntry *__restrict__ tab) {
-    const int sub = threadIdx.x >> 6;
+    const int sub = wave_id();
     SPMM_XCD_WALK(x_vec, vec_end, vec_base, 4, (vector_item_var<VT, BT, E, CPL, VAR>(tab[d].P, tab[d].a, item)));
 }
 
