@@ -1011,7 +1011,7 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
     const int wi = partial ? P.wpart_win[j_item] : (P.win_order ? P.win_order[j_item] : j_item);
     const int ncol0 = panel * NPW, ncols = min(NPW, P.n - ncol0);
     const bool full = a.vec_ok && ncols == NPW;  // every staging chunk is whole
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, wave = wave_id(), lane = tid & 63;
     const int g = lane >> 4, l16 = lane & 15;
     const int t0 = partial ? P.wpart_t0[j_item] : P.win_tile_ptr[wi];
     const int t1 = partial ? P.wpart_t1[j_item] : min(P.win_tile_ptr[wi + 1], t0 + P.win_tmax);
