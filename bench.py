@@ -318,7 +318,7 @@ def main():
                     help="only run the device copy kernel over this many bytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        raise SystemExit("bench.py measures one GPU: this build has no multi-GPU path "
+        raise SystemExit("bench.py measures one GPU: the library runs on one GPU and has no multi-GPU path "
                          "(run with --gpus 1)")
 
     import torch
