@@ -12,9 +12,10 @@
 //   window   -- one workgroup per (row window, 128-column panel): the B rows
 //               of the window's compacted tile columns are staged in LDS once
 //               and reused by every row of the window (Sec. 6.2, intra-core
-//               reuse; Sec. 5.1, matrix-engine execution), the tile bitmap is
-//               expanded into MFMA operands (bf16 / f16 in, f32 accumulate),
-//               then each row adds its remainder and is written once.
+//               reuse; Sec. 5.1, matrix-engine execution), each tile's bitmap
+//               and packed values are expanded into dense rows in LDS and read
+//               as MFMA operands (bf16 / f16 in, f32 accumulate), then each
+//               row adds its remainder and is written once.
 //
 // Summation order of a remainder segment (identical in every kernel that
 // computes one, so a row's bits depend only on the plan and N, never on the
@@ -980,10 +981,11 @@ __device__ __forceinline__ int bswz(int k) { return ((k >> 3) & 3) << 1; }
 // Every thread of the workgroup calls it with the same item.  Per round of up
 // to TC tiles, with one barrier: each thread loads the columns of its own B
 // staging chunks and then those B rows (16-bit B straight into LDS, f32 B
-// through registers, converted to bf16), each wave its tile's bitmap words
-// and computes the rows' value offsets, and the bitmaps, packed values and
-// (first round) the window's row metadata go to LDS; then MFMA from LDS only.
-// Then each row adds its remainder and is written once.
+// through registers, converted to bf16), wave w expands tile w of the round
+// from bitmap + packed values into dense 16-bit rows in LDS, and (first
+// round) the window's row metadata goes to LDS; then MFMA from LDS only (an
+// A operand is one 16-byte read, a B operand two transposing reads).  Then
+// each row adds its remainder and is written once.
 // A workgroup spends most of its life waiting on chains of dependent loads,
 // so the loads of a round are issued level by level (item -> tile range and
 // window rows -> tile columns, bitmaps, value base and row ranges -> B rows,
@@ -1002,7 +1004,7 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
     constexpr int U1 = MB == 1 ? 4 : 2;           // remainder entries per row gathered early
     static_assert(MB <= SMB, "LDS sized for a smaller window");
     static_assert(H * NPW * 4 <= KROWS * BSTR * 2, "C tile must fit in the B stage");
-    static_assert(TC * H <= 256, "one staged bitmap word per thread");
+    static_assert(TC <= 4, "wave w expands tile w of a round");
     unsigned short *Bs = sm.Bs;
 
     // owner items: (window in launch order, panel), tiles [t0, t0 + win_tmax);
