@@ -58,3 +58,36 @@ def test_random_case_exact(seed):
     p.run(Bd, C)
     torch.cuda.synchronize()
     exact(C, A, B, bk)
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_random_batch_exact(seed):
+    """A submission of 2-7 random problems (each with its own options and
+    types): every batched result equals its solo run bit for bit and the
+    oracle exactly."""
+    import torch
+    r = np.random.default_rng(5000 + seed)
+    count = int(r.integers(2, 8))
+    items, solos, cases = [], [], []
+    for j in range(count):
+        case = 200 + 10 * seed + j
+        vk, bk, m, k, n, density, opts, _ = draw(case)
+        A = synth.random_csr(m, k, density, 50 + case, val_kind=vk, int_values=(-2, 2),
+                             dup_frac=0.03, empty_rows=0.05)
+        B = synth.int_dense(70 + case, (k, n), -8, 8, kind=bk)
+        p = api.Plan(A, n, bk, api.default_opts(**opts))
+        Bd = device_B(B, bk)
+        Cs = device_C(A.m, n)
+        p.run(Bd, Cs)
+        Cb = device_C(A.m, n)
+        items.append(api.WorkItem(p, Bd, Cb))
+        solos.append(Cs)
+        cases.append((A, B, bk, p))
+    print("batch", seed, count, flush=True)
+    torch.cuda.synchronize()
+    t = api.spmm_submit(items)
+    api.spmm_wait(t)
+    torch.cuda.synchronize()
+    for it, Cs, (A, B, bk, _) in zip(items, solos, cases):
+        assert torch.equal(it.C, Cs)
+        exact(it.C, A, B, bk)
