@@ -511,11 +511,17 @@ spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_
     P.rem_col.reserve(nnz - (int64_t)P.tile_src.size());
     P.rem_val.reserve((size_t)(nnz - (int64_t)P.tile_src.size()) * sval);
     for (int64_t r = 0; r < m; ++r) {
-        for (int64_t p = rowptr[r]; p < rowptr[r + 1]; ++p) {
-            if (in_tile[p]) continue;
-            P.rem_src.push_back(p);
-            P.rem_col.push_back(colidx[p]);
-            P.rem_val.insert(P.rem_val.end(), vbytes + p * sval, vbytes + (p + 1) * sval);
+        // runs of consecutive entries outside the tiles are copied in bulk
+        int64_t p = rowptr[r];
+        const int64_t pe = rowptr[r + 1];
+        while (p < pe) {
+            if (in_tile[p]) { ++p; continue; }
+            int64_t q = p + 1;
+            while (q < pe && !in_tile[q]) ++q;
+            for (int64_t x = p; x < q; ++x) P.rem_src.push_back(x);
+            P.rem_col.insert(P.rem_col.end(), colidx + p, colidx + q);
+            P.rem_val.insert(P.rem_val.end(), vbytes + p * sval, vbytes + q * sval);
+            p = q;
         }
         P.rem_ptr[r + 1] = (int64_t)P.rem_src.size();
         P.rem_ptr32[r + 1] = (int32_t)P.rem_src.size();
