@@ -16,7 +16,10 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <thread>
 
 namespace spmm {
 
@@ -422,110 +425,197 @@ spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_
     }
 
     // ---- column stage, K-tiles, density test, packing ----
+    // Candidate windows are independent (each row is in one window, so the
+    // in_tile flags they set are disjoint): ranges of them run on separate
+    // threads into their own buffers, which are then appended in window order,
+    // so the plan is the same for any number of threads.
     const int64_t col_thr = (int64_t)std::floor((double)o.alpha_c * (double)H);
     const double keep_thr = (double)o.alpha * (double)(H * kt);
-    std::vector<int32_t> cnt(k, 0), pos(k, -1), touched, mcols;
     std::vector<uint8_t> in_tile(nnz, 0);
-    std::vector<int64_t> src;  // [kept tiles of window][H][kt]
-    std::vector<std::pair<int64_t, int64_t>> kept_chunks;  // (start in mcols, ncols)
-    P.tile_val_ptr.push_back(0);
-    P.win_tile_ptr.push_back(0);
-    for (auto &slots : cand) {
-        if (slots.empty()) continue;
-        touched.clear();
-        for (int32_t r : slots) {
-            if (r < 0) continue;
-            for (int64_t p = rowptr[r]; p < rowptr[r + 1]; ++p) {
-                int32_t c = colidx[p];
-                if (cnt[c]++ == 0) touched.push_back(c);
-            }
-        }
-        mcols.clear();
-        for (int32_t c : touched)
-            if ((int64_t)cnt[c] > col_thr) mcols.push_back(c);
-        std::sort(mcols.begin(), mcols.end());
-        kept_chunks.clear();
-        for (size_t j0 = 0; j0 < mcols.size(); j0 += kt) {
-            size_t nc = std::min<size_t>(kt, mcols.size() - j0);
-            int64_t tnnz = 0;
-            for (size_t j = 0; j < nc; ++j) tnnz += cnt[mcols[j0 + j]];
-            if ((double)tnnz >= keep_thr) kept_chunks.push_back({(int64_t)j0, (int64_t)nc});
-        }
-        for (int32_t c : touched) cnt[c] = 0;
-        if (kept_chunks.empty()) continue;  // dissolved: rows stay vector rows
-
-        const int32_t widx = (int32_t)(P.windows.size() / H);
-        P.windows.insert(P.windows.end(), slots.begin(), slots.end());
-        const size_t nkt = kept_chunks.size();
-        for (size_t t = 0; t < nkt; ++t)
-            for (int64_t j = 0; j < kept_chunks[t].second; ++j)
-                pos[mcols[kept_chunks[t].first + j]] = (int32_t)(t * kt + j);
-        src.assign(nkt * H * kt, -1);
-        for (int s = 0; s < H; ++s) {
-            int32_t r = slots[s];
-            if (r < 0) continue;
-            for (int64_t p = rowptr[r]; p < rowptr[r + 1]; ++p) {
-                int32_t q = pos[colidx[p]];
-                if (q < 0) continue;
-                int64_t t = q / kt, j = q % kt;
-                int64_t &slot = src[(t * H + s) * kt + j];
-                if (slot < 0) { slot = p; in_tile[p] = 1; }  // first occurrence only
-            }
-        }
-        for (size_t t = 0; t < nkt; ++t) {
-            P.tile_window.push_back(widx);
-            for (int j = 0; j < kt; ++j)
-                P.tile_cols.push_back(j < kept_chunks[t].second ? mcols[kept_chunks[t].first + j] : -1);
-            for (int s = 0; s < H; ++s) {
-                uint32_t word = 0;
-                for (int j = 0; j < kt; ++j) {
-                    int64_t p = src[(t * H + s) * kt + j];
-                    if (p < 0) continue;
-                    word |= 1u << j;
-                    P.tile_src.push_back(p);
-                    uint16_t bits;
-                    if (A->val_type == SPMM_F32) {
-                        float f;
-                        std::memcpy(&f, vbytes + p * 4, 4);
-                        bits = f32_to_bf16_rne(f);
-                    } else {
-                        std::memcpy(&bits, vbytes + p * 2, 2);
-                    }
-                    P.tile_vals.push_back(bits);
+    struct StageOut {
+        std::vector<int32_t> windows, win_ntiles, tile_cols;
+        std::vector<uint32_t> tile_bitmap;
+        std::vector<int64_t> tile_nval, tile_src;
+        std::vector<uint16_t> tile_vals;
+    };
+    auto stage = [&](size_t c0, size_t c1, StageOut &out) {
+        std::vector<int32_t> cnt(k, 0), pos(k, -1), touched, mcols;
+        std::vector<int64_t> src;  // [kept tiles of window][H][kt]
+        std::vector<std::pair<int64_t, int64_t>> kept_chunks;  // (start in mcols, ncols)
+        for (size_t ci = c0; ci < c1; ++ci) {
+            const std::vector<int32_t> &slots = cand[ci];
+            if (slots.empty()) continue;
+            touched.clear();
+            for (int32_t r : slots) {
+                if (r < 0) continue;
+                for (int64_t p = rowptr[r]; p < rowptr[r + 1]; ++p) {
+                    int32_t c = colidx[p];
+                    if (cnt[c]++ == 0) touched.push_back(c);
                 }
-                P.tile_bitmap.push_back(word);
             }
-            P.tile_val_ptr.push_back((int64_t)P.tile_src.size());
+            mcols.clear();
+            for (int32_t c : touched)
+                if ((int64_t)cnt[c] > col_thr) mcols.push_back(c);
+            std::sort(mcols.begin(), mcols.end());
+            kept_chunks.clear();
+            for (size_t j0 = 0; j0 < mcols.size(); j0 += kt) {
+                size_t nc = std::min<size_t>(kt, mcols.size() - j0);
+                int64_t tnnz = 0;
+                for (size_t j = 0; j < nc; ++j) tnnz += cnt[mcols[j0 + j]];
+                if ((double)tnnz >= keep_thr) kept_chunks.push_back({(int64_t)j0, (int64_t)nc});
+            }
+            for (int32_t c : touched) cnt[c] = 0;
+            if (kept_chunks.empty()) continue;  // dissolved: rows stay vector rows
+
+            out.windows.insert(out.windows.end(), slots.begin(), slots.end());
+            const size_t nkt = kept_chunks.size();
+            out.win_ntiles.push_back((int32_t)nkt);
+            for (size_t t = 0; t < nkt; ++t)
+                for (int64_t j = 0; j < kept_chunks[t].second; ++j)
+                    pos[mcols[kept_chunks[t].first + j]] = (int32_t)(t * kt + j);
+            src.assign(nkt * H * kt, -1);
+            for (int s = 0; s < H; ++s) {
+                int32_t r = slots[s];
+                if (r < 0) continue;
+                for (int64_t p = rowptr[r]; p < rowptr[r + 1]; ++p) {
+                    int32_t q = pos[colidx[p]];
+                    if (q < 0) continue;
+                    int64_t t = q / kt, j = q % kt;
+                    int64_t &slot = src[(t * H + s) * kt + j];
+                    if (slot < 0) { slot = p; in_tile[p] = 1; }  // first occurrence only
+                }
+            }
+            for (size_t t = 0; t < nkt; ++t) {
+                for (int j = 0; j < kt; ++j)
+                    out.tile_cols.push_back(j < kept_chunks[t].second ? mcols[kept_chunks[t].first + j] : -1);
+                const size_t v0 = out.tile_src.size();
+                for (int s = 0; s < H; ++s) {
+                    uint32_t word = 0;
+                    for (int j = 0; j < kt; ++j) {
+                        int64_t p = src[(t * H + s) * kt + j];
+                        if (p < 0) continue;
+                        word |= 1u << j;
+                        out.tile_src.push_back(p);
+                        uint16_t bits;
+                        if (A->val_type == SPMM_F32) {
+                            float f;
+                            std::memcpy(&f, vbytes + p * 4, 4);
+                            bits = f32_to_bf16_rne(f);
+                        } else {
+                            std::memcpy(&bits, vbytes + p * 2, 2);
+                        }
+                        out.tile_vals.push_back(bits);
+                    }
+                    out.tile_bitmap.push_back(word);
+                }
+                out.tile_nval.push_back((int64_t)(out.tile_src.size() - v0));
+            }
+            for (size_t t = 0; t < nkt; ++t)
+                for (int64_t j = 0; j < kept_chunks[t].second; ++j)
+                    pos[mcols[kept_chunks[t].first + j]] = -1;
         }
-        P.win_tile_ptr.push_back((int32_t)P.tile_window.size());
-        for (size_t t = 0; t < nkt; ++t)
-            for (int64_t j = 0; j < kept_chunks[t].second; ++j)
-                pos[mcols[kept_chunks[t].first + j]] = -1;
+    };
+    {
+        // threads: only for many windows, and bounded by the 8 bytes per
+        // column that each one's counters take; SPMM_PLAN_THREADS sets the
+        // count (tests use it to compare plans built with different counts)
+        const size_t nc = cand.size();
+        size_t nth = std::max<size_t>(1, std::min<size_t>(std::thread::hardware_concurrency(), 16));
+        nth = std::min(nth, std::max<size_t>(1, nc / 512));
+        if (const char *env = std::getenv("SPMM_PLAN_THREADS")) {
+            const long v = std::strtol(env, nullptr, 10);
+            if (v >= 1) nth = (size_t)std::min<long>(v, 64);
+        }
+        nth = std::min(nth, std::max<size_t>(1, nc));
+        nth = std::min(nth, std::max<size_t>(1, (size_t(1) << 30) / (8 * (size_t)std::max<int64_t>(k, 1))));
+        std::vector<StageOut> outs(nth);
+        if (nth == 1) {
+            stage(0, nc, outs[0]);
+        } else {
+            std::vector<std::thread> th;
+            for (size_t i = 0; i < nth; ++i)
+                th.emplace_back(stage, nc * i / nth, nc * (i + 1) / nth, std::ref(outs[i]));
+            for (auto &t : th) t.join();
+        }
+        P.tile_val_ptr.push_back(0);
+        P.win_tile_ptr.push_back(0);
+        for (StageOut &out : outs) {
+            size_t t = 0;
+            for (int32_t ntiles : out.win_ntiles) {
+                const int32_t widx = (int32_t)(P.win_tile_ptr.size() - 1);
+                for (int32_t i = 0; i < ntiles; ++i, ++t) {
+                    P.tile_window.push_back(widx);
+                    P.tile_val_ptr.push_back(P.tile_val_ptr.back() + out.tile_nval[t]);
+                }
+                P.win_tile_ptr.push_back((int32_t)P.tile_window.size());
+            }
+            P.windows.insert(P.windows.end(), out.windows.begin(), out.windows.end());
+            P.tile_cols.insert(P.tile_cols.end(), out.tile_cols.begin(), out.tile_cols.end());
+            P.tile_bitmap.insert(P.tile_bitmap.end(), out.tile_bitmap.begin(), out.tile_bitmap.end());
+            P.tile_vals.insert(P.tile_vals.end(), out.tile_vals.begin(), out.tile_vals.end());
+            P.tile_src.insert(P.tile_src.end(), out.tile_src.begin(), out.tile_src.end());
+            out = StageOut();
+        }
     }
     const int64_t W = (int64_t)P.windows.size() / H;
 
     // ---- remainder (CSR order per row) ----
+    // Row ranges run on threads: each counts its rows' remainder entries, a
+    // prefix over the ranges places them, and each copies its runs of
+    // consecutive non-tile entries in bulk.
+    size_t nth_rows = nnz < (int64_t)(1 << 20)
+                          ? 1
+                          : std::max<size_t>(1, std::min<size_t>(std::thread::hardware_concurrency(), 16));
+    if (const char *env = std::getenv("SPMM_PLAN_THREADS")) {
+        const long v = std::strtol(env, nullptr, 10);
+        if (v >= 1) nth_rows = (size_t)std::min<long>(v, 64);
+    }
+    auto parallel_rows = [&](auto &&body) {  // body(r0, r1, range index)
+        if (nth_rows == 1 || m < 2) {
+            body((int64_t)0, m, (size_t)0);
+            return;
+        }
+        std::vector<std::thread> th;
+        for (size_t i = 0; i < nth_rows; ++i)
+            th.emplace_back([&, i] { body(m * (int64_t)i / (int64_t)nth_rows, m * (int64_t)(i + 1) / (int64_t)nth_rows, i); });
+        for (auto &t : th) t.join();
+    };
     P.rem_ptr.assign(m + 1, 0);
     P.rem_ptr32.assign(m + 1, 0);
-    P.rem_src.reserve(nnz - (int64_t)P.tile_src.size());
-    P.rem_col.reserve(nnz - (int64_t)P.tile_src.size());
-    P.rem_val.reserve((size_t)(nnz - (int64_t)P.tile_src.size()) * sval);
-    for (int64_t r = 0; r < m; ++r) {
-        // runs of consecutive entries outside the tiles are copied in bulk
-        int64_t p = rowptr[r];
-        const int64_t pe = rowptr[r + 1];
-        while (p < pe) {
-            if (in_tile[p]) { ++p; continue; }
-            int64_t q = p + 1;
-            while (q < pe && !in_tile[q]) ++q;
-            for (int64_t x = p; x < q; ++x) P.rem_src.push_back(x);
-            P.rem_col.insert(P.rem_col.end(), colidx + p, colidx + q);
-            P.rem_val.insert(P.rem_val.end(), vbytes + p * sval, vbytes + q * sval);
-            p = q;
+    std::vector<int64_t> range_base(nth_rows + 1, 0);
+    parallel_rows([&](int64_t r0, int64_t r1, size_t i) {
+        int64_t c = 0;
+        for (int64_t r = r0; r < r1; ++r) {
+            for (int64_t p = rowptr[r]; p < rowptr[r + 1]; ++p) c += !in_tile[p];
+            P.rem_ptr[r + 1] = c;  // local prefix, made global below
         }
-        P.rem_ptr[r + 1] = (int64_t)P.rem_src.size();
-        P.rem_ptr32[r + 1] = (int32_t)P.rem_src.size();
-    }
+        range_base[i + 1] = c;
+    });
+    for (size_t i = 0; i < nth_rows; ++i) range_base[i + 1] += range_base[i];
+    const int64_t nrem = range_base[nth_rows];
+    P.rem_src.resize(nrem);
+    P.rem_col.resize(nrem);
+    P.rem_val.resize((size_t)nrem * sval);
+    parallel_rows([&](int64_t r0, int64_t r1, size_t i) {
+        const int64_t base = range_base[i];
+        int64_t at = base;
+        for (int64_t r = r0; r < r1; ++r) {
+            int64_t p = rowptr[r];
+            const int64_t pe = rowptr[r + 1];
+            while (p < pe) {
+                if (in_tile[p]) { ++p; continue; }
+                int64_t q = p + 1;
+                while (q < pe && !in_tile[q]) ++q;
+                for (int64_t x = p; x < q; ++x) P.rem_src[at + (x - p)] = x;
+                std::memcpy(P.rem_col.data() + at, colidx + p, (size_t)(q - p) * 4);
+                std::memcpy(P.rem_val.data() + (size_t)at * sval, vbytes + p * sval, (size_t)(q - p) * sval);
+                at += q - p;
+                p = q;
+            }
+            P.rem_ptr[r + 1] += base;
+            P.rem_ptr32[r + 1] = (int32_t)P.rem_ptr[r + 1];
+        }
+    });
 
     // ---- hot columns: the most-gathered B rows of the vector path (ties: lower id) ----
     if (o.hot_cols > 0 && !P.rem_col.empty()) {
@@ -546,12 +636,23 @@ spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_
         P.hot_cols = (int64_t)nh;
     }
 
-    // ---- distinct referenced columns ----
+    // ---- distinct referenced columns (per-range bitmaps, then their union) ----
     {
-        std::vector<uint8_t> seen(k, 0);
+        const size_t words = (size_t)(k + 63) / 64;
+        std::vector<std::vector<uint64_t>> seen(nth_rows, std::vector<uint64_t>(words, 0));
+        parallel_rows([&](int64_t r0, int64_t r1, size_t i) {
+            std::vector<uint64_t> &b = seen[i];
+            for (int64_t p = rowptr[r0]; p < rowptr[r1]; ++p) {
+                const uint32_t c = (uint32_t)colidx[p];
+                b[c >> 6] |= uint64_t(1) << (c & 63);
+            }
+        });
         int64_t kr = 0;
-        for (int64_t p = 0; p < nnz; ++p)
-            if (!seen[colidx[p]]) { seen[colidx[p]] = 1; ++kr; }
+        for (size_t w = 0; w < words; ++w) {
+            uint64_t x = 0;
+            for (size_t i = 0; i < nth_rows; ++i) x |= seen[i][w];
+            kr += __builtin_popcountll(x);
+        }
         P.k_ref = kr;
     }
 

@@ -447,3 +447,22 @@ def test_adapt_next_keeps_the_last_measured_rate(lib):
     st2 = api.adapt_state(0.3)
     api.adapt_next(st2, 1.0, 0.0, 1e6, 0.0, 0.0, 5e8, 1e12, 0.05)
     assert st2.p_mfma == 1e12 and st2.alpha_star == pytest.approx(1e9 / 1e12)
+
+
+@pytest.mark.parametrize("order", ["original_ranges", "compacted", "clustered"])
+def test_plan_same_for_any_thread_count(order, monkeypatch):
+    """The column stage runs ranges of windows on threads and appends their
+    output in window order: the plan is the same array for array whatever
+    the thread count (SPMM_PLAN_THREADS)."""
+    A, _ = synth.block_community(n=8192, band=8, n_cols=8, seed=3)
+    kw = dict(mode="mixed", row_order=order, seg_len=16, alpha=0.05)
+    dumps = []
+    for nth in ("1", "5", "16"):
+        monkeypatch.setenv("SPMM_PLAN_THREADS", nth)
+        p = api.Plan(A, 8, "bf16", api.default_opts(**kw), upload=False)
+        dumps.append(p.export())
+    assert dumps[0]["tile_window"].size > 0
+    for d in dumps[1:]:
+        for key in dumps[0]:
+            if isinstance(dumps[0][key], np.ndarray):
+                assert np.array_equal(dumps[0][key], d[key]), key
