@@ -357,9 +357,11 @@ extern "C" spmm_status spmm_plan_device(const spmm_csr *A, int32_t n, int32_t b_
         // of an empty range may read)
         const bool sorted = o.pipeline == 3 && m > 0;
         size_t poff = 0;
+        std::vector<size_t> tails;  // offsets of the 16-byte zero tails
         auto pcarve = [&](size_t bytes) {
             poff = (poff + 255) & ~size_t(255);
             size_t a = poff;
+            tails.push_back(a + bytes);
             poff += bytes + 16;
             return a;
         };
@@ -383,7 +385,8 @@ extern "C" spmm_status spmm_plan_device(const spmm_csr *A, int32_t n, int32_t b_
         auto *seg_begin = reinterpret_cast<int32_t *>(pat(p_sb));
         auto *seg_end = reinterpret_cast<int32_t *>(pat(p_se));
         auto *seg_row = reinterpret_cast<int32_t *>(pat(p_sr));  // host bookkeeping only
-        SPMM_TRY_HIP(hipMemsetAsync(d, 0, ptotal, s), "hipMemsetAsync");
+        for (size_t t : tails)
+            SPMM_TRY_HIP(hipMemsetAsync(pat(t), 0, 16, s), "hipMemsetAsync");
         SPMM_TRY_HIP(hipMemcpyAsync(pat(p_rem_ptr), rp32, 4 * (size_t)(m + 1), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
         if (nnz > 0) {
             SPMM_TRY_HIP(hipMemcpyAsync(pat(p_rem_col), A->colidx, 4 * (size_t)nnz, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
