@@ -260,8 +260,6 @@ static void local_reorder(const std::vector<int32_t> &D, int H, int64_t crows,
                           const int64_t *rowptr, const int32_t *colidx,
                           const std::vector<int64_t> &len, int64_t k,
                           std::vector<std::vector<int32_t>> &out) {
-    std::vector<int64_t> stamp(std::max<int64_t>(k, 1), 0);
-    int64_t now = 0;
     struct Cand {
         int64_t inter, uni;
         int32_t pos;
@@ -271,63 +269,90 @@ static void local_reorder(const std::vector<int32_t> &D, int H, int64_t crows,
         return l != r ? l > r : a.pos < b.pos;
     };
     const int64_t nD = (int64_t)D.size();
-    for (int64_t c0 = 0; c0 < nD; c0 += crows) {
-        const int32_t n = (int32_t)std::min(crows, nD - c0);
-        // distinct columns of each row of the cluster
-        std::vector<int64_t> cptr(n + 1, 0);
-        std::vector<int32_t> cols;
-        for (int32_t i = 0; i < n; ++i) {
-            const int32_t r = D[c0 + i];
-            const size_t b = cols.size();
-            cols.insert(cols.end(), colidx + rowptr[r], colidx + rowptr[r + 1]);
-            std::sort(cols.begin() + b, cols.end());
-            cols.erase(std::unique(cols.begin() + b, cols.end()), cols.end());
-            cptr[i + 1] = (int64_t)cols.size();
-        }
-        std::vector<uint8_t> used(n, 0);
+    const int64_t nchunks = (nD + crows - 1) / crows;
+    // clusters are independent: ranges of them run on threads (each with its
+    // own column stamps) and their windows are appended in cluster order
+    auto run = [&](int64_t k0, int64_t k1, std::vector<std::vector<int32_t>> &wins) {
+        std::vector<int64_t> stamp(std::max<int64_t>(k, 1), 0);
+        int64_t now = 0;
         std::vector<Cand> cs;
-        for (int32_t w0 = 0; w0 < n; w0 += H) {
-            int32_t a = -1;
-            for (int32_t i = w0; i < std::min(w0 + H, n); ++i)
-                if (!used[i] && (a < 0 || len[D[c0 + i]] > len[D[c0 + a]])) a = i;
-            if (a < 0) continue;
-            used[a] = 1;
-            ++now;
-            for (int64_t q = cptr[a]; q < cptr[a + 1]; ++q) stamp[cols[q]] = now;
-            const int64_t na = cptr[a + 1] - cptr[a];
-            cs.clear();
+        for (int64_t ck = k0; ck < k1; ++ck) {
+            const int64_t c0 = ck * crows;
+            const int32_t n = (int32_t)std::min(crows, nD - c0);
+            // distinct columns of each row of the cluster
+            std::vector<int64_t> cptr(n + 1, 0);
+            std::vector<int32_t> cols;
+            for (int32_t i = 0; i < n; ++i) {
+                const int32_t r = D[c0 + i];
+                const size_t b = cols.size();
+                cols.insert(cols.end(), colidx + rowptr[r], colidx + rowptr[r + 1]);
+                std::sort(cols.begin() + b, cols.end());
+                cols.erase(std::unique(cols.begin() + b, cols.end()), cols.end());
+                cptr[i + 1] = (int64_t)cols.size();
+            }
+            std::vector<uint8_t> used(n, 0);
+            for (int32_t w0 = 0; w0 < n; w0 += H) {
+                int32_t a = -1;
+                for (int32_t i = w0; i < std::min(w0 + H, n); ++i)
+                    if (!used[i] && (a < 0 || len[D[c0 + i]] > len[D[c0 + a]])) a = i;
+                if (a < 0) continue;
+                used[a] = 1;
+                ++now;
+                for (int64_t q = cptr[a]; q < cptr[a + 1]; ++q) stamp[cols[q]] = now;
+                const int64_t na = cptr[a + 1] - cptr[a];
+                cs.clear();
+                for (int32_t i = 0; i < n; ++i) {
+                    if (used[i]) continue;
+                    int64_t inter = 0;
+                    for (int64_t q = cptr[i]; q < cptr[i + 1]; ++q) inter += stamp[cols[q]] == now;
+                    int64_t uni = na + (cptr[i + 1] - cptr[i]) - inter;
+                    if (uni == 0) { inter = 0; uni = 1; }
+                    cs.push_back({inter, uni, i});
+                }
+                const size_t take = std::min<size_t>((size_t)(H - 1), cs.size());
+                std::partial_sort(cs.begin(), cs.begin() + take, cs.end(), better);
+                std::vector<int32_t> slots(H, -1);
+                slots[0] = D[c0 + a];
+                for (size_t j = 0; j < take; ++j) {
+                    slots[j + 1] = D[c0 + cs[j].pos];
+                    used[cs[j].pos] = 1;
+                }
+                wins.push_back(std::move(slots));
+            }
+            std::vector<int32_t> slots;
             for (int32_t i = 0; i < n; ++i) {
                 if (used[i]) continue;
-                int64_t inter = 0;
-                for (int64_t q = cptr[i]; q < cptr[i + 1]; ++q) inter += stamp[cols[q]] == now;
-                int64_t uni = na + (cptr[i + 1] - cptr[i]) - inter;
-                if (uni == 0) { inter = 0; uni = 1; }
-                cs.push_back({inter, uni, i});
+                slots.push_back(D[c0 + i]);
+                if ((int)slots.size() == H) {
+                    wins.push_back(slots);
+                    slots.clear();
+                }
             }
-            const size_t take = std::min<size_t>((size_t)(H - 1), cs.size());
-            std::partial_sort(cs.begin(), cs.begin() + take, cs.end(), better);
-            std::vector<int32_t> slots(H, -1);
-            slots[0] = D[c0 + a];
-            for (size_t j = 0; j < take; ++j) {
-                slots[j + 1] = D[c0 + cs[j].pos];
-                used[cs[j].pos] = 1;
-            }
-            out.push_back(std::move(slots));
-        }
-        std::vector<int32_t> slots;
-        for (int32_t i = 0; i < n; ++i) {
-            if (used[i]) continue;
-            slots.push_back(D[c0 + i]);
-            if ((int)slots.size() == H) {
-                out.push_back(slots);
-                slots.clear();
+            if (!slots.empty()) {
+                slots.resize(H, -1);
+                wins.push_back(slots);
             }
         }
-        if (!slots.empty()) {
-            slots.resize(H, -1);
-            out.push_back(slots);
-        }
+    };
+    size_t nth = std::max<size_t>(1, std::min<size_t>(std::thread::hardware_concurrency(), 16));
+    if (const char *env = std::getenv("SPMM_PLAN_THREADS")) {
+        const long v = std::strtol(env, nullptr, 10);
+        if (v >= 1) nth = (size_t)std::min<long>(v, 64);
     }
+    nth = std::min<size_t>(nth, (size_t)std::max<int64_t>(nchunks, 1));
+    nth = std::min(nth, std::max<size_t>(1, (size_t(1) << 30) / (8 * (size_t)std::max<int64_t>(k, 1))));
+    std::vector<std::vector<std::vector<int32_t>>> parts(nth);
+    if (nth == 1) {
+        run(0, nchunks, parts[0]);
+    } else {
+        std::vector<std::thread> th;
+        for (size_t i = 0; i < nth; ++i)
+            th.emplace_back(run, nchunks * (int64_t)i / (int64_t)nth, nchunks * (int64_t)(i + 1) / (int64_t)nth,
+                            std::ref(parts[i]));
+        for (auto &t : th) t.join();
+    }
+    for (auto &pw : parts)
+        for (auto &w : pw) out.push_back(std::move(w));
 }
 
 spmm_status validate_opts(const spmm_opts &o, std::string &err) {

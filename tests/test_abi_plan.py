@@ -449,13 +449,16 @@ def test_adapt_next_keeps_the_last_measured_rate(lib):
     assert st2.p_mfma == 1e12 and st2.alpha_star == pytest.approx(1e9 / 1e12)
 
 
-@pytest.mark.parametrize("order", ["original_ranges", "compacted", "clustered"])
-def test_plan_same_for_any_thread_count(order, monkeypatch):
-    """The column stage runs ranges of windows on threads and appends their
-    output in window order: the plan is the same array for array whatever
-    the thread count (SPMM_PLAN_THREADS)."""
+@pytest.mark.parametrize("order,local", [("original_ranges", 0), ("compacted", 0), ("clustered", 0),
+                                         ("compacted", 64), ("clustered", 256)])
+def test_plan_same_for_any_thread_count(order, local, monkeypatch):
+    """The column stage, the remainder and the local reordering run ranges of
+    windows, rows or clusters on threads and append their output in order:
+    the plan is the same array for array whatever the thread count
+    (SPMM_PLAN_THREADS)."""
     A, _ = synth.block_community(n=8192, band=8, n_cols=8, seed=3)
-    kw = dict(mode="mixed", row_order=order, seg_len=16, alpha=0.05)
+    A = synth.permute_rows(A, 4) if local else A
+    kw = dict(mode="mixed", row_order=order, seg_len=16, alpha=0.05, local_reorder=local)
     dumps = []
     for nth in ("1", "5", "16"):
         monkeypatch.setenv("SPMM_PLAN_THREADS", nth)
