@@ -184,13 +184,17 @@ static std::vector<int64_t> rabbit_rank(int64_t m, int64_t k, const int64_t *row
             }
     }
     const __int128 two_m = 2 * (__int128)nnz;
-    std::vector<int64_t> deg(n), parent(n), next(n, -1), tail(n);
+    std::vector<int64_t> deg(n), parent(n);
     std::vector<int64_t> acc(n, 0), touched;
     std::vector<std::vector<int64_t>> children(n);
+    // agg[r]: the edges of the vertices merged into root r so far, aggregated
+    // as (neighbour, edge count) when each of them was visited; a root's own
+    // edges are read from the adjacency when it is visited.  This gives the
+    // same counts as scanning every member's adjacency at each visit.
+    std::vector<std::vector<std::pair<int64_t, int64_t>>> agg(n);
     for (int64_t v = 0; v < n; ++v) {
         deg[v] = aptr[v + 1] - aptr[v];
         parent[v] = v;
-        tail[v] = v;
     }
     auto find = [&](int64_t v) {
         int64_t r = v;
@@ -208,12 +212,18 @@ static std::vector<int64_t> rabbit_rank(int64_t m, int64_t k, const int64_t *row
     std::vector<int64_t> roots;
     for (int64_t u : visit) {
         touched.clear();
-        for (int64_t x = u; x >= 0; x = next[x])
-            for (int64_t q = aptr[x]; q < aptr[x + 1]; ++q) {
-                const int64_t ry = find(adj[q]);
-                if (ry == u) continue;
-                if (acc[ry]++ == 0) touched.push_back(ry);
-            }
+        for (int64_t q = aptr[u]; q < aptr[u + 1]; ++q) {
+            const int64_t ry = find(adj[q]);
+            if (ry == u) continue;
+            if (acc[ry]++ == 0) touched.push_back(ry);
+        }
+        for (const auto &e : agg[u]) {
+            const int64_t ry = find(e.first);
+            if (ry == u) continue;
+            if (acc[ry] == 0) touched.push_back(ry);
+            acc[ry] += e.second;
+        }
+        std::vector<std::pair<int64_t, int64_t>>().swap(agg[u]);
         int64_t best = -1;
         __int128 best_gain = 0;
         for (int64_t v : touched) {
@@ -222,16 +232,18 @@ static std::vector<int64_t> rabbit_rank(int64_t m, int64_t k, const int64_t *row
                 best = v;
                 best_gain = gain;
             }
-            acc[v] = 0;
         }
+        if (best >= 0) {
+            std::vector<std::pair<int64_t, int64_t>> &to = agg[best];
+            for (int64_t v : touched) to.push_back({v, acc[v]});
+        }
+        for (int64_t v : touched) acc[v] = 0;
         if (best < 0) {
             roots.push_back(u);
             continue;
         }
         parent[u] = best;
         children[best].push_back(u);
-        next[tail[best]] = u;  // members of best, then of u
-        tail[best] = tail[u];
         deg[best] += deg[u];
     }
     std::vector<int64_t> rank(m, 0), stack;
