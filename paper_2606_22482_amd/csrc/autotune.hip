@@ -279,7 +279,16 @@ extern "C" spmm_status spmm_autotune(const spmm_csr *A, int32_t n, int32_t b_typ
         if (s_ != SPMM_OK) return s_;     \
     } while (0)
 
-    // stage 1: vector-only vs mixed with each window order (Sec. 6.1)
+    // stage 1: vector-only vs mixed with each window order (Sec. 6.1), and the
+    // mixed plan that AUTO builds without a profile (the plain one is the
+    // base), so that a tuned plan is never slower than the untuned default
+    {
+        spmm_opts d, o;
+        spmm_opts_default(&d);
+        d.mode = SPMM_MODE_MIXED;
+        resolve_options(&d, A, n, b_type, &o);
+        SPMM_TRY(try_opts(o));
+    }
     for (int order : {SPMM_ORDER_ORIGINAL_RANGES, SPMM_ORDER_LENGTH_SORTED, SPMM_ORDER_COMPACTED}) {
         spmm_opts o;
         spmm_opts_default(&o);
