@@ -607,20 +607,21 @@ spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_
         const long v = std::strtol(env, nullptr, 10);
         if (v >= 1) nth_rows = (size_t)std::min<long>(v, 64);
     }
-    auto parallel_rows = [&](auto &&body) {  // body(r0, r1, range index)
-        if (nth_rows == 1 || m < 2) {
+    // body(r0, r1, range index) over `nth` contiguous row ranges
+    auto parallel_rows = [&](size_t nth, auto &&body) {
+        if (nth == 1 || m < 2) {
             body((int64_t)0, m, (size_t)0);
             return;
         }
         std::vector<std::thread> th;
-        for (size_t i = 0; i < nth_rows; ++i)
-            th.emplace_back([&, i] { body(m * (int64_t)i / (int64_t)nth_rows, m * (int64_t)(i + 1) / (int64_t)nth_rows, i); });
+        for (size_t i = 0; i < nth; ++i)
+            th.emplace_back([&, i] { body(m * (int64_t)i / (int64_t)nth, m * (int64_t)(i + 1) / (int64_t)nth, i); });
         for (auto &t : th) t.join();
     };
     P.rem_ptr.assign(m + 1, 0);
     P.rem_ptr32.assign(m + 1, 0);
     std::vector<int64_t> range_base(nth_rows + 1, 0);
-    parallel_rows([&](int64_t r0, int64_t r1, size_t i) {
+    parallel_rows(nth_rows, [&](int64_t r0, int64_t r1, size_t i) {
         int64_t c = 0;
         for (int64_t r = r0; r < r1; ++r) {
             for (int64_t p = rowptr[r]; p < rowptr[r + 1]; ++p) c += !in_tile[p];
@@ -633,7 +634,7 @@ spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_
     P.rem_src.resize(nrem);
     P.rem_col.resize(nrem);
     P.rem_val.resize((size_t)nrem * sval);
-    parallel_rows([&](int64_t r0, int64_t r1, size_t i) {
+    parallel_rows(nth_rows, [&](int64_t r0, int64_t r1, size_t i) {
         const int64_t base = range_base[i];
         int64_t at = base;
         for (int64_t r = r0; r < r1; ++r) {
@@ -676,8 +677,10 @@ spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_
     // ---- distinct referenced columns (per-range bitmaps, then their union) ----
     {
         const size_t words = (size_t)(k + 63) / 64;
-        std::vector<std::vector<uint64_t>> seen(nth_rows, std::vector<uint64_t>(words, 0));
-        parallel_rows([&](int64_t r0, int64_t r1, size_t i) {
+        // one bitmap of k bits per thread, at most 1 GiB of them in all
+        const size_t nth_k = std::min(nth_rows, std::max<size_t>(1, (size_t(1) << 30) / (8 * words + 8)));
+        std::vector<std::vector<uint64_t>> seen(nth_k, std::vector<uint64_t>(words, 0));
+        parallel_rows(nth_k, [&](int64_t r0, int64_t r1, size_t i) {
             std::vector<uint64_t> &b = seen[i];
             for (int64_t p = rowptr[r0]; p < rowptr[r1]; ++p) {
                 const uint32_t c = (uint32_t)colidx[p];
@@ -687,7 +690,7 @@ spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_
         int64_t kr = 0;
         for (size_t w = 0; w < words; ++w) {
             uint64_t x = 0;
-            for (size_t i = 0; i < nth_rows; ++i) x |= seen[i][w];
+            for (size_t i = 0; i < nth_k; ++i) x |= seen[i][w];
             kr += __builtin_popcountll(x);
         }
         P.k_ref = kr;
