@@ -54,10 +54,30 @@ def _matrix(kind, vk):
 
 @pytest.mark.parametrize("case", range(len(CASES)))
 def test_device_plan_equals_host_plan(case):
-    import torch
     kind, vk, bk, n, kw = CASES[case]
     A = _matrix(kind, vk)
-    opts = api.default_opts(mode="plain", **kw)
+    _compare(A, n, bk, api.default_opts(mode="plain", **kw), case)
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_device_plan_random(seed):
+    """Seeded random shapes, types and plain-plan options: device plan =
+    host plan array for array, and the same C bit for bit."""
+    r = np.random.default_rng(700 + seed)
+    vk, bk = [("f32", "f32"), ("f32", "bf16"), ("bf16", "bf16"), ("f16", "f16")][r.integers(4)]
+    m = int(r.choice([1, 3, int(r.integers(2, 6000))]))
+    k = int(r.choice([1, int(r.integers(2, 4000))]))
+    A = synth.random_csr(m, k, float(r.choice([0.001, 0.01, 0.05])), 800 + seed, val_kind=vk,
+                         dup_frac=0.03, empty_rows=float(r.choice([0.0, 0.3])))
+    n = int(r.choice([1, 8, 33, 64, 128, int(r.integers(1, 200))]))
+    kw = dict(seg_len=int(r.choice([2, 9, 64, 256])), pipeline=int(r.integers(0, 4)),
+              item_cost=int(r.choice([0, 16, 300, 4096])))
+    print("case", seed, vk, bk, m, k, n, kw, flush=True)
+    _compare(A, n, bk, api.default_opts(mode="plain", **kw), seed)
+
+
+def _compare(A, n, bk, opts, case):
+    import torch
     host = api.Plan(A, n, bk, opts)
     rp, ci, vt = device_csr(A)
     dev = api.Plan.on_device(rp, ci, vt, A.m, A.k, n, bk, opts)
