@@ -152,11 +152,14 @@ extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *
         const int32_t vt = key & 0xF, bt = (key >> 4) & 0xF, tt = (key >> 8) & 0xF;
         const int vec_ok = (key >> 12) & 0xF, cpl = (key >> 16) & 0xF, var = (key >> 20) & 0xF;
         // Work of each matrix (~ entries * N plus rows * N).  Whole matrices go
-        // to the 8 XCDs by longest processing time when that keeps the XCDs
-        // within 20% of an even share (each XCD's L2 then serves one matrix's
-        // B at a time); otherwise, as for a batch of a few matrices, each
-        // matrix's items of every kind are cut into 8 contiguous chunks, one
-        // per XCD, so that no XCD idles.
+        // to the 8 XCDs by longest processing time, so that each XCD's L2
+        // serves one matrix's B at a time.  While that leaves an XCD above 120%
+        // of an even share, the largest matrix still placed whole is instead
+        // cut into 8 contiguous chunks of its items of every kind, one per XCD
+        // (a batch of a few matrices ends with all of them cut, so no XCD
+        // idles), and the others are placed again.  Longest processing time
+        // keeps every XCD below the even share plus the largest whole cost, so
+        // no more than the matrices above 2.5% of the total are ever cut.
         std::vector<int32_t> order(idx.size());
         for (size_t j = 0; j < idx.size(); ++j) order[j] = (int32_t)j;
         auto cost = [&](int32_t j) {
@@ -166,16 +169,25 @@ extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *
         std::stable_sort(order.begin(), order.end(),
                          [&](int32_t x, int32_t y) { return cost(x) > cost(y); });
         std::vector<int32_t> xcd_of(idx.size(), 0);
-        double load[8] = {0, 0, 0, 0, 0, 0, 0, 0}, total = 0;
-        for (int32_t j : order) {
-            int best = 0;
-            for (int x = 1; x < 8; ++x)
-                if (load[x] < load[best]) best = x;
-            xcd_of[j] = best;
-            load[best] += cost(j);
-            total += cost(j);
+        std::vector<uint8_t> split(idx.size(), 0);
+        double total = 0;
+        for (int32_t j : order) total += cost(j);
+        for (size_t ns = 0; ns <= order.size(); ++ns) {  // the ns largest are cut
+            double load[8], share = 0;
+            for (size_t t = 0; t < ns; ++t) share += cost(order[t]) / 8.0;
+            for (int x = 0; x < 8; ++x) load[x] = share;
+            for (size_t t = ns; t < order.size(); ++t) {
+                int best = 0;
+                for (int x = 1; x < 8; ++x)
+                    if (load[x] < load[best]) best = x;
+                xcd_of[order[t]] = best;
+                load[best] += cost(order[t]);
+            }
+            if (*std::max_element(load, load + 8) <= 1.2 * total / 8.0 || ns == order.size()) {
+                for (size_t t = 0; t < ns; ++t) split[order[t]] = 1;
+                break;
+            }
         }
-        const bool whole = *std::max_element(load, load + 8) <= 1.2 * total / 8.0;
         struct Ent {
             int32_t j;
             int64_t base[4], cnt[4];
@@ -192,7 +204,7 @@ extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *
                                        (int64_t)p->dp.n_win * a.win_panels,
                                        (int64_t)p->dp.n_wpart * a.win_panels};
                 Ent e{j, {0, 0, 0, 0}, {0, 0, 0, 0}};
-                if (whole) {
+                if (!split[j]) {
                     if (xcd_of[j] != x) continue;
                     for (int q = 0; q < 4; ++q) e.cnt[q] = n4[q];
                 } else {

@@ -418,17 +418,21 @@ def test_local_reorder_shuffled_communities():
     parity(C, A, B, "bf16", TOL_16)
 
 
-@pytest.mark.parametrize("shape", ["equal16", "one_big"])
+@pytest.mark.parametrize("shape", ["equal16", "one_big", "two_big_many_small"])
 def test_submit_xcd_assignment_bitwise(shape):
-    """16 matrices of equal work (whole matrices per XCD) and one large
-    matrix with three small ones (every matrix cut into 8 chunks, one per
-    XCD): both equal their solo runs bit for bit."""
+    """16 matrices of equal work (whole matrices per XCD); one large matrix
+    with three small ones (every matrix cut into 8 chunks, one per XCD); two
+    large matrices with 20 small ones (the two cut, the small ones whole):
+    all equal their solo runs bit for bit."""
     import torch
     if shape == "equal16":
         mats = [synth.random_csr(3000, 3000, 0.004, 60 + i) for i in range(16)]
-    else:
+    elif shape == "one_big":
         mats = [synth.chung_lu_graph(60000, 2.1, 16.0, 3000.0, 61)] + \
                [synth.random_csr(500, 500, 0.01, 62 + i) for i in range(3)]
+    else:
+        mats = [synth.chung_lu_graph(60000, 2.1, 16.0, 3000.0, 61 + i) for i in range(2)] + \
+               [synth.random_csr(1500, 1500, 0.004, 70 + i) for i in range(20)]
     items, solos = [], []
     for i, A in enumerate(mats):
         B = np.random.default_rng(i).standard_normal((A.k, 64)).astype(np.float32)
