@@ -21,6 +21,7 @@ struct DevPlan {
     const int32_t *vitem_seg;  // [n_vitems]
     const int32_t *seg_begin;  // [n_seg]
     const int32_t *seg_end;    // [n_seg]
+    const int32_t *seg_order;  // [n_seg] launch order of segments, or null for id order
     const int32_t *windows;    // [n_win*H]
     const int32_t *win_tile_ptr;  // [n_win+1]
     const int32_t *win_seg;    // [n_win]

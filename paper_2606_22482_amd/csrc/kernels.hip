@@ -538,7 +538,8 @@ constexpr int unroll_of() { return E == 1 ? 4 : (CPL == 1 ? 8 : 4); }
 // One segment (of one panel) per wavefront: wid in [0, n_seg * n_panels).
 template <int VT, int BT, int E, int CPL, bool POL>
 __device__ __forceinline__ void segment_item(const DevPlan &P, const RunArgs &a, int wid) {
-    const int panel = wid / P.n_seg, sid = wid - panel * P.n_seg;
+    const int panel = wid / P.n_seg, li = wid - panel * P.n_seg;
+    const int sid = P.seg_order ? P.seg_order[li] : li;  // the partial's slot
     const int ncol0 = panel * a.np, ncols = min(a.np, P.n - ncol0);
     const Lanes L(a.lpr_log2);
     float acc[CPL][E];

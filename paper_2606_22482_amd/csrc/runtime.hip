@@ -152,6 +152,25 @@ extern "C" spmm_status spmm_plan_upload(spmm_plan_t *p) {
         const size_t i_win_tile_ptr = add_vec(a, win_tile_ptr32);
         const size_t i_win_seg = add_vec(a, h.win_seg);
         const size_t i_win_order = add_vec(a, h.win_order);
+        // Launch order of the segments: by the column of each segment's middle
+        // entry (stable).  Rows keep their columns in CSR order, so segments
+        // that run together gather B rows from one stretch of B and share them
+        // in L2 and the Infinity Cache; each partial still lands in its own
+        // slot and is summed in segment order, so C does not change.
+        std::vector<int32_t> seg_order(h.seg_begin.size());
+        {
+            std::vector<int32_t> key(h.seg_begin.size());
+            for (size_t i = 0; i < key.size(); ++i) {
+                seg_order[i] = (int32_t)i;
+                key[i] = h.rem_col[(size_t)(h.seg_begin[i] + h.seg_end[i] - 1) / 2];
+            }
+            std::stable_sort(seg_order.begin(), seg_order.end(),
+                             [&](int32_t x, int32_t y) { return key[x] < key[y]; });
+            bool id = true;
+            for (size_t i = 0; i < seg_order.size() && id; ++i) id = seg_order[i] == (int32_t)i;
+            if (id) seg_order.clear();
+        }
+        const size_t i_seg_order = add_vec(a, seg_order);
         const size_t i_tile_cols = add_vec(a, h.tile_cols);
         const size_t i_tile_bitmap = add_vec(a, h.tile_bitmap);
         const size_t i_tile_val_ptr = add_vec(a, tile_val_ptr32);
@@ -197,6 +216,7 @@ extern "C" spmm_status spmm_plan_upload(spmm_plan_t *p) {
         dp.vitem_seg = reinterpret_cast<const int32_t *>(at(i_vitem_seg));
         dp.seg_begin = reinterpret_cast<const int32_t *>(at(i_seg_begin));
         dp.seg_end = reinterpret_cast<const int32_t *>(at(i_seg_end));
+        dp.seg_order = seg_order.empty() ? nullptr : reinterpret_cast<const int32_t *>(at(i_seg_order));
         dp.windows = reinterpret_cast<const int32_t *>(at(i_windows));
         dp.win_tile_ptr = reinterpret_cast<const int32_t *>(at(i_win_tile_ptr));
         dp.win_seg = reinterpret_cast<const int32_t *>(at(i_win_seg));
