@@ -162,7 +162,7 @@ extern "C" spmm_status spmm_plan_upload(spmm_plan_t *p) {
             std::vector<int32_t> key(h.seg_begin.size());
             for (size_t i = 0; i < key.size(); ++i) {
                 seg_order[i] = (int32_t)i;
-                key[i] = h.rem_col[(size_t)(h.seg_begin[i] + h.seg_end[i] - 1) / 2];
+                key[i] = h.rem_col[(size_t)(h.seg_begin[i] + h.seg_end[i] - 1) / 2] & 0x7fffffff;  // bit 31: hot
             }
             std::stable_sort(seg_order.begin(), seg_order.end(),
                              [&](int32_t x, int32_t y) { return key[x] < key[y]; });
