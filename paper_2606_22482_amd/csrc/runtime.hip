@@ -153,10 +153,12 @@ extern "C" spmm_status spmm_plan_upload(spmm_plan_t *p) {
         const size_t i_win_seg = add_vec(a, h.win_seg);
         const size_t i_win_order = add_vec(a, h.win_order);
         // Launch order of the segments: by the column of each segment's middle
-        // entry (stable).  Rows keep their columns in CSR order, so segments
-        // that run together gather B rows from one stretch of B and share them
-        // in L2 and the Infinity Cache; each partial still lands in its own
-        // slot and is summed in segment order, so C does not change.
+        // entry (stable).  A row's entries keep their CSR order, which is column
+        // order when the CSR's columns are sorted; then segments that run
+        // together gather B rows from one stretch of B and share them in L2 and
+        // the Infinity Cache.  Any order is correct: each partial lands in its
+        // own slot and a row's partials are summed in segment order, so C does
+        // not depend on it.
         std::vector<int32_t> seg_order(h.seg_begin.size());
         {
             std::vector<int32_t> key(h.seg_begin.size());
