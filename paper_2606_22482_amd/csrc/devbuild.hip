@@ -238,7 +238,40 @@ __global__ __launch_bounds__(kThreads) void k_segments(int64_t m, int64_t S, int
     }
 }
 
+// Sort key of each segment's launch: the column of its middle entry (the
+// hot-column flag is never set in a plan built here).
+__global__ __launch_bounds__(kThreads) void k_seg_keys(int64_t S, const int32_t *__restrict__ seg_begin,
+                                                       const int32_t *__restrict__ seg_end,
+                                                       const int32_t *__restrict__ col,
+                                                       int32_t *__restrict__ key) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= S) return;
+    key[i] = col[((int64_t)seg_begin[i] + seg_end[i] - 1) / 2] & 0x7fffffff;
+}
+
 unsigned blocks_for(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + kThreads - 1) / kThreads); }
+
+// 0 .. n-1 stably sorted by non-negative keys: two counting passes over
+// 16-bit digits, lowest first (the order a stable comparison sort gives).
+std::vector<int32_t> order_by_key(const std::vector<int32_t> &key) {
+    const size_t n = key.size();
+    std::vector<int32_t> a(n), b(n);
+    std::iota(a.begin(), a.end(), 0);
+    std::vector<size_t> cnt((size_t)1 << 16);
+    for (int shift = 0; shift < 32; shift += 16) {
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (size_t i = 0; i < n; ++i) ++cnt[((uint32_t)key[a[i]] >> shift) & 0xFFFFu];
+        size_t sum = 0;
+        for (size_t &c : cnt) {
+            const size_t t = c;
+            c = sum;
+            sum += t;
+        }
+        for (size_t i = 0; i < n; ++i) b[cnt[((uint32_t)key[a[i]] >> shift) & 0xFFFFu]++] = a[i];
+        a.swap(b);
+    }
+    return a;
+}
 
 // exclusive (or inclusive) scan of n int64 values; *total (device) = sum
 hipError_t scan64(const int64_t *in, int64_t *out, int64_t n, int inclusive, int64_t *sums,
@@ -369,7 +402,8 @@ extern "C" spmm_status spmm_plan_device(const spmm_csr *A, int32_t n, int32_t b_
                      p_rem_val = pcarve((size_t)sval * (size_t)nnz),
                      p_vec = pcarve(sorted ? 4 * (size_t)m : 0), p_vptr = pcarve(4 * (size_t)(V + 1)),
                      p_vseg = pcarve(4 * (size_t)V), p_sb = pcarve(4 * (size_t)S),
-                     p_se = pcarve(4 * (size_t)S), p_sr = pcarve(4 * (size_t)S);
+                     p_se = pcarve(4 * (size_t)S), p_sr = pcarve(4 * (size_t)S),
+                     p_so = pcarve(4 * (size_t)S);
         const size_t ptotal = std::max<size_t>(poff, 256);
         int dev = 0;
         SPMM_TRY_HIP(hipGetDevice(&dev), "hipGetDevice");
@@ -385,6 +419,7 @@ extern "C" spmm_status spmm_plan_device(const spmm_csr *A, int32_t n, int32_t b_
         auto *seg_begin = reinterpret_cast<int32_t *>(pat(p_sb));
         auto *seg_end = reinterpret_cast<int32_t *>(pat(p_se));
         auto *seg_row = reinterpret_cast<int32_t *>(pat(p_sr));  // host bookkeeping only
+        auto *seg_order = reinterpret_cast<int32_t *>(pat(p_so));  // sort keys, then the launch order
         for (size_t t : tails)
             SPMM_TRY_HIP(hipMemsetAsync(pat(t), 0, 16, s), "hipMemsetAsync");
         SPMM_TRY_HIP(hipMemcpyAsync(pat(p_rem_ptr), rp32, 4 * (size_t)(m + 1), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
@@ -403,6 +438,9 @@ extern "C" spmm_status spmm_plan_device(const spmm_csr *A, int32_t n, int32_t b_
             hipLaunchKernelGGL(k_item_seg, dim3(blocks_for(V)), dim3(kThreads), 0, s, V, vitem_ptr, start, vitem_seg);
             hipLaunchKernelGGL(k_segments, dim3(blocks_for(m)), dim3(kThreads), 0, s, m, S, o.seg_len, order, nseg,
                                rp32, start, seg_begin, seg_end, seg_row);
+            if (S > 0)
+                hipLaunchKernelGGL(k_seg_keys, dim3(blocks_for(S)), dim3(kThreads), 0, s, S, seg_begin, seg_end,
+                                   reinterpret_cast<const int32_t *>(pat(p_rem_col)), seg_order);
         }
         if (k > 0)
             hipLaunchKernelGGL(k_count_seen, dim3((unsigned)std::min<int64_t>(blocks_for(k), 4096)), dim3(kThreads),
@@ -428,9 +466,21 @@ extern "C" spmm_status spmm_plan_device(const spmm_csr *A, int32_t n, int32_t b_
         SPMM_TRY_HIP(d2h(h.seg_begin.data(), seg_begin, 4 * (size_t)S), "hipMemcpyAsync");
         SPMM_TRY_HIP(d2h(h.seg_end.data(), seg_end, 4 * (size_t)S), "hipMemcpyAsync");
         SPMM_TRY_HIP(d2h(h.seg_row.data(), seg_row, 4 * (size_t)S), "hipMemcpyAsync");
+        std::vector<int32_t> seg_key((size_t)S);
+        SPMM_TRY_HIP(d2h(seg_key.data(), seg_order, 4 * (size_t)S), "hipMemcpyAsync");
         if (sorted) SPMM_TRY_HIP(d2h(h.vexec.data(), order, 4 * (size_t)m), "hipMemcpyAsync");
         SPMM_TRY_HIP(d2h(&kref, kcount, 8), "hipMemcpyAsync");
         SPMM_TRY_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+        // Launch order of the segments by the column of their middle entry
+        // (stable), as for an uploaded host plan: segments that run together
+        // gather from one stretch of B.  C does not depend on the order.
+        const std::vector<int32_t> so = order_by_key(seg_key);
+        bool so_id = true;
+        for (int64_t i = 0; i < S && so_id; ++i) so_id = so[i] == (int32_t)i;
+        if (!so_id) {
+            SPMM_TRY_HIP(hipMemcpyAsync(seg_order, so.data(), 4 * (size_t)S, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+            SPMM_TRY_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+        }
         h.rem_ptr.assign(h.rem_ptr32.begin(), h.rem_ptr32.end());
         h.vector_rows.resize(m);
         std::iota(h.vector_rows.begin(), h.vector_rows.end(), 0);
@@ -454,6 +504,7 @@ extern "C" spmm_status spmm_plan_device(const spmm_csr *A, int32_t n, int32_t b_
         dp.vitem_seg = vitem_seg;
         dp.seg_begin = seg_begin;
         dp.seg_end = seg_end;
+        dp.seg_order = so_id ? nullptr : seg_order;
         dp.n_wpart = 0;
         dp.win_tmax = kWinTiles;
         p->dev = d;
