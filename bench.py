@@ -123,9 +123,9 @@ def cpu_baseline(A, B, b_kind, n, budget_s=12.0):
     oracle.spmm(A.rowptr[: rows + 1], A.colidx, A.vals, B, val_kind=A.val_kind, b_kind=b_kind,
                 nthreads=threads, want_scale=False)
     dt = time.perf_counter() - t0
-    # when the whole matrix takes less than the budget, repeat it (at most 20
-    # passes) so that the rate rests on several seconds of work
-    reps = int(min(20, max(1, budget_s / max(dt, 1e-6)))) if rows == m else 1
+    # when the whole matrix takes less than the budget, repeat it (at most 64
+    # passes) so that the rate rests on about the budget's seconds of work
+    reps = int(min(64, max(1, budget_s / max(dt, 1e-6)))) if rows == m else 1
     if reps > 1:
         t0 = time.perf_counter()
         for _ in range(reps):
