@@ -45,13 +45,22 @@ typedef int32_t spmm_status;
 #define SPMM_ERR_BUDGET 5      /* request exceeds a memory budget */
 #define SPMM_ERR_BUSY 6        /* object still referenced by unfinished work */
 
+/* precision classes of a plan (spmm_plan_stats_t.tol_class) and the error bound each is
+ * held to, max |C - C*| / sum_p |v_p| |B[col_p][j]| against the FP64 result C* */
+#define SPMM_TOL_FP32 0       /* 1e-5 */
+#define SPMM_TOL_ROUNDED16 1  /* 2e-2 */
+
 /* element types */
 #define SPMM_F32 0
 #define SPMM_BF16 1
 #define SPMM_F16 2
 
-/* execution modes (Sec. 8.2 ablation: vector-only, matrix-only, coordinated) */
-#define SPMM_MODE_AUTO 0       /* use the tuned profile of this sparsity pattern, else MIXED defaults */
+/* execution modes (Sec. 8.3 ablation: vector-only, matrix-only, coordinated) */
+#define SPMM_MODE_AUTO 0       /* the tuned profile of this sparsity pattern, else MIXED defaults when
+                                  tiles would hold most entries, else PLAIN_F32.  AUTO keeps the
+                                  precision class of the inputs: with f32 B (the FP32 path) it
+                                  always plans PLAIN_F32 (a tuned profile keeps its other options);
+                                  with 16-bit B tiles may round f32 values to bf16 (tol_class) */
 #define SPMM_MODE_PLAIN_F32 1  /* every entry on the FP32 vector path */
 #define SPMM_MODE_MIXED 2      /* dense-enough tiles on MFMA, the rest on the vector path */
 #define SPMM_MODE_MFMA_ONLY 3  /* every row in a window, every column in a tile (alpha = 0) */
@@ -114,7 +123,7 @@ typedef struct {
                           xor butterfly (classes 1 and all-groups sum as in variant 2); < 0: auto */
     int32_t win_sched; /* launch order of windows: 0 = by window id (neighbouring windows, which
                           tend to gather the same B rows, run together on one XCD); 1 = heaviest
-                          first (LPT, Sec. 6.3); < 0: auto */
+                          first (LPT, Sec. 7 row-window lists); < 0: auto */
     int32_t local_reorder; /* Sec. 6.1 local reordering: > 0 = rows per cluster (rounded up to a
                               multiple of H) of the compacted or length-sorted row list, inside
                               which windows are rebuilt: the longest unassigned row of each
@@ -149,7 +158,11 @@ typedef struct {
     double flops;               /* 2 * nnz * N */
     double plan_ms;             /* host time spent building the plan */
     int32_t uploaded;           /* 1 after spmm_plan_upload */
-    int32_t reserved;
+    int32_t tol_class;          /* precision class of the plan's results: SPMM_TOL_FP32 when every
+                                   product is formed from the operands as given (FP32 FMAs, or
+                                   16-bit operands widened exactly) and summed in FP32;
+                                   SPMM_TOL_ROUNDED16 when MFMA tiles round f32 values or f32 B
+                                   to bf16 (round to nearest even) */
     double work_vec;            /* entries gathered by the segment and vector kernels */
     double work_tile;           /* tile slots: tiles * H * kt */
     double work_winrem;         /* remainder entries of window rows (gathered in the window kernels) */
@@ -294,7 +307,7 @@ spmm_status spmm_wait(spmm_ticket t);
  * vector-path throughput (entries*N per second) and MFMA-tile throughput
  * (tile slots*N per second) for this N and B type on the current device. */
 spmm_status spmm_dryrun(int32_t n, int32_t b_type, void *stream, double *p_vec, double *p_mfma);
-/* Autotuner (Sec. 5.2.1 cost model, Sec. 6.2.2 tile shaping, Sec. 8.2 threshold
+/* Autotuner (Sec. 5.2.1 cost model, Sec. 6.2.2 tile shaping, Sec. 8.3 threshold
  * sensitivity).  Derives alpha = P_vec / P_mfma from the dry run (Eq. 3 with
  * r = 1), then times candidate plans of A on the device (B, C: device buffers
  * of the run's shapes; C is overwritten) in a staged search over mode, window

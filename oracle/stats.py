@@ -6,7 +6,7 @@
 * Table 1 (Sec. 3.2): tile a matrix into t x t tiles, call a tile active if it
   holds at least one nonzero, and report the fraction of zeros over all
   active tiles.
-* Sec. 8.3 density of the matrix-engine workload: nnz / (tile area) over the
+* Sec. 8.4 density of the matrix-engine workload: nnz / (tile area) over the
   tiles handed to it.
 """
 from __future__ import annotations

@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(HERE, "libspmm.so")
 
 SPMM_OK, SPMM_ERR_INVALID, SPMM_ERR_OOM, SPMM_ERR_DEVICE = 0, 1, 2, 3
 SPMM_ERR_UNSUPPORTED, SPMM_ERR_BUDGET, SPMM_ERR_BUSY = 4, 5, 6
+SPMM_TOL_FP32, SPMM_TOL_ROUNDED16 = 0, 1
 F32, BF16, F16 = 0, 1, 2
 MODE_AUTO, MODE_PLAIN_F32, MODE_MIXED, MODE_MFMA_ONLY = 0, 1, 2, 3
 ORDER_AUTO, ORDER_ORIGINAL_RANGES, ORDER_COMPACTED, ORDER_LENGTH_SORTED = 0, 1, 2, 3
@@ -46,7 +47,7 @@ class PlanStats(C.Structure):
                 ("mean_tile_density", C.c_double), ("zero_fraction_tiles", C.c_double),
                 ("device_bytes", C.c_int64), ("workspace_bytes", C.c_int64),
                 ("algorithmic_bytes", C.c_double), ("flops", C.c_double),
-                ("plan_ms", C.c_double), ("uploaded", C.c_int32), ("reserved", C.c_int32),
+                ("plan_ms", C.c_double), ("uploaded", C.c_int32), ("tol_class", C.c_int32),
                 ("work_vec", C.c_double), ("work_tile", C.c_double), ("work_winrem", C.c_double)]
 
 

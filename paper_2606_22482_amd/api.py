@@ -73,6 +73,31 @@ def _dev2d(t, what):
     return t.data_ptr(), t.stride(0)
 
 
+_TORCH_DTYPE = {"f32": "float32", "bf16": "bfloat16", "f16": "float16"}
+
+
+def _operands(m: int, k: int, n: int, b_kind: str, B, Cout):
+    """Device pointers and leading dimensions of B and C after checking them
+    against the problem, before anything reaches the device: B of the plan's
+    B type with at least k rows and n columns, C float32 with at least m rows
+    and n columns, both 2-D device tensors with unit column stride.  (The C
+    ABI only sees pointers and leading dimensions, so a wrong dtype or a short
+    B would make the kernels read or write out of bounds.)"""
+    import torch
+    want = getattr(torch, _TORCH_DTYPE[b_kind])
+    if B.dtype != want:
+        raise ValueError("B must be %s for this plan (B type %s), got %s" % (want, b_kind, B.dtype))
+    if Cout.dtype != torch.float32:
+        raise ValueError("C must be torch.float32, got %s" % Cout.dtype)
+    if B.dim() != 2 or B.shape[0] < k or B.shape[1] < n:
+        raise ValueError("B must be at least %d x %d, got %s" % (k, n, tuple(B.shape)))
+    if Cout.dim() != 2 or Cout.shape[0] < m or Cout.shape[1] < n:
+        raise ValueError("C must be at least %d x %d, got %s" % (m, n, tuple(Cout.shape)))
+    bp, ldb = _dev2d(B, "B")
+    cp, ldc = _dev2d(Cout, "C")
+    return bp, ldb, cp, ldc
+
+
 def _csr_struct(A):
     rowptr = np.ascontiguousarray(A.rowptr, dtype=np.int64)
     colidx = np.ascontiguousarray(A.colidx, dtype=np.int32)
@@ -213,15 +238,18 @@ class Plan:
             "vexec_rows": arr(d.vexec_rows, d.n_vector_rows, np.int32),
         }
 
+    def operands(self, B, Cout):
+        """(B pointer, ldb, C pointer, ldc) after checking B and C against
+        this plan (see _operands)."""
+        return _operands(self.m, self.k, self.n, self.b_kind, B, Cout)
+
     def run(self, B, Cout, stream=None):
         """spmm_run: Cout = A @ B on the stream (torch's current one by default)."""
-        bp, ldb = _dev2d(B, "B")
-        cp, ldc = _dev2d(Cout, "C")
+        bp, ldb, cp, ldc = self.operands(B, Cout)
         L.check(self._lib.spmm_run(self._h, bp, ldb, cp, ldc, _stream_handle(stream)))
 
     def run_timed(self, B, Cout, timer: "Timer", stream=None):
-        bp, ldb = _dev2d(B, "B")
-        cp, ldc = _dev2d(Cout, "C")
+        bp, ldb, cp, ldc = self.operands(B, Cout)
         L.check(self._lib.spmm_run_timed(self._h, bp, ldb, cp, ldc, _stream_handle(stream),
                                          timer.handle))
 
@@ -231,8 +259,7 @@ class Plan:
         the plan, this object takes the new plan's handle.  A must be the
         matrix this plan was built from.  Returns ``state``."""
         csr, keep = _csr_struct(A)
-        bp, ldb = _dev2d(B, "B")
-        cp, ldc = _dev2d(Cout, "C")
+        bp, ldb, cp, ldc = self.operands(B, Cout)
         L.check(self._lib.spmm_adapt_epoch(C.byref(csr), C.byref(self._h), bp, ldb, cp, ldc,
                                            _stream_handle(stream), float(eps), C.byref(state)))
         del keep
@@ -298,8 +325,7 @@ def spmm_submit(items, stream=None) -> int:
     lib = L.load()
     arr = (L.Work * max(1, len(items)))()
     for i, it in enumerate(items):
-        bp, ldb = _dev2d(it.B, "B")
-        cp, ldc = _dev2d(it.C, "C")
+        bp, ldb, cp, ldc = it.plan.operands(it.B, it.C)
         arr[i] = L.Work(it.plan.handle.value, bp, ldb, cp, ldc)
     t = C.c_uint64()
     L.check(lib.spmm_submit(arr, len(items), _stream_handle(stream), C.byref(t)))
@@ -330,8 +356,7 @@ def spmm_autotune(A, B, Cout, b_kind: str, budget_ms: float = 20000.0, stream=No
     under A's profile key for spmm_plan(mode=AUTO)."""
     lib = L.load()
     csr, keep = _csr_struct(A)
-    bp, ldb = _dev2d(B, "B")
-    cp, ldc = _dev2d(Cout, "C")
+    bp, ldb, cp, ldc = _operands(int(A.m), int(A.k), int(B.shape[1]), b_kind, B, Cout)
     o = L.Opts()
     rep = L.TuneReport()
     L.check(lib.spmm_autotune(C.byref(csr), int(B.shape[1]), L.KIND_CODE[b_kind], L.F32, bp, ldb,

@@ -5,7 +5,7 @@
 // threshold alpha = r * P_vec / P_mfma from a dry run; on CDNA4 r = 1 (one
 // engine pool, a cost crossover rather than balanced co-running).  The paper
 // then tunes the tile shape (Sec. 6.2.2) and shows the threshold's
-// sensitivity (Sec. 8.2); here the remaining knobs are chosen by timing
+// sensitivity (Sec. 8.3); here the remaining knobs are chosen by timing
 // candidate plans on the device, staged so that each stage varies one group
 // of options around the best plan so far.
 #include <hip/hip_runtime.h>
@@ -281,8 +281,11 @@ extern "C" spmm_status spmm_autotune(const spmm_csr *A, int32_t n, int32_t b_typ
 
     // stage 1: vector-only vs mixed with each window order (Sec. 6.1), and the
     // mixed plan that AUTO builds without a profile (the plain one is the
-    // base), so that a tuned plan is never slower than the untuned default
-    {
+    // base), so that a tuned plan is never slower than the untuned default.
+    // With f32 B the problem is on the FP32 path: mixed plans would round
+    // tile operands to bf16, so only vector-path options are searched.
+    const bool fp32_class = b_type == SPMM_F32;
+    if (!fp32_class) {
         spmm_opts d, o;
         spmm_opts_default(&d);
         d.mode = SPMM_MODE_MIXED;
@@ -290,6 +293,7 @@ extern "C" spmm_status spmm_autotune(const spmm_csr *A, int32_t n, int32_t b_typ
         SPMM_TRY(try_opts(o));
     }
     for (int order : {SPMM_ORDER_ORIGINAL_RANGES, SPMM_ORDER_LENGTH_SORTED, SPMM_ORDER_COMPACTED}) {
+        if (fp32_class) break;
         spmm_opts o;
         spmm_opts_default(&o);
         o.mode = SPMM_MODE_MIXED;

@@ -379,6 +379,7 @@ spmm_status validate_opts(const spmm_opts &o, std::string &err) {
     if (o.seg_len < 1 || o.seg_len > (1 << 30)) { err = "seg_len"; return SPMM_ERR_UNSUPPORTED; }
     if (o.item_cost < 1) { err = "item_cost"; return SPMM_ERR_UNSUPPORTED; }
     if (o.n_panel < 0) { err = "n_panel"; return SPMM_ERR_UNSUPPORTED; }
+    if (o.xcd_remap < 0 || o.xcd_remap > 1) { err = "xcd_remap must be 0 or 1"; return SPMM_ERR_UNSUPPORTED; }
     if (o.hot_cols < 0) { err = "hot_cols"; return SPMM_ERR_UNSUPPORTED; }
     if (o.pipeline < 0 || o.pipeline > 3) { err = "pipeline must be 0, 1, 2 or 3"; return SPMM_ERR_UNSUPPORTED; }
     if (o.win_sched < 0 || o.win_sched > 1) { err = "win_sched must be 0 or 1"; return SPMM_ERR_UNSUPPORTED; }

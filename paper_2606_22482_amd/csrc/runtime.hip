@@ -108,8 +108,23 @@ extern "C" spmm_status spmm_plan_build(const spmm_csr *A, int32_t n, int32_t b_t
         const bool auto_mode = !opts || opts->mode == SPMM_MODE_AUTO;
         spmm_opts tuned;
         const bool have_tuned = auto_mode && cache_lookup(profile_key(A, n, b_type), &tuned);
+        // AUTO keeps the caller's precision class: with f32 B the problem is
+        // on the FP32 path (1e-5), and a mixed plan would round B and the
+        // values to bf16 in its tiles, so AUTO plans it on the vector path
+        // (a tuned profile keeps its other options).  16-bit B is the 16-bit
+        // input class (2e-2), where tiles may round f32 values.
+        const bool rounds = b_type == SPMM_F32;
         spmm_opts o;
-        resolve_options(have_tuned ? &tuned : opts, A, n, b_type, &o);
+        if (auto_mode && rounds) {
+            spmm_opts d;
+            if (have_tuned) d = tuned;
+            else if (opts) d = *opts;
+            else spmm_opts_default(&d);
+            d.mode = SPMM_MODE_PLAIN_F32;
+            resolve_options(&d, A, n, b_type, &o);
+        } else {
+            resolve_options(have_tuned ? &tuned : opts, A, n, b_type, &o);
+        }
         std::unique_ptr<spmm_plan_s> p(new spmm_plan_s());
         st = build_host_plan(A, n, b_type, c_type, o, p->hp, err);
         if (st != SPMM_OK) return set_error(st, err);
@@ -117,7 +132,7 @@ extern "C" spmm_status spmm_plan_build(const spmm_csr *A, int32_t n, int32_t b_t
         // tiles hold most of the entries, else plan the plain path.  Measured on
         // gfx950: power-law graphs with 1-30% of the entries in tiles run faster
         // plain; block-community matrices with 95% in tiles run 2x faster mixed.
-        if (auto_mode && !have_tuned && A->nnz > 0 &&
+        if (auto_mode && !rounds && !have_tuned && A->nnz > 0 &&
             (double)p->hp.tile_src.size() < 0.5 * (double)A->nnz) {
             o.mode = SPMM_MODE_PLAIN_F32;
             st = build_host_plan(A, n, b_type, c_type, o, p->hp, err);
@@ -360,6 +375,9 @@ extern "C" spmm_status spmm_plan_stats(const spmm_plan_t *p, spmm_plan_stats_t *
     out->flops = 2.0 * (double)h.nnz * (double)h.n;
     out->plan_ms = h.plan_ms;
     out->uploaded = p->dev != nullptr;
+    out->tol_class = (!h.tile_src.empty() && (h.val_type == SPMM_F32 || h.b_type == SPMM_F32))
+                         ? SPMM_TOL_ROUNDED16
+                         : SPMM_TOL_FP32;
     plan_path_work(h, &out->work_vec, &out->work_tile, &out->work_winrem);
     return SPMM_OK;
 }
@@ -422,12 +440,14 @@ std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
 }  // namespace
 
 namespace spmm {
-spmm_status workspace_for(hipStream_t s, size_t bytes, float **out) {
+spmm_status workspace_for(hipStream_t s, size_t bytes, float **out, std::unique_lock<std::mutex> &lk) {
     *out = nullptr;
     if (bytes == 0) return SPMM_OK;
     int dev = 0;
     SPMM_TRY_HIP(hipGetDevice(&dev), "hipGetDevice");
-    std::lock_guard<std::mutex> lk(g_ws_mu);
+    // held by the caller until its kernels are enqueued, so that another
+    // thread growing this stream's workspace cannot free it in between
+    lk = std::unique_lock<std::mutex>(g_ws_mu);
     Workspace &w = g_ws[{dev, s}];
     if (w.bytes < bytes) {
         const size_t old = w.bytes;
@@ -615,7 +635,8 @@ static spmm_status run_impl(const spmm_plan_t *p, const void *B, int64_t ldb, vo
     hipStream_t s = static_cast<hipStream_t>(stream);
     RunArgs a;
     make_run_args(p, B, ldb, C, ldc, a);
-    st = workspace_for(s, workspace_floats(p->hp) * sizeof(float), &a.work);
+    std::unique_lock<std::mutex> ws_lock;
+    st = workspace_for(s, workspace_floats(p->hp) * sizeof(float), &a.work, ws_lock);
     if (st != SPMM_OK) return st;
     return launch_plan(p, a, s, t);
 }

@@ -26,7 +26,9 @@ struct spmm_plan_s {
 namespace spmm {
 spmm_status set_error(spmm_status s, const std::string &msg);
 spmm_status hip_error(hipError_t e, const char *what);
-spmm_status workspace_for(hipStream_t s, size_t bytes, float **out);
+// The stream's workspace of at least `bytes`; `lk` holds the workspace table
+// until the caller has enqueued the kernels that use it.
+spmm_status workspace_for(hipStream_t s, size_t bytes, float **out, std::unique_lock<std::mutex> &lk);
 spmm_status make_run_args(const spmm_plan_t *p, const void *B, int64_t ldb, void *C, int64_t ldc,
                           RunArgs &a);
 spmm_status check_run(const spmm_plan_t *p, const void *B, int64_t ldb, void *C, int64_t ldc);

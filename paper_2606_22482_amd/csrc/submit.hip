@@ -26,19 +26,29 @@ using namespace spmm;
     } while (0)
 
 namespace {
+// A ticket's completion event and the plans its work uses.  The table holds
+// one reference; spmm_wait holds another while it waits, so the event stays
+// valid even when a concurrent spmm_poll retires the ticket meanwhile.
 struct Ticket {
     hipEvent_t done = nullptr;
     std::vector<spmm_plan_t *> plans;
+    Ticket() = default;
+    Ticket(const Ticket &) = delete;
+    Ticket &operator=(const Ticket &) = delete;
+    ~Ticket() {
+        if (done) (void)hipEventDestroy(done);
+    }
 };
 std::mutex g_tk_mu;
-std::map<spmm_ticket, Ticket> g_tickets;
+std::map<spmm_ticket, std::shared_ptr<Ticket>> g_tickets;
 std::atomic<uint64_t> g_next_ticket{1};
 
-void release(Ticket &t) {
-    for (auto *p : t.plans) p->busy.fetch_sub(1);
-    if (t.done) (void)hipEventDestroy(t.done);
-    t.plans.clear();
-    t.done = nullptr;
+// Under g_tk_mu: the ticket's plans are released exactly once, by whichever
+// call takes it out of the table.
+void retire(std::map<spmm_ticket, std::shared_ptr<Ticket>>::iterator it) {
+    for (auto *p : it->second->plans) p->busy.fetch_sub(1);
+    it->second->plans.clear();
+    g_tickets.erase(it);
 }
 }  // namespace
 
@@ -322,18 +332,18 @@ extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *
         SPMM_TRY_HIP(hipGraphLaunch(vg.exec, s), "hipGraphLaunch");
     }
 
-    Ticket t;
-    hipError_t e = hipEventCreateWithFlags(&t.done, hipEventDisableTiming);
-    if (e != hipSuccess) return hip_error(e, "hipEventCreate");
-    e = hipEventRecord(t.done, s);
+    auto t = std::make_shared<Ticket>();
+    hipError_t e = hipEventCreateWithFlags(&t->done, hipEventDisableTiming);
     if (e != hipSuccess) {
-        (void)hipEventDestroy(t.done);
-        return hip_error(e, "hipEventRecord");
+        t->done = nullptr;
+        return hip_error(e, "hipEventCreate");
     }
+    e = hipEventRecord(t->done, s);
+    if (e != hipSuccess) return hip_error(e, "hipEventRecord");
     for (int32_t i = 0; i < count; ++i) {
         auto *p = const_cast<spmm_plan_t *>(items[i].plan);
         p->busy.fetch_add(1);
-        t.plans.push_back(p);
+        t->plans.push_back(p);
     }
     const spmm_ticket id = g_next_ticket.fetch_add(1);
     std::lock_guard<std::mutex> lk2(g_tk_mu);
@@ -350,34 +360,30 @@ extern "C" spmm_status spmm_poll(spmm_ticket id, int32_t *done) {
         *done = 1;
         return SPMM_OK;
     }
-    hipError_t e = hipEventQuery(it->second.done);
+    hipError_t e = hipEventQuery(it->second->done);
     if (e == hipErrorNotReady) {
         *done = 0;
         return SPMM_OK;
     }
     if (e != hipSuccess) return hip_error(e, "hipEventQuery");
-    release(it->second);
-    g_tickets.erase(it);
+    retire(it);
     *done = 1;
     return SPMM_OK;
 }
 
 extern "C" spmm_status spmm_wait(spmm_ticket id) {
-    hipEvent_t ev = nullptr;
+    std::shared_ptr<Ticket> t;  // keeps the event alive while this call waits
     {
         std::lock_guard<std::mutex> lk(g_tk_mu);
         auto it = g_tickets.find(id);
         if (it == g_tickets.end()) return SPMM_OK;
-        ev = it->second.done;
+        t = it->second;
     }
-    hipError_t e = hipEventSynchronize(ev);
+    hipError_t e = hipEventSynchronize(t->done);
     if (e != hipSuccess) return hip_error(e, "hipEventSynchronize");
     std::lock_guard<std::mutex> lk(g_tk_mu);
     auto it = g_tickets.find(id);
-    if (it != g_tickets.end()) {
-        release(it->second);
-        g_tickets.erase(it);
-    }
+    if (it != g_tickets.end()) retire(it);
     return SPMM_OK;
 }
 

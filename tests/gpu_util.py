@@ -6,6 +6,20 @@ import oracle
 
 TOL_F32 = 1e-5     # FP32 path, error normalised by sum |A||B|
 TOL_16 = 2e-2      # 16-bit MFMA operands
+# FP32 path, plain relative error |C - C*| / |C*| on the entries whose |C*| is
+# at least REL_FLOOR * sum |A||B| (below it cancellation makes the relative
+# error unbounded for any FP32 summation and the normalised error applies)
+REL_FLOOR = 0.1
+
+
+def max_relative_error(C, Cs, S, floor=REL_FLOOR):
+    """max |C - C*| / |C*| over entries with |C*| >= floor * S, and how many
+    entries that covers."""
+    sel = np.abs(Cs) >= floor * S
+    sel &= S > 0
+    if not sel.any():
+        return 0.0, 0
+    return float(np.max(np.abs(C[sel] - Cs[sel]) / np.abs(Cs[sel]))), int(sel.sum())
 
 
 def device_B(B, kind, pad_cols=0):
@@ -44,6 +58,9 @@ def parity(Cdev, A, B, b_kind, tol, rows=None):
     Cs, S = oracle_of(A, B, b_kind, rows=rows)
     err = oracle.max_normalised_error(C, Cs, S)
     assert err <= tol, "normalised error %g > %g" % (err, tol)
+    if tol <= TOL_F32:
+        rel, count = max_relative_error(C, Cs, S)
+        assert rel <= TOL_F32, "relative error %g > %g over %d entries" % (rel, TOL_F32, count)
     return err
 
 

@@ -314,8 +314,22 @@ def test_auto_mode_falls_back_to_plain_without_tiles(lib):
     p = api.Plan(A, 16, "f32", None, upload=False)
     assert p.stats()["opts"]["mode"] == L.MODE_PLAIN_F32
     B, _ = synth.block_community(n=1024, band=4, n_cols=8, seed=2)
-    q = api.Plan(B, 16, "f32", None, upload=False)
+    # 16-bit B: the tiles hold most entries, so AUTO keeps the mixed plan (its
+    # tiles round the f32 values to bf16, which the plan reports)
+    q = api.Plan(B, 16, "bf16", None, upload=False)
     assert q.stats()["opts"]["mode"] == L.MODE_MIXED and q.stats()["tiles"] > 0
+    assert q.stats()["tol_class"] == L.SPMM_TOL_ROUNDED16
+    # f32 B is the FP32 path: AUTO never rounds its operands
+    r = api.Plan(B, 16, "f32", None, upload=False)
+    assert r.stats()["opts"]["mode"] == L.MODE_PLAIN_F32 and r.stats()["tiles"] == 0
+    assert r.stats()["tol_class"] == L.SPMM_TOL_FP32
+    # an explicit mixed plan of f32 B rounds, and says so
+    x = api.Plan(B, 16, "f32", api.default_opts(mode="mixed"), upload=False)
+    assert x.stats()["tiles"] > 0 and x.stats()["tol_class"] == L.SPMM_TOL_ROUNDED16
+    # 16-bit values and B: the tiles' products are exact, so the class stays FP32
+    Bb = synth.CSR(B.m, B.k, B.rowptr, B.colidx, synth.to_bf16_bits(B.vals), "bf16")
+    y = api.Plan(Bb, 16, "bf16", api.default_opts(mode="mixed"), upload=False)
+    assert y.stats()["tiles"] > 0 and y.stats()["tol_class"] == L.SPMM_TOL_FP32
 
 
 def test_plan_stats_consistency(lib):

@@ -51,7 +51,15 @@ def test_auto_plan_uses_cached_profile():
     tuned = api.default_opts(mode="mixed", window_h=32, t_row=-1, alpha_c=0.0, alpha=0.0,
                              seg_len=33)
     api.tune_cache_put(key, tuned)
+    # f32 B: the profile's other options apply, but AUTO stays on the FP32 path
     q = api.Plan(A, 16, "f32", api.default_opts(mode="auto"), upload=False)
+    so = q.stats()["opts"]
+    assert so["mode"] == L.MODE_PLAIN_F32 and so["seg_len"] == 33 and q.stats()["tiles"] == 0
+    # 16-bit B (its own profile key): the tuned mixed plan is used as stored
+    key16 = api.spmm_profile_key(A, 16, "bf16")
+    assert key16 != key
+    api.tune_cache_put(key16, tuned)
+    q = api.Plan(A, 16, "bf16", api.default_opts(mode="auto"), upload=False)
     so = q.stats()["opts"]
     assert so["mode"] == L.MODE_MIXED and so["window_h"] == 32 and so["seg_len"] == 33
     assert q.stats()["tiles"] > 0

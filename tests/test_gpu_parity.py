@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 from gpu_util import TOL_16, TOL_F32, device_B, device_C, exact, parity
+from paper_2606_22482_amd import _lib as L
 from paper_2606_22482_amd import api, synth
 
 pytestmark = pytest.mark.gpu
@@ -489,10 +490,19 @@ def test_destroy_busy_plan_rejected():
     p = api.Plan(A, 64, "f32", api.default_opts(mode="plain"))
     Bd = device_B(B, "f32")
     C = device_C(A.m, 64)
-    t = api.spmm_submit([api.WorkItem(p, Bd, C)])
+    t = api.spmm_submit([api.WorkItem(p, Bd, C), api.WorkItem(p, Bd, device_C(A.m, 64))])
+    # the ticket is outstanding until spmm_poll or spmm_wait retires it, so
+    # destroy refuses with BUSY however far the device has got, and leaves
+    # the plan usable
+    with pytest.raises(L.SpmmError) as ei:
+        p.destroy()
+    assert ei.value.status == L.SPMM_ERR_BUSY
+    assert p.handle and p.stats()["m"] == A.m
     api.spmm_wait(t)
     p.destroy()  # the ticket is retired, so destroy succeeds
+    assert p.handle is None
     torch.cuda.synchronize()
+    parity(C, A, B, "f32", TOL_F32)
 
 
 def test_autotune_picks_and_caches():
@@ -511,7 +521,10 @@ def test_autotune_picks_and_caches():
     C2 = device_C(A.m, 128)
     p.run(Bd, C2)
     torch.cuda.synchronize()
-    parity(C2, A, B, "bf16", TOL_16 if opts.mode != 1 else TOL_F32)
+    # the plan states its precision class; the tolerance follows it
+    st = p.stats()
+    assert st["tol_class"] == (1 if st["tiles"] > 0 else 0)
+    parity(C2, A, B, "bf16", TOL_16 if st["tol_class"] == L.SPMM_TOL_ROUNDED16 else TOL_F32)
     api.tune_cache_clear()
 
 

@@ -230,7 +230,7 @@ def test_local_reorder_is_a_partition():
 
 def test_local_reorder_raises_tile_density():
     """Shuffled community rows: the rebuilt windows keep more entries in
-    tiles at a higher density than the shuffled order (Sec. 8.2 measure)."""
+    tiles at a higher density than the shuffled order (Sec. 8.4 measure)."""
     A, _ = synth.block_community(n=2048, band=4, n_cols=8, seed=5)
     rng = np.random.default_rng(1)
     perm = rng.permutation(A.m)
