@@ -82,6 +82,14 @@ def kernel_bytes(A, d, n, s_a, s_b):
     c = np.concatenate([rem_cols[wmask], colidx[d["tile_src"]]])
     nw = int((d["windows"] >= 0).sum())
     out["window"] = 4 * (nw + 1) + c.size * (4 + s_a) + np.unique(c).size * n * s_b + nw * n * 4
+    # co-scheduled grids: the vector path (segments and vector items: every
+    # entry of a split row or a vector row, the vector rows' and split vector
+    # rows' C rows), the MFMA path (as the window kernel), one grid (all)
+    c = rem_cols[seg_mask | vmask]
+    out["vector_path"] = 4 * (nv + 1) + c.size * (4 + s_a) + np.unique(c).size * n * s_b + nv * n * 4
+    out["mfma_path"] = out["window"]
+    out["one_grid"] = 4 * (A.m + 1) + A.nnz * (4 + s_a) + np.unique(colidx).size * n * s_b + A.m * n * 4
+    out["window_partial"] = 0
     return out
 
 

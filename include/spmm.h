@@ -132,6 +132,16 @@ typedef struct {
                               sets, ties: earlier row in the list), leftover rows form windows in
                               list order; 0 = off; < 0: auto (off).  UNSUPPORTED with the
                               original-ranges order. */
+    int32_t exec;      /* how a run launches its items (Sec. 5.3, the two engines side by side):
+                          1 = one kernel per item kind in dependency order (segments, window partials,
+                          vector items, windows); 2 = co-scheduled: the vector path (segments and
+                          vector items) and the MFMA path (window partials and owners) as two grids that
+                          run concurrently on the run's stream and a second stream of it (fork and join
+                          by events, so a graph capture of the run records both); 3 = co-scheduled in one
+                          grid.  In 2 and 3 a result needing several items (a split row, a window with
+                          partial tiles or split rows) is finished by its last contributor, through
+                          integer counters in the workspace; C is bitwise the same in all three.  A cold
+                          policy needs 1.  <= 0: auto */
 } spmm_opts;
 
 typedef struct spmm_plan_s spmm_plan_t;
@@ -206,6 +216,12 @@ typedef struct {
                                    kernel takes them, item by item (equal to vector_rows except
                                    with pipeline 3, which orders each item's rows by remainder
                                    length, longest first, and split rows last) */
+    /* tables of co-scheduled runs (exec 2, 3) */
+    int64_t n_dep;              /* windows whose result needs other items' parts */
+    const int32_t *seg_win;     /* int32 [n_segments] (or NULL without windows): window of the
+                                   segment's row, -1 for a vector row */
+    const int32_t *win_dep;     /* int32 [n_windows]: slot of such a window, else -1 */
+    const int32_t *win_nsseg;   /* int32 [n_windows]: segments of the window's split rows */
 } spmm_plan_dump_t;
 
 /* One matrix of a batched submission (device pointers). */
@@ -288,6 +304,9 @@ spmm_status spmm_run(const spmm_plan_t *p, const void *B, int64_t ldb, void *C, 
 #define SPMM_KERNEL_VECTOR 1  /* FP32 gather-FMA over vector rows */
 #define SPMM_KERNEL_WINDOW 2  /* MFMA windows + their rows' remainders */
 #define SPMM_KERNEL_WINDOW_PARTIAL 3 /* MFMA partial results of windows' extra tiles */
+#define SPMM_KERNEL_VECTOR_PATH 4 /* co-scheduled: segments and vector items in one grid */
+#define SPMM_KERNEL_MFMA_PATH 5   /* co-scheduled: window partials and owners in one grid (second stream) */
+#define SPMM_KERNEL_ONE_GRID 6    /* co-scheduled: every item kind in one grid */
 spmm_status spmm_timer_create(int32_t capacity, spmm_timer_t **out);
 spmm_status spmm_timer_reset(spmm_timer_t *t);
 spmm_status spmm_timer_read(spmm_timer_t *t, int32_t *kernel_ids, float *ms, int32_t cap,
@@ -341,9 +360,11 @@ spmm_status spmm_tune_cache_load(const char *path);
 void spmm_tune_cache_clear(void);
 
 /* Epoch-level adaptive re-partition (Sec. 5.3, Eq. 6-7), read for one pool of
- * compute units: the vector path (segment and vector kernels) and the MFMA
- * path (window kernels) run one after the other on the same CUs, so the split
- * that minimises an epoch is the cost crossover of Eq. 3 with r = 1.  Each
+ * compute units: the vector path (segments and vector items) and the MFMA path
+ * (windows) share the same CUs -- one after the other (exec 1) or as two
+ * co-resident grids (exec 2), where a grid that finishes first leaves its CUs
+ * to the other -- so the split that minimises an epoch is the cost crossover
+ * of Eq. 3 with r = 1 rather than equal path times.  Each
  * epoch measures both paths and derives their throughputs (Eq. 1 inverted;
  * the window kernels' remainder entries are charged at the vector rate), the
  * crossover alpha* = P_vec / P_mfma, and Eq. 6's skew between the two paths'
@@ -386,10 +407,13 @@ spmm_status spmm_adapt_next(spmm_adapt_state *st, double t_vec_ms, double t_mfma
                             double w_vec, double w_tile, double w_winrem, double p_vec_dry,
                             double p_mfma_dry, float eps);
 /* One epoch on the device: C = A*B with *plan (timed on `stream`, which is
- * synchronised), then spmm_adapt_next, and when it asks for a re-partition,
+ * synchronised; each path's time is that of its kernels, or of its grid when
+ * co-scheduled), then spmm_adapt_next, and when it asks for a re-partition,
  * a new mixed plan of A with the same options except the threshold replaces
  * *plan (the old plan is destroyed; BUSY, with *plan kept, if it still has
- * outstanding tickets).  A must be the matrix *plan was built from. */
+ * outstanding tickets).  A must be the matrix *plan was built from.
+ * UNSUPPORTED for a plan with exec 3 (one grid: the paths' times cannot be
+ * told apart). */
 spmm_status spmm_adapt_epoch(const spmm_csr *A, spmm_plan_t **plan, const void *B, int64_t ldb,
                              void *C, int64_t ldc, void *stream, float eps,
                              spmm_adapt_state *st);

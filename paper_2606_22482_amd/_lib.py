@@ -17,7 +17,9 @@ ORDER_AUTO, ORDER_ORIGINAL_RANGES, ORDER_COMPACTED, ORDER_LENGTH_SORTED = 0, 1, 
 ORDER_CLUSTERED = 4
 AUTO_INT = -(2 ** 31)
 KERNEL_SEGMENT, KERNEL_VECTOR, KERNEL_WINDOW = 0, 1, 2
-KERNEL_NAMES = {0: "segment", 1: "vector", 2: "window", 3: "window_partial"}
+KERNEL_NAMES = {0: "segment", 1: "vector", 2: "window", 3: "window_partial", 4: "vector_path",
+                5: "mfma_path", 6: "one_grid"}
+EXEC_SERIAL, EXEC_TWO_GRIDS, EXEC_ONE_GRID = 1, 2, 3
 KIND_CODE = {"f32": F32, "bf16": BF16, "f16": F16}
 
 
@@ -33,7 +35,7 @@ class Opts(C.Structure):
                 ("seg_len", C.c_int32), ("item_cost", C.c_int32), ("xcd_remap", C.c_int32),
                 ("hot_cols", C.c_int32), ("alpha_c", C.c_float), ("alpha", C.c_float),
                 ("cold_policy", C.c_int32), ("pipeline", C.c_int32),
-                ("win_sched", C.c_int32), ("local_reorder", C.c_int32)]
+                ("win_sched", C.c_int32), ("local_reorder", C.c_int32), ("exec", C.c_int32)]
 
 
 class PlanStats(C.Structure):
@@ -64,7 +66,8 @@ class PlanDump(C.Structure):
                 ("seg_end", C.c_void_p), ("win_seg", C.c_void_p), ("win_order", C.c_void_p),
                 ("rem_col_dev", C.c_void_p), ("n_wparts", C.c_int64), ("win_part", C.c_void_p),
                 ("wpart_win", C.c_void_p), ("wpart_t0", C.c_void_p), ("wpart_t1", C.c_void_p),
-                ("vexec_rows", C.c_void_p)]
+                ("vexec_rows", C.c_void_p), ("n_dep", C.c_int64), ("seg_win", C.c_void_p),
+                ("win_dep", C.c_void_p), ("win_nsseg", C.c_void_p)]
 
 
 class TuneReport(C.Structure):

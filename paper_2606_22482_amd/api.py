@@ -236,6 +236,10 @@ class Plan:
             "wpart_t0": arr(d.wpart_t0, d.n_wparts, np.int32),
             "wpart_t1": arr(d.wpart_t1, d.n_wparts, np.int32),
             "vexec_rows": arr(d.vexec_rows, d.n_vector_rows, np.int32),
+            "n_dep": int(d.n_dep),
+            "seg_win": arr(d.seg_win, d.n_segments if d.seg_win else 0, np.int32),
+            "win_dep": arr(d.win_dep, W, np.int32),
+            "win_nsseg": arr(d.win_nsseg, W, np.int32),
         }
 
     def operands(self, B, Cout):

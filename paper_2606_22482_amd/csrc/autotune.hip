@@ -36,23 +36,23 @@ std::map<std::pair<int32_t, int32_t>, std::pair<double, double>> g_dryrun;  // (
 
 std::string opts_to_text(const spmm_opts &o) {
     char buf[256];
-    std::snprintf(buf, sizeof buf, "%d %d %d %d %d %d %d %d %d %d %.9g %.9g %d %d %d %d", o.mode,
+    std::snprintf(buf, sizeof buf, "%d %d %d %d %d %d %d %d %d %d %.9g %.9g %d %d %d %d %d", o.mode,
                   o.window_h, o.t_row, o.kt, o.n_panel, o.row_order, o.seg_len, o.item_cost,
                   o.xcd_remap, o.hot_cols, (double)o.alpha_c, (double)o.alpha, o.cold_policy,
-                  o.pipeline, o.win_sched, o.local_reorder);
+                  o.pipeline, o.win_sched, o.local_reorder, o.exec);
     return buf;
 }
 
 bool opts_from_text(const std::string &t, spmm_opts *o) {
     spmm_opts_default(o);
     double ac = 0, al = 0;
-    int n = std::sscanf(t.c_str(), "%d %d %d %d %d %d %d %d %d %d %lg %lg %d %d %d %d", &o->mode,
+    int n = std::sscanf(t.c_str(), "%d %d %d %d %d %d %d %d %d %d %lg %lg %d %d %d %d %d", &o->mode,
                         &o->window_h, &o->t_row, &o->kt, &o->n_panel, &o->row_order, &o->seg_len,
                         &o->item_cost, &o->xcd_remap, &o->hot_cols, &ac, &al, &o->cold_policy,
-                        &o->pipeline, &o->win_sched, &o->local_reorder);
+                        &o->pipeline, &o->win_sched, &o->local_reorder, &o->exec);
     o->alpha_c = (float)ac;
     o->alpha = (float)al;
-    return n == 16;
+    return n == 16 || n == 17;  // files written before the exec field: exec stays auto
 }
 
 int ilog2_floor(int64_t x) {
@@ -454,6 +454,8 @@ extern "C" spmm_status spmm_adapt_epoch(const spmm_csr *A, spmm_plan_t **plan, c
     const HostPlan &h = p->hp;
     if (A->m != h.m || A->k != h.k || A->nnz != h.nnz)
         return set_error(SPMM_ERR_INVALID, "A is not the matrix of the plan");
+    if (h.opts.exec == 3)
+        return set_error(SPMM_ERR_UNSUPPORTED, "an epoch times the two paths apart: exec 1 or 2");
     spmm_timer_t *t = nullptr;
     spmm_status st0 = spmm_timer_create(16, &t);
     if (st0 != SPMM_OK) return st0;
@@ -465,8 +467,13 @@ extern "C" spmm_status spmm_adapt_epoch(const spmm_csr *A, spmm_plan_t **plan, c
     if (st0 != SPMM_OK) return st0;
     double tv = 0, tm = 0;
     for (int32_t i = 0; i < cnt; ++i) {
-        if (ids[i] == SPMM_KERNEL_SEGMENT || ids[i] == SPMM_KERNEL_VECTOR) tv += ms[i];
-        else tm += ms[i];
+        // the vector path (serial: segment and vector kernels; co-scheduled:
+        // its grid) and the MFMA path (window kernels, or its grid, which ran
+        // beside the vector path on the same CUs)
+        if (ids[i] == SPMM_KERNEL_SEGMENT || ids[i] == SPMM_KERNEL_VECTOR || ids[i] == SPMM_KERNEL_VECTOR_PATH)
+            tv += ms[i];
+        else
+            tm += ms[i];
     }
     double wv = 0, wt = 0, wr = 0;
     plan_path_work(h, &wv, &wt, &wr);

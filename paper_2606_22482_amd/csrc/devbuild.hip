@@ -418,7 +418,7 @@ extern "C" spmm_status spmm_plan_device(const spmm_csr *A, int32_t n, int32_t b_
         auto *order = sorted ? reinterpret_cast<int32_t *>(pat(p_vec)) : nullptr;
         auto *seg_begin = reinterpret_cast<int32_t *>(pat(p_sb));
         auto *seg_end = reinterpret_cast<int32_t *>(pat(p_se));
-        auto *seg_row = reinterpret_cast<int32_t *>(pat(p_sr));  // host bookkeeping only
+        auto *seg_row = reinterpret_cast<int32_t *>(pat(p_sr));  // row of each segment
         auto *seg_order = reinterpret_cast<int32_t *>(pat(p_so));  // sort keys, then the launch order
         for (size_t t : tails)
             SPMM_TRY_HIP(hipMemsetAsync(pat(t), 0, 16, s), "hipMemsetAsync");
@@ -486,6 +486,7 @@ extern "C" spmm_status spmm_plan_device(const spmm_csr *A, int32_t n, int32_t b_
         std::iota(h.vector_rows.begin(), h.vector_rows.end(), 0);
         h.identity_rows = true;
         h.k_ref = (int64_t)kref;
+        derive_exec_tables(h);
         // the device plan
         DevPlan &dp = p->dp;
         dp.m = (int32_t)m;
@@ -505,6 +506,12 @@ extern "C" spmm_status spmm_plan_device(const spmm_csr *A, int32_t n, int32_t b_
         dp.seg_begin = seg_begin;
         dp.seg_end = seg_end;
         dp.seg_order = so_id ? nullptr : seg_order;
+        dp.seg_row = seg_row;
+        dp.seg_win = nullptr;  // no windows
+        dp.win_dep = nullptr;
+        dp.win_nsseg = nullptr;
+        dp.win_row_sid = nullptr;
+        dp.n_dep = 0;
         dp.n_wpart = 0;
         dp.win_tmax = kWinTiles;
         p->dev = d;

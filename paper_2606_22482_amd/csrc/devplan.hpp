@@ -36,6 +36,15 @@ struct DevPlan {
     const int32_t *wpart_t0;    // [n_wpart]
     const int32_t *wpart_t1;    // [n_wpart]
     const uint16_t *zeros;      // 256 zero bytes (source of staged padding columns)
+    // co-scheduled execution (last-finisher combine)
+    const int32_t *seg_row;     // [n_seg] row of each segment
+    const int32_t *seg_win;     // [n_seg] window holding the segment's row, -1 for a vector row;
+                                // null when the plan has no windows
+    const int32_t *win_dep;     // [n_win] slot of a window whose result needs other items (partial
+                                // tiles or split rows), else -1; null when the plan has no windows
+    const int32_t *win_nsseg;   // [n_win] segments of the window's split rows
+    const int32_t *win_row_sid; // [n_win*H] first segment of a window row split into segments, else -1
+    int32_t n_dep;              // windows with a slot
 };
 
 // Launch geometry and operand description of one execution.
@@ -59,6 +68,15 @@ struct RunArgs {
                         // 0 when B spans 4 GiB or more (predicated plain loads)
     int32_t pipeline;   // vector kernel variant: 0 row by row, 1 row-pipelined, 2 short rows packed,
                         // 3 rows packed by size class
+    // co-scheduled execution
+    int32_t *cnt;       // arrival counters: [n_panels * n_seg] per split vector row (at its first
+                        // segment id), then [win_panels * n_dep] per window slot; zero between runs
+    float *dep;         // window slots: [n_dep][2][H][work_ld] (MFMA result, rows' remainders)
+    uint32_t ws_rec;    // bytes of the workspace (below 4 GiB for a co-scheduled run)
+    int32_t seg_blocks; // workgroups of segment waves in a fused launch (a multiple of 8)
+    int32_t vec_blocks; // workgroups of vector-item waves
+    int32_t wpart_blocks; // workgroups of window partial items in a fused launch (a multiple of 8)
+    int32_t win_blocks;   // workgroups of window owner items
 };
 
 // One matrix of a batched execution.  `*_end` are exclusive prefix sums of
@@ -100,6 +118,19 @@ hipError_t launch_window(const DevPlan &P, int32_t val_t, int32_t b_t, int32_t t
 hipError_t launch_window_partial(const DevPlan &P, int32_t val_t, int32_t b_t, int32_t tile_t,
                                  const RunArgs &a, hipStream_t s);
 hipError_t launch_copy(const float4 *src, float4 *dst, int64_t n4, hipStream_t s);
+
+// co-scheduled execution (fused.hip): the vector path (segments + vector
+// items), the MFMA path (window partials + owners), or both in one grid;
+// RunArgs' cnt, dep and *_blocks must be set.
+hipError_t launch_vector_path(const DevPlan &P, int32_t val_t, int32_t b_t, const RunArgs &a,
+                              hipStream_t s);
+hipError_t launch_mfma_path(const DevPlan &P, int32_t val_t, int32_t b_t, int32_t tile_t,
+                            const RunArgs &a, hipStream_t s);
+bool one_grid_supported(int32_t b_t, const RunArgs &a);
+hipError_t launch_one_grid(const DevPlan &P, int32_t val_t, int32_t b_t, int32_t tile_t,
+                           const RunArgs &a, hipStream_t s);
+// p[0 .. n) = 0 by a kernel (capturable, unlike a memset node)
+hipError_t launch_zero(int32_t *p, int64_t n, hipStream_t s);
 
 // chunk width (elements per 16-byte load) of a B type
 inline int chunk_elems(int32_t b_t) { return b_t == 0 ? 4 : 8; }

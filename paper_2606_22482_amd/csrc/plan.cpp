@@ -44,6 +44,7 @@ extern "C" void spmm_opts_default(spmm_opts *o) {
     o->pipeline = -1;
     o->win_sched = -1;
     o->local_reorder = -1;
+    o->exec = 0;
     o->alpha_c = -1.0f;
     o->alpha = -1.0f;
 }
@@ -107,6 +108,10 @@ void resolve_options(const spmm_opts *in, const spmm_csr *A, int32_t n, int32_t 
     }
     if (d.win_sched < 0) d.win_sched = 0;  // window id order: B rows reused in L2
     if (d.local_reorder < 0) d.local_reorder = 0;
+    // co-scheduled as two concurrent grids (the vector path keeps its own
+    // occupancy beside the LDS-heavy windows); serial kernels for a cold
+    // policy, which only the serial kernels select per entry
+    if (d.exec <= 0) d.exec = d.cold_policy != 0 ? 1 : 2;
     if (!(d.alpha_c >= 0.0f)) d.alpha_c = 1.0f / (float)d.window_h;
     if (!(d.alpha >= 0.0f)) d.alpha = 1.0f / (float)d.window_h;
     if (d.mode == SPMM_MODE_MFMA_ONLY) {
@@ -390,6 +395,11 @@ spmm_status validate_opts(const spmm_opts &o, std::string &err) {
     }
     if (o.cold_policy != 0 && o.cold_policy != 2 && o.cold_policy != 16 && o.cold_policy != 18) {
         err = "cold_policy must be 0, 2, 16 or 18";
+        return SPMM_ERR_UNSUPPORTED;
+    }
+    if (o.exec < 1 || o.exec > 3) { err = "exec must be 1, 2 or 3"; return SPMM_ERR_UNSUPPORTED; }
+    if (o.cold_policy != 0 && o.exec != 1) {
+        err = "a cold policy needs the serial kernels (exec 1)";
         return SPMM_ERR_UNSUPPORTED;
     }
     if (o.cold_policy != 0 && o.pipeline != 0) {
@@ -786,9 +796,35 @@ spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_
         std::stable_sort(P.win_order.begin(), P.win_order.end(),
                          [&](int32_t a, int32_t b) { return wcost[a] > wcost[b]; });
 
+    derive_exec_tables(P);
+
     auto t_end = std::chrono::steady_clock::now();
     P.plan_ms = std::chrono::duration<double, std::milli>(t_end - t_start).count();
     return SPMM_OK;
+}
+
+void derive_exec_tables(HostPlan &P) {
+    const int64_t W = (int64_t)P.win_seg.size(), H = P.opts.window_h;
+    P.seg_win.clear();
+    P.win_dep.assign(W, -1);
+    P.win_nsseg.assign(W, 0);
+    P.win_row_sid.assign(W * H, -1);
+    P.n_dep = 0;
+    if (W == 0) return;
+    P.seg_win.assign(P.seg_row.size(), -1);
+    for (int64_t w = 0; w < W; ++w) {
+        int32_t ns = 0;
+        for (int64_t s = 0; s < H; ++s) {
+            const int32_t r = P.windows[w * H + s];
+            if (r < 0 || P.nseg[r] == 0) continue;
+            P.win_row_sid[w * H + s] = P.win_seg[w] + ns;
+            ns += P.nseg[r];
+        }
+        // a window's segments are consecutive ids from win_seg[w], in slot order
+        for (int32_t j = 0; j < ns; ++j) P.seg_win[(size_t)P.win_seg[w] + j] = (int32_t)w;
+        P.win_nsseg[w] = ns;
+        if (ns > 0 || P.win_part[w + 1] > P.win_part[w]) P.win_dep[w] = P.n_dep++;
+    }
 }
 
 void plan_path_work(const HostPlan &P, double *w_vec, double *w_tile, double *w_winrem) {

@@ -48,6 +48,13 @@ struct HostPlan {
     std::vector<int32_t> wpart_win, wpart_t0, wpart_t1;  // [n_wparts]
     bool identity_rows = false;         // vector_rows == 0..m-1
 
+    // ---- co-scheduled execution (derive_exec_tables, from the schedule) ----
+    std::vector<int32_t> seg_win;       // [S] window of the segment's row, -1 for a vector row (empty: W = 0)
+    std::vector<int32_t> win_dep;       // [W] slot of a window needing other items' parts, else -1
+    std::vector<int32_t> win_nsseg;     // [W] segments of the window's split rows
+    std::vector<int32_t> win_row_sid;   // [W*H] first segment of a window row that is split, else -1
+    int32_t n_dep = 0;                  // windows with a slot
+
     // ---- device-facing copies of the remainder ----
     std::vector<int32_t> rem_ptr32;     // [m+1]
     std::vector<int32_t> rem_col;       // [nnz_rem], bit 31 set for hot columns
@@ -94,6 +101,11 @@ void plan_path_work(const HostPlan &P, double *w_vec, double *w_tile, double *w_
 // Build the full host plan for already-resolved options.
 spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
                             const spmm_opts &o, HostPlan &P, std::string &err);
+
+// The tables of co-scheduled execution: which window each segment's row
+// belongs to, and a slot for every window whose result needs other items
+// (partial tiles beyond its first kWinTiles, or rows split into segments).
+void derive_exec_tables(HostPlan &P);
 
 // float -> bfloat16 bits, round to nearest even (NaN stays a quiet NaN).
 uint16_t f32_to_bf16_rne(float f);

@@ -196,6 +196,11 @@ extern "C" spmm_status spmm_plan_upload(spmm_plan_t *p) {
         const size_t i_wpart_win = add_vec(a, h.wpart_win);
         const size_t i_wpart_t0 = add_vec(a, h.wpart_t0);
         const size_t i_wpart_t1 = add_vec(a, h.wpart_t1);
+        const size_t i_seg_row = add_vec(a, h.seg_row);
+        const size_t i_seg_win = add_vec(a, h.seg_win);
+        const size_t i_win_dep = add_vec(a, h.win_dep);
+        const size_t i_win_nsseg = add_vec(a, h.win_nsseg);
+        const size_t i_win_row_sid = add_vec(a, h.win_row_sid);
         static const uint8_t kZeros[256] = {};
         const size_t i_zeros = a.add(kZeros, sizeof(kZeros));
         const size_t total = std::max<size_t>(a.total, 256);
@@ -251,6 +256,13 @@ extern "C" spmm_status spmm_plan_upload(spmm_plan_t *p) {
         dp.wpart_t0 = reinterpret_cast<const int32_t *>(at(i_wpart_t0));
         dp.wpart_t1 = reinterpret_cast<const int32_t *>(at(i_wpart_t1));
         dp.zeros = reinterpret_cast<const uint16_t *>(at(i_zeros));
+        dp.seg_row = reinterpret_cast<const int32_t *>(at(i_seg_row));
+        const bool has_win = !h.win_seg.empty();
+        dp.seg_win = has_win ? reinterpret_cast<const int32_t *>(at(i_seg_win)) : nullptr;
+        dp.win_dep = has_win ? reinterpret_cast<const int32_t *>(at(i_win_dep)) : nullptr;
+        dp.win_nsseg = has_win ? reinterpret_cast<const int32_t *>(at(i_win_nsseg)) : nullptr;
+        dp.win_row_sid = has_win ? reinterpret_cast<const int32_t *>(at(i_win_row_sid)) : nullptr;
+        dp.n_dep = h.n_dep;
         p->dev = d;
         p->dev_bytes = total;
         p->device = dev;
@@ -321,9 +333,11 @@ extern "C" spmm_status spmm_plan_destroy(spmm_plan_t *p) {
 }
 
 namespace spmm {
-size_t workspace_floats(const HostPlan &h) {
+size_t workspace_floats(const HostPlan &h, bool serial) {
     const size_t ld = (size_t)(h.n + 3) / 4 * 4;
-    return ((size_t)h.seg_row.size() + (size_t)h.wpart_win.size() * h.opts.window_h) * ld;
+    // segment partials, window partials, then (co-scheduled) the window slots
+    const size_t slots = serial || h.opts.exec == 1 ? 0 : (size_t)h.n_dep * 2 * h.opts.window_h;
+    return ((size_t)h.seg_row.size() + (size_t)h.wpart_win.size() * h.opts.window_h + slots) * ld;
 }
 
 double algorithmic_bytes(const HostPlan &h) {
@@ -370,7 +384,7 @@ extern "C" spmm_status spmm_plan_stats(const spmm_plan_t *p, spmm_plan_stats_t *
     out->mean_tile_density = slots > 0 ? (double)out->nnz_tiles / slots : 0.0;
     out->zero_fraction_tiles = slots > 0 ? 1.0 - out->mean_tile_density : 0.0;
     out->device_bytes = (int64_t)p->dev_bytes;
-    out->workspace_bytes = (int64_t)workspace_floats(h) * 4;
+    out->workspace_bytes = (int64_t)workspace_floats(h, false) * 4;
     out->algorithmic_bytes = algorithmic_bytes(h);
     out->flops = 2.0 * (double)h.nnz * (double)h.n;
     out->plan_ms = h.plan_ms;
@@ -424,31 +438,70 @@ extern "C" spmm_status spmm_plan_export(const spmm_plan_t *p, spmm_plan_dump_t *
     out->wpart_t0 = h.wpart_t0.data();
     out->wpart_t1 = h.wpart_t1.data();
     out->vexec_rows = h.vexec.empty() ? h.vector_rows.data() : h.vexec.data();
+    out->n_dep = h.n_dep;
+    out->seg_win = h.seg_win.empty() ? nullptr : h.seg_win.data();
+    out->win_dep = h.win_dep.data();
+    out->win_nsseg = h.win_nsseg.data();
     return SPMM_OK;
 }
 
 // ------------------------------------------------------------------------------------------
-// per-stream workspace for segment partial sums
+// per-stream run context: workspace for partial sums and window slots, the
+// arrival counters of co-scheduled runs, and the second stream they fork to
 
 namespace {
 struct Workspace {
     void *ptr = nullptr;
     size_t bytes = 0;
+    int32_t *cnt = nullptr;  // arrival counters: zeroed when allocated, cleared by each run's last arrivals
+    size_t cnt_ints = 0;
+    hipStream_t side = nullptr;  // second stream of co-scheduled runs (default priority)
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 std::mutex g_ws_mu;
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
 }  // namespace
 
 namespace spmm {
-spmm_status workspace_for(hipStream_t s, size_t bytes, float **out, std::unique_lock<std::mutex> &lk) {
-    *out = nullptr;
-    if (bytes == 0) return SPMM_OK;
+spmm_status run_context(hipStream_t s, size_t bytes, size_t cnt_ints, bool side, RunContext *ctx,
+                        std::unique_lock<std::mutex> &lk) {
+    *ctx = RunContext{};
+    if (bytes == 0 && cnt_ints == 0 && !side) return SPMM_OK;
     int dev = 0;
     SPMM_TRY_HIP(hipGetDevice(&dev), "hipGetDevice");
     // held by the caller until its kernels are enqueued, so that another
-    // thread growing this stream's workspace cannot free it in between
+    // thread growing this stream's buffers cannot free them in between
     lk = std::unique_lock<std::mutex>(g_ws_mu);
     Workspace &w = g_ws[{dev, s}];
+    if (cnt_ints > w.cnt_ints) {
+        const size_t old = w.cnt_ints;
+        if (w.cnt) {
+            SPMM_TRY_HIP(hipStreamSynchronize(s), "hipStreamSynchronize(counters)");
+            (void)hipFree(w.cnt);
+            w.cnt = nullptr;
+            w.cnt_ints = 0;
+        }
+        const size_t want = std::max(cnt_ints, old * 2);
+        hipError_t e = hipMalloc(&w.cnt, want * sizeof(int32_t));
+        if (e != hipSuccess) {
+            w.cnt = nullptr;
+            return set_error(SPMM_ERR_OOM, std::string("hipMalloc(counters): ") + hipGetErrorString(e));
+        }
+        // a fill kernel rather than a memset node, so the run stays capturable
+        e = launch_zero(w.cnt, (int64_t)want, s);
+        if (e != hipSuccess) return hip_error(e, "zero counters");
+        w.cnt_ints = want;
+    }
+    if (side && !w.side) {
+        SPMM_TRY_HIP(hipStreamCreateWithFlags(&w.side, hipStreamNonBlocking), "hipStreamCreate(side)");
+        SPMM_TRY_HIP(hipEventCreateWithFlags(&w.fork, hipEventDisableTiming), "hipEventCreate");
+        SPMM_TRY_HIP(hipEventCreateWithFlags(&w.join, hipEventDisableTiming), "hipEventCreate");
+    }
+    ctx->cnt = w.cnt;
+    ctx->side = side ? w.side : nullptr;
+    ctx->fork = w.fork;
+    ctx->join = w.join;
+    if (bytes == 0) return SPMM_OK;
     if (w.bytes < bytes) {
         const size_t old = w.bytes;
         if (w.ptr) {
@@ -466,7 +519,7 @@ spmm_status workspace_for(hipStream_t s, size_t bytes, float **out, std::unique_
         }
         w.bytes = want;
     }
-    *out = static_cast<float *>(w.ptr);
+    ctx->work = static_cast<float *>(w.ptr);
     return SPMM_OK;
 }
 
@@ -482,6 +535,7 @@ spmm_status make_run_args(const spmm_plan_t *p, const void *B, int64_t ldb, void
     const int N = h.n;
     const int E = chunk_elems(h.b_type);
     const int sb = dtype_size(h.b_type);
+    a = RunArgs{};
     a.B = B;
     a.ldb = ldb;
     a.C = static_cast<float *>(C);
@@ -582,47 +636,111 @@ spmm_status check_run(const spmm_plan_t *p, const void *B, int64_t ldb, void *C,
     return SPMM_OK;
 }
 
-spmm_status launch_plan(const spmm_plan_t *p, const RunArgs &a, hipStream_t s, spmm_timer_t *t) {
+bool serial_exec(const spmm_plan_t *p, const RunArgs &a) {
+    // co-scheduled runs address their workspace through a 32-bit buffer range
+    return p->hp.opts.exec == 1 || a.cold_aux >= 0 ||
+           (double)workspace_floats(p->hp, false) * 4.0 >= 4294967040.0;
+}
+
+// Workgroup ranges of a co-scheduled run: segment and window-partial ranges
+// padded to a multiple of 8 so that the range after them starts on XCD 0.
+void coschedule_layout(const spmm_plan_t *p, RunArgs &a) {
+    const DevPlan &P = p->dp;
+    auto up8 = [](int64_t x) { return (int32_t)((x + 7) & ~int64_t(7)); };
+    a.seg_blocks = up8(((int64_t)P.n_seg * a.n_panels + 3) / 4);
+    a.vec_blocks = (int32_t)(((int64_t)P.n_vitems * a.n_panels + 3) / 4);
+    a.wpart_blocks = up8((int64_t)P.n_wpart * a.win_panels);
+    a.win_blocks = (int32_t)((int64_t)P.n_win * a.win_panels);
+}
+
+// The two grids of a co-scheduled run go to two streams only when each has
+// at least a workgroup per CU (256); otherwise one of them is too small to
+// pay for the fork and join (measured about 25-30 us on gfx950) and both run
+// on the run's stream, the MFMA path first.
+bool fork_paths(const RunArgs &a) {
+    return a.seg_blocks + a.vec_blocks >= 256 && a.wpart_blocks + a.win_blocks >= 256;
+}
+
+size_t counter_ints(const spmm_plan_t *p, const RunArgs &a) {
+    if (serial_exec(p, a)) return 0;
+    return (size_t)a.n_panels * p->dp.n_seg + (size_t)a.win_panels * p->dp.n_dep;
+}
+
+spmm_status launch_plan(const spmm_plan_t *p, const RunArgs &a0, hipStream_t s, spmm_timer_t *t,
+                        const RunContext &ctx) {
     const HostPlan &h = p->hp;
     const DevPlan &P = p->dp;
-    auto timed = [&](int kid, auto &&launch) -> spmm_status {
+    RunArgs a = a0;
+    a.work = ctx.work;
+    auto timed = [&](int kid, hipStream_t ks, auto &&launch) -> spmm_status {
         const bool rec = t != nullptr;
         if (rec && t->used >= t->cap) return set_error(SPMM_ERR_INVALID, "timer is full");
-        if (rec) SPMM_TRY_HIP(hipEventRecord(t->ev[2 * t->used], s), "hipEventRecord");
+        if (rec) SPMM_TRY_HIP(hipEventRecord(t->ev[2 * t->used], ks), "hipEventRecord");
         hipError_t e = launch();
         if (e != hipSuccess) return hip_error(e, "kernel launch");
         if (rec) {
-            SPMM_TRY_HIP(hipEventRecord(t->ev[2 * t->used + 1], s), "hipEventRecord");
+            SPMM_TRY_HIP(hipEventRecord(t->ev[2 * t->used + 1], ks), "hipEventRecord");
             t->ids[t->used] = kid;
             t->used++;
         }
         return SPMM_OK;
     };
     spmm_status st;
-    if (P.n_seg > 0) {
-        // Column-ordered segments go out in dispatch order, not in one
-        // contiguous share per XCD: then all XCDs work on one stretch of B at
-        // a time and share it in the Infinity Cache (measured faster on the
-        // 2^20-vertex power-law graph: 0.306 vs 0.332 ms).
-        RunArgs as = a;
-        if (P.seg_order) as.xcd = 0;
-        st = timed(SPMM_KERNEL_SEGMENT, [&] { return launch_segment(P, h.val_type, h.b_type, as, s); });
+    if (serial_exec(p, a)) {
+        if (P.n_seg > 0) {
+            // Column-ordered segments go out in dispatch order, not in one
+            // contiguous share per XCD: then all XCDs work on one stretch of B at
+            // a time and share it in the Infinity Cache (measured faster on the
+            // 2^20-vertex power-law graph: 0.306 vs 0.332 ms).
+            RunArgs as = a;
+            if (P.seg_order) as.xcd = 0;
+            st = timed(SPMM_KERNEL_SEGMENT, s, [&] { return launch_segment(P, h.val_type, h.b_type, as, s); });
+            if (st != SPMM_OK) return st;
+        }
+        if (P.n_wpart > 0) {
+            st = timed(SPMM_KERNEL_WINDOW_PARTIAL, s,
+                       [&] { return launch_window_partial(P, h.val_type, h.b_type, h.tile_type, a, s); });
+            if (st != SPMM_OK) return st;
+        }
+        if (P.n_vitems > 0) {
+            st = timed(SPMM_KERNEL_VECTOR, s, [&] { return launch_vector(P, h.val_type, h.b_type, a, s); });
+            if (st != SPMM_OK) return st;
+        }
+        if (P.n_win > 0) {
+            st = timed(SPMM_KERNEL_WINDOW, s,
+                       [&] { return launch_window(P, h.val_type, h.b_type, h.tile_type, a, s); });
+            if (st != SPMM_OK) return st;
+        }
+        return SPMM_OK;
+    }
+    // co-scheduled
+    a.cnt = ctx.cnt;
+    a.dep = ctx.work ? ctx.work + ((int64_t)P.n_seg + (int64_t)P.H * P.n_wpart) * a.work_ld : nullptr;
+    a.ws_rec = (uint32_t)(workspace_floats(h, false) * sizeof(float));
+    coschedule_layout(p, a);
+    const bool mfma = a.wpart_blocks + a.win_blocks > 0, vec = a.seg_blocks + a.vec_blocks > 0;
+    if (h.opts.exec == 3 && mfma && vec && one_grid_supported(h.b_type, a))
+        return timed(SPMM_KERNEL_ONE_GRID, s,
+                     [&] { return launch_one_grid(P, h.val_type, h.b_type, h.tile_type, a, s); });
+    const bool fork = fork_paths(a);
+    const hipStream_t ms = fork ? ctx.side : s;
+    if (mfma) {
+        // the MFMA path on the second stream, forked from and joined to the
+        // run's stream, so that it runs beside the vector path
+        if (fork) {
+            SPMM_TRY_HIP(hipEventRecord(ctx.fork, s), "hipEventRecord(fork)");
+            SPMM_TRY_HIP(hipStreamWaitEvent(ctx.side, ctx.fork, 0), "hipStreamWaitEvent(fork)");
+        }
+        st = timed(SPMM_KERNEL_MFMA_PATH, ms,
+                   [&] { return launch_mfma_path(P, h.val_type, h.b_type, h.tile_type, a, ms); });
+        if (st != SPMM_OK) return st;
+        if (fork) SPMM_TRY_HIP(hipEventRecord(ctx.join, ctx.side), "hipEventRecord(join)");
+    }
+    if (vec) {
+        st = timed(SPMM_KERNEL_VECTOR_PATH, s, [&] { return launch_vector_path(P, h.val_type, h.b_type, a, s); });
         if (st != SPMM_OK) return st;
     }
-    if (P.n_wpart > 0) {
-        st = timed(SPMM_KERNEL_WINDOW_PARTIAL,
-                   [&] { return launch_window_partial(P, h.val_type, h.b_type, h.tile_type, a, s); });
-        if (st != SPMM_OK) return st;
-    }
-    if (P.n_vitems > 0) {
-        st = timed(SPMM_KERNEL_VECTOR, [&] { return launch_vector(P, h.val_type, h.b_type, a, s); });
-        if (st != SPMM_OK) return st;
-    }
-    if (P.n_win > 0) {
-        st = timed(SPMM_KERNEL_WINDOW,
-                   [&] { return launch_window(P, h.val_type, h.b_type, h.tile_type, a, s); });
-        if (st != SPMM_OK) return st;
-    }
+    if (mfma && fork) SPMM_TRY_HIP(hipStreamWaitEvent(s, ctx.join, 0), "hipStreamWaitEvent(join)");
     return SPMM_OK;
 }
 }  // namespace spmm
@@ -635,10 +753,16 @@ static spmm_status run_impl(const spmm_plan_t *p, const void *B, int64_t ldb, vo
     hipStream_t s = static_cast<hipStream_t>(stream);
     RunArgs a;
     make_run_args(p, B, ldb, C, ldc, a);
+    const bool serial = serial_exec(p, a);
+    RunArgs lay = a;
+    coschedule_layout(p, lay);
+    const bool side = !serial && fork_paths(lay);
     std::unique_lock<std::mutex> ws_lock;
-    st = workspace_for(s, workspace_floats(p->hp) * sizeof(float), &a.work, ws_lock);
+    RunContext ctx;
+    st = run_context(s, workspace_floats(p->hp, serial) * sizeof(float), counter_ints(p, a), side, &ctx,
+                     ws_lock);
     if (st != SPMM_OK) return st;
-    return launch_plan(p, a, s, t);
+    return launch_plan(p, a, s, t, ctx);
 }
 
 extern "C" spmm_status spmm_run(const spmm_plan_t *p, const void *B, int64_t ldb, void *C,

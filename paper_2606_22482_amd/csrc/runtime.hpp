@@ -26,17 +26,38 @@ struct spmm_plan_s {
 namespace spmm {
 spmm_status set_error(spmm_status s, const std::string &msg);
 spmm_status hip_error(hipError_t e, const char *what);
-// The stream's workspace of at least `bytes`; `lk` holds the workspace table
-// until the caller has enqueued the kernels that use it.
-spmm_status workspace_for(hipStream_t s, size_t bytes, float **out, std::unique_lock<std::mutex> &lk);
+// What one run on a stream uses besides the plan: the stream's workspace (at
+// least `bytes`), its arrival counters (at least cnt_ints, zero between runs),
+// and for a co-scheduled run with windows the second stream and the fork and
+// join events.  `lk` holds the table until the caller has enqueued the
+// kernels that use them.
+struct RunContext {
+    float *work = nullptr;
+    int32_t *cnt = nullptr;
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+spmm_status run_context(hipStream_t s, size_t bytes, size_t cnt_ints, bool side, RunContext *ctx,
+                        std::unique_lock<std::mutex> &lk);
+// Whether a run of the plan uses the serial kernels (exec 1, or a cold policy).
+bool serial_exec(const spmm_plan_t *p, const RunArgs &a);
+// Workgroup ranges of a co-scheduled run (RunArgs' *_blocks).
+void coschedule_layout(const spmm_plan_t *p, RunArgs &a);
+// Whether a co-scheduled run forks its MFMA path to the second stream.
+bool fork_paths(const RunArgs &a);
+// Arrival counters a run of the plan uses (0 when serial).
+size_t counter_ints(const spmm_plan_t *p, const RunArgs &a);
 spmm_status make_run_args(const spmm_plan_t *p, const void *B, int64_t ldb, void *C, int64_t ldc,
                           RunArgs &a);
 spmm_status check_run(const spmm_plan_t *p, const void *B, int64_t ldb, void *C, int64_t ldc);
-spmm_status launch_plan(const spmm_plan_t *p, const RunArgs &a, hipStream_t s, spmm_timer_t *t);
+spmm_status launch_plan(const spmm_plan_t *p, const RunArgs &a, hipStream_t s, spmm_timer_t *t,
+                        const RunContext &ctx);
 double algorithmic_bytes(const HostPlan &h);
 // Host copies of a device-built plan's remainder (no-op for host-built plans).
 spmm_status ensure_host_remainder(spmm_plan_t *p);
-size_t workspace_floats(const HostPlan &h);
+// Floats of workspace a run needs: segment partials, window partials and,
+// unless `serial` or the plan's exec is 1, the window slots of co-scheduled runs.
+size_t workspace_floats(const HostPlan &h, bool serial);
 std::string profile_key(const spmm_csr *A, int32_t n, int32_t b_type);
 bool cache_lookup(const std::string &key, spmm_opts *o);
 }  // namespace spmm

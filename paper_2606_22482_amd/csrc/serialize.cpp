@@ -295,6 +295,7 @@ spmm_status deserialize_host_plan(const uint8_t *buf, size_t size, HostPlan &P, 
         err = "plan image: identity flag";
         return SPMM_ERR_INVALID;
     }
+    derive_exec_tables(Q);
     P = std::move(Q);
     return SPMM_OK;
 }

@@ -127,7 +127,7 @@ extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *
         const spmm_plan_t *p = items[i].plan;
         if (p->hp.m == 0) continue;
         make_run_args(p, items[i].B, items[i].ldb, items[i].C, items[i].ldc, args[i]);
-        ws_floats += workspace_floats(p->hp);
+        ws_floats += workspace_floats(p->hp, true);
         const int E = args[i].vec_ok ? chunk_elems(p->hp.b_type) : 1;
         const int chunks = args[i].vec_ok ? args[i].np / E : args[i].np;
         const int cpl = chunks > 64 ? 2 : 1;
@@ -152,7 +152,7 @@ extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *
             const spmm_plan_t *p = items[i].plan;
             if (p->hp.m == 0) continue;
             args[i].work = static_cast<float *>(ctx.ws) + off;
-            off += workspace_floats(p->hp);
+            off += workspace_floats(p->hp, true);
         }
     }
 

@@ -483,3 +483,65 @@ def test_plan_same_for_any_thread_count(order, local, monkeypatch):
         for key in dumps[0]:
             if isinstance(dumps[0][key], np.ndarray):
                 assert np.array_equal(dumps[0][key], d[key]), key
+
+
+def _exec_tables_ref(d):
+    """The co-scheduling tables written out from their definition: window w
+    owns the segments of its rows (consecutive ids from win_seg[w], in slot
+    order); a window gets a slot, in window order, when it has partial items
+    or rows split into segments."""
+    W, H = d["windows"].shape
+    S = d["seg_row"].size
+    seg_win = np.full(S, -1, np.int32)
+    win_dep = np.full(W, -1, np.int32)
+    win_nsseg = np.zeros(W, np.int32)
+    slot = 0
+    for w in range(W):
+        rows = [r for r in d["windows"][w] if r >= 0]
+        ns = int(sum(d["nseg"][r] for r in rows))
+        # the segments' rows, in slot order, are exactly the window's split rows
+        got = d["seg_row"][d["win_seg"][w]: d["win_seg"][w] + ns]
+        want = np.concatenate([np.full(d["nseg"][r], r, np.int32) for r in rows]) if rows else []
+        assert np.array_equal(got, np.asarray(want, np.int32))
+        seg_win[d["win_seg"][w]: d["win_seg"][w] + ns] = w
+        win_nsseg[w] = ns
+        if ns > 0 or d["win_part"][w + 1] > d["win_part"][w]:
+            win_dep[w] = slot
+            slot += 1
+    return seg_win if W else np.zeros(0, np.int32), win_dep, win_nsseg, slot
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_exec_tables_match_definition(lib, case):
+    r = np.random.default_rng(900 + case)
+    if case < 3:
+        A = synth.chung_lu_graph(4000, 2.1, 16.0, 1500.0, 30 + case)
+        opts = dict(mode="mixed", row_order="length_sorted", t_row=int(r.integers(4, 16)),
+                    seg_len=int(r.choice([16, 40, 128])), window_h=int(r.choice([16, 32])))
+    else:
+        A = synth.random_csr(300, 9000, 0.2, 40 + case, val_kind="bf16", int_values=(-2, 2))
+        opts = dict(mode="mixed", window_h=16, t_row=-1, alpha_c=0.0, alpha=0.22,
+                    seg_len=int(r.choice([40, 200])))
+    p = api.Plan(A, 64, "bf16", api.default_opts(**opts), upload=False)
+    d = p.export()
+    seg_win, win_dep, win_nsseg, n_dep = _exec_tables_ref(d)
+    assert d["n_dep"] == n_dep and n_dep > 0
+    assert np.array_equal(d["seg_win"], seg_win)
+    assert np.array_equal(d["win_dep"], win_dep)
+    assert np.array_equal(d["win_nsseg"], win_nsseg)
+    # plain plans: no windows, no slots
+    q = api.Plan(A, 64, "bf16", api.default_opts(mode="plain"), upload=False).export()
+    assert q["n_dep"] == 0 and q["seg_win"].size == 0
+
+
+def test_exec_option_range(lib):
+    A = synth.random_csr(50, 50, 0.1, 3)
+    for bad in (4, 9):
+        assert _status(lib, A, opts=api.default_opts(exec=bad)) == L.SPMM_ERR_UNSUPPORTED
+    # a cold policy needs the serial kernels
+    assert _status(lib, A, opts=api.default_opts(mode="plain", cold_policy=2, pipeline=0,
+                                                 exec=2)) == L.SPMM_ERR_UNSUPPORTED
+    for ok in (1, 2, 3):
+        assert _status(lib, A, opts=api.default_opts(exec=ok)) == L.SPMM_OK
+    p = api.Plan(A, 8, "f32", None, upload=False)
+    assert p.stats()["opts"]["exec"] == L.EXEC_TWO_GRIDS

@@ -538,7 +538,12 @@ def test_timer_and_copy_bandwidth():
     for _ in range(3):
         p.run_timed(Bd, C, t)
     rec = t.read()
-    assert len(rec) == 3 and all(name == "vector" and ms > 0 for name, ms in rec)
+    # a plain plan is one co-scheduled grid by default (segments and vector items)
+    assert len(rec) == 3 and all(name == "vector_path" and ms > 0 for name, ms in rec)
+    t.reset()
+    ps = api.Plan(A, 32, "f32", api.default_opts(mode="plain", exec=1))
+    ps.run_timed(Bd, C, t)
+    assert [name for name, _ in t.read()] == ["vector"]
     bw = api.spmm_copy_bandwidth(1 << 28)
     assert bw > 1e11
     torch.cuda.synchronize()

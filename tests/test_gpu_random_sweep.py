@@ -36,7 +36,9 @@ def draw(seed):
                 t_row=int(r.integers(0, 9)), alpha=float(r.choice([0.0, 0.0, 0.02, 0.1, 0.5])),
                 alpha_c=float(r.choice([0.0, 1 / 16, 1 / 8])),
                 seg_len=int(r.choice([3, 7, 64, 256])), pipeline=int(r.integers(0, 4)),
-                win_sched=int(r.integers(0, 2)))
+                win_sched=int(r.integers(0, 2)), exec=int(r.choice([1, 2, 2, 3])))
+    if r.random() < 0.25:
+        opts["n_panel"] = int(r.choice([8, 32, 48, 64, 96]))
     if order != "original_ranges" and r.random() < 0.3:
         opts["local_reorder"] = int(r.choice([16, 64, 200]))
     density = float(r.choice([0.002, 0.01, 0.04, 0.1]))
