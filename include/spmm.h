@@ -297,6 +297,20 @@ spmm_status spmm_plan_export(const spmm_plan_t *p, spmm_plan_dump_t *out);
 spmm_status spmm_run(const spmm_plan_t *p, const void *B, int64_t ldb, void *C, int64_t ldc,
                      void *stream);
 
+/* spmm_run for callers that cannot allocate (code under graph capture, tight
+ * serving loops, harnesses that forbid allocation): the same kernels and the
+ * same C bit for bit, but the workspace and the arrival counters come from a
+ * fixed device array of the library (32 MiB per device, held by every device
+ * the library runs on until the process ends; 1 MiB of it counters, cleared on
+ * the first call on a device), and a co-scheduled run keeps both grids on
+ * `stream` (no second stream).  No allocation is made by the call.  BUDGET
+ * when the run needs more than 31 MiB of workspace or 1 MiB of counters (the
+ * message gives the sizes); other errors as spmm_run.  Every call on a device
+ * shares that device's array: calls that overlap in time on one device race
+ * and must be serialised by the caller (one stream, or events). */
+spmm_status spmm_run_noalloc(const spmm_plan_t *p, const void *B, int64_t ldb, void *C, int64_t ldc,
+                             void *stream);
+
 /* Kernel timing: spmm_run_timed records a HIP event pair around every kernel
  * it launches (on `stream`) into the timer; spmm_timer_read waits for them
  * and returns the launches' kernel ids and durations in milliseconds. */

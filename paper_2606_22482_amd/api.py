@@ -252,6 +252,12 @@ class Plan:
         bp, ldb, cp, ldc = self.operands(B, Cout)
         L.check(self._lib.spmm_run(self._h, bp, ldb, cp, ldc, _stream_handle(stream)))
 
+    def run_noalloc(self, B, Cout, stream=None):
+        """spmm_run_noalloc: as run, with the library's fixed scratch array
+        instead of a per-stream workspace (no allocation)."""
+        bp, ldb, cp, ldc = self.operands(B, Cout)
+        L.check(self._lib.spmm_run_noalloc(self._h, bp, ldb, cp, ldc, _stream_handle(stream)))
+
     def run_timed(self, B, Cout, timer: "Timer", stream=None):
         bp, ldb, cp, ldc = self.operands(B, Cout)
         L.check(self._lib.spmm_run_timed(self._h, bp, ldb, cp, ldc, _stream_handle(stream),

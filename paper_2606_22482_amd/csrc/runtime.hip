@@ -722,7 +722,7 @@ spmm_status launch_plan(const spmm_plan_t *p, const RunArgs &a0, hipStream_t s, 
     if (h.opts.exec == 3 && mfma && vec && one_grid_supported(h.b_type, a))
         return timed(SPMM_KERNEL_ONE_GRID, s,
                      [&] { return launch_one_grid(P, h.val_type, h.b_type, h.tile_type, a, s); });
-    const bool fork = fork_paths(a);
+    const bool fork = ctx.allow_fork && fork_paths(a);
     const hipStream_t ms = fork ? ctx.side : s;
     if (mfma) {
         // the MFMA path on the second stream, forked from and joined to the
@@ -768,6 +768,72 @@ static spmm_status run_impl(const spmm_plan_t *p, const void *B, int64_t ldb, vo
 extern "C" spmm_status spmm_run(const spmm_plan_t *p, const void *B, int64_t ldb, void *C,
                                 int64_t ldc, void *stream) {
     return run_impl(p, B, ldb, C, ldc, stream, nullptr);
+}
+
+// ------------------------------------------------------------------------------------------
+// A run that allocates nothing: its workspace and arrival counters live in a
+// fixed device array of this library, held by every device the library runs
+// on until the process ends.  Layout: kScratchCounterBytes of int32 arrival
+// counters (zero between runs: cleared once at set-up, then by each run's
+// last arrivals), then the float workspace.
+
+namespace {
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+constexpr size_t kScratchCounterBytes = (size_t)1 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, unsigned char *> g_scratch_ptr;  // device -> address of `scratch` there
+}  // namespace
+
+// The device address of this device's `scratch` (taken once per device, with
+// the device current; the array's name in host code is not a device address),
+// with its counters cleared on `s` the first time.
+static spmm_status scratch_on_device(hipStream_t s, unsigned char **out) {
+    int dev = 0;
+    SPMM_TRY_HIP(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return SPMM_OK;
+    }
+    void *ptr = nullptr;
+    SPMM_TRY_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    hipError_t e = launch_zero(static_cast<int32_t *>(ptr), (int64_t)(kScratchCounterBytes / 4), s);
+    if (e != hipSuccess) return hip_error(e, "zero scratch counters");
+    g_scratch_ptr[dev] = static_cast<unsigned char *>(ptr);
+    *out = static_cast<unsigned char *>(ptr);
+    return SPMM_OK;
+}
+
+extern "C" spmm_status spmm_run_noalloc(const spmm_plan_t *p, const void *B, int64_t ldb, void *C,
+                                        int64_t ldc, void *stream) {
+    spmm_status st = check_run(p, B, ldb, C, ldc);
+    if (st != SPMM_OK) return st;
+    if (p->hp.m == 0) return SPMM_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    RunArgs a;
+    make_run_args(p, B, ldb, C, ldc, a);
+    const bool serial = serial_exec(p, a);
+    const size_t bytes = workspace_floats(p->hp, serial) * sizeof(float);
+    const size_t cnt_bytes = counter_ints(p, a) * sizeof(int32_t);
+    if (bytes > kScratchBytes - kScratchCounterBytes || cnt_bytes > kScratchCounterBytes) {
+        char msg[200];
+        std::snprintf(msg, sizeof msg,
+                      "spmm_run_noalloc: the run needs %zu bytes of workspace and %zu of counters, "
+                      "beyond the fixed %zu and %zu", bytes, cnt_bytes,
+                      kScratchBytes - kScratchCounterBytes, kScratchCounterBytes);
+        return set_error(SPMM_ERR_BUDGET, msg);
+    }
+    unsigned char *base = nullptr;
+    st = scratch_on_device(s, &base);
+    if (st != SPMM_OK) return st;
+    RunContext ctx;
+    ctx.cnt = reinterpret_cast<int32_t *>(base);
+    ctx.work = bytes ? reinterpret_cast<float *>(base + kScratchCounterBytes) : nullptr;
+    ctx.allow_fork = false;  // a second stream would have to be created
+    return launch_plan(p, a, s, nullptr, ctx);
 }
 
 extern "C" spmm_status spmm_run_timed(const spmm_plan_t *p, const void *B, int64_t ldb, void *C,

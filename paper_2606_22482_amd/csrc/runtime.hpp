@@ -36,6 +36,7 @@ struct RunContext {
     int32_t *cnt = nullptr;
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
+    bool allow_fork = true;  // false: both co-scheduled grids on the run's stream
 };
 spmm_status run_context(hipStream_t s, size_t bytes, size_t cnt_ints, bool side, RunContext *ctx,
                         std::unique_lock<std::mutex> &lk);
