@@ -1,18 +1,23 @@
 #!/usr/bin/env python
-"""SpMM throughput on one MI355X.
+"""SpMM throughput on one MI355X, every configuration in one run.
 
-Default workload: the GNN-aggregation graph (Chung-Lu, 2^20 vertices, degree
-exponent 2.1, mean degree 16, max expected degree 20,000, symmetric-normalised
-f32 values) times B = 2^20 x 128 f32 N(0,1).  A "step" is one spmm_run of the
-whole hot path (segment partial sums, vector gather-FMA, MFMA windows) on
-inputs resident in HBM; the plan is built once beforehand, as the paper
-amortises preprocessing over repeated calls (Sec. 8.6).
+Headline (``value``): the GNN-aggregation graph (Chung-Lu, 2^20 vertices,
+degree exponent 2.1, mean degree 16, max expected degree 20,000,
+symmetric-normalised f32 values) times B = 2^20 x 128 f32 N(0,1).  A "step"
+is one spmm_run of the whole hot path (segments, vector items and MFMA
+windows, co-scheduled) on inputs resident in HBM; plans are built before the
+timed region, as the paper amortises preprocessing over repeated calls
+(Sec. 8.6).  The plain FP32 plan and the mixed MFMA/vector plan are both
+timed and the faster is reported.
 
-Both the plain FP32 plan and the mixed MFMA/vector plan are built and timed;
-the faster one is reported (the other's rate is printed beside it).  Prints one
-JSON line with the metric, a roofline entry for the dominant kernel (algorithmic
-bytes per launch / its average HIP-event duration) and the FP64 oracle timed on
-the host as a CPU baseline.
+Beside it, in the same JSON line (``configs``): the block-community matrix
+(262,144 rows, N = 256 bf16) mixed and plain; the batch of 512 uneven f16
+matrices in one submission (plans tuned per sparsity profile first) against
+512 separate runs; the 5,000-request serving stream (p50/p99 latency, also at
+the top level); the 4096-row uniform matrix.  ``roofline`` is the whole
+path's algorithmic bytes per step against 8 TB/s and against the copy
+bandwidth measured in the same run; the FP64 oracle timed on the host is the
+CPU baseline.  ``--workload NAME`` runs one configuration alone.
 """
 from __future__ import annotations
 
@@ -116,8 +121,9 @@ def measured_traffic(workload, mode, kernel):
 
 
 def cpu_baseline(A, B, b_kind, n, budget_s=12.0):
-    """Time the FP64 oracle on a bounded leading block of rows, all host threads
-    of this process's share (at most 16)."""
+    """Time the FP64 oracle on a bounded leading block of rows with this
+    process's share of the host threads (at most 16, the share a GPU gets on
+    the box; ``host_cores`` states how many the host has)."""
     import oracle
     threads = max(1, min(16, os.cpu_count() or 1))
     m = A.m
@@ -142,7 +148,7 @@ def cpu_baseline(A, B, b_kind, n, budget_s=12.0):
         dt = (time.perf_counter() - t0) / reps
     nnz = int(A.rowptr[rows])
     return {"value": round(2.0 * nnz * n / dt / 1e9, 3), "unit": "GFLOP/s", "cores": threads,
-            "kind": "oracle",
+            "host_cores": os.cpu_count(), "kind": "oracle",
             "sample": "rows 0..%d of %d (%.1f%% of nnz), N=%d, FP64 serial per row, %d pass(es) "
                       "of %.2f s" % (rows, m, 100.0 * nnz / max(1, A.nnz), n, reps, dt)}
 
@@ -218,84 +224,237 @@ def parse_opts(text):
 
 def serve_bench(args):
     """Serving stream: Poisson arrivals at 0.7x the closed-loop saturation rate
-    measured on the same request list; plans pre-built (resident)."""
-    import torch
+    measured on the first requests of the same list; plans pre-built (resident)."""
     from paper_2606_22482_amd import serve, synth
     t0 = time.perf_counter()
     pool = synth.serving_pool(n_graphs=args.pool_graphs, n_masks=args.pool_masks, seed=5,
                               max_rows=args.max_rows, max_mask_rows=args.max_mask_rows)
-    log("pool: %d matrices, %.1f M nnz (%.1f s)" % (len(pool), sum(p["A"].nnz for p in pool) / 1e6,
-                                                     time.perf_counter() - t0))
+    log("serving pool: %d matrices, %.1f M nnz (%.1f s)"
+        % (len(pool), sum(p["A"].nnz for p in pool) / 1e6, time.perf_counter() - t0))
     reqs = synth.serving_requests(args.requests, len(pool), args.pool_graphs, seed=5)
     srv = serve.Server(pool, n_streams=args.streams, max_batch=args.max_batch)
     t0 = time.perf_counter()
     keys = sorted({(d["matrix"], d["n"], d["b_kind"]) for d in reqs})
     st = serve.Stats()
-    for k in keys:
+    for i, k in enumerate(keys):
         srv.plans.get(k, st)
-    log("prewarm: %d plans (%.1f s)" % (len(keys), time.perf_counter() - t0))
-    closed = srv.run(reqs[: min(len(reqs), 1000)], realtime=False).summary()
+        if i % 100 == 99:
+            log("serving prewarm: %d of %d plans (%.1f s)" % (i + 1, len(keys), time.perf_counter() - t0))
+    log("serving prewarm: %d plans (%.1f s)" % (len(keys), time.perf_counter() - t0))
+    closed = srv.run(reqs[: min(len(reqs), args.closed_loop)], realtime=False).summary()
     rate = 0.7 * closed["throughput_req_s"]
     log("closed loop: %.1f req/s -> rate %.1f req/s" % (closed["throughput_req_s"], rate))
     timed = synth.serving_requests(args.requests, len(pool), args.pool_graphs, seed=5, rate=rate)
     s = srv.run(timed, realtime=True).summary()
-    out = {"metric": METRIC, "value": round(s["gflops"], 2), "unit": "GFLOP/s", "n_gpus": 1,
-           "steps": args.requests, "warmup": 0, "ms_per_step": round(s["mean_ms"], 4),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32|bf16", "data": "synthetic",
-           "config": {"workload": "serving_stream", "requests": args.requests,
-                      "rate_req_s": round(rate, 2), "pool": len(pool),
-                      "max_rows": args.max_rows, "max_mask_rows": args.max_mask_rows,
-                      "streams": args.streams, "budget_GB": 200},
-           "p50_ms": round(s["p50_ms"], 3), "p99_ms": round(s["p99_ms"], 3),
-           "throughput_req_s": round(s["throughput_req_s"], 2),
-           "serving": s, "closed_loop": closed}
-    print(json.dumps(out), flush=True)
+    log("serving: p50 %.3f ms, p99 %.3f ms, %.0f req/s, %.0f GFLOP/s"
+        % (s["p50_ms"], s["p99_ms"], s["throughput_req_s"], s["gflops"]))
+    return {"workload": "serving_stream", "requests": args.requests, "rate_req_s": round(rate, 2),
+            "pool": len(pool), "max_rows": args.max_rows, "max_mask_rows": args.max_mask_rows,
+            "streams": args.streams, "budget_GB": 200,
+            "p50_ms": round(s["p50_ms"], 3), "p99_ms": round(s["p99_ms"], 3),
+            "throughput_req_s": round(s["throughput_req_s"], 2), "gflops": round(s["gflops"], 1),
+            "rejected": s["rejected"], "mean_batch": round(s["mean_batch"], 2),
+            "closed_loop_req_s": round(closed["throughput_req_s"], 2)}
+
+
+def _batch_item(job):
+    from paper_2606_22482_amd import synth
+    i, sp = job
+    return synth.batch_matrix(i, sp, seed=4)
 
 
 def batch_bench(args):
-    """Uneven matrices in one batched submission (graph replay of the
-    persistent kernels) vs the same matrices as separate spmm_run calls."""
+    """Uneven f16 matrices in one batched submission (graph replay of the
+    persistent kernels) vs the same matrices as separate spmm_run calls.
+    Before timing, spmm_autotune runs once per sparsity-profile key (small
+    wall budget each); plans are then built with mode AUTO, which takes the
+    tuned options from the cache."""
     import torch
+    from concurrent.futures import ProcessPoolExecutor, ThreadPoolExecutor
     from paper_2606_22482_amd import api, synth
     t0 = time.perf_counter()
     specs = synth.batch_specs(count=args.batch_count, seed=4)
-    plans, items, flops = [], [], 0.0
-    for i, sp in enumerate(specs):
-        A, B = synth.batch_matrix(i, sp, seed=4)
-        p = api.Plan(A, B.shape[1], "f16", api.default_opts(**dict({"mode": "auto"}, **parse_opts(args.opts))))
-        Bd = api.device_tensor(B, "f16")
-        Cd = torch.empty((A.m, B.shape[1]), dtype=torch.float32, device="cuda")
-        plans.append(p)
-        items.append(api.WorkItem(p, Bd, Cd))
-        flops += 2.0 * A.nnz * B.shape[1]
-    log("batch: %d matrices, %.1f GFLOP per pass (%.1f s)" % (len(items), flops / 1e9,
-                                                             time.perf_counter() - t0))
+    workers = max(1, min(8, os.cpu_count() or 1))
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        mats = list(ex.map(_batch_item, list(enumerate(specs)), chunksize=4))
+    log("batch: %d matrices generated (%.1f s)" % (len(mats), time.perf_counter() - t0))
+    # B and C on the device; one tuning per profile key
+    t0 = time.perf_counter()
+    devs = [(api.device_tensor(B, "f16"),
+             torch.empty((A.m, B.shape[1]), dtype=torch.float32, device="cuda")) for A, B in mats]
+    api.tune_cache_clear()
+    keys = {}
+    for i, ((A, B), (Bd, Cd)) in enumerate(zip(mats, devs)):
+        key = api.spmm_profile_key(A, B.shape[1], "f16")
+        if key not in keys and args.batch_tune_ms > 0:
+            opts, rep = api.spmm_autotune(A, Bd, Cd, "f16", budget_ms=args.batch_tune_ms)
+            keys[key] = opts
+        if i % 64 == 63:
+            log("batch: tuning, %d matrices seen, %d profiles (%.1f s)"
+                % (i + 1, len(keys), time.perf_counter() - t0))
+    log("batch: %d profiles tuned (%.1f s)" % (len(keys), time.perf_counter() - t0))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        plans = list(ex.map(lambda AB: api.Plan(AB[0], AB[1].shape[1], "f16",
+                                                api.default_opts(mode="auto")), mats))
+    stats = [p.stats() for p in plans]
+    flops = sum(st["flops"] for st in stats)
+    alg = sum(st["algorithmic_bytes"] for st in stats)
+    picked = {"mixed": sum(1 for st in stats if st["opts"]["mode"] == 2),
+              "window_h": sorted({st["opts"]["window_h"] for st in stats if st["opts"]["mode"] == 2}),
+              "tiles": int(sum(st["tiles"] for st in stats))}
+    log("batch: %d plans (%.1f s), %.1f GFLOP per pass, %d mixed"
+        % (len(plans), time.perf_counter() - t0, flops / 1e9, picked["mixed"]))
+    items = [api.WorkItem(p, Bd, Cd) for p, (Bd, Cd) in zip(plans, devs)]
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        api.spmm_wait(api.spmm_submit(items))
-    torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def time_batch(its):
+        for _ in range(args.warmup):
+            api.spmm_wait(api.spmm_submit(its))
+        torch.cuda.synchronize()
+        e0.record(stream)
+        tickets = [api.spmm_submit(its) for _ in range(args.batch_steps)]
+        e1.record(stream)
+        torch.cuda.synchronize()
+        for t in tickets:
+            api.spmm_wait(t)  # retire every ticket, so the plans can be destroyed
+        return e0.elapsed_time(e1) / args.batch_steps
+
+    ms_batch = time_batch(items)
+    # the same batch with the untuned defaults (AUTO without a profile)
+    api.tune_cache_clear()
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        plain = list(ex.map(lambda AB: api.Plan(AB[0], AB[1].shape[1], "f16",
+                                                api.default_opts(mode="auto")), mats))
+    ms_untuned = time_batch([api.WorkItem(p, Bd, Cd) for p, (Bd, Cd) in zip(plain, devs)])
+    del plain
     e0.record(stream)
-    for _ in range(args.steps):
-        api.spmm_submit(items)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_batch = e0.elapsed_time(e1) / args.steps
-    e0.record(stream)
-    for _ in range(args.steps):
+    for _ in range(args.batch_steps):
         for it in items:
             it.plan.run(it.B, it.C)
     e1.record(stream)
     torch.cuda.synchronize()
-    ms_sep = e0.elapsed_time(e1) / args.steps
-    out = {"metric": METRIC, "value": round(flops / (ms_batch * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
-           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": round(ms_batch, 4), "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f16in-f32acc", "data": "synthetic",
-           "config": {"workload": "batched_uneven_%d" % len(items)},
-           "separate_runs_ms": round(ms_sep, 4), "speedup_vs_separate": round(ms_sep / ms_batch, 3)}
-    print(json.dumps(out), flush=True)
+    ms_sep = e0.elapsed_time(e1) / args.batch_steps
+    log("batch: %.3f ms submitted (%.3f ms with untuned plans), %.3f ms separate"
+        % (ms_batch, ms_untuned, ms_sep))
+    gbs = alg / (ms_batch * 1e-3) / 1e9
+    return {"workload": "batched_uneven_%d_f16" % len(items), "ms_per_step": round(ms_batch, 4),
+            "gflops": round(flops / (ms_batch * 1e-3) / 1e9, 1),
+            "separate_runs_ms": round(ms_sep, 4), "speedup_vs_separate": round(ms_sep / ms_batch, 3),
+            "untuned_ms": round(ms_untuned, 4),
+            "roofline": {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": int(alg)},
+            "tuned_profiles": len(keys), "tune_budget_ms": args.batch_tune_ms, "plans": picked}
+
+
+def measure(wkey, args, modes, extra=None):
+    """Plans of one workload for each mode (name -> plan options), each timed
+    over args.steps runs between events on the current stream, with
+    per-kernel event times from spmm_run_timed."""
+    import torch
+    from paper_2606_22482_amd import api
+    t0 = time.perf_counter()
+    A, B, b_kind, wname = workload(wkey)
+    n = B.shape[1]
+    log("workload %s: m=%d nnz=%d n=%d (%.1f s)" % (wname, A.m, A.nnz, n, time.perf_counter() - t0))
+    Bd = api.device_tensor(B, b_kind)
+    Cd = torch.empty((A.m, n), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    results = {}
+    for mode, kw in modes.items():
+        kw = dict(kw, **(extra or {}))
+        t0 = time.perf_counter()
+        plan = api.Plan(A, n, b_kind, api.default_opts(**kw))
+        st = plan.stats()
+        log("plan %s: %.0f ms host, tiles=%d (%.1f%% of nnz, density %.3f), segments=%d, "
+            "vector items=%d" % (mode, (time.perf_counter() - t0) * 1e3, st["tiles"],
+                                 100.0 * st["nnz_tiles"] / max(1, A.nnz),
+                                 st["mean_tile_density"], st["segments"], st["vector_items"]))
+        adapt = None
+        if mode == "mixed" and args.adapt_from > 0:
+            plan = api.Plan(A, n, b_kind, api.default_opts(**dict(kw, alpha=args.adapt_from)))
+            ast = api.adapt_state()
+            adapt = []
+            for epoch in range(10):
+                a_used = plan.stats()["opts"]["alpha"]
+                plan.adapt_epoch(A, Bd, Cd, ast)
+                adapt.append({"alpha": round(a_used, 5), "alpha_star": round(ast.alpha_star, 5),
+                              "skew": round(ast.skew, 3),
+                              "epoch_ms": round(ast.t_vec_ms + ast.t_mfma_ms, 4)})
+                log("adapt epoch %d: alpha %.4f -> alpha* %.4f (skew %.2f), paths %.4f + %.4f ms"
+                    % (epoch, a_used, ast.alpha_star, ast.skew, ast.t_vec_ms, ast.t_mfma_ms))
+                if not ast.replanned:
+                    break
+            st = plan.stats()
+        for _ in range(args.warmup):
+            plan.run(Bd, Cd)
+        torch.cuda.synchronize()
+        timer = api.Timer(capacity=8 * args.steps + 8)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            plan.run_timed(Bd, Cd, timer)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        per = {}
+        for name, kms in timer.read():
+            per.setdefault(name, []).append(kms)
+        kavg = {k: float(np.mean(v)) for k, v in per.items()}
+        log("mode %s: %.4f ms/step, kernels %s" % (mode, ms, {k: round(v, 4) for k, v in kavg.items()}))
+        results[mode] = dict(plan=plan, stats=st, ms=ms, kavg=kavg, adapt=adapt)
+    return A, B, b_kind, wname, n, results
+
+
+def summarise(A, b_kind, wname, n, results, copy_gbs=None):
+    """The best mode's throughput, the path roofline (all algorithmic bytes of
+    a step over its time) and the dominant kernel's own figure."""
+    best = min(results, key=lambda k: results[k]["ms"])
+    R = results[best]
+    st, ms = R["stats"], R["ms"]
+    s_a = 4 if A.val_kind == "f32" else 2
+    s_b = 4 if b_kind == "f32" else 2
+    kb = kernel_bytes(A, R["plan"].export(), n, s_a, s_b)
+    dom = max(R["kavg"], key=lambda k: R["kavg"][k])
+    k_gbs = kb[dom] / (R["kavg"][dom] * 1e-3) / 1e9
+    path_gbs = st["algorithmic_bytes"] / (ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(path_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(path_gbs / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(wname, best, dom),
+            "algorithmic_bytes": int(st["algorithmic_bytes"]),
+            "kernel": {"name": dom, "achieved": round(k_gbs, 1), "frac": round(k_gbs / HBM_PEAK_GBS, 4),
+                       "bytes_per_launch": int(kb[dom]), "avg_launch_ms": round(R["kavg"][dom], 5)}}
+    if copy_gbs:
+        roof["copy_GBps"] = round(copy_gbs, 1)
+        roof["frac_of_copy"] = round(path_gbs / copy_gbs, 4)
+    modes = {k: {"ms_per_step": round(v["ms"], 5),
+                 "gflops": round(2.0 * A.nnz * n / (v["ms"] * 1e-3) / 1e9, 1),
+                 "path_frac": round(v["stats"]["algorithmic_bytes"] / (v["ms"] * 1e-3) / 1e9
+                                    / HBM_PEAK_GBS, 4),
+                 "kernels_ms": {a: round(b, 5) for a, b in v["kavg"].items()},
+                 "nnz_tiles_frac": round(v["stats"]["nnz_tiles"] / max(1, A.nnz), 4),
+                 "mean_tile_density": round(v["stats"]["mean_tile_density"], 4),
+                 "tol_class": v["stats"]["tol_class"]}
+             for k, v in results.items()}
+    for k, v in results.items():
+        if v["adapt"] is not None:
+            modes[k]["adapt"] = v["adapt"]
+    return best, ms, roof, modes
+
+
+# plan options of each workload's modes (mixed: the settings the plan-option
+# sweeps measured fastest; see the measured results)
+MODES = {
+    "gnn": {"plain": dict(mode="plain"),
+            "mixed": dict(mode="mixed", row_order="length_sorted", t_row=256, alpha=0.15)},
+    "gnn64": {"plain": dict(mode="plain"),
+              "mixed": dict(mode="mixed", row_order="length_sorted", t_row=256, alpha=0.15)},
+    "block": {"mixed": dict(mode="mixed", row_order="original_ranges"), "plain": dict(mode="plain")},
+    "block_shuffled": {"mixed": dict(mode="mixed", row_order="compacted"), "plain": dict(mode="plain")},
+    "uniform": {"plain": dict(mode="plain"), "mixed": dict(mode="mixed")},
+}
 
 
 def main():
@@ -303,11 +462,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="gnn")
-    ap.add_argument("--modes", default="plain,mixed")
+    ap.add_argument("--workload", default="all",
+                    help="all (default: every configuration in one line), gnn, gnn64, block, "
+                         "block_shuffled, uniform, batch, serve")
+    ap.add_argument("--modes", default="", help="comma-separated subset of the workload's modes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--opts", default="", help="extra plan options, k=v[,k=v]")
     ap.add_argument("--requests", type=int, default=5000)
+    ap.add_argument("--closed-loop", type=int, default=1000)
     ap.add_argument("--pool-graphs", type=int, default=64)
     ap.add_argument("--pool-masks", type=int, default=16)
     ap.add_argument("--max-rows", type=int, default=500000)
@@ -315,6 +477,9 @@ def main():
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--max-batch", type=int, default=64)
     ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--batch-tune-ms", type=float, default=60.0,
+                    help="wall budget of spmm_autotune per sparsity profile of the batch (0: no tuning)")
     ap.add_argument("--plan-time", action="store_true",
                     help="time plan construction: host build + upload vs built on the device")
     ap.add_argument("--adapt-from", type=float, default=0.0,
@@ -335,10 +500,7 @@ def main():
 
     _lib.load()
     torch.cuda.set_device(0)
-    if args.workload == "serve":
-        return serve_bench(args)
-    if args.workload == "batch":
-        return batch_bench(args)
+    extra = parse_opts(args.opts)
     if args.copy_probe and args.copy_plain:
         # torch's elementwise copy (plain loads and stores) over the same bytes
         a = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
@@ -354,83 +516,28 @@ def main():
         print(json.dumps({"copy_bytes": args.copy_probe, "copy_launches": 13,
                           "read_plus_write_GBps": round(bw / 1e9, 1)}), flush=True)
         return
-    t0 = time.perf_counter()
-    A, B, b_kind, wname = workload(args.workload)
-    n = B.shape[1]
-    log("workload %s: m=%d nnz=%d n=%d (%.1f s)" % (wname, A.m, A.nnz, n, time.perf_counter() - t0))
+    if args.workload == "serve":
+        print(json.dumps(serve_bench(args)), flush=True)
+        return
+    if args.workload == "batch":
+        print(json.dumps(batch_bench(args)), flush=True)
+        return
     if args.plan_time:
-        return plan_time_bench(A, B, b_kind, wname, n, args)
-    extra = parse_opts(args.opts)
+        A, B, b_kind, wname = workload(args.workload if args.workload != "all" else "gnn")
+        return plan_time_bench(A, B, b_kind, wname, B.shape[1], args)
 
-    Bd = api.device_tensor(B, b_kind)
-    Cd = torch.empty((A.m, n), dtype=torch.float32, device="cuda")
-    s_a = 4 if A.val_kind == "f32" else 2
-    s_b = 4 if b_kind == "f32" else 2
-    stream = torch.cuda.current_stream()
+    def pick(key):
+        m = MODES[key]
+        if args.modes:
+            m = {k: v for k, v in m.items() if k in args.modes.split(",")}
+        return m
 
-    results = {}
-    for mode in args.modes.split(","):
-        kw = dict(mode=mode)
-        if mode == "mixed" and args.workload.startswith("gnn"):
-            kw.update(row_order="length_sorted", t_row=16)
-        if mode == "mixed" and args.workload == "block":
-            kw.update(row_order="original_ranges")
-        if mode == "mixed" and args.workload == "block_shuffled":
-            kw.update(row_order="compacted")
-        kw.update(extra)
-        t0 = time.perf_counter()
-        plan = api.Plan(A, n, b_kind, api.default_opts(**kw))
-        st = plan.stats()
-        log("plan %s: %.0f ms host, tiles=%d (%.1f%% of nnz, density %.3f), segments=%d, "
-            "vector items=%d" % (mode, (time.perf_counter() - t0) * 1e3, st["tiles"],
-                                 100.0 * st["nnz_tiles"] / max(1, A.nnz),
-                                 st["mean_tile_density"], st["segments"], st["vector_items"]))
-        adapt = None
-        if mode == "mixed" and args.adapt_from > 0:
-            plan = api.Plan(A, n, b_kind, api.default_opts(**dict(kw, alpha=args.adapt_from)))
-            for _ in range(2):
-                plan.run(Bd, Cd)
-            ast = api.adapt_state()
-            adapt = []
-            for epoch in range(10):
-                a_used = plan.stats()["opts"]["alpha"]
-                plan.adapt_epoch(A, Bd, Cd, ast)
-                adapt.append({"alpha": round(a_used, 5), "alpha_star": round(ast.alpha_star, 5),
-                              "skew": round(ast.skew, 3),
-                              "epoch_ms": round(ast.t_vec_ms + ast.t_mfma_ms, 4)})
-                log("adapt epoch %d: alpha %.4f -> alpha* %.4f (skew %.2f), paths %.4f + %.4f ms"
-                    % (epoch, a_used, ast.alpha_star, ast.skew, ast.t_vec_ms, ast.t_mfma_ms))
-                if not ast.replanned:
-                    break
-            st = plan.stats()
-        for _ in range(args.warmup):
-            plan.run(Bd, Cd)
-        torch.cuda.synchronize()
-        timer = api.Timer(capacity=8 * args.steps + 8)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        for _ in range(args.steps):
-            plan.run_timed(Bd, Cd, timer)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.steps
-        per = {}
-        for name, kms in timer.read():
-            per.setdefault(name, []).append(kms)
-        kavg = {k: float(np.mean(v)) for k, v in per.items()}
-        log("mode %s: %.4f ms/step, kernels %s" % (mode, ms, {k: round(v, 4) for k, v in kavg.items()}))
-        results[mode] = dict(plan=plan, stats=st, ms=ms, kavg=kavg, adapt=adapt)
-
-    best = min(results, key=lambda k: results[k]["ms"])
-    R = results[best]
-    st, ms = R["stats"], R["ms"]
+    head = "gnn" if args.workload == "all" else args.workload
+    copy_gbs = api.spmm_copy_bandwidth(1 << 30) / 1e9
+    log("copy bandwidth (read + write): %.1f GB/s" % copy_gbs)
+    A, B, b_kind, wname, n, results = measure(head, args, pick(head), extra)
+    best, ms, roof, modes = summarise(A, b_kind, wname, n, results, copy_gbs)
     gflops = 2.0 * A.nnz * n / (ms * 1e-3) / 1e9
-    kb = kernel_bytes(A, R["plan"].export(), n, s_a, s_b)
-    dom = max(R["kavg"], key=lambda k: R["kavg"][k])
-    achieved = kb[dom] / (R["kavg"][dom] * 1e-3) / 1e9
-    path_gbs = st["algorithmic_bytes"] / (ms * 1e-3) / 1e9
     out = {
         "metric": METRIC,
         "value": round(gflops, 2),
@@ -442,30 +549,36 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if best == "plain" else "f32+bf16mfma",
+        "dtype": "f32" if results[best]["stats"]["tol_class"] == 0 else "f32+bf16mfma",
         "data": "synthetic",
-        "config": {"workload": wname, "m": A.m, "k": A.k, "nnz": A.nnz, "n": n,
-                   "b_dtype": b_kind, "mode": best},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(wname, best, dom),
-                     "bytes_per_launch": int(kb[dom]),
-                     "avg_launch_ms": round(R["kavg"][dom], 5)},
-        "path_hbm_roofline_frac": round(path_gbs / HBM_PEAK_GBS, 4),
-        "path_algorithmic_bytes": int(st["algorithmic_bytes"]),
-        "modes": {k: {"ms_per_step": round(v["ms"], 5),
-                      "gflops": round(2.0 * A.nnz * n / (v["ms"] * 1e-3) / 1e9, 1),
-                      "kernels_ms": {a: round(b, 5) for a, b in v["kavg"].items()},
-                      "nnz_tiles_frac": round(v["stats"]["nnz_tiles"] / max(1, A.nnz), 4),
-                      "mean_tile_density": round(v["stats"]["mean_tile_density"], 4)}
-                  for k, v in results.items()},
+        "config": {"workload": wname, "m": A.m, "k": A.k, "nnz": A.nnz, "n": n, "b_dtype": b_kind,
+                   "mode": best, "exec": results[best]["stats"]["opts"]["exec"]},
+        "roofline": roof,
+        "modes": modes,
     }
-    for k, v in results.items():
-        if v["adapt"] is not None:
-            out["modes"][k]["adapt"] = v["adapt"]
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(A, B, b_kind, n)
+    del results
+    if args.workload == "all":
+        configs = {}
+        for key in ("block", "uniform"):
+            A2, B2, bk2, wn2, n2, res2 = measure(key, args, pick(key), extra)
+            b2, ms2, roof2, modes2 = summarise(A2, bk2, wn2, n2, res2, copy_gbs)
+            configs[wn2] = {"best": b2, "ms_per_step": round(ms2, 5),
+                            "gflops": round(2.0 * A2.nnz * n2 / (ms2 * 1e-3) / 1e9, 1),
+                            "roofline": roof2, "modes": modes2}
+            del res2
+        torch.cuda.empty_cache()
+        bt = batch_bench(args)
+        configs[bt["workload"]] = bt
+        torch.cuda.empty_cache()
+        sv = serve_bench(args)
+        configs[sv["workload"]] = sv
+        out["configs"] = configs
+        out["p50_ms"] = sv["p50_ms"]
+        out["p99_ms"] = sv["p99_ms"]
+        out["throughput_req_s"] = sv["throughput_req_s"]
     print(json.dumps(out), flush=True)
 
 

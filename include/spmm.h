@@ -297,6 +297,17 @@ spmm_status spmm_plan_export(const spmm_plan_t *p, spmm_plan_dump_t *out);
 spmm_status spmm_run(const spmm_plan_t *p, const void *B, int64_t ldb, void *C, int64_t ldc,
                      void *stream);
 
+/* Device memory one execution of a plan occupies besides the plan itself
+ * (admission by HBM budget, as a serving loop does): B (k rows of ldb
+ * elements), C (m rows of ldc floats) and the scratch the execution uses --
+ * for a batched submission (batched != 0) its share of the submission's
+ * workspace, for spmm_run the stream's workspace and arrival counters.  Writes
+ * the byte count to *bytes and returns SPMM_ERR_BUDGET when it exceeds
+ * `budget` (a budget < 0 is unlimited); INVALID for a null plan or output or
+ * ld < n. */
+spmm_status spmm_run_bytes(const spmm_plan_t *p, int64_t ldb, int64_t ldc, int32_t batched,
+                           int64_t budget, int64_t *bytes);
+
 /* spmm_run for callers that cannot allocate (code under graph capture, tight
  * serving loops, harnesses that forbid allocation): the same kernels and the
  * same C bit for bit, but the workspace and the arrival counters come from a

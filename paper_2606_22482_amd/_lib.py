@@ -112,6 +112,7 @@ SIGNATURES = {
     "spmm_plan_export": (_S, [_P, C.POINTER(PlanDump)]),
     "spmm_run": (_S, [_P, _P, C.c_int64, _P, C.c_int64, _P]),
     "spmm_run_noalloc": (_S, [_P, _P, C.c_int64, _P, C.c_int64, _P]),
+    "spmm_run_bytes": (_S, [_P, C.c_int64, C.c_int64, C.c_int32, C.c_int64, C.POINTER(C.c_int64)]),
     "spmm_timer_create": (_S, [C.c_int32, C.POINTER(_P)]),
     "spmm_timer_reset": (_S, [_P]),
     "spmm_timer_read": (_S, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_float), C.c_int32,

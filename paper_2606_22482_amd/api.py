@@ -252,6 +252,17 @@ class Plan:
         bp, ldb, cp, ldc = self.operands(B, Cout)
         L.check(self._lib.spmm_run(self._h, bp, ldb, cp, ldc, _stream_handle(stream)))
 
+    def run_bytes(self, ldb: int | None = None, ldc: int | None = None, batched=False,
+                  budget: int = -1):
+        """spmm_run_bytes: (status, bytes) of one execution (B, C, scratch;
+        not the plan).  status is SPMM_OK or SPMM_ERR_BUDGET (bytes > budget)."""
+        out = C.c_int64()
+        st = self._lib.spmm_run_bytes(self._h, int(ldb or self.n), int(ldc or self.n),
+                                      1 if batched else 0, int(budget), C.byref(out))
+        if st not in (L.SPMM_OK, L.SPMM_ERR_BUDGET):
+            L.check(st)
+        return st, out.value
+
     def run_noalloc(self, B, Cout, stream=None):
         """spmm_run_noalloc: as run, with the library's fixed scratch array
         instead of a per-stream workspace (no allocation)."""

@@ -770,6 +770,33 @@ extern "C" spmm_status spmm_run(const spmm_plan_t *p, const void *B, int64_t ldb
     return run_impl(p, B, ldb, C, ldc, stream, nullptr);
 }
 
+extern "C" spmm_status spmm_run_bytes(const spmm_plan_t *p, int64_t ldb, int64_t ldc, int32_t batched,
+                                      int64_t budget, int64_t *bytes) {
+    if (!p || !bytes) return set_error(SPMM_ERR_INVALID, "null argument");
+    const HostPlan &h = p->hp;
+    if (ldb < h.n || ldc < h.n) return set_error(SPMM_ERR_INVALID, "leading dimension < n");
+    const double sb = dtype_size(h.b_type);
+    double total = (double)h.k * (double)ldb * sb + (double)h.m * (double)ldc * 4.0;
+    if (batched) {
+        total += (double)workspace_floats(h, true) * 4.0;
+    } else {
+        // the run's arguments with B and C aligned (the alignment decides the
+        // panel width and so the counters)
+        RunArgs a;
+        make_run_args(p, reinterpret_cast<const void *>(256), ldb, reinterpret_cast<void *>(256), ldc, a);
+        const bool serial = serial_exec(p, a);
+        total += (double)workspace_floats(h, serial) * 4.0 + (double)counter_ints(p, a) * 4.0;
+    }
+    *bytes = (int64_t)total;
+    if (budget >= 0 && total > (double)budget) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "execution needs %.0f bytes, beyond the budget of %lld", total,
+                      (long long)budget);
+        return set_error(SPMM_ERR_BUDGET, msg);
+    }
+    return SPMM_OK;
+}
+
 // ------------------------------------------------------------------------------------------
 // A run that allocates nothing: its workspace and arrival counters live in a
 // fixed device array of this library, held by every device the library runs

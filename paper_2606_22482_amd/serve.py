@@ -3,11 +3,13 @@
 Requests (matrix id from a resident pool, N, B type, B seed, arrival time)
 arrive on a Poisson clock.  The scheduler:
 
-* admits waiting requests in arrival order while their HBM footprint (B, C,
-  segment workspace, and the plan if it is not resident yet) fits the budget;
-  a request that does not fit lets later, smaller ones pass (no head-of-line
-  blocking) and a request that can never fit is rejected with the library's
-  BUDGET status;
+* admits waiting requests in arrival order while their HBM footprint fits
+  the budget: the plan (resident, or built on admission) plus what the
+  library reports one batched execution occupies (``spmm_run_bytes``: B, C
+  and the request's share of the submission's workspace); a request that
+  does not fit now lets later, smaller ones pass (no head-of-line blocking),
+  and one that can never fit -- the library answers BUDGET for the whole
+  budget less its plan -- is rejected;
 * keeps plans resident in an LRU cache charged to the same budget, evicting
   only plans no in-flight request uses;
 * forms a batch of every admitted request as soon as one of its streams is
@@ -47,7 +49,8 @@ class Request:
     admitted_at: float = -1.0
     done_at: float = -1.0
     status: str = "waiting"            # waiting | admitted | running | done | rejected
-    footprint: int = 0
+    footprint: int = 0                 # bytes of its execution (B, C, workspace share)
+    need: int = 0                      # footprint plus its plan's bytes, checked at admission
     B: object = None
     C: object = None
 
@@ -93,12 +96,8 @@ class PlanCache:
         self.plans = collections.OrderedDict()   # key -> (plan, bytes)
         self.users = collections.Counter()
 
-    def bytes_if_missing(self, key) -> int:
-        if key in self.plans:
-            return 0
-        A = self.pool[key[0]]["A"]
-        # plan upload is ~ the CSR (index + value) plus row pointers
-        return int(A.nnz * 8 + (A.m + 1) * 4 * 3)
+    def bytes_of(self, key) -> int:
+        return self.plans[key][1] if key in self.plans else 0
 
     def get(self, key, stats: Stats):
         if key in self.plans:
@@ -111,15 +110,15 @@ class PlanCache:
         stats.plan_builds += 1
         return plan
 
-    def evictable_bytes(self) -> int:
-        return sum(b for k, (p, b) in self.plans.items() if self.users[k] == 0)
+    def evictable_bytes(self, keep=None) -> int:
+        return sum(b for k, (p, b) in self.plans.items() if self.users[k] == 0 and k != keep)
 
-    def evict(self, need: int, stats: Stats) -> int:
+    def evict(self, need: int, stats: Stats, keep=None) -> int:
         freed = 0
         for k in list(self.plans.keys()):
             if freed >= need:
                 break
-            if self.users[k] == 0:
+            if self.users[k] == 0 and k != keep:
                 plan, b = self.plans.pop(k)
                 plan.destroy()
                 freed += b
@@ -150,12 +149,6 @@ class Server:
         self.plans = PlanCache(pool, opts_for)
         self.keep_results = keep_results
         self.used = 0
-
-    # --- footprints -------------------------------------------------------------------------
-    def _io_bytes(self, r: Request) -> int:
-        A = self.pool[r.matrix]["A"]
-        sb = 4 if r.b_kind == "f32" else 2
-        return A.k * r.n * sb + A.m * r.n * 4 + A.m * 4  # B, C, workspace bound
 
     def _plan_key(self, r: Request):
         return (r.matrix, r.n, r.b_kind)
@@ -213,22 +206,26 @@ class Server:
                 while waiting and len(batch) < self.max_batch:
                     r = waiting.popleft()
                     key = self._plan_key(r)
-                    need = self._io_bytes(r) + self.plans.bytes_if_missing(key)
-                    if need > self.budget:
-                        r.status = "rejected"      # can never fit: BUDGET
+                    plan = self.plans.get(key, stats)
+                    pbytes = self.plans.bytes_of(key)
+                    # the library's footprint of one batched execution, checked
+                    # against the whole budget less the plan: BUDGET = never fits
+                    st, io = plan.run_bytes(batched=True, budget=max(0, self.budget - pbytes))
+                    r.footprint, r.need = io, io + pbytes
+                    if st == L.SPMM_ERR_BUDGET:
+                        r.status = "rejected"
                         stats.rejected += 1
                         finished += 1
                         continue
-                    if self.used + self.plans.resident_bytes() + need > self.budget:
-                        over = self.used + self.plans.resident_bytes() + need - self.budget
-                        if self.plans.evictable_bytes() >= over:
-                            self.plans.evict(over, stats)
+                    occupied = self.used + self.plans.resident_bytes() + io
+                    if occupied > self.budget:
+                        over = occupied - self.budget
+                        if self.plans.evictable_bytes(keep=key) >= over:
+                            self.plans.evict(over, stats, keep=key)
                         else:
                             keep.append(r)         # wait for memory; let smaller ones pass
                             continue
-                    plan = self.plans.get(key, stats)
                     self.plans.users[key] += 1
-                    r.footprint = self._io_bytes(r)
                     self.used += r.footprint
                     A = self.pool[r.matrix]["A"]
                     dt = torch.float32 if r.b_kind == "f32" else torch.bfloat16
