@@ -27,7 +27,8 @@ HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-pthread", "-I", INCLUDE, "-I", CSRC,
              "-I", "/opt/rocm/include"]
 
-HIP_SOURCES = ["kernels.hip", "fused.hip", "runtime.hip", "submit.hip", "autotune.hip", "devbuild.hip"]
+HIP_SOURCES = ["kernels.hip", "fused.hip", "runtime.hip", "submit.hip", "autotune.hip", "devbuild.hip",
+               "devmixed.hip"]
 CXX_SOURCES = ["plan.cpp", "serialize.cpp"]
 
 

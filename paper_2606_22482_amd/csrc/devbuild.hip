@@ -273,16 +273,6 @@ std::vector<int32_t> order_by_key(const std::vector<int32_t> &key) {
     return a;
 }
 
-// exclusive (or inclusive) scan of n int64 values; *total (device) = sum
-hipError_t scan64(const int64_t *in, int64_t *out, int64_t n, int inclusive, int64_t *sums,
-                  hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    const int64_t nb = (n + kTile - 1) / kTile;
-    hipLaunchKernelGGL(k_tile_sums, dim3((unsigned)nb), dim3(kThreads), 0, s, n, in, sums);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kThreads), 0, s, nb, sums);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kThreads), 0, s, n, in, sums, out, inclusive);
-    return hipGetLastError();
-}
 
 struct DevBuf {
     void *p = nullptr;
@@ -292,6 +282,20 @@ struct DevBuf {
 };
 
 }  // namespace
+
+namespace spmm {
+// exclusive (or inclusive) scan of n int64 values; sums[nb] (device) = total
+hipError_t scan64(const int64_t *in, int64_t *out, int64_t n, int inclusive, int64_t *sums,
+                  hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int64_t nb = (n + kTile - 1) / kTile;
+    hipLaunchKernelGGL(k_tile_sums, dim3((unsigned)nb), dim3(kThreads), 0, s, n, in, sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kThreads), 0, s, nb, sums);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kThreads), 0, s, n, in, sums, out, inclusive);
+    return hipGetLastError();
+}
+int64_t scan_sums_len(int64_t n) { return std::max<int64_t>(1, (n + kTile - 1) / kTile) + 1; }
+}  // namespace spmm
 
 extern "C" spmm_status spmm_plan_device(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
                                         const spmm_opts *opts, void *stream, spmm_plan_t **out) {
@@ -306,9 +310,13 @@ extern "C" spmm_status spmm_plan_device(const spmm_csr *A, int32_t n, int32_t b_
         if (opts) in = *opts;
         else spmm_opts_default(&in);
         if (in.mode == SPMM_MODE_AUTO) in.mode = SPMM_MODE_PLAIN_F32;
-        if (in.mode != SPMM_MODE_PLAIN_F32)
-            return set_error(SPMM_ERR_UNSUPPORTED, "device-built plans are plain");
         resolve_options(&in, A, n, b_type, &o);
+    }
+    if (o.mode != SPMM_MODE_PLAIN_F32) {
+        // windows of fixed row ranges, partitioned on the device
+        if (o.row_order != SPMM_ORDER_ORIGINAL_RANGES)
+            return set_error(SPMM_ERR_UNSUPPORTED, "device-built mixed plans use original-ranges windows");
+        return plan_device_mixed(A, n, b_type, c_type, o, static_cast<hipStream_t>(stream), out);
     }
     if (o.cold_policy != 0) return set_error(SPMM_ERR_UNSUPPORTED, "device-built plans gather with the default policy");
     if (o.item_cost > 4096) return set_error(SPMM_ERR_UNSUPPORTED, "device-built plans need item_cost <= 4096");

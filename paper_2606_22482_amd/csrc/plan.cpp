@@ -413,6 +413,103 @@ spmm_status validate_opts(const spmm_opts &o, std::string &err) {
     return SPMM_OK;
 }
 
+// The schedule of a partitioned plan (windows, their tiles and every row's
+// remainder known): vector rows, segments of long remainders, cost-balanced
+// vector items, window segment ids, window partial items and the window
+// launch order (Sec. 7).  Shared by the host builder and the device builder,
+// which computes the partition on the device and the schedule here.
+void build_schedule(HostPlan &P) {
+    const spmm_opts &o = P.opts;
+    const int64_t m = P.m;
+    const int H = o.window_h, kt = o.kt, S = o.seg_len;
+    const int64_t W = (int64_t)P.windows.size() / H;
+    // ---- vector rows, segments ----
+    std::vector<uint8_t> covered(m, 0);
+    for (int32_t r : P.windows)
+        if (r >= 0) covered[r] = 1;
+    for (int64_t r = 0; r < m; ++r)
+        if (!covered[r]) P.vector_rows.push_back((int32_t)r);
+    P.identity_rows = (int64_t)P.vector_rows.size() == m;
+    P.nseg.assign(m, 0);
+    for (int64_t r = 0; r < m; ++r) {
+        int64_t L = P.rem_ptr[r + 1] - P.rem_ptr[r];
+        if (L > S) P.nseg[r] = (int32_t)((L + S - 1) / S);
+    }
+    auto add_segments = [&](int32_t r) {
+        for (int32_t j = 0; j < P.nseg[r]; ++j) {
+            int64_t b = P.rem_ptr[r] + (int64_t)j * S;
+            int64_t e = std::min<int64_t>(b + S, P.rem_ptr[r + 1]);
+            P.seg_row.push_back(r);
+            P.seg_begin.push_back((int32_t)b);
+            P.seg_end.push_back((int32_t)e);
+        }
+    };
+
+    // vector items: consecutive vector rows with balanced cost (Sec. 7).  Row i
+    // (in vector-row order) belongs to item floor(c_i / item_cost), c_i the
+    // summed cost of the rows before it (empty items dropped): a rule of prefix
+    // sums, so a device-side builder reproduces it exactly.
+    P.vitem_ptr.push_back(0);
+    {
+        int64_t before = 0, bucket = -1;
+        const int64_t nv = (int64_t)P.vector_rows.size();
+        for (int64_t i = 0; i < nv; ++i) {
+            int32_t r = P.vector_rows[i];
+            int64_t L = P.rem_ptr[r + 1] - P.rem_ptr[r];
+            const int64_t b = before / o.item_cost;
+            if (i > 0 && b != bucket) P.vitem_ptr.push_back((int32_t)i);
+            bucket = b;
+            before += kRowCost + (P.nseg[r] ? P.nseg[r] : L);
+        }
+        if (nv > 0) P.vitem_ptr.push_back((int32_t)nv);
+        // the size-class variant takes each item's rows longest first, so that
+        // rows of one size class are packed side by side; split rows go last
+        if (o.pipeline == 3 && nv > 0) {
+            P.vexec = P.vector_rows;
+            auto key = [&](int32_t r) -> int64_t {
+                return P.nseg[r] ? -1 : P.rem_ptr[r + 1] - P.rem_ptr[r];
+            };
+            for (size_t it = 0; it + 1 < P.vitem_ptr.size(); ++it)
+                std::stable_sort(P.vexec.begin() + P.vitem_ptr[it], P.vexec.begin() + P.vitem_ptr[it + 1],
+                                 [&](int32_t a, int32_t b) { return key(a) > key(b); });
+        }
+        const std::vector<int32_t> &order = P.vexec.empty() ? P.vector_rows : P.vexec;
+        for (size_t it = 0; it + 1 < P.vitem_ptr.size(); ++it) {
+            P.vitem_seg.push_back((int32_t)P.seg_row.size());
+            for (int32_t i = P.vitem_ptr[it]; i < P.vitem_ptr[it + 1]; ++i) add_segments(order[i]);
+        }
+    }
+    // windows: segment ids in slot order; launch order by window id or heaviest first
+    std::vector<int64_t> wcost(W, 0);
+    P.win_part.push_back(0);
+    for (int64_t w = 0; w < W; ++w) {
+        P.win_seg.push_back((int32_t)P.seg_row.size());
+        const int32_t ta = P.win_tile_ptr[w], tb = P.win_tile_ptr[w + 1];
+        // tiles beyond the first kWinTiles become partial items of kWinTiles each
+        for (int32_t t = ta + kWinTiles; t < tb; t += kWinTiles) {
+            P.wpart_win.push_back((int32_t)w);
+            P.wpart_t0.push_back(t);
+            P.wpart_t1.push_back(std::min(t + kWinTiles, tb));
+        }
+        P.win_part.push_back((int32_t)P.wpart_win.size());
+        wcost[w] = (int64_t)std::min(tb - ta, kWinTiles) * kt +
+                   (int64_t)(P.win_part[w + 1] - P.win_part[w]) * H;
+        for (int s = 0; s < H; ++s) {
+            int32_t r = P.windows[w * H + s];
+            if (r < 0) continue;
+            int64_t L = P.rem_ptr[r + 1] - P.rem_ptr[r];
+            wcost[w] += kRowCost + (P.nseg[r] ? P.nseg[r] : L);
+            add_segments(r);
+        }
+    }
+    P.win_order.resize(W);
+    for (int64_t w = 0; w < W; ++w) P.win_order[w] = (int32_t)w;
+    if (o.win_sched == 1)
+        std::stable_sort(P.win_order.begin(), P.win_order.end(),
+                         [&](int32_t a, int32_t b) { return wcost[a] > wcost[b]; });
+
+}
+
 spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
                             const spmm_opts &o, HostPlan &P, std::string &err) {
     auto t_start = std::chrono::steady_clock::now();
@@ -424,7 +521,7 @@ spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_
     const int64_t m = A->m, k = A->k, nnz = A->nnz;
     const int64_t *rowptr = A->rowptr;
     const int32_t *colidx = A->colidx;
-    const int H = o.window_h, kt = o.kt, S = o.seg_len;
+    const int H = o.window_h, kt = o.kt;
     const int sval = dtype_size(A->val_type);
     const uint8_t *vbytes = static_cast<const uint8_t *>(A->vals);
 
@@ -609,7 +706,6 @@ spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_
             out = StageOut();
         }
     }
-    const int64_t W = (int64_t)P.windows.size() / H;
 
     // ---- remainder (CSR order per row) ----
     // Row ranges run on threads: each counts its rows' remainder entries, a
@@ -711,90 +807,7 @@ spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_
         P.k_ref = kr;
     }
 
-    // ---- vector rows, segments ----
-    std::vector<uint8_t> covered(m, 0);
-    for (int32_t r : P.windows)
-        if (r >= 0) covered[r] = 1;
-    for (int64_t r = 0; r < m; ++r)
-        if (!covered[r]) P.vector_rows.push_back((int32_t)r);
-    P.identity_rows = (int64_t)P.vector_rows.size() == m;
-    P.nseg.assign(m, 0);
-    for (int64_t r = 0; r < m; ++r) {
-        int64_t L = P.rem_ptr[r + 1] - P.rem_ptr[r];
-        if (L > S) P.nseg[r] = (int32_t)((L + S - 1) / S);
-    }
-    auto add_segments = [&](int32_t r) {
-        for (int32_t j = 0; j < P.nseg[r]; ++j) {
-            int64_t b = P.rem_ptr[r] + (int64_t)j * S;
-            int64_t e = std::min<int64_t>(b + S, P.rem_ptr[r + 1]);
-            P.seg_row.push_back(r);
-            P.seg_begin.push_back((int32_t)b);
-            P.seg_end.push_back((int32_t)e);
-        }
-    };
-
-    // vector items: consecutive vector rows with balanced cost (Sec. 7).  Row i
-    // (in vector-row order) belongs to item floor(c_i / item_cost), c_i the
-    // summed cost of the rows before it (empty items dropped): a rule of prefix
-    // sums, so a device-side builder reproduces it exactly.
-    P.vitem_ptr.push_back(0);
-    {
-        int64_t before = 0, bucket = -1;
-        const int64_t nv = (int64_t)P.vector_rows.size();
-        for (int64_t i = 0; i < nv; ++i) {
-            int32_t r = P.vector_rows[i];
-            int64_t L = P.rem_ptr[r + 1] - P.rem_ptr[r];
-            const int64_t b = before / o.item_cost;
-            if (i > 0 && b != bucket) P.vitem_ptr.push_back((int32_t)i);
-            bucket = b;
-            before += kRowCost + (P.nseg[r] ? P.nseg[r] : L);
-        }
-        if (nv > 0) P.vitem_ptr.push_back((int32_t)nv);
-        // the size-class variant takes each item's rows longest first, so that
-        // rows of one size class are packed side by side; split rows go last
-        if (o.pipeline == 3 && nv > 0) {
-            P.vexec = P.vector_rows;
-            auto key = [&](int32_t r) -> int64_t {
-                return P.nseg[r] ? -1 : P.rem_ptr[r + 1] - P.rem_ptr[r];
-            };
-            for (size_t it = 0; it + 1 < P.vitem_ptr.size(); ++it)
-                std::stable_sort(P.vexec.begin() + P.vitem_ptr[it], P.vexec.begin() + P.vitem_ptr[it + 1],
-                                 [&](int32_t a, int32_t b) { return key(a) > key(b); });
-        }
-        const std::vector<int32_t> &order = P.vexec.empty() ? P.vector_rows : P.vexec;
-        for (size_t it = 0; it + 1 < P.vitem_ptr.size(); ++it) {
-            P.vitem_seg.push_back((int32_t)P.seg_row.size());
-            for (int32_t i = P.vitem_ptr[it]; i < P.vitem_ptr[it + 1]; ++i) add_segments(order[i]);
-        }
-    }
-    // windows: segment ids in slot order; launch order by window id or heaviest first
-    std::vector<int64_t> wcost(W, 0);
-    P.win_part.push_back(0);
-    for (int64_t w = 0; w < W; ++w) {
-        P.win_seg.push_back((int32_t)P.seg_row.size());
-        const int32_t ta = P.win_tile_ptr[w], tb = P.win_tile_ptr[w + 1];
-        // tiles beyond the first kWinTiles become partial items of kWinTiles each
-        for (int32_t t = ta + kWinTiles; t < tb; t += kWinTiles) {
-            P.wpart_win.push_back((int32_t)w);
-            P.wpart_t0.push_back(t);
-            P.wpart_t1.push_back(std::min(t + kWinTiles, tb));
-        }
-        P.win_part.push_back((int32_t)P.wpart_win.size());
-        wcost[w] = (int64_t)std::min(tb - ta, kWinTiles) * kt +
-                   (int64_t)(P.win_part[w + 1] - P.win_part[w]) * H;
-        for (int s = 0; s < H; ++s) {
-            int32_t r = P.windows[w * H + s];
-            if (r < 0) continue;
-            int64_t L = P.rem_ptr[r + 1] - P.rem_ptr[r];
-            wcost[w] += kRowCost + (P.nseg[r] ? P.nseg[r] : L);
-            add_segments(r);
-        }
-    }
-    P.win_order.resize(W);
-    for (int64_t w = 0; w < W; ++w) P.win_order[w] = (int32_t)w;
-    if (o.win_sched == 1)
-        std::stable_sort(P.win_order.begin(), P.win_order.end(),
-                         [&](int32_t a, int32_t b) { return wcost[a] > wcost[b]; });
+    build_schedule(P);
 
     derive_exec_tables(P);
 

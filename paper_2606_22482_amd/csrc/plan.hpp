@@ -102,6 +102,11 @@ void plan_path_work(const HostPlan &P, double *w_vec, double *w_tile, double *w_
 spmm_status build_host_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
                             const spmm_opts &o, HostPlan &P, std::string &err);
 
+// The schedule of a partitioned plan (P.opts, m, windows, win_tile_ptr and
+// rem_ptr set): vector rows, segments, vector items, window segment ids,
+// window partial items and the window launch order (Sec. 7).
+void build_schedule(HostPlan &P);
+
 // The tables of co-scheduled execution: which window each segment's row
 // belongs to, and a slot for every window whose result needs other items
 // (partial tiles beyond its first kWinTiles, or rows split into segments).

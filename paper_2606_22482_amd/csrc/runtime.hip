@@ -80,11 +80,13 @@ namespace {
 struct Arena {
     std::vector<std::pair<const void *, size_t>> parts;
     std::vector<size_t> offs;
+    std::vector<uint8_t> on_device;  // the part's source is device memory
     size_t total = 0;
-    size_t add(const void *p, size_t bytes) {
+    size_t add(const void *p, size_t bytes, bool dev = false) {
         total = (total + 255) & ~size_t(255);
         offs.push_back(total);
         parts.push_back({p, bytes});
+        on_device.push_back(dev ? 1 : 0);
         total += bytes + 16;
         return parts.size() - 1;
     }
@@ -147,7 +149,10 @@ extern "C" spmm_status spmm_plan_build(const spmm_csr *A, int32_t n, int32_t b_t
     }
 }
 
-extern "C" spmm_status spmm_plan_upload(spmm_plan_t *p) {
+namespace spmm {
+// The plan's one device allocation, from its host arrays or, for the arrays
+// `da` names, from device memory (a plan partitioned on the device).
+spmm_status upload_plan(spmm_plan_t *p, const DeviceArrays *da) {
     if (!p) return set_error(SPMM_ERR_INVALID, "plan is null");
     if (p->dev) return SPMM_OK;
     try {
@@ -156,8 +161,9 @@ extern "C" spmm_status spmm_plan_upload(spmm_plan_t *p) {
         std::vector<int32_t> win_tile_ptr32(h.win_tile_ptr.begin(), h.win_tile_ptr.end());
         std::vector<int32_t> tile_val_ptr32(h.tile_val_ptr.begin(), h.tile_val_ptr.end());
         const size_t i_rem_ptr = add_vec(a, h.rem_ptr32);
-        const size_t i_rem_col = add_vec(a, h.rem_col);
-        const size_t i_rem_val = add_vec(a, h.rem_val);
+        const size_t i_rem_col = da ? a.add(da->rem_col, 4 * da->nrem, true) : add_vec(a, h.rem_col);
+        const size_t i_rem_val = da ? a.add(da->rem_val, da->nrem * (size_t)dtype_size(h.val_type), true)
+                                    : add_vec(a, h.rem_val);
         const size_t i_vec_rows = add_vec(a, h.vexec.empty() ? h.vector_rows : h.vexec);
         const size_t i_vitem_ptr = add_vec(a, h.vitem_ptr);
         const size_t i_vitem_seg = add_vec(a, h.vitem_seg);
@@ -175,7 +181,9 @@ extern "C" spmm_status spmm_plan_upload(spmm_plan_t *p) {
         // own slot and a row's partials are summed in segment order, so C does
         // not depend on it.
         std::vector<int32_t> seg_order(h.seg_begin.size());
-        {
+        if (da) {
+            seg_order = da->seg_order;  // computed from the device copy of the columns
+        } else {
             std::vector<int32_t> key(h.seg_begin.size());
             for (size_t i = 0; i < key.size(); ++i) {
                 seg_order[i] = (int32_t)i;
@@ -188,10 +196,12 @@ extern "C" spmm_status spmm_plan_upload(spmm_plan_t *p) {
             if (id) seg_order.clear();
         }
         const size_t i_seg_order = add_vec(a, seg_order);
-        const size_t i_tile_cols = add_vec(a, h.tile_cols);
-        const size_t i_tile_bitmap = add_vec(a, h.tile_bitmap);
+        const size_t nt = h.tile_window.size();
+        const size_t i_tile_cols = da ? a.add(da->tile_cols, 4 * nt * h.opts.kt, true) : add_vec(a, h.tile_cols);
+        const size_t i_tile_bitmap =
+            da ? a.add(da->tile_bitmap, 4 * nt * h.opts.window_h, true) : add_vec(a, h.tile_bitmap);
         const size_t i_tile_val_ptr = add_vec(a, tile_val_ptr32);
-        const size_t i_tile_vals = add_vec(a, h.tile_vals);
+        const size_t i_tile_vals = da ? a.add(da->tile_vals, 2 * da->nvals, true) : add_vec(a, h.tile_vals);
         const size_t i_win_part = add_vec(a, h.win_part);
         const size_t i_wpart_win = add_vec(a, h.wpart_win);
         const size_t i_wpart_t0 = add_vec(a, h.wpart_t0);
@@ -207,7 +217,8 @@ extern "C" spmm_status spmm_plan_upload(spmm_plan_t *p) {
 
         std::vector<uint8_t> image(total, 0);
         for (size_t i = 0; i < a.parts.size(); ++i)
-            if (a.parts[i].second) std::memcpy(image.data() + a.offs[i], a.parts[i].first, a.parts[i].second);
+            if (a.parts[i].second && !a.on_device[i])
+                std::memcpy(image.data() + a.offs[i], a.parts[i].first, a.parts[i].second);
 
         int dev = 0;
         SPMM_TRY_HIP(hipGetDevice(&dev), "hipGetDevice");
@@ -215,6 +226,10 @@ extern "C" spmm_status spmm_plan_upload(spmm_plan_t *p) {
         hipError_t e = hipMalloc(&d, total);
         if (e != hipSuccess) return set_error(SPMM_ERR_OOM, std::string("hipMalloc(plan): ") + hipGetErrorString(e));
         e = hipMemcpy(d, image.data(), total, hipMemcpyHostToDevice);
+        for (size_t i = 0; i < a.parts.size() && e == hipSuccess; ++i)
+            if (a.parts[i].second && a.on_device[i])
+                e = hipMemcpy(static_cast<uint8_t *>(d) + a.offs[i], a.parts[i].first, a.parts[i].second,
+                              hipMemcpyDeviceToDevice);
         if (e != hipSuccess) {
             (void)hipFree(d);
             return hip_error(e, "hipMemcpy(plan)");
@@ -271,6 +286,9 @@ extern "C" spmm_status spmm_plan_upload(spmm_plan_t *p) {
         return set_error(SPMM_ERR_OOM, "host allocation failed while uploading");
     }
 }
+}  // namespace spmm
+
+extern "C" spmm_status spmm_plan_upload(spmm_plan_t *p) { return upload_plan(p, nullptr); }
 
 extern "C" spmm_status spmm_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
                                  const spmm_opts *opts, spmm_plan_t **out) {
@@ -328,6 +346,7 @@ extern "C" spmm_status spmm_plan_destroy(spmm_plan_t *p) {
     if (!p) return SPMM_OK;
     if (p->busy.load() > 0) return set_error(SPMM_ERR_BUSY, "plan has unfinished submissions");
     if (p->dev) (void)hipFree(p->dev);
+    if (p->aux) (void)hipFree(p->aux);
     delete p;
     return SPMM_OK;
 }
@@ -351,6 +370,32 @@ namespace spmm {
 spmm_status ensure_host_remainder(spmm_plan_t *p) {
     std::lock_guard<std::mutex> lk(p->host_mu);
     HostPlan &h = p->hp;
+    if (p->aux && !p->host_views) {
+        // partitioned on the device: the remainder, the tiles and the CSR
+        // entry of each of their values
+        const size_t nrem = (size_t)p->dev_nrem, nv = (size_t)p->dev_nvals, nt = h.tile_window.size();
+        const size_t sval = (size_t)dtype_size(h.val_type);
+        h.rem_col.resize(nrem);
+        h.rem_val.resize(nrem * sval);
+        h.tile_cols.resize(nt * h.opts.kt);
+        h.tile_bitmap.resize(nt * h.opts.window_h);
+        h.tile_vals.resize(nv);
+        std::vector<int32_t> rs(nrem), ts(nv);
+        auto d2h = [](void *dst, const void *src, size_t bytes) {
+            return bytes ? hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost) : hipSuccess;
+        };
+        SPMM_TRY_HIP(d2h(h.rem_col.data(), p->dp.rem_col, 4 * nrem), "hipMemcpy(plan)");
+        SPMM_TRY_HIP(d2h(h.rem_val.data(), p->dp.rem_val, sval * nrem), "hipMemcpy(plan)");
+        SPMM_TRY_HIP(d2h(h.tile_cols.data(), p->dp.tile_cols, 4 * h.tile_cols.size()), "hipMemcpy(plan)");
+        SPMM_TRY_HIP(d2h(h.tile_bitmap.data(), p->dp.tile_bitmap, 4 * h.tile_bitmap.size()), "hipMemcpy(plan)");
+        SPMM_TRY_HIP(d2h(h.tile_vals.data(), p->dp.tile_vals, 2 * nv), "hipMemcpy(plan)");
+        SPMM_TRY_HIP(d2h(rs.data(), p->aux, 4 * nrem), "hipMemcpy(plan)");
+        SPMM_TRY_HIP(d2h(ts.data(), static_cast<const int32_t *>(p->aux) + nrem, 4 * nv), "hipMemcpy(plan)");
+        h.rem_src.assign(rs.begin(), rs.end());
+        h.tile_src.assign(ts.begin(), ts.end());
+        p->host_views = true;
+        return SPMM_OK;
+    }
     if (!p->rem_device_only || (int64_t)h.rem_col.size() == h.nnz) return SPMM_OK;
     const size_t n = (size_t)h.nnz, sval = (size_t)dtype_size(h.val_type);
     h.rem_col.resize(n);
@@ -373,8 +418,9 @@ extern "C" spmm_status spmm_plan_stats(const spmm_plan_t *p, spmm_plan_stats_t *
     out->opts = h.opts;
     out->windows = (int64_t)h.win_order.size();
     out->tiles = (int64_t)h.tile_window.size();
-    out->nnz_tiles = (int64_t)h.tile_src.size();
-    out->nnz_remainder = p->rem_device_only ? h.nnz : (int64_t)h.rem_src.size();
+    const bool dev_parts = p->aux != nullptr;  // tiles and remainder partitioned on the device
+    out->nnz_tiles = dev_parts ? p->dev_nvals : (int64_t)h.tile_src.size();
+    out->nnz_remainder = dev_parts ? p->dev_nrem : p->rem_device_only ? h.nnz : (int64_t)h.rem_src.size();
     out->vector_rows = (int64_t)h.vector_rows.size();
     out->segments = (int64_t)h.seg_row.size();
     out->vector_items = (int64_t)h.vitem_ptr.size() - 1;
@@ -389,7 +435,7 @@ extern "C" spmm_status spmm_plan_stats(const spmm_plan_t *p, spmm_plan_stats_t *
     out->flops = 2.0 * (double)h.nnz * (double)h.n;
     out->plan_ms = h.plan_ms;
     out->uploaded = p->dev != nullptr;
-    out->tol_class = (!h.tile_src.empty() && (h.val_type == SPMM_F32 || h.b_type == SPMM_F32))
+    out->tol_class = (out->nnz_tiles > 0 && (h.val_type == SPMM_F32 || h.b_type == SPMM_F32))
                          ? SPMM_TOL_ROUNDED16
                          : SPMM_TOL_FP32;
     plan_path_work(h, &out->work_vec, &out->work_tile, &out->work_winrem);

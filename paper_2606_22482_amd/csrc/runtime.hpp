@@ -6,6 +6,7 @@
 #include <atomic>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "devplan.hpp"
 #include "plan.hpp"
@@ -20,10 +21,33 @@ struct spmm_plan_s {
     // built on the device: the remainder columns and values live only in the
     // device allocation until a host view is asked for (export, serialize)
     bool rem_device_only = false;
+    // partitioned on the device (mixed plans): the CSR entry of every
+    // remainder entry and then of every packed tile value (int32), kept for
+    // host views; the remainder and tile arrays live only in `dev`
+    void *aux = nullptr;
+    int64_t dev_nrem = 0, dev_nvals = 0;
+    bool host_views = false;  // the device-only arrays have been copied to hp
     std::mutex host_mu;
 };
 
 namespace spmm {
+// Arrays of a plan partitioned on the device, uploaded device to device.
+struct DeviceArrays {
+    const void *rem_col = nullptr, *rem_val = nullptr;     // [nrem]
+    const void *tile_cols = nullptr, *tile_bitmap = nullptr;  // [T * kt], [T * H]
+    const void *tile_vals = nullptr;                        // [nvals]
+    size_t nrem = 0, nvals = 0;
+    std::vector<int32_t> seg_order;  // launch order of the segments (empty: id order)
+};
+spmm_status upload_plan(spmm_plan_t *p, const DeviceArrays *da);
+// Device builders (devbuild.hip): exclusive (inclusive != 0: inclusive) scan of
+// n int64 values; `sums` holds ceil(n / 2048) + 1 values, its last the total.
+hipError_t scan64(const int64_t *in, int64_t *out, int64_t n, int inclusive, int64_t *sums,
+                  hipStream_t s);
+int64_t scan_sums_len(int64_t n);
+// The mixed plan (original-ranges windows) built on the device (devmixed.hip).
+spmm_status plan_device_mixed(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
+                              const spmm_opts &o, hipStream_t s, spmm_plan_t **out);
 spmm_status set_error(spmm_status s, const std::string &msg);
 spmm_status hip_error(hipError_t e, const char *what);
 // What one run on a stream uses besides the plan: the stream's workspace (at

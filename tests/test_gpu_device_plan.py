@@ -1,6 +1,8 @@
-"""Plain plans built on the device (spmm_plan_device) from a CSR in device
-memory equal the host builder's plans array for array, run to the same C bit
-for bit, and a malformed device CSR is refused by the device-side checks."""
+"""Plans built on the device (spmm_plan_device) from a CSR in device memory --
+plain plans, and mixed plans with original-ranges windows (the column stage,
+K-tiles, density test, bitmaps and packed values computed on the device) --
+equal the host builder's plans array for array, run to the same C bit for
+bit, and a malformed device CSR is refused by the device-side checks."""
 import ctypes as C
 
 import numpy as np
@@ -129,5 +131,124 @@ def test_device_checks_refuse_a_bad_csr():
     bad_ci = ci.clone()
     bad_ci[7] = A.k                                    # column out of range
     assert _status(rp, bad_ci, vt, A.m, A.k) == (L.SPMM_ERR_INVALID, "column index out of range")
-    st, _ = _status(rp, ci, vt, A.m, A.k, api.default_opts(mode="mixed"))
+    # mixed plans are built with original-ranges windows only
+    st, _ = _status(rp, ci, vt, A.m, A.k, api.default_opts(mode="mixed", row_order="length_sorted"))
     assert st == L.SPMM_ERR_UNSUPPORTED
+    assert _status(rp, ci, vt, A.m, A.k, api.default_opts(mode="mixed"))[0] == L.SPMM_OK
+
+
+MIXED_KEYS = ("windows", "tile_window", "tile_cols", "tile_bitmap", "tile_val_ptr", "tile_vals",
+              "tile_src", "rem_ptr", "rem_src", "vector_rows", "nseg", "vitem_ptr", "vitem_seg",
+              "vexec_rows", "seg_row", "seg_begin", "seg_end", "win_seg", "win_order", "rem_col_dev",
+              "win_part", "wpart_win", "wpart_t0", "wpart_t1", "seg_win", "win_dep", "win_nsseg")
+MIXED_STATS = ("windows", "tiles", "nnz_tiles", "nnz_remainder", "vector_rows", "segments",
+               "vector_items", "k_ref", "workspace_bytes", "algorithmic_bytes", "tol_class")
+
+
+def _compare_mixed(A, n, bk, opts, case, exact_ints):
+    import torch
+    from gpu_util import TOL_16, exact
+    host = api.Plan(A, n, bk, opts)
+    rp, ci, vt = device_csr(A)
+    dev = api.Plan.on_device(rp, ci, vt, A.m, A.k, n, bk, opts)
+    sh, sd = host.stats(), dev.stats()
+    for key in MIXED_STATS:
+        assert sh[key] == sd[key], key
+    assert sh["opts"] == sd["opts"]
+    dh, dd = host.export(), dev.export()
+    assert dh["n_dep"] == dd["n_dep"]
+    for key in MIXED_KEYS:
+        assert np.array_equal(dh[key], dd[key]), key
+    if A.m == 0:
+        return sh
+    if exact_ints:
+        B = synth.int_dense(case, (A.k, n), -8, 8, kind=bk)
+    else:
+        B = synth.dense_values(np.random.default_rng(case), (A.k, n), bk)
+    Bd = device_B(B, bk)
+    C1, C2 = device_C(A.m, n), device_C(A.m, n)
+    host.run(Bd, C1)
+    dev.run(Bd, C2)
+    torch.cuda.synchronize()
+    assert torch.equal(C1, C2)
+    if exact_ints:
+        exact(C2, A, B, bk)
+    else:
+        parity(C2, A, B, bk, TOL_16)
+    q = api.Plan.deserialize(dev.serialize())
+    C3 = device_C(A.m, n)
+    q.run(Bd, C3)
+    torch.cuda.synchronize()
+    assert torch.equal(C1, C3)
+    return sh
+
+
+def _int_vals(A, seed):
+    v = np.random.default_rng(seed).integers(-2, 3, A.nnz).astype(np.float32)
+    A.vals = v if A.val_kind == "f32" else (synth.to_bf16_bits(v) if A.val_kind == "bf16"
+                                            else synth.to_f16_bits(v))
+    return A
+
+
+MIXED_CASES = [
+    # block community, bf16 values and B: dense windows, every tile kept
+    ("block", "bf16", "bf16", 256, dict(mode="mixed")),
+    # f32 values and B: tiles round both to bf16
+    ("block", "f32", "f32", 96, dict(mode="mixed", window_h=32)),
+    # duplicates and empty rows, low thresholds: repeated pairs, sparse tiles demoted
+    ("random", "f32", "bf16", 64, dict(mode="mixed", t_row=2, alpha_c=1 / 16, alpha=0.05, seg_len=9)),
+    # every row in a window, every column in a tile
+    ("graph", "f16", "f16", 40, dict(mode="mfma_only", window_h=64, seg_len=33)),
+    # windows of hundreds of tiles (partial items) and split remainders
+    ("wide", "bf16", "bf16", 160, dict(mode="mixed", window_h=16, t_row=-1, alpha_c=0.0, alpha=0.2,
+                                       seg_len=40)),
+    # no tile dense enough: every window dissolves into vector rows
+    ("graph", "f32", "f32", 32, dict(mode="mixed", alpha=2.0)),
+]
+
+
+def _mixed_matrix(kind, vk, seed):
+    if kind == "block":
+        A, _ = synth.block_community(n=8192, band=8, n_cols=8, seed=seed, val_kind=vk)
+        return A
+    if kind == "random":
+        return synth.random_csr(3001, 2000, 0.01, seed, val_kind=vk, dup_frac=0.1, empty_rows=0.2)
+    if kind == "wide":
+        return synth.random_csr(300, 9000, 0.2, seed, val_kind=vk)
+    return synth.chung_lu_graph(6000, 2.1, 14.0, 1500.0, seed, val_kind=vk, values="uniform")
+
+
+@pytest.mark.parametrize("case", range(len(MIXED_CASES)))
+def test_device_mixed_plan_equals_host_plan(case):
+    kind, vk, bk, n, kw = MIXED_CASES[case]
+    A = _int_vals(_mixed_matrix(kind, vk, 40 + case), case)
+    print("case", case, kind, vk, bk, n, kw, flush=True)
+    sh = _compare_mixed(A, n, bk, api.default_opts(**kw), case, exact_ints=True)
+    if case < 5:
+        assert sh["tiles"] > 0
+    else:
+        assert sh["tiles"] == 0 and sh["windows"] == 0
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_device_mixed_plan_random(seed):
+    """Seeded random shapes, types and mixed-plan options (window height, row
+    and column thresholds, tile density, segment length, variants, launch
+    forms): device plan = host plan array for array, same C bit for bit,
+    integer-exact against the oracle."""
+    r = np.random.default_rng(900 + seed)
+    vk, bk = [("f32", "f32"), ("f32", "bf16"), ("bf16", "bf16"), ("f16", "f16")][r.integers(4)]
+    m = int(r.choice([1, 17, int(r.integers(2, 5000))]))
+    k = int(r.choice([1, 31, int(r.integers(2, 3000))]))
+    A = synth.random_csr(m, k, float(r.choice([0.005, 0.02, 0.08, 0.2])), 950 + seed, val_kind=vk,
+                         int_values=(-2, 2), dup_frac=float(r.choice([0.0, 0.05])),
+                         empty_rows=float(r.choice([0.0, 0.3])))
+    H = int(r.choice([16, 32, 64]))
+    n = int(r.choice([1, 8, 33, 64, 128, 256, int(r.integers(1, 300))]))
+    kw = dict(mode=str(r.choice(["mixed", "mixed", "mfma_only"])), window_h=H,
+              t_row=int(r.choice([-1, 0, 2, 8])), alpha_c=float(r.choice([0.0, 1.0 / H, 2.0 / H])),
+              alpha=float(r.choice([0.0, 0.02, 0.1, 0.5])), seg_len=int(r.choice([3, 17, 64, 256])),
+              pipeline=int(r.integers(0, 4)), win_sched=int(r.integers(0, 2)),
+              exec=int(r.choice([1, 2, 3])))
+    print("case", seed, vk, bk, m, k, n, kw, flush=True)
+    _compare_mixed(A, n, bk, api.default_opts(**kw), seed, exact_ints=True)
