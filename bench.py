@@ -228,7 +228,8 @@ def serve_bench(args):
     from paper_2606_22482_amd import serve, synth
     t0 = time.perf_counter()
     pool = synth.serving_pool(n_graphs=args.pool_graphs, n_masks=args.pool_masks, seed=5,
-                              max_rows=args.max_rows, max_mask_rows=args.max_mask_rows)
+                              max_rows=args.max_rows, max_mask_rows=args.max_mask_rows,
+                              device_masks=True)
     log("serving pool: %d matrices, %.1f M nnz (%.1f s)"
         % (len(pool), sum(p["A"].nnz for p in pool) / 1e6, time.perf_counter() - t0))
     reqs = synth.serving_requests(args.requests, len(pool), args.pool_graphs, seed=5)
@@ -251,6 +252,8 @@ def serve_bench(args):
     return {"workload": "serving_stream", "requests": args.requests, "rate_req_s": round(rate, 2),
             "pool": len(pool), "max_rows": args.max_rows, "max_mask_rows": args.max_mask_rows,
             "streams": args.streams, "budget_GB": 200,
+            "largest_mask_rows": max((p["A"].m for p in pool if p["kind"] == "mask"), default=0),
+            "largest_mask_nnz": max((p["A"].nnz for p in pool if p["kind"] == "mask"), default=0),
             "p50_ms": round(s["p50_ms"], 3), "p99_ms": round(s["p99_ms"], 3),
             "throughput_req_s": round(s["throughput_req_s"], 2), "gflops": round(s["gflops"], 1),
             "rejected": s["rejected"], "mean_batch": round(s["mean_batch"], 2),
@@ -473,7 +476,9 @@ def main():
     ap.add_argument("--pool-graphs", type=int, default=64)
     ap.add_argument("--pool-masks", type=int, default=16)
     ap.add_argument("--max-rows", type=int, default=500000)
-    ap.add_argument("--max-mask-rows", type=int, default=8192)
+    ap.add_argument("--max-mask-rows", type=int, default=140000,
+                    help="attention masks have rows log-uniform in [1e3, this]; built and planned on "
+                         "the device (1.4e5 rows: about 2e9 entries, the 32-bit entry-index limit)")
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--max-batch", type=int, default=64)
     ap.add_argument("--batch-count", type=int, default=512)

@@ -105,7 +105,12 @@ class PlanCache:
             return self.plans[key][0]
         mid, n, b_kind = key
         A = self.pool[mid]["A"]
-        plan = api.Plan(A, n, b_kind, self.opts_for(self.pool[mid], n, b_kind))
+        opts = self.opts_for(self.pool[mid], n, b_kind)
+        if hasattr(A, "host_rows"):
+            # a matrix held on the device: the plan is built there (spmm_plan_device)
+            plan = api.Plan.on_device(A.rowptr, A.colidx, A.vals, A.m, A.k, n, b_kind, opts)
+        else:
+            plan = api.Plan(A, n, b_kind, opts)
         self.plans[key] = (plan, plan.stats()["device_bytes"])
         stats.plan_builds += 1
         return plan
@@ -130,10 +135,12 @@ class PlanCache:
 
 
 def default_opts_for(item, n, b_kind):
-    """Plan options per matrix kind: block masks use aligned windows (their
-    64x64 blocks fill 16-row windows), graphs the tuned/heuristic default."""
+    """Plan options per matrix kind: block masks use aligned windows of 64
+    rows (one window per 64-row block-row, whose dense 64x64 blocks fill its
+    tiles, so each block-row stages its B rows once), graphs the
+    tuned/heuristic default."""
     if item["kind"] == "mask":
-        return api.default_opts(mode="mixed", row_order="original_ranges")
+        return api.default_opts(mode="mixed", row_order="original_ranges", window_h=64)
     return api.default_opts(mode="auto")
 
 

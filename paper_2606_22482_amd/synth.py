@@ -348,11 +348,119 @@ def attention_mask(rows: int, block=64, block_density=0.1, band=512, seed=0, val
     return CSR(rows, rows, rowptr, cc.astype(np.int32), vals, val_kind)
 
 
-def serving_pool(n_graphs=64, n_masks=16, seed=5, max_rows=500000, max_mask_rows=16384):
+class DeviceCSR:
+    """A CSR held in torch tensors (``rowptr`` int64, ``colidx`` int32,
+    ``vals``) on one device, with the host CSR's size attributes."""
+
+    def __init__(self, m, k, rowptr, colidx, vals, val_kind):
+        self.m, self.k = int(m), int(k)
+        self.rowptr, self.colidx, self.vals, self.val_kind = rowptr, colidx, vals, val_kind
+
+    @property
+    def nnz(self) -> int:
+        return int(self.colidx.numel())
+
+    def host_rows(self, rows):
+        """A host CSR of the given rows only (in that order), for checks."""
+        import torch
+        rp = self.rowptr.cpu().numpy()
+        rows = np.asarray(rows, dtype=np.int64)
+        lens = rp[rows + 1] - rp[rows]
+        rowptr = np.zeros(rows.size + 1, dtype=np.int64)
+        np.cumsum(lens, out=rowptr[1:])
+        idx = torch.from_numpy(np.concatenate([np.arange(rp[r], rp[r + 1]) for r in rows])
+                               if rows.size else np.zeros(0, np.int64)).to(self.colidx.device)
+        cols = self.colidx[idx].cpu().numpy()
+        v = self.vals[idx].cpu()
+        if self.val_kind == "f32":
+            vals = v.numpy().astype(np.float32)
+        else:
+            vals = v.view(torch.int16).numpy().view(np.uint16)
+        return CSR(int(rows.size), self.k, rowptr, cols.astype(np.int32), vals, self.val_kind)
+
+
+def attention_mask_device(rows: int, block=64, block_density=0.1, band=512, seed=0, val_kind="f32",
+                          device="cuda", chunk_entries=1 << 27):
+    """attention_mask's structure built with torch on ``device`` (the same
+    block draws from the same seed, so the same rows and columns), for masks
+    too large to build on the host: every row's columns are the union of its
+    block-row's dense blocks and the sliding window, laid out as sorted
+    intervals and expanded chunk by chunk.  Values U(0,1) from torch's
+    generator on the device (not attention_mask's values).  Returns a
+    DeviceCSR."""
+    import torch
+    r_blk, _ = _rngs(seed, 2)
+    nb = (rows + block - 1) // block
+    per = max(1, int(math.ceil(block_density * nb)))
+    bj = np.stack([np.sort(r_blk.choice(nb, size=per, replace=False)) for _ in range(nb)])
+    dev = torch.device(device)
+    bjt = torch.from_numpy(bj.astype(np.int64)).to(dev)                       # nb x per
+    present = torch.zeros((nb, nb), dtype=torch.bool, device=dev)
+    present.scatter_(1, bjt, True)
+    half = band // 2
+    ncand = band // block + 2                                                   # block columns a window touches
+    # row lengths and, per row, its sorted intervals [start, end)
+    def intervals(r0, r1):
+        rr = torch.arange(r0, r1, device=dev)
+        bi = rr // block
+        ps = bjt[bi] * block                                                    # R x per
+        pe = torch.clamp(ps + block, max=rows)
+        lo = torch.clamp(rr - half, min=0)
+        hi = torch.clamp(rr + half, max=rows)
+        cb = (lo // block)[:, None] + torch.arange(ncand, device=dev)[None, :]  # R x ncand
+        cs = torch.maximum(lo[:, None], cb * block)
+        ce = torch.minimum(hi[:, None], cb * block + block)
+        inb = cb < nb
+        pres = torch.zeros_like(inb)
+        pres[inb] = present[bi[:, None].expand_as(cb)[inb], cb[inb]]
+        ok = inb & (cs < ce) & ~pres
+        cs = torch.where(ok, cs, torch.full_like(cs, rows))                      # invalid: empty, sorted last
+        ce = torch.where(ok, ce, torch.full_like(ce, rows))
+        st = torch.cat([ps, cs], dim=1)
+        en = torch.cat([pe, ce], dim=1)
+        order = torch.argsort(st, dim=1, stable=True)
+        st = torch.gather(st, 1, order)
+        en = torch.gather(en, 1, order)
+        return st, en
+    lens = torch.zeros(rows, dtype=torch.int64, device=dev)
+    step = max(1, chunk_entries // (per * block + band))
+    for r0 in range(0, rows, step):
+        st, en = intervals(r0, min(rows, r0 + step))
+        lens[r0:r0 + st.shape[0]] = (en - st).sum(dim=1)
+    rowptr = torch.zeros(rows + 1, dtype=torch.int64, device=dev)
+    rowptr[1:] = torch.cumsum(lens, 0)
+    nnz = int(rowptr[-1])
+    colidx = torch.empty(nnz, dtype=torch.int32, device=dev)
+    for r0 in range(0, rows, step):
+        st, en = intervals(r0, min(rows, r0 + step))
+        ln = (en - st).reshape(-1)
+        s0 = st.reshape(-1)
+        keep = ln > 0
+        ln, s0 = ln[keep], s0[keep]
+        total = int(ln.sum())
+        if total == 0:
+            continue
+        off = torch.cumsum(ln, 0) - ln
+        col = torch.repeat_interleave(s0 - off, ln) + torch.arange(total, device=dev)
+        b = int(rowptr[r0])
+        colidx[b:b + total] = col.to(torch.int32)
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed * 7 + 3)
+    vals = torch.rand(nnz, generator=g, device=dev, dtype=torch.float32)
+    if val_kind == "bf16":
+        vals = vals.to(torch.bfloat16)
+    elif val_kind == "f16":
+        vals = vals.to(torch.float16)
+    return DeviceCSR(rows, rows, rowptr, colidx, vals, val_kind)
+
+
+def serving_pool(n_graphs=64, n_masks=16, seed=5, max_rows=500000, max_mask_rows=16384,
+                 device_masks=False):
     """Resident matrices the serving stream draws from: power-law graphs
     (Chung-Lu exponent 2.1, mean degree 16, rows log-uniform in [1e3,
     max_rows]) and block-sparse attention masks (rows log-uniform in [1e3,
-    max_mask_rows]), values in f32.  Returns a list of dicts."""
+    max_mask_rows]; with ``device_masks`` built on the GPU as DeviceCSR),
+    values in f32.  Returns a list of dicts."""
     (r,) = _rngs(seed, 1)
     pool = []
     for g in range(n_graphs):
@@ -361,7 +469,10 @@ def serving_pool(n_graphs=64, n_masks=16, seed=5, max_rows=500000, max_mask_rows
         pool.append({"kind": "graph", "A": A})
     for k in range(n_masks):
         rows = int(round(math.exp(r.uniform(math.log(1000), math.log(max_mask_rows)))))
-        A = attention_mask(rows, seed=seed * 104729 + k)
+        if device_masks:
+            A = attention_mask_device(rows, seed=seed * 104729 + k)
+        else:
+            A = attention_mask(rows, seed=seed * 104729 + k)
         pool.append({"kind": "mask", "A": A})
     return pool
 

@@ -82,3 +82,37 @@ def test_library_footprint_and_budget_status(pool):
     assert p.run_bytes(batched=True, budget=b_batch)[0] == L.SPMM_OK
     # wider leading dimensions count
     assert p.run_bytes(ldb=80, ldc=96, batched=True)[1] == b_batch + A.k * 16 * 4 + A.m * 32 * 4
+
+
+def test_device_mask_pool_mix_equals_solo_and_oracle():
+    """A pool with an attention mask built on the device (and planned there):
+    every request equals its solo run bit for bit; sampled rows of every
+    request match the oracle."""
+    import torch
+    pool = synth.serving_pool(n_graphs=2, n_masks=0, seed=9, max_rows=8000)
+    pool.append({"kind": "mask", "A": synth.attention_mask_device(12000, seed=31)})
+    reqs = synth.serving_requests(40, len(pool), 2, seed=9, rate=3000.0)
+    srv = serve.Server(pool, n_streams=3, max_batch=8, keep_results=True)
+    s = srv.run(reqs, realtime=True).summary()
+    assert s["completed"] == 40 and s["rejected"] == 0
+    masks = [r for r in srv.requests if pool[r.matrix]["kind"] == "mask"]
+    assert masks
+    mplan = srv.plans.plans[(masks[0].matrix, masks[0].n, masks[0].b_kind)][0]
+    assert mplan.stats()["tiles"] > 0 and mplan.stats()["opts"]["window_h"] == 64
+    rng = np.random.default_rng(4)
+    for d, r in zip(reqs, srv.requests):
+        B, C = srv.solo(d)
+        assert torch.equal(C, r.C), "request %d differs alone vs in the mix" % r.rid
+        A = pool[r.matrix]["A"]
+        plan = srv.plans.plans[(r.matrix, r.n, r.b_kind)][0]
+        tol = TOL_16 if plan.stats()["tol_class"] == 1 else TOL_F32
+        Bh = r.B.float().cpu().numpy()
+        if hasattr(A, "host_rows"):
+            rows = np.unique(np.concatenate([rng.choice(A.m, 200, replace=False), [0, A.m - 1]]))
+            Ar = A.host_rows(rows)
+            Cs, S = oracle_of(Ar, Bh, "f32")
+            err = oracle.max_normalised_error(r.C.cpu().numpy()[rows], Cs, S)
+        else:
+            Cs, S = oracle_of(A, Bh, "f32")
+            err = oracle.max_normalised_error(r.C.cpu().numpy(), Cs, S)
+        assert err <= tol, (r.rid, err, tol)
