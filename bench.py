@@ -98,10 +98,17 @@ def kernel_bytes(A, d, n, s_a, s_b):
     return out
 
 
+KERNEL_SOURCES = ("items.hpp", "kernels.hip", "fused.hip")
+
+
 def kernels_sha1():
+    """SHA-1 over the device code the counters were taken with."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_2606_22482_amd", "csrc", "kernels.hip"), "rb") as f:
-        return hashlib.sha1(f.read()).hexdigest()
+    h = hashlib.sha1()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2606_22482_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(workload, mode, kernel):
@@ -270,8 +277,8 @@ def batch_bench(args):
     """Uneven f16 matrices in one batched submission (graph replay of the
     persistent kernels) vs the same matrices as separate spmm_run calls.
     Before timing, spmm_autotune runs once per sparsity-profile key (small
-    wall budget each); plans are then built with mode AUTO, which takes the
-    tuned options from the cache."""
+    wall budget each), timing its candidates as batched executions; plans are
+    then built with mode AUTO, which takes the tuned options from the cache."""
     import torch
     from concurrent.futures import ProcessPoolExecutor, ThreadPoolExecutor
     from paper_2606_22482_amd import api, synth
@@ -290,7 +297,8 @@ def batch_bench(args):
     for i, ((A, B), (Bd, Cd)) in enumerate(zip(mats, devs)):
         key = api.spmm_profile_key(A, B.shape[1], "f16")
         if key not in keys and args.batch_tune_ms > 0:
-            opts, rep = api.spmm_autotune(A, Bd, Cd, "f16", budget_ms=args.batch_tune_ms)
+            opts, rep = api.spmm_autotune(A, Bd, Cd, "f16", budget_ms=args.batch_tune_ms,
+                                          batched=True)
             keys[key] = opts
         if i % 64 == 63:
             log("batch: tuning, %d matrices seen, %d profiles (%.1f s)"

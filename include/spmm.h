@@ -356,22 +356,35 @@ spmm_status spmm_dryrun(int32_t n, int32_t b_type, void *stream, double *p_vec, 
  * r = 1), then times candidate plans of A on the device (B, C: device buffers
  * of the run's shapes; C is overwritten) in a staged search over mode, window
  * height, row order, column/tile thresholds, segment length and N-panel width,
- * within about budget_ms of wall time.  The best options are written to *out
- * and cached under A's sparsity-profile key, so spmm_plan with
- * mode = SPMM_MODE_AUTO reuses them for matrices of the same profile. */
+ * within about budget_ms of wall time, each candidate timed the way the
+ * plan will run (context: SPMM_TUNE_RUN or SPMM_TUNE_SUBMIT; anything else is
+ * INVALID).  A winner other than the plain plan
+ * is timed again against it over 10 runs each and kept only when at least 3%
+ * faster (otherwise the plain plan's options are the result).  The options
+ * are written to *out and cached under A's sparsity-profile key, so
+ * spmm_plan with mode = SPMM_MODE_AUTO reuses them for matrices of the same
+ * profile. */
 typedef struct {
     int32_t candidates;     /* plans timed */
     int32_t reserved;
-    double default_ms;      /* run time with the library defaults */
-    double best_ms;         /* run time with *out */
+    double default_ms;      /* run time of the plain plan (the verification timing when
+                               another candidate won the search) */
+    double best_ms;         /* run time with *out (the same timing as default_ms when the
+                               plain plan is the result) */
     double alpha_cost;      /* alpha from Eq. 3 (r = 1) */
     double p_vec, p_mfma;   /* dry-run throughputs (entries*N/s, slots*N/s) */
     double search_ms;       /* wall time spent */
 } spmm_tune_report;
 
+#define SPMM_TUNE_RUN 0    /* candidates timed as spmm_run calls */
+#define SPMM_TUNE_SUBMIT 1 /* candidates timed as spmm_submit batches of copies of A (up to
+                              64, about 4M entries in all, writing the same C): the batched
+                              kernels' throughput, for plans that will run among other
+                              matrices in spmm_submit */
 spmm_status spmm_autotune(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
                           const void *B, int64_t ldb, void *C, int64_t ldc, void *stream,
-                          double budget_ms, spmm_opts *out, spmm_tune_report *report);
+                          double budget_ms, int32_t context, spmm_opts *out,
+                          spmm_tune_report *report);
 /* Sparsity-profile key of A for N and the B type: log2 sizes, the log2 row-
  * length histogram of the entries and the window co-occurrence share of a
  * sample of 16-row windows, as text.  INVALID if cap is too small. */

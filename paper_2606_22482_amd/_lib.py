@@ -20,6 +20,7 @@ KERNEL_SEGMENT, KERNEL_VECTOR, KERNEL_WINDOW = 0, 1, 2
 KERNEL_NAMES = {0: "segment", 1: "vector", 2: "window", 3: "window_partial", 4: "vector_path",
                 5: "mfma_path", 6: "one_grid"}
 EXEC_SERIAL, EXEC_TWO_GRIDS, EXEC_ONE_GRID = 1, 2, 3
+TUNE_RUN, TUNE_SUBMIT = 0, 1
 KIND_CODE = {"f32": F32, "bf16": BF16, "f16": F16}
 
 
@@ -130,7 +131,8 @@ SIGNATURES = {
     "spmm_adapt_epoch": (_S, [C.POINTER(Csr), C.POINTER(_P), _P, C.c_int64, _P, C.c_int64, _P,
                               C.c_float, C.POINTER(AdaptState)]),
     "spmm_autotune": (_S, [C.POINTER(Csr), C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64, _P,
-                           C.c_int64, _P, C.c_double, C.POINTER(Opts), C.POINTER(TuneReport)]),
+                           C.c_int64, _P, C.c_double, C.c_int32, C.POINTER(Opts),
+                           C.POINTER(TuneReport)]),
     "spmm_profile_key": (_S, [C.POINTER(Csr), C.c_int32, C.c_int32, C.c_char_p, C.c_int32]),
     "spmm_tune_cache_put": (_S, [C.c_char_p, C.POINTER(Opts)]),
     "spmm_tune_cache_get": (_S, [C.c_char_p, C.POINTER(Opts), C.POINTER(C.c_int32)]),

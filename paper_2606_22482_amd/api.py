@@ -372,17 +372,20 @@ def spmm_dryrun(n: int, b_kind: str, stream=None):
     return pv.value, pm.value
 
 
-def spmm_autotune(A, B, Cout, b_kind: str, budget_ms: float = 20000.0, stream=None):
+def spmm_autotune(A, B, Cout, b_kind: str, budget_ms: float = 20000.0, stream=None,
+                  batched: bool = False):
     """spmm_autotune: returns (opts, report dict); also caches the options
-    under A's profile key for spmm_plan(mode=AUTO)."""
+    under A's profile key for spmm_plan(mode=AUTO).  ``batched`` times the
+    candidates as spmm_submit batches of copies of A (their throughput among
+    other work, for plans that will run in batches)."""
     lib = L.load()
     csr, keep = _csr_struct(A)
     bp, ldb, cp, ldc = _operands(int(A.m), int(A.k), int(B.shape[1]), b_kind, B, Cout)
     o = L.Opts()
     rep = L.TuneReport()
     L.check(lib.spmm_autotune(C.byref(csr), int(B.shape[1]), L.KIND_CODE[b_kind], L.F32, bp, ldb,
-                              cp, ldc, _stream_handle(stream), float(budget_ms), C.byref(o),
-                              C.byref(rep)))
+                              cp, ldc, _stream_handle(stream), float(budget_ms),
+                              L.TUNE_SUBMIT if batched else L.TUNE_RUN, C.byref(o), C.byref(rep)))
     del keep
     return o, {f: getattr(rep, f) for f, _ in L.TuneReport._fields_ if f != "reserved"}
 

@@ -72,3 +72,19 @@ def test_operand_check_is_exact_at_the_boundary():
     with pytest.raises(ValueError, match="device tensor"):
         api._operands(M, K, N, "f16", B, torch.zeros(M, N))
     assert np.dtype(np.float32).itemsize == 4
+
+
+def test_autotune_context_is_validated(plans):
+    """spmm_autotune refuses a tuning context other than run or submit before
+    it touches the device."""
+    import ctypes as C
+    from paper_2606_22482_amd import _lib as L
+    A = plans[0]
+    lib = L.load()
+    csr, keep = api._csr_struct(A)
+    o, rep = L.Opts(), L.TuneReport()
+    st = lib.spmm_autotune(C.byref(csr), N, L.F32, L.F32, None, N, None, N, None, 10.0, 7,
+                           C.byref(o), C.byref(rep))
+    assert st == L.SPMM_ERR_INVALID
+    assert b"context" in lib.spmm_last_error()
+    del keep
