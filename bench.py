@@ -112,9 +112,10 @@ def kernels_sha1():
 
 
 def measured_traffic(workload, mode, kernel):
-    """HBM traffic per launch of a kernel from the committed counter summary
-    (profiles/traffic.json: FETCH_SIZE x2 + WRITE_SIZE x1, see the copy-kernel
-    calibration), only when it was taken with the current kernel source."""
+    """Traffic below L2 per launch of a kernel from the committed counter
+    summary (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE, each scaled by
+    what it reads for a copy kernel of 1 GiB), only when it was taken with the
+    current kernel sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
@@ -231,7 +232,8 @@ def parse_opts(text):
 
 def serve_bench(args):
     """Serving stream: Poisson arrivals at 0.7x the closed-loop saturation rate
-    measured on the first requests of the same list; plans pre-built (resident)."""
+    measured on the first requests of the same list (after an untimed pass
+    over 300 of them); plans pre-built (resident)."""
     from paper_2606_22482_amd import serve, synth
     t0 = time.perf_counter()
     pool = synth.serving_pool(n_graphs=args.pool_graphs, n_masks=args.pool_masks, seed=5,
@@ -240,7 +242,8 @@ def serve_bench(args):
     log("serving pool: %d matrices, %.1f M nnz (%.1f s)"
         % (len(pool), sum(p["A"].nnz for p in pool) / 1e6, time.perf_counter() - t0))
     reqs = synth.serving_requests(args.requests, len(pool), args.pool_graphs, seed=5)
-    srv = serve.Server(pool, n_streams=args.streams, max_batch=args.max_batch)
+    srv = serve.Server(pool, n_streams=args.streams, max_batch=args.max_batch,
+                       large_ms=args.large_ms, large_streams=args.large_streams)
     t0 = time.perf_counter()
     keys = sorted({(d["matrix"], d["n"], d["b_kind"]) for d in reqs})
     st = serve.Stats()
@@ -249,19 +252,26 @@ def serve_bench(args):
         if i % 100 == 99:
             log("serving prewarm: %d of %d plans (%.1f s)" % (i + 1, len(keys), time.perf_counter() - t0))
     log("serving prewarm: %d plans (%.1f s)" % (len(keys), time.perf_counter() - t0))
+    # untimed pass: every stream's run context and batch workspace reach their sizes
+    srv.run(reqs[: min(len(reqs), 300)], realtime=False)
     closed = srv.run(reqs[: min(len(reqs), args.closed_loop)], realtime=False).summary()
     rate = 0.7 * closed["throughput_req_s"]
     log("closed loop: %.1f req/s -> rate %.1f req/s" % (closed["throughput_req_s"], rate))
     timed = synth.serving_requests(args.requests, len(pool), args.pool_graphs, seed=5, rate=rate)
     s = srv.run(timed, realtime=True).summary()
-    log("serving: p50 %.3f ms, p99 %.3f ms, %.0f req/s, %.0f GFLOP/s"
-        % (s["p50_ms"], s["p99_ms"], s["throughput_req_s"], s["gflops"]))
+    log("serving: p50 %.3f ms, p99 %.3f ms, %.0f req/s, %.0f GFLOP/s; %d large (p50 %.3f, p99 %.3f "
+        "ms), small p50 %.3f, p99 %.3f ms"
+        % (s["p50_ms"], s["p99_ms"], s["throughput_req_s"], s["gflops"], s["large"],
+           s["p50_large_ms"], s["p99_large_ms"], s["p50_small_ms"], s["p99_small_ms"]))
     return {"workload": "serving_stream", "requests": args.requests, "rate_req_s": round(rate, 2),
             "pool": len(pool), "max_rows": args.max_rows, "max_mask_rows": args.max_mask_rows,
             "streams": args.streams, "budget_GB": 200,
             "largest_mask_rows": max((p["A"].m for p in pool if p["kind"] == "mask"), default=0),
             "largest_mask_nnz": max((p["A"].nnz for p in pool if p["kind"] == "mask"), default=0),
             "p50_ms": round(s["p50_ms"], 3), "p99_ms": round(s["p99_ms"], 3),
+            "large_requests": s["large"], "large_ms": srv.large_ms, "large_streams": srv.large_streams,
+            "p50_small_ms": round(s["p50_small_ms"], 3), "p99_small_ms": round(s["p99_small_ms"], 3),
+            "p50_large_ms": round(s["p50_large_ms"], 3), "p99_large_ms": round(s["p99_large_ms"], 3),
             "throughput_req_s": round(s["throughput_req_s"], 2), "gflops": round(s["gflops"], 1),
             "rejected": s["rejected"], "mean_batch": round(s["mean_batch"], 2),
             "closed_loop_req_s": round(closed["throughput_req_s"], 2)}
@@ -271,6 +281,39 @@ def _batch_item(job):
     from paper_2606_22482_amd import synth
     i, sp = job
     return synth.batch_matrix(i, sp, seed=4)
+
+
+def gather_probe(args):
+    """Random-gather ceiling of the FP32 vector path: 2^20 rows of 16
+    uniformly random columns over K columns of a 128-wide f32 B (B of K * 512
+    bytes), plain plans; reports the gathered B bytes (entries x 512) per
+    second, and the algorithmic rate (CSR + distinct B rows + C)."""
+    import torch
+    from paper_2606_22482_amd import api, synth
+    m, deg, n = 1 << 20, 16, 128
+    rng = np.random.default_rng(1)
+    for K in (1 << 20, 1 << 17, 1 << 13):
+        cols = rng.integers(0, K, size=m * deg).astype(np.int32)
+        A = synth.CSR(m, K, np.arange(0, m * deg + 1, deg, dtype=np.int64), cols,
+                      rng.uniform(-1, 1, m * deg).astype(np.float32), "f32")
+        B = torch.randn(K, n, device="cuda")
+        C = torch.empty(m, n, device="cuda")
+        p = api.Plan(A, n, "f32", api.default_opts(mode="plain"))
+        for _ in range(3):
+            p.run(B, C)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            p.run(B, C)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        alg = m * deg * 8 + np.unique(cols).size * n * 4 + m * n * 4
+        print(json.dumps({"K": K, "B_MiB": K * n * 4 / 2 ** 20, "ms": round(ms, 4),
+                          "gathered_GBps": round(m * deg * n * 4 / ms / 1e6, 1),
+                          "algorithmic_GBps": round(alg / ms / 1e6, 1)}), flush=True)
+        del B, C, p
 
 
 def batch_bench(args):
@@ -489,6 +532,10 @@ def main():
                          "the device (1.4e5 rows: about 2e9 entries, the 32-bit entry-index limit)")
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--max-batch", type=int, default=64)
+    ap.add_argument("--large-ms", type=float, default=1.0,
+                    help="serving: requests estimated above this many ms run alone (spmm_run)")
+    ap.add_argument("--large-streams", type=int, default=None,
+                    help="serving: streams that may run large requests at once (default half)")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--batch-tune-ms", type=float, default=60.0,
@@ -500,6 +547,9 @@ def main():
                          "re-partition (spmm_adapt_epoch) until it stops, before timing")
     ap.add_argument("--copy-plain", action="store_true",
                     help="with --copy-probe: use torch's plain copy kernel instead")
+    ap.add_argument("--gather-probe", action="store_true",
+                    help="only time the plain plan on uniformly random rows of 16 entries over B of "
+                         "512 MiB, 64 MiB and 4 MiB (N = 128, f32): the random-gather ceiling")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run the device copy kernel over this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -528,6 +578,9 @@ def main():
         bw = api.spmm_copy_bandwidth(args.copy_probe)
         print(json.dumps({"copy_bytes": args.copy_probe, "copy_launches": 13,
                           "read_plus_write_GBps": round(bw / 1e9, 1)}), flush=True)
+        return
+    if args.gather_probe:
+        gather_probe(args)
         return
     if args.workload == "serve":
         print(json.dumps(serve_bench(args)), flush=True)

@@ -12,13 +12,20 @@ arrive on a Poisson clock.  The scheduler:
   budget less its plan -- is rejected;
 * keeps plans resident in an LRU cache charged to the same budget, evicting
   only plans no in-flight request uses;
-* forms a batch of every admitted request as soon as one of its streams is
-  free and launches it with one ``spmm_submit`` (one graph replay of the
-  persistent kernels), so batches on different streams overlap on the device
-  while new requests keep being admitted as earlier ones complete;
-* polls tickets and retires finished requests immediately, freeing their
-  memory, and records latency = completion - arrival on the host monotonic
-  clock.
+* forms a batch as soon as one of its streams is free and launches it with
+  one ``spmm_submit`` (one graph replay of the persistent kernels), so
+  batches on different streams overlap on the device while new requests keep
+  being admitted as earlier ones complete.  Requests are sized by their
+  plan's algorithmic bytes: a large one (estimated above ``large_ms`` at
+  ``est_rate`` bytes/s) runs alone, as an ``spmm_run`` (one workgroup per
+  item, so the device interleaves other streams' work with it, which the
+  persistent batched kernels would lock out), on at most ``large_streams``
+  streams at once (half of them by default), so small requests always have a
+  stream; small ones batch together
+  (up to ``max_batch``), overtaking large ones that wait for a stream;
+* polls tickets (an event for a large request) and retires finished
+  requests immediately, freeing their memory, and records latency =
+  completion - arrival on the host monotonic clock.
 
 The arithmetic of every request is fixed by its plan and N, so a request's
 result is bitwise the same alone and in any mix.
@@ -51,6 +58,7 @@ class Request:
     status: str = "waiting"            # waiting | admitted | running | done | rejected
     footprint: int = 0                 # bytes of its execution (B, C, workspace share)
     need: int = 0                      # footprint plus its plan's bytes, checked at admission
+    large: bool = False                # runs in a batch of its own (see Server)
     B: object = None
     C: object = None
 
@@ -58,6 +66,8 @@ class Request:
 @dataclass
 class Stats:
     latencies_ms: list = field(default_factory=list)
+    small_latencies_ms: list = field(default_factory=list)
+    large_latencies_ms: list = field(default_factory=list)
     rejected: int = 0
     batches: int = 0
     batch_sizes: list = field(default_factory=list)
@@ -68,13 +78,20 @@ class Stats:
     plan_evictions: int = 0
 
     def summary(self) -> dict:
-        lat = np.array(self.latencies_ms) if self.latencies_ms else np.zeros(1)
+        def arr(x):
+            return np.array(x) if x else np.zeros(1)
+        lat, small, large = arr(self.latencies_ms), arr(self.small_latencies_ms), arr(self.large_latencies_ms)
         done = len(self.latencies_ms)
         return {
             "completed": done,
             "rejected": self.rejected,
             "p50_ms": float(np.percentile(lat, 50)),
             "p99_ms": float(np.percentile(lat, 99)),
+            "large": len(self.large_latencies_ms),
+            "p50_small_ms": float(np.percentile(small, 50)),
+            "p99_small_ms": float(np.percentile(small, 99)),
+            "p50_large_ms": float(np.percentile(large, 50)),
+            "p99_large_ms": float(np.percentile(large, 99)),
             "mean_ms": float(lat.mean()),
             "throughput_req_s": done / self.wall_s if self.wall_s > 0 else 0.0,
             "gflops": self.flops / self.wall_s / 1e9 if self.wall_s > 0 else 0.0,
@@ -95,9 +112,13 @@ class PlanCache:
         self.opts_for = opts_for
         self.plans = collections.OrderedDict()   # key -> (plan, bytes)
         self.users = collections.Counter()
+        self.alg = {}                            # key -> algorithmic bytes of one run
 
     def bytes_of(self, key) -> int:
         return self.plans[key][1] if key in self.plans else 0
+
+    def alg_bytes(self, key) -> float:
+        return self.alg.get(key, 0.0)
 
     def get(self, key, stats: Stats):
         if key in self.plans:
@@ -111,7 +132,9 @@ class PlanCache:
             plan = api.Plan.on_device(A.rowptr, A.colidx, A.vals, A.m, A.k, n, b_kind, opts)
         else:
             plan = api.Plan(A, n, b_kind, opts)
-        self.plans[key] = (plan, plan.stats()["device_bytes"])
+        st = plan.stats()
+        self.plans[key] = (plan, st["device_bytes"])
+        self.alg[key] = float(st["algorithmic_bytes"])
         stats.plan_builds += 1
         return plan
 
@@ -146,7 +169,8 @@ def default_opts_for(item, n, b_kind):
 
 class Server:
     def __init__(self, pool, budget_bytes=200 * GiB, n_streams=4, max_batch=64,
-                 opts_for=default_opts_for, keep_results=False):
+                 opts_for=default_opts_for, keep_results=False, large_ms=1.0, est_rate=1.5e12,
+                 large_streams=None):
         import torch
         self.torch = torch
         self.pool = pool
@@ -156,6 +180,11 @@ class Server:
         self.plans = PlanCache(pool, opts_for)
         self.keep_results = keep_results
         self.used = 0
+        self.large_ms = large_ms
+        # streams that may run a large request at once (at least one stays for small ones)
+        self.large_streams = max(1, min(n_streams - 1, n_streams // 2 if large_streams is None
+                                        else large_streams)) if n_streams > 1 else 1
+        self.large_bytes = large_ms * 1e-3 * est_rate
 
     def _plan_key(self, r: Request):
         return (r.matrix, r.n, r.b_kind)
@@ -170,7 +199,7 @@ class Server:
                 for d in requests]
         stats = Stats()
         waiting = collections.deque()
-        inflight = {}          # stream index -> (ticket, [requests])
+        inflight = {}          # stream index -> (ticket, [requests], large batch)
         free_streams = list(range(len(self.streams)))
         t0 = time.monotonic()
         nxt = 0
@@ -187,13 +216,15 @@ class Server:
             stats.max_queue = max(stats.max_queue, len(waiting))
             # completions
             for si in list(inflight.keys()):
-                ticket, batch = inflight[si]
-                if api.spmm_poll(ticket):
+                done, batch, _ = inflight[si]
+                if done():
                     tdone = time.monotonic() - t0
                     for r in batch:
                         r.done_at = tdone
                         r.status = "done"
                         stats.latencies_ms.append((tdone - r.arrival) * 1e3)
+                        (stats.large_latencies_ms if r.large else
+                         stats.small_latencies_ms).append((tdone - r.arrival) * 1e3)
                         A = self.pool[r.matrix]["A"]
                         stats.flops += 2.0 * A.nnz * r.n
                         self.used -= r.footprint
@@ -209,15 +240,23 @@ class Server:
                 si = free_streams[0]
                 stream = self.streams[si]
                 batch = []
+                big_batch = False
                 keep = collections.deque()
+                # a large request may take this stream while fewer than
+                # large_streams run (so small ones always keep a stream)
+                large_ok = sum(1 for v in inflight.values() if v[2]) < self.large_streams
                 while waiting and len(batch) < self.max_batch:
                     r = waiting.popleft()
                     key = self._plan_key(r)
                     plan = self.plans.get(key, stats)
+                    big = self.plans.alg_bytes(key) > self.large_bytes
+                    if big and (batch or not large_ok):
+                        keep.append(r)             # alone, on a later stream
+                        continue
                     pbytes = self.plans.bytes_of(key)
                     # the library's footprint of one batched execution, checked
                     # against the whole budget less the plan: BUDGET = never fits
-                    st, io = plan.run_bytes(batched=True, budget=max(0, self.budget - pbytes))
+                    st, io = plan.run_bytes(batched=not big, budget=max(0, self.budget - pbytes))
                     r.footprint, r.need = io, io + pbytes
                     if st == L.SPMM_ERR_BUDGET:
                         r.status = "rejected"
@@ -244,14 +283,31 @@ class Server:
                         r.C = torch.empty((A.m, r.n), device="cuda", dtype=torch.float32)
                     r.status = "running"
                     r.admitted_at = time.monotonic() - t0
+                    r.large = big
                     batch.append((r, plan))
+                    if big:
+                        big_batch = True
+                        break
                 keep.extend(waiting)
                 waiting = keep
                 if batch:
                     free_streams.pop(0)
-                    items = [api.WorkItem(plan, r.B, r.C) for r, plan in batch]
-                    ticket = api.spmm_submit(items, stream=stream)
-                    inflight[si] = (ticket, [r for r, _ in batch])
+                    if big_batch:
+                        # one large request: spmm_run, whose grids hold one
+                        # item per workgroup, so the device keeps dispatching
+                        # other streams' work between its workgroups (the
+                        # batched kernels are persistent and would hold every
+                        # CU until they finish)
+                        (r, plan), = batch
+                        plan.run(r.B, r.C, stream=stream)
+                        ev = torch.cuda.Event()
+                        ev.record(stream)
+                        done = ev.query
+                    else:
+                        items = [api.WorkItem(plan, r.B, r.C) for r, plan in batch]
+                        ticket = api.spmm_submit(items, stream=stream)
+                        done = (lambda t: lambda: api.spmm_poll(t))(ticket)
+                    inflight[si] = (done, [r for r, _ in batch], big_batch)
                     stats.batches += 1
                     stats.batch_sizes.append(len(batch))
             elif not inflight and not waiting and nxt < total and realtime:

@@ -116,3 +116,21 @@ def test_device_mask_pool_mix_equals_solo_and_oracle():
             Cs, S = oracle_of(A, Bh, "f32")
             err = oracle.max_normalised_error(r.C.cpu().numpy(), Cs, S)
         assert err <= tol, (r.rid, err, tol)
+
+
+def test_large_requests_run_alone_and_small_ones_keep_a_stream(pool):
+    """With every request classed large (threshold 0), each request runs
+    alone (as a run, on at most half the streams at once); results equal the
+    solo runs.  With no request large the classes do not change the results."""
+    import torch
+    reqs = synth.serving_requests(24, len(pool), 4, seed=12, rate=None)
+    for large_ms, one_each in ((0.0, True), (1e9, False)):
+        srv = serve.Server(pool, n_streams=3, max_batch=8, keep_results=True, large_ms=large_ms)
+        s = srv.run(reqs, realtime=False).summary()
+        assert s["completed"] == 24 and s["rejected"] == 0
+        assert s["large"] == (24 if one_each else 0)
+        if one_each:
+            assert s["batches"] == 24 and s["mean_batch"] == 1.0
+        for d, r in zip(reqs, srv.requests):
+            B, C = srv.solo(d)
+            assert torch.equal(C, r.C), (large_ms, r.rid)
