@@ -162,12 +162,12 @@ def cpu_baseline(A, B, b_kind, n, budget_s=12.0):
 
 
 def plan_time_bench(A, B, b_kind, wname, n, args):
-    """Plain-plan construction: host build + upload (A on the host) vs the
-    device builder (A already in device memory), median of several builds,
-    and both plans' run time."""
+    """Plan construction (plain unless --opts names another mode): host
+    build + upload (A on the host) vs the device builder (A already in device
+    memory), median of several builds, and both plans' run time."""
     import torch
     from paper_2606_22482_amd import api
-    opts = api.default_opts(mode="plain", **parse_opts(args.opts))
+    opts = api.default_opts(**{"mode": "plain", **parse_opts(args.opts)})
     rp = torch.from_numpy(np.ascontiguousarray(A.rowptr, dtype=np.int64)).cuda()
     ci = torch.from_numpy(np.ascontiguousarray(A.colidx, dtype=np.int32)).cuda()
     vt = torch.from_numpy(np.ascontiguousarray(A.vals, dtype=np.float32)).cuda() \
