@@ -128,6 +128,38 @@ def measured_traffic(workload, mode, kernel):
     return None if e is None else int(e["fetch_bytes"] + e["write_bytes"])
 
 
+def vendor_baseline(A, B, b_kind, n, steps):
+    """Context number: the same product through PyTorch's sparse CSR x dense
+    on ROCm (torch.sparse.mm) on the same GPU, f32 values and B (16-bit
+    operands are widened to f32 first), timed with events like the library's
+    runs.  Run only, never inspected."""
+    import torch
+    from paper_2606_22482_amd import api
+    try:
+        def f32(x, kind):
+            return api.device_tensor(x, kind).float() if kind != "f32" else api.device_tensor(x, "f32")
+        S = torch.sparse_csr_tensor(torch.from_numpy(np.ascontiguousarray(A.rowptr, dtype=np.int64)).cuda(),
+                                    torch.from_numpy(np.ascontiguousarray(A.colidx, dtype=np.int64)).cuda(),
+                                    f32(A.vals, A.val_kind), size=(A.m, A.k))
+        Bd = f32(B, b_kind)
+        for _ in range(3):
+            C = torch.sparse.mm(S, Bd)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            C = torch.sparse.mm(S, Bd)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        del C, S, Bd
+        torch.cuda.empty_cache()
+        return {"library": "torch.sparse.mm on ROCm, CSR f32 x dense f32",
+                "ms": round(ms, 5), "gflops": round(2.0 * A.nnz * n / (ms * 1e-3) / 1e9, 1)}
+    except Exception as e:  # report, do not fail the benchmark line
+        return {"library": "torch.sparse.mm on ROCm", "error": str(e)[:200]}
+
+
 def cpu_baseline(A, B, b_kind, n, budget_s=12.0):
     """Time the FP64 oracle on a bounded leading block of rows with this
     process's share of the host threads (at most 16, the share a GPU gets on
@@ -622,6 +654,8 @@ def main():
         "roofline": roof,
         "modes": modes,
     }
+    out["vendor_baseline"] = vendor_baseline(A, B, b_kind, n, args.steps)
+    log("vendor SpMM: %s" % out["vendor_baseline"])
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(A, B, b_kind, n)
@@ -633,7 +667,8 @@ def main():
             b2, ms2, roof2, modes2 = summarise(A2, bk2, wn2, n2, res2, copy_gbs)
             configs[wn2] = {"best": b2, "ms_per_step": round(ms2, 5),
                             "gflops": round(2.0 * A2.nnz * n2 / (ms2 * 1e-3) / 1e9, 1),
-                            "roofline": roof2, "modes": modes2}
+                            "roofline": roof2, "modes": modes2,
+                            "vendor_baseline": vendor_baseline(A2, B2, bk2, n2, args.steps)}
             del res2
         torch.cuda.empty_cache()
         bt = batch_bench(args)
