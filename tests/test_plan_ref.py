@@ -1,6 +1,8 @@
 """Pins for the numpy partition reference (NeutronSparse Sec. 5.2.2, Sec. 6.1):
 hand-worked examples, the printed tie rules of Eq. 5, coverage, the
 reduction cases and an FP64 re-execution of the decomposition."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -282,6 +284,17 @@ def test_rabbit_gain_is_the_modularity_gain():
         w = sum(1 for a, b in edges if (comm[a], comm[b]) in ((cu, cv), (cv, cu)))
         du, dv = d[comm == cu].sum(), d[comm == cv].sum()
         assert (after - before) * two_m ** 2 / 2 == pytest.approx(w * two_m - du * dv, abs=1e-9)
+
+
+def test_rabbit_order_hand_worked_example():
+    """The clustering order on a 4 x 4 matrix of two interleaved communities,
+    worked by hand from the algorithm's definition (tests/golden): pins the
+    visit order, the exact gain comparison and its tie rule, and the
+    depth-first walk of the merge tree."""
+    import json
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "rabbit_order_hand_example.json")))
+    rank = pr.rabbit_order(np.array(g["rowptr"]), np.array(g["colidx"]), g["m"], g["k"])
+    assert rank.tolist() == g["rank"]
 
 
 def test_rabbit_order_keeps_components_together():
