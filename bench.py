@@ -315,37 +315,41 @@ def _batch_item(job):
     return synth.batch_matrix(i, sp, seed=4)
 
 
-def gather_probe(args):
-    """Random-gather ceiling of the FP32 vector path: 2^20 rows of 16
-    uniformly random columns over K columns of a 128-wide f32 B (B of K * 512
-    bytes), plain plans; reports the gathered B bytes (entries x 512) per
-    second, and the algorithmic rate (CSR + distinct B rows + C)."""
+def gather_rate(K, steps, m=1 << 20, deg=16, n=128):
+    """Random-gather ceiling of the FP32 vector path: m rows of deg uniformly
+    random columns over K columns of an n-wide f32 B (B of K * n * 4 bytes),
+    a plain plan; the gathered B bytes (entries x n x 4) per second, and the
+    algorithmic rate (CSR + distinct B rows + C)."""
     import torch
     from paper_2606_22482_amd import api, synth
-    m, deg, n = 1 << 20, 16, 128
     rng = np.random.default_rng(1)
+    cols = rng.integers(0, K, size=m * deg).astype(np.int32)
+    A = synth.CSR(m, K, np.arange(0, m * deg + 1, deg, dtype=np.int64), cols,
+                  rng.uniform(-1, 1, m * deg).astype(np.float32), "f32")
+    B = torch.randn(K, n, device="cuda")
+    C = torch.empty(m, n, device="cuda")
+    p = api.Plan(A, n, "f32", api.default_opts(mode="plain"))
+    for _ in range(3):
+        p.run(B, C)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        p.run(B, C)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    alg = m * deg * 8 + np.unique(cols).size * n * 4 + m * n * 4
+    del B, C, p
+    return {"K": K, "B_MiB": K * n * 4 / 2 ** 20, "ms": round(ms, 4),
+            "gathered_GBps": round(m * deg * n * 4 / ms / 1e6, 1),
+            "algorithmic_GBps": round(alg / ms / 1e6, 1)}
+
+
+def gather_probe(args):
+    """The random-gather ceiling for B of 512 MiB, 64 MiB and 4 MiB."""
     for K in (1 << 20, 1 << 17, 1 << 13):
-        cols = rng.integers(0, K, size=m * deg).astype(np.int32)
-        A = synth.CSR(m, K, np.arange(0, m * deg + 1, deg, dtype=np.int64), cols,
-                      rng.uniform(-1, 1, m * deg).astype(np.float32), "f32")
-        B = torch.randn(K, n, device="cuda")
-        C = torch.empty(m, n, device="cuda")
-        p = api.Plan(A, n, "f32", api.default_opts(mode="plain"))
-        for _ in range(3):
-            p.run(B, C)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(args.steps):
-            p.run(B, C)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.steps
-        alg = m * deg * 8 + np.unique(cols).size * n * 4 + m * n * 4
-        print(json.dumps({"K": K, "B_MiB": K * n * 4 / 2 ** 20, "ms": round(ms, 4),
-                          "gathered_GBps": round(m * deg * n * 4 / ms / 1e6, 1),
-                          "algorithmic_GBps": round(alg / ms / 1e6, 1)}), flush=True)
-        del B, C, p
+        print(json.dumps(gather_rate(K, args.steps)), flush=True)
 
 
 def batch_bench(args):
@@ -642,6 +646,16 @@ def main():
     log("copy bandwidth (read + write): %.1f GB/s" % copy_gbs)
     A, B, b_kind, wname, n, results = measure(head, args, pick(head), extra)
     best, ms, roof, modes = summarise(A, b_kind, wname, n, results, copy_gbs)
+    if b_kind == "f32" and n == 128 and best == "plain":
+        # the dominant grid's B gathers against uniformly random gathers over
+        # a B of the same size (the ceiling of this access pattern)
+        probe = gather_rate(A.k, 10)
+        g = A.nnz * n * 4 / (roof["kernel"]["avg_launch_ms"] * 1e-3) / 1e9
+        roof["gather"] = {"gathered_bytes": int(A.nnz * n * 4), "GBps": round(g, 1),
+                          "uniform_random_GBps": probe["gathered_GBps"],
+                          "frac_of_uniform_random": round(g / probe["gathered_GBps"], 3)}
+        log("gathers: %.1f GB/s vs %.1f GB/s uniformly random over the same B size"
+            % (g, probe["gathered_GBps"]))
     gflops = 2.0 * A.nnz * n / (ms * 1e-3) / 1e9
     out = {
         "metric": METRIC,
