@@ -61,7 +61,8 @@ struct RunArgs {
     int32_t n_panels;
     int32_t lpr_log2;   // log2(lanes per entry group) for the vector / segment kernels
     int32_t xcd;        // remap consecutive items onto one XCD
-    int32_t win_panels; // panels of the window kernel (128 columns each)
+    int32_t win_panels; // panels of the window items (win_np columns each)
+    int32_t win_np;     // columns per window panel: 128, or 64 / 32 for 16-bit B with N <= 64
     int32_t win_lpr_log2;
     int32_t cold_aux;   // buffer-load policy bits for non-hot B rows; -1: plain loads for all
     uint32_t b_rec;     // bytes of B reachable through a buffer resource (its span);

@@ -45,17 +45,18 @@ __device__ __forceinline__ void vector_path(const DevPlan &P, const RunArgs &a, 
 
 // Workgroup b of the MFMA path: window partial items first, then the owners
 // (in window launch order, each XCD taking consecutive windows).
-template <int VT, int BT, int TT, int MB, int E, int CPL>
-__device__ __forceinline__ void mfma_path(const DevPlan &P, const RunArgs &a, int b, WinSmem<MB> &sm) {
+template <int VT, int BT, int TT, int MB, int E, int CPL, int NPW = 128>
+__device__ __forceinline__ void mfma_path(const DevPlan &P, const RunArgs &a, int b, WinSmem<MB, NPW> &sm) {
     if (b < a.wpart_blocks) {
-        if (b < P.n_wpart * a.win_panels) window_item<VT, BT, TT, MB, E, CPL, MB, true>(P, a, b, sm, true);
+        if (b < P.n_wpart * a.win_panels)
+            window_item<VT, BT, TT, MB, E, CPL, MB, true, NPW>(P, a, b, sm, true);
     } else {
         // padding workgroups of the one-grid form (j beyond the range) stay
         // idle: the remap is a permutation of [0, win_blocks) only
         const int j = b - a.wpart_blocks;
         if (j >= a.win_blocks) return;
         const int item = a.xcd ? remap_block(j, a.win_blocks) : j;
-        window_item<VT, BT, TT, MB, E, CPL, MB, true>(P, a, item, sm, false);
+        window_item<VT, BT, TT, MB, E, CPL, MB, true, NPW>(P, a, item, sm, false);
     }
 }
 
@@ -64,10 +65,10 @@ __global__ __launch_bounds__(256) void vector_path_kernel(DevPlan P, RunArgs a) 
     vector_path<VT, BT, E, CPL, VAR>(P, a, blockIdx.x);
 }
 
-template <int VT, int BT, int TT, int MB, int E, int CPL>
+template <int VT, int BT, int TT, int MB, int E, int CPL, int NPW>
 __global__ __launch_bounds__(256) void mfma_path_kernel(DevPlan P, RunArgs a) {
-    __shared__ WinSmem<MB> sm;
-    mfma_path<VT, BT, TT, MB, E, CPL>(P, a, blockIdx.x, sm);
+    __shared__ WinSmem<MB, NPW> sm;
+    mfma_path<VT, BT, TT, MB, E, CPL, NPW>(P, a, blockIdx.x, sm);
 }
 
 // The MFMA path's workgroups (padded to a multiple of 8), then the vector path's.
@@ -116,8 +117,19 @@ template <int VT, int BT, int TT, int MB>
 static hipError_t mp_mb(const DevPlan &P, const RunArgs &a, hipStream_t s) {
     constexpr int EV = BT == DT_F32 ? 4 : 8;
     const dim3 grid((unsigned)(a.wpart_blocks + a.win_blocks)), block(256);
-    if (a.vec_ok) hipLaunchKernelGGL((mfma_path_kernel<VT, BT, TT, MB, EV, 1>), grid, block, 0, s, P, a);
-    else hipLaunchKernelGGL((mfma_path_kernel<VT, BT, TT, MB, 1, 2>), grid, block, 0, s, P, a);
+    if (!a.vec_ok) {
+        hipLaunchKernelGGL((mfma_path_kernel<VT, BT, TT, MB, 1, 2, 128>), grid, block, 0, s, P, a);
+    } else if constexpr (BT == DT_F32) {
+        hipLaunchKernelGGL((mfma_path_kernel<VT, BT, TT, MB, EV, 1, 128>), grid, block, 0, s, P, a);
+    } else {
+        // narrow 16-bit B stages 64- or 32-column panels
+        if (a.win_np == 128)
+            hipLaunchKernelGGL((mfma_path_kernel<VT, BT, TT, MB, EV, 1, 128>), grid, block, 0, s, P, a);
+        else if (a.win_np == 64)
+            hipLaunchKernelGGL((mfma_path_kernel<VT, BT, TT, MB, EV, 1, 64>), grid, block, 0, s, P, a);
+        else
+            hipLaunchKernelGGL((mfma_path_kernel<VT, BT, TT, MB, EV, 1, 32>), grid, block, 0, s, P, a);
+    }
     return hipGetLastError();
 }
 
@@ -141,9 +153,9 @@ hipError_t launch_mfma_path(const DevPlan &P, int32_t vt, int32_t bt, int32_t tt
     return hipErrorInvalidValue;
 }
 
-// One grid: built for 16-byte chunks with one chunk per lane and the packed
-// vector variants (2, 3), which cover the defaults; other plans report
-// hipErrorNotSupported and run as two grids.
+// One grid: built for 16-byte chunks with one chunk per lane, the packed
+// vector variants (2, 3), which cover the defaults, and 128-column window
+// panels; other plans report hipErrorNotSupported and run as two grids.
 template <int VT, int BT, int TT, int MB>
 static hipError_t og_mb(const DevPlan &P, const RunArgs &a, hipStream_t s) {
     constexpr int EV = BT == DT_F32 ? 4 : 8;
@@ -168,7 +180,8 @@ static hipError_t og_types(const DevPlan &P, const RunArgs &a, hipStream_t s) {
 
 bool one_grid_supported(int32_t b_t, const RunArgs &a) {
     const int ev = b_t == DT_F32 ? 4 : 8;
-    return a.vec_ok && (a.np + ev - 1) / ev <= 64 && (a.pipeline == 2 || a.pipeline == 3);
+    return a.vec_ok && (a.np + ev - 1) / ev <= 64 && (a.pipeline == 2 || a.pipeline == 3) &&
+           a.win_np == 128;
 }
 
 hipError_t launch_one_grid(const DevPlan &P, int32_t vt, int32_t bt, int32_t tt, const RunArgs &a,

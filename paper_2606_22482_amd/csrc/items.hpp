@@ -10,7 +10,8 @@
 //               gather-FMA over each row's remainder (Sec. 5.1, gather then
 //               accumulate), or the fixed-order sum of its segment partials,
 //               then one write of the C row.
-//   window   -- one workgroup per (row window, 128-column panel): the B rows
+//   window   -- one workgroup per (row window, column panel of 128, or of 64
+//               or 32 for narrow 16-bit B): the B rows
 //               of the window's compacted tile columns are staged in LDS once
 //               and reused by every row of the window (Sec. 6.2, intra-core
 //               reuse; Sec. 5.1, matrix-engine execution), each tile's bitmap
@@ -649,7 +650,7 @@ __device__ __forceinline__ bool group_arrive(int32_t *cnt, int target, int32_t *
     return *flag != 0;
 }
 
-// Counter of window slot `dep` in window panel q (128 columns).
+// Counter of window slot `dep` in window panel q (win_np columns).
 __device__ __forceinline__ int32_t *win_counter(const DevPlan &P, const RunArgs &a, int q, int dep) {
     return a.cnt + (int64_t)a.n_panels * P.n_seg + (int64_t)q * P.n_dep + dep;
 }
@@ -658,7 +659,7 @@ __device__ __forceinline__ int32_t *win_counter(const DevPlan &P, const RunArgs 
 // segment panel (width np) overlapping the window panel for each segment of
 // the window's split rows.
 __device__ __forceinline__ int win_target(const DevPlan &P, const RunArgs &a, int w, int q) {
-    const int c0 = q * 128, c1 = min(P.n, c0 + 128) - 1;
+    const int c0 = q * a.win_np, c1 = min(P.n, c0 + a.win_np) - 1;
     return 1 + (P.win_part[w + 1] - P.win_part[w]) + P.win_nsseg[w] * (c1 / a.np - c0 / a.np + 1);
 }
 
@@ -671,7 +672,7 @@ __device__ __forceinline__ int win_target(const DevPlan &P, const RunArgs &a, in
 __device__ __forceinline__ void window_combine(const DevPlan &P, const RunArgs &a, int w, int q, int dep,
                                                int t, int T) {
     const int H = P.H;
-    const int ncol0 = q * 128, ncols = min(128, P.n - ncol0), nch = (ncols + 3) >> 2;
+    const int ncol0 = q * a.win_np, ncols = min(a.win_np, P.n - ncol0), nch = (ncols + 3) >> 2;
     const int pa = P.win_part[w], pb = P.win_part[w + 1];
     const int64_t ld = a.work_ld;
     const __amdgpu_buffer_rsrc_t rs = ws_resource(a);
@@ -771,7 +772,7 @@ __device__ __forceinline__ void segment_item(const DevPlan &P, const RunArgs &a,
             }
         } else {
             const int dep = P.win_dep[w];
-            for (int q = ncol0 / 128; q <= (ncol0 + ncols - 1) / 128; ++q)
+            for (int q = ncol0 / a.win_np; q <= (ncol0 + ncols - 1) / a.win_np; ++q)
                 if (wave_arrive(win_counter(P, a, q, dep), win_target(P, a, w, q)))
                     window_combine(P, a, w, q, dep, threadIdx.x & 63, 64);
         }
@@ -1119,19 +1120,22 @@ __device__ __forceinline__ void vector_item_var(const DevPlan &P, const RunArgs 
 
 // LDS of a window item: the staged B rows (reused for the f32 C tile), the
 // round's tiles expanded from bitmap + packed values to dense 16-bit rows, and
-// the window's rows, remainder ranges and segment ids.  MB = H / 16.
-// Staged B row k occupies 256 bytes (16 chunks of 8 elements) with chunk c
-// stored in slot c ^ bswz(k): the four 8-row groups that one MFMA operand
-// read touches then fall in different banks without padding, so a wave's
-// 64 x 16-byte chunks are one contiguous kilobyte and can be written by one
-// direct global-to-LDS load.
-template <int MB>
+// the window's rows, remainder ranges and segment ids.  MB = H / 16; NPWv =
+// the panel width of an item (128 columns, or 64 / 32 for narrow 16-bit B).
+// Staged B row k occupies NPWv * 2 bytes (NCH chunks of 8 elements) with
+// chunk c stored in slot c ^ bswz<NCH>(k): the 8-row groups that one MFMA
+// operand read touches then fall in different banks without padding, so a
+// wave's 64 x 16-byte chunks are one contiguous kilobyte and can be written
+// by one direct global-to-LDS load.
+template <int MB, int NPWv = 128>
 struct WinSmem {
-    static constexpr int NPW = 128;          // panel columns of a window item
+    static constexpr int NPW = NPWv;         // panel columns of a window item
+    static constexpr int NCH = NPW / 8;      // 16-byte chunks of a staged B row
     static constexpr int TC = 4;             // tiles staged per round
     static constexpr int KROWS = TC * 32;    // B rows staged per round
     static constexpr int BSTR = NPW;         // LDS row stride (16-bit elements)
     static constexpr int H = MB * 16;
+    static_assert(NPW == 32 || NPW == 64 || NPW == 128, "panel width");
     __attribute__((aligned(16))) unsigned short Bs[KROWS * BSTR];
     __attribute__((aligned(16))) unsigned short As[TC * H * 32];  // expanded tiles, row-major
     int32_t rows[H], rb[H], re[H], sid[H];
@@ -1183,9 +1187,10 @@ __device__ __forceinline__ void stage_b8(const void *B, int64_t off, int valid, 
 typedef short v4i16 __attribute__((ext_vector_type(4)));
 
 // Slot of a chunk in a staged B row (see WinSmem).
-__device__ __forceinline__ int bswz(int k) { return ((k >> 3) & 3) << 1; }
+template <int NCH>
+__device__ __forceinline__ int bswz(int k) { return ((k >> 3) & (NCH / 4 - 1)) << 1; }
 
-// One (window, 128-column panel) per workgroup: item in [0, n_win * win_panels),
+// One (window, NPWv-column panel) per workgroup: item in [0, n_win * win_panels),
 // panel innermost, so a window's panels run side by side on one XCD and share
 // its tile data in that XCD's L2.
 // Every thread of the workgroup calls it with the same item.  Per round of up
@@ -1208,13 +1213,16 @@ __device__ __forceinline__ int bswz(int k) { return ((k >> 3) & 3) << 1; }
 // their parts in the workspace and arrive at the window panel's counter; the
 // last arrival combines (window_combine).  Owners skip split rows, which the
 // combine takes from the segments' partials.
-template <int VT, int BT, int TT, int MB, int E, int CPL, int SMB, bool FUSED = false>
+template <int VT, int BT, int TT, int MB, int E, int CPL, int SMB, bool FUSED = false, int NPWv = 128>
 __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, int item,
-                                            WinSmem<SMB> &sm, bool partial) {
+                                            WinSmem<SMB, NPWv> &sm, bool partial) {
     constexpr int H = MB * 16;
-    using S = WinSmem<SMB>;
-    constexpr int NPW = S::NPW, TC = S::TC, BSTR = S::BSTR, KROWS = S::KROWS;
-    constexpr int PER = KROWS * (NPW / 8) / 256;  // 16-byte staging chunks per thread
+    using S = WinSmem<SMB, NPWv>;
+    constexpr int NPW = S::NPW, NCH = S::NCH, TC = S::TC, BSTR = S::BSTR, KROWS = S::KROWS;
+    constexpr int PER = KROWS * NCH / 256;        // 16-byte staging chunks per thread
+    constexpr int RPP = 256 / NCH;                // B rows staged per pass
+    constexpr int NB = NPW / 16;                  // 16-column MFMA blocks of the panel
+    constexpr int NBW = (NB + 3) / 4;             // ... per wave (block wave + 4 nbi)
     constexpr int U1 = MB == 1 ? 4 : 2;           // remainder entries per row gathered early
     static_assert(MB <= SMB, "LDS sized for a smaller window");
     static_assert(H * NPW * 4 <= KROWS * BSTR * 2, "C tile must fit in the B stage");
@@ -1253,11 +1261,11 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
     Raw<BT, E> g1[U1][CPL];
     int b1 = 0, e1 = 0;
 
-    f32x4 acc[MB][2];
+    f32x4 acc[MB][NBW];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[mb][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int j = 0; j < NBW; ++j) acc[mb][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
     auto round = [&](auto first_tag, int tc0) {
         constexpr bool FIRST = decltype(first_tag)::value;
@@ -1266,7 +1274,7 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
         int colr[PER];
 #pragma unroll
         for (int it = 0; it < PER; ++it) {
-            const int kr = (tid + it * 256) >> 4;
+            const int kr = (tid + it * 256) / NCH;
             const int c = P.tile_cols[(int64_t)tc0 * 32 + min(kr, nt * 32 - 1)];
             colr[it] = kr < nt * 32 ? c : -1;
         }
@@ -1326,8 +1334,8 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
             }
         }
         // B rows of the staging chunks: thread tid stages, in pass it, row
-        // kr = 16 it + tid / 16 into LDS bytes [4096 it + 16 tid, +16), i.e.
-        // slot tid % 16 of that row, which holds chunk (tid % 16) ^ bswz(kr)
+        // kr = RPP it + tid / NCH into LDS bytes [4096 it + 16 tid, +16), i.e.
+        // slot tid % NCH of that row, which holds chunk (tid % NCH) ^ bswz(kr)
         if constexpr (BT != DT_F32) {
             if (full) {
                 // one direct global-to-LDS load per pass and wave; chunks
@@ -1335,7 +1343,7 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
                 // the plan's zero block
 #pragma unroll
                 for (int it = 0; it < PER; ++it) {
-                    const int kr = 16 * it + (tid >> 4), cg = (tid & 15) ^ bswz(kr);
+                    const int kr = RPP * it + tid / NCH, cg = (tid & (NCH - 1)) ^ bswz<NCH>(kr);
                     const unsigned short *src =
                         colr[it] >= 0 ? static_cast<const unsigned short *>(a.B) +
                                             (int64_t)colr[it] * a.ldb + ncol0 + cg * 8
@@ -1347,7 +1355,7 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
             } else {
 #pragma unroll
                 for (int it = 0; it < PER; ++it) {
-                    const int kr = 16 * it + (tid >> 4), cg = (tid & 15) ^ bswz(kr);
+                    const int kr = RPP * it + tid / NCH, cg = (tid & (NCH - 1)) ^ bswz<NCH>(kr);
                     uint32_t w[4] = {0u, 0u, 0u, 0u};
                     const int valid = min(8, ncols - cg * 8);
                     if (colr[it] >= 0 && valid > 0)
@@ -1362,7 +1370,7 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
                 uint32_t w[2][4];
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
-                    const int it = h + q, kr = 16 * it + (tid >> 4), cg = (tid & 15) ^ bswz(kr);
+                    const int it = h + q, kr = RPP * it + tid / NCH, cg = (tid & (NCH - 1)) ^ bswz<NCH>(kr);
                     w[q][0] = w[q][1] = w[q][2] = w[q][3] = 0u;
                     const int valid = min(8, ncols - cg * 8);
                     if (full) {
@@ -1428,8 +1436,9 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
             for (int mb = 0; mb < MB; ++mb)
                 af[mb] = *reinterpret_cast<const u16x8 *>(&sm.As[((j * H + mb * 16 + l16) * 32) + 8 * g]);
 #pragma unroll
-            for (int nbi = 0; nbi < 2; ++nbi) {
+            for (int nbi = 0; nbi < NBW; ++nbi) {
                 const int nb = wave + 4 * nbi;
+                if (NB < 4 && nb >= NB) continue;  // narrow panels: waves without a block
                 // B operand: lane (g, n) needs rows 8g .. 8g+7 of column n.
                 // ds_read_b64_tr_b16 transposes within each 16-lane block:
                 // lane a of the block reads 4 consecutive columns of one row,
@@ -1441,7 +1450,7 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
                     const int k = j * 32 + 8 * g + 4 * h + (l16 >> 2), n0 = nb * 16 + 4 * (l16 & 3);
                     const v4i16 t = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
                         (__attribute__((address_space(3))) v4i16 *)(Bs + k * BSTR +
-                                                                    (((n0 >> 3) ^ bswz(k)) << 3) + (n0 & 7)));
+                                                                    (((n0 >> 3) ^ bswz<NCH>(k)) << 3) + (n0 & 7)));
 #pragma unroll
                     for (int i = 0; i < 4; ++i) bf[4 * h + i] = (unsigned short)t[i];
                 }
@@ -1467,9 +1476,9 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-            for (int nbi = 0; nbi < 2; ++nbi) {
+            for (int nbi = 0; nbi < NBW; ++nbi) {
                 const int col = (wave + 4 * nbi) * 16 + l16;
-                if (col < ncols) {
+                if (wave + 4 * nbi < NB && col < ncols) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         float *d = dst + (int64_t)(mb * 16 + 4 * g + i) * a.work_ld + col;
@@ -1502,10 +1511,11 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-            for (int nbi = 0; nbi < 2; ++nbi)
+            for (int nbi = 0; nbi < NBW; ++nbi)
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    Cs[(mb * 16 + 4 * g + i) * NPW + (wave + 4 * nbi) * 16 + l16] = acc[mb][nbi][i];
+                    if (wave + 4 * nbi < NB)
+                        Cs[(mb * 16 + 4 * g + i) * NPW + (wave + 4 * nbi) * 16 + l16] = acc[mb][nbi][i];
     }
     // add the partial results of the window's other tiles, in tile order
     // (fused: a window with partial items has a slot, combined at the end)

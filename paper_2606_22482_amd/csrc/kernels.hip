@@ -19,18 +19,20 @@ __global__ __launch_bounds__(256) void vector_kernel(DevPlan P, RunArgs a) {
 }
 
 
-template <int VT, int BT, int TT, int MB, int E, int CPL>
+template <int VT, int BT, int TT, int MB, int E, int CPL, int NPW>
 __global__ __launch_bounds__(256) void window_kernel(DevPlan P, RunArgs a) {
-    __shared__ WinSmem<MB> sm;
+    __shared__ WinSmem<MB, NPW> sm;
     const int item = logical_block(a.xcd);
-    if (item < P.n_win * a.win_panels) window_item<VT, BT, TT, MB, E, CPL, MB>(P, a, item, sm, false);
+    if (item < P.n_win * a.win_panels)
+        window_item<VT, BT, TT, MB, E, CPL, MB, false, NPW>(P, a, item, sm, false);
 }
 
-template <int VT, int BT, int TT, int MB, int E, int CPL>
+template <int VT, int BT, int TT, int MB, int E, int CPL, int NPW>
 __global__ __launch_bounds__(256) void window_partial_kernel(DevPlan P, RunArgs a) {
-    __shared__ WinSmem<MB> sm;
+    __shared__ WinSmem<MB, NPW> sm;
     const int item = logical_block(a.xcd);
-    if (item < P.n_wpart * a.win_panels) window_item<VT, BT, TT, MB, E, CPL, MB>(P, a, item, sm, true);
+    if (item < P.n_wpart * a.win_panels)
+        window_item<VT, BT, TT, MB, E, CPL, MB, false, NPW>(P, a, item, sm, true);
 }
 
 
@@ -163,16 +165,27 @@ static hipError_t win_dispatch(const DevPlan &P, const RunArgs &a, hipStream_t s
     if (wgs == 0) return hipSuccess;
     constexpr int EV = BT == DT_F32 ? 4 : 8;
     dim3 grid((unsigned)wgs), block(256);
+#define SPMM_WIN_NP(MB, NP)                                                                          \
+    do {                                                                                             \
+        if (partial)                                                                                 \
+            hipLaunchKernelGGL((window_partial_kernel<VT, BT, TT, MB, EV, 1, NP>), grid, block, 0, s, P, a); \
+        else                                                                                         \
+            hipLaunchKernelGGL((window_kernel<VT, BT, TT, MB, EV, 1, NP>), grid, block, 0, s, P, a);  \
+    } while (0)
 #define SPMM_WIN(MB)                                                                                 \
     do {                                                                                             \
-        if (partial && a.vec_ok)                                                                     \
-            hipLaunchKernelGGL((window_partial_kernel<VT, BT, TT, MB, EV, 1>), grid, block, 0, s, P, a); \
-        else if (partial)                                                                            \
-            hipLaunchKernelGGL((window_partial_kernel<VT, BT, TT, MB, 1, 2>), grid, block, 0, s, P, a);  \
-        else if (a.vec_ok)                                                                           \
-            hipLaunchKernelGGL((window_kernel<VT, BT, TT, MB, EV, 1>), grid, block, 0, s, P, a);     \
-        else                                                                                         \
-            hipLaunchKernelGGL((window_kernel<VT, BT, TT, MB, 1, 2>), grid, block, 0, s, P, a);      \
+        if (!a.vec_ok) {                                                                             \
+            if (partial)                                                                             \
+                hipLaunchKernelGGL((window_partial_kernel<VT, BT, TT, MB, 1, 2, 128>), grid, block, 0, s, P, a); \
+            else                                                                                     \
+                hipLaunchKernelGGL((window_kernel<VT, BT, TT, MB, 1, 2, 128>), grid, block, 0, s, P, a); \
+        } else if constexpr (BT == DT_F32) {                                                         \
+            SPMM_WIN_NP(MB, 128);                                                                    \
+        } else {                                                                                     \
+            if (a.win_np == 128) SPMM_WIN_NP(MB, 128);                                               \
+            else if (a.win_np == 64) SPMM_WIN_NP(MB, 64);                                            \
+            else SPMM_WIN_NP(MB, 32);                                                                \
+        }                                                                                            \
     } while (0)
     switch (P.H) {
     case 16: SPMM_WIN(1); break;
@@ -181,6 +194,7 @@ static hipError_t win_dispatch(const DevPlan &P, const RunArgs &a, hipStream_t s
     default: return hipErrorInvalidValue;
     }
 #undef SPMM_WIN
+#undef SPMM_WIN_NP
     return hipGetLastError();
 }
 

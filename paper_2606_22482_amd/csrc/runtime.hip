@@ -604,10 +604,19 @@ spmm_status make_run_args(const spmm_plan_t *p, const void *B, int64_t ldb, void
     a.cold_aux = (b_span < 4294967295.0 && h.opts.cold_policy != 0) ? h.opts.cold_policy : -1;
     a.b_rec = b_span < 4294967040.0 ? (uint32_t)b_span : 0u;
     a.pipeline = h.opts.pipeline;
-    a.win_panels = (N + 127) / 128;
-    const int wchunks = a.vec_ok ? 128 / E : 128;
-    a.win_lpr_log2 = ilog2_ceil(std::min(wchunks, 64));
+    // narrow 16-bit B: windows stage panels of 64 or 32 columns, so that no
+    // staged column and no MFMA block is padding
+    int wnp = 128;
+    if (a.vec_ok && sb == 2) wnp = N <= 32 ? 32 : N <= 64 ? 64 : 128;
+    set_window_panels(a, N, E, wnp);
     return SPMM_OK;
+}
+
+void set_window_panels(RunArgs &a, int N, int E, int np) {
+    a.win_np = np;
+    a.win_panels = (N + np - 1) / np;
+    const int wchunks = a.vec_ok ? np / E : np;
+    a.win_lpr_log2 = ilog2_ceil(std::min(wchunks, 64));
 }
 }  // namespace spmm
 

@@ -74,6 +74,8 @@ bool fork_paths(const RunArgs &a);
 size_t counter_ints(const spmm_plan_t *p, const RunArgs &a);
 spmm_status make_run_args(const spmm_plan_t *p, const void *B, int64_t ldb, void *C, int64_t ldc,
                           RunArgs &a);
+// Window panels of np columns (128, 64 or 32) for a run with N columns.
+void set_window_panels(RunArgs &a, int N, int E, int np);
 spmm_status check_run(const spmm_plan_t *p, const void *B, int64_t ldb, void *C, int64_t ldc);
 spmm_status launch_plan(const spmm_plan_t *p, const RunArgs &a, hipStream_t s, spmm_timer_t *t,
                         const RunContext &ctx);

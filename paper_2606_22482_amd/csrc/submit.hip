@@ -127,6 +127,8 @@ extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *
         const spmm_plan_t *p = items[i].plan;
         if (p->hp.m == 0) continue;
         make_run_args(p, items[i].B, items[i].ldb, items[i].C, items[i].ldc, args[i]);
+        // the batched window kernels stage 128-column panels
+        set_window_panels(args[i], (int)p->hp.n, chunk_elems(p->hp.b_type), 128);
         ws_floats += workspace_floats(p->hp, true);
         const int E = args[i].vec_ok ? chunk_elems(p->hp.b_type) : 1;
         const int chunks = args[i].vec_ok ? args[i].np / E : args[i].np;

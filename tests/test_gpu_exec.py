@@ -183,3 +183,37 @@ def test_float_inputs_within_tolerance_all_forms():
             outs.append(C)
         assert all(torch.equal(outs[0], C) for C in outs[1:]), mode
         parity(outs[0], A, B, "f32", tol)
+
+
+@pytest.mark.parametrize("n", [32, 48, 64, 96])
+def test_narrow_panels_bitwise_across_forms_and_batch(n):
+    """16-bit B with N <= 64 stages 32- or 64-column window panels (128 in a
+    batch): every execution form and the batched kernels give C bitwise
+    equal, and integer-exact against the oracle -- for block windows and for
+    wide windows with split rows and partial items."""
+    import torch
+    cases = []
+    A, _ = synth.block_community(n=4096, band=8, n_cols=8, seed=13, val_kind="bf16")
+    A.vals[:] = synth.to_bf16_bits(np.round(np.random.default_rng(13).uniform(-2, 2, A.nnz)))
+    cases.append((A, "bf16", dict(mode="mixed", row_order="original_ranges", window_h=16)))
+    A = synth.random_csr(300, 9000, 0.2, 43, val_kind="f16", int_values=(-2, 2))
+    cases.append((A, "f16", dict(mode="mixed", window_h=64, t_row=-1, alpha_c=0.0, alpha=0.19,
+                                 seg_len=200)))
+    for A, bk, opts in cases:
+        B = synth.int_dense(17, (A.k, n), -8, 8, kind=bk)
+        Bd = device_B(B, bk)
+        outs = []
+        for ex in EXECS:
+            print("narrow panels n", n, bk, "exec", ex, flush=True)
+            p = api.Plan(A, n, bk, api.default_opts(exec=ex, **opts))
+            C = device_C(A.m, n)
+            p.run(Bd, C)
+            torch.cuda.synchronize()
+            outs.append(C)
+        p = api.Plan(A, n, bk, api.default_opts(**opts))
+        assert p.stats()["tiles"] > 0
+        Cb = device_C(A.m, n)
+        api.spmm_wait(api.spmm_submit([api.WorkItem(p, Bd, Cb)]))
+        for C in outs[1:] + [Cb]:
+            assert torch.equal(outs[0], C), (n, bk)
+        exact(outs[0], A, B, bk)
