@@ -558,7 +558,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="all",
                     help="all (default: every configuration in one line), gnn, gnn64, block, "
                          "block_shuffled, uniform, batch, serve")
