@@ -1,6 +1,7 @@
 // devplan.hpp -- the uploaded plan as seen by the kernels, and kernel launchers.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -123,6 +124,26 @@ hipError_t launch_copy(const float4 *src, float4 *dst, int64_t n4, hipStream_t s
 // co-scheduled execution (fused.hip): the vector path (segments + vector
 // items), the MFMA path (window partials + owners), or both in one grid;
 // RunArgs' cnt, dep and *_blocks must be set.
+// Events that the next kernel launched through launch_kernel on this thread
+// records around itself, inside its own dispatch (a timed run sets them; no
+// separate marker commands sit between the run's kernels).
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+LaunchEvents &launch_events();
+
+template <typename F, typename... Args>
+inline void launch_kernel(F kernel, dim3 grid, dim3 block, uint32_t shm, hipStream_t s, Args... args) {
+    LaunchEvents &ev = launch_events();
+    if (ev.start) {
+        const LaunchEvents e = ev;
+        ev = LaunchEvents{};
+        hipExtLaunchKernelGGL(kernel, grid, block, shm, s, e.start, e.stop, 0u, args...);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, shm, s, args...);
+    }
+}
+
 hipError_t launch_vector_path(const DevPlan &P, int32_t val_t, int32_t b_t, const RunArgs &a,
                               hipStream_t s);
 hipError_t launch_mfma_path(const DevPlan &P, int32_t val_t, int32_t b_t, int32_t tile_t,

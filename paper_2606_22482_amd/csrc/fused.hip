@@ -88,10 +88,10 @@ template <int VT, int BT, int E, int CPL>
 static hipError_t vp_var(const DevPlan &P, const RunArgs &a, hipStream_t s) {
     const dim3 grid((unsigned)(a.seg_blocks + a.vec_blocks)), block(256);
     switch (a.pipeline) {
-    case 3: hipLaunchKernelGGL((vector_path_kernel<VT, BT, E, CPL, 3>), grid, block, 0, s, P, a); break;
-    case 2: hipLaunchKernelGGL((vector_path_kernel<VT, BT, E, CPL, 2>), grid, block, 0, s, P, a); break;
-    case 1: hipLaunchKernelGGL((vector_path_kernel<VT, BT, E, CPL, 1>), grid, block, 0, s, P, a); break;
-    default: hipLaunchKernelGGL((vector_path_kernel<VT, BT, E, CPL, 0>), grid, block, 0, s, P, a); break;
+    case 3: launch_kernel((vector_path_kernel<VT, BT, E, CPL, 3>), grid, block, 0, s, P, a); break;
+    case 2: launch_kernel((vector_path_kernel<VT, BT, E, CPL, 2>), grid, block, 0, s, P, a); break;
+    case 1: launch_kernel((vector_path_kernel<VT, BT, E, CPL, 1>), grid, block, 0, s, P, a); break;
+    default: launch_kernel((vector_path_kernel<VT, BT, E, CPL, 0>), grid, block, 0, s, P, a); break;
     }
     return hipGetLastError();
 }
@@ -118,17 +118,17 @@ static hipError_t mp_mb(const DevPlan &P, const RunArgs &a, hipStream_t s) {
     constexpr int EV = BT == DT_F32 ? 4 : 8;
     const dim3 grid((unsigned)(a.wpart_blocks + a.win_blocks)), block(256);
     if (!a.vec_ok) {
-        hipLaunchKernelGGL((mfma_path_kernel<VT, BT, TT, MB, 1, 2, 128>), grid, block, 0, s, P, a);
+        launch_kernel((mfma_path_kernel<VT, BT, TT, MB, 1, 2, 128>), grid, block, 0, s, P, a);
     } else if constexpr (BT == DT_F32) {
-        hipLaunchKernelGGL((mfma_path_kernel<VT, BT, TT, MB, EV, 1, 128>), grid, block, 0, s, P, a);
+        launch_kernel((mfma_path_kernel<VT, BT, TT, MB, EV, 1, 128>), grid, block, 0, s, P, a);
     } else {
         // narrow 16-bit B stages 64- or 32-column panels
         if (a.win_np == 128)
-            hipLaunchKernelGGL((mfma_path_kernel<VT, BT, TT, MB, EV, 1, 128>), grid, block, 0, s, P, a);
+            launch_kernel((mfma_path_kernel<VT, BT, TT, MB, EV, 1, 128>), grid, block, 0, s, P, a);
         else if (a.win_np == 64)
-            hipLaunchKernelGGL((mfma_path_kernel<VT, BT, TT, MB, EV, 1, 64>), grid, block, 0, s, P, a);
+            launch_kernel((mfma_path_kernel<VT, BT, TT, MB, EV, 1, 64>), grid, block, 0, s, P, a);
         else
-            hipLaunchKernelGGL((mfma_path_kernel<VT, BT, TT, MB, EV, 1, 32>), grid, block, 0, s, P, a);
+            launch_kernel((mfma_path_kernel<VT, BT, TT, MB, EV, 1, 32>), grid, block, 0, s, P, a);
     }
     return hipGetLastError();
 }
@@ -162,9 +162,9 @@ static hipError_t og_mb(const DevPlan &P, const RunArgs &a, hipStream_t s) {
     const unsigned wb = (unsigned)(a.wpart_blocks + ((a.win_blocks + 7) & ~7));
     const dim3 grid(wb + (unsigned)(a.seg_blocks + a.vec_blocks)), block(256);
     if (a.pipeline == 3)
-        hipLaunchKernelGGL((one_grid_kernel<VT, BT, TT, MB, EV, 1, 3>), grid, block, 0, s, P, a);
+        launch_kernel((one_grid_kernel<VT, BT, TT, MB, EV, 1, 3>), grid, block, 0, s, P, a);
     else
-        hipLaunchKernelGGL((one_grid_kernel<VT, BT, TT, MB, EV, 1, 2>), grid, block, 0, s, P, a);
+        launch_kernel((one_grid_kernel<VT, BT, TT, MB, EV, 1, 2>), grid, block, 0, s, P, a);
     return hipGetLastError();
 }
 

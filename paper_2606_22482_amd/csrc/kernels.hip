@@ -120,10 +120,10 @@ static hipError_t seg_dispatch_pol(const DevPlan &P, const RunArgs &a, hipStream
     const int chunks = a.vec_ok ? (a.np + EV - 1) / EV : a.np;
     dim3 grid(grid_for_waves(waves)), block(256);
     if (a.vec_ok) {
-        if (chunks <= 64) hipLaunchKernelGGL((segment_kernel<VT, BT, EV, 1, POL>), grid, block, 0, s, P, a);
-        else hipLaunchKernelGGL((segment_kernel<VT, BT, EV, 2, POL>), grid, block, 0, s, P, a);
+        if (chunks <= 64) launch_kernel((segment_kernel<VT, BT, EV, 1, POL>), grid, block, 0, s, P, a);
+        else launch_kernel((segment_kernel<VT, BT, EV, 2, POL>), grid, block, 0, s, P, a);
     } else {
-        hipLaunchKernelGGL((segment_kernel<VT, BT, 1, 2, POL>), grid, block, 0, s, P, a);
+        launch_kernel((segment_kernel<VT, BT, 1, 2, POL>), grid, block, 0, s, P, a);
     }
     return hipGetLastError();
 }
@@ -143,10 +143,10 @@ static hipError_t vec_dispatch_var(const DevPlan &P, const RunArgs &a, hipStream
     const int chunks = a.vec_ok ? (a.np + EV - 1) / EV : a.np;
     dim3 grid(grid_for_waves(waves)), block(256);
     if (a.vec_ok) {
-        if (chunks <= 64) hipLaunchKernelGGL((vector_kernel<VT, BT, EV, 1, VAR>), grid, block, 0, s, P, a);
-        else hipLaunchKernelGGL((vector_kernel<VT, BT, EV, 2, VAR>), grid, block, 0, s, P, a);
+        if (chunks <= 64) launch_kernel((vector_kernel<VT, BT, EV, 1, VAR>), grid, block, 0, s, P, a);
+        else launch_kernel((vector_kernel<VT, BT, EV, 2, VAR>), grid, block, 0, s, P, a);
     } else {
-        hipLaunchKernelGGL((vector_kernel<VT, BT, 1, 2, VAR>), grid, block, 0, s, P, a);
+        launch_kernel((vector_kernel<VT, BT, 1, 2, VAR>), grid, block, 0, s, P, a);
     }
     return hipGetLastError();
 }
@@ -168,17 +168,17 @@ static hipError_t win_dispatch(const DevPlan &P, const RunArgs &a, hipStream_t s
 #define SPMM_WIN_NP(MB, NP)                                                                          \
     do {                                                                                             \
         if (partial)                                                                                 \
-            hipLaunchKernelGGL((window_partial_kernel<VT, BT, TT, MB, EV, 1, NP>), grid, block, 0, s, P, a); \
+            launch_kernel((window_partial_kernel<VT, BT, TT, MB, EV, 1, NP>), grid, block, 0, s, P, a); \
         else                                                                                         \
-            hipLaunchKernelGGL((window_kernel<VT, BT, TT, MB, EV, 1, NP>), grid, block, 0, s, P, a);  \
+            launch_kernel((window_kernel<VT, BT, TT, MB, EV, 1, NP>), grid, block, 0, s, P, a);  \
     } while (0)
 #define SPMM_WIN(MB)                                                                                 \
     do {                                                                                             \
         if (!a.vec_ok) {                                                                             \
             if (partial)                                                                             \
-                hipLaunchKernelGGL((window_partial_kernel<VT, BT, TT, MB, 1, 2, 128>), grid, block, 0, s, P, a); \
+                launch_kernel((window_partial_kernel<VT, BT, TT, MB, 1, 2, 128>), grid, block, 0, s, P, a); \
             else                                                                                     \
-                hipLaunchKernelGGL((window_kernel<VT, BT, TT, MB, 1, 2, 128>), grid, block, 0, s, P, a); \
+                launch_kernel((window_kernel<VT, BT, TT, MB, 1, 2, 128>), grid, block, 0, s, P, a); \
         } else if constexpr (BT == DT_F32) {                                                         \
             SPMM_WIN_NP(MB, 128);                                                                    \
         } else {                                                                                     \

@@ -691,6 +691,11 @@ spmm_status check_run(const spmm_plan_t *p, const void *B, int64_t ldb, void *C,
     return SPMM_OK;
 }
 
+LaunchEvents &launch_events() {
+    thread_local LaunchEvents ev;
+    return ev;
+}
+
 bool serial_exec(const spmm_plan_t *p, const RunArgs &a) {
     // co-scheduled runs address their workspace through a 32-bit buffer range
     return p->hp.opts.exec == 1 || a.cold_aux >= 0 ||
@@ -727,14 +732,20 @@ spmm_status launch_plan(const spmm_plan_t *p, const RunArgs &a0, hipStream_t s, 
     const DevPlan &P = p->dp;
     RunArgs a = a0;
     a.work = ctx.work;
+    // a timed kernel records its pair of events inside its own dispatch
     auto timed = [&](int kid, hipStream_t ks, auto &&launch) -> spmm_status {
         const bool rec = t != nullptr;
         if (rec && t->used >= t->cap) return set_error(SPMM_ERR_INVALID, "timer is full");
-        if (rec) SPMM_TRY_HIP(hipEventRecord(t->ev[2 * t->used], ks), "hipEventRecord");
+        if (rec) launch_events() = LaunchEvents{t->ev[2 * t->used], t->ev[2 * t->used + 1]};
         hipError_t e = launch();
+        const bool launched = launch_events().start == nullptr;
+        launch_events() = LaunchEvents{};
         if (e != hipSuccess) return hip_error(e, "kernel launch");
         if (rec) {
-            SPMM_TRY_HIP(hipEventRecord(t->ev[2 * t->used + 1], ks), "hipEventRecord");
+            if (!launched) {  // nothing to launch: an empty interval
+                SPMM_TRY_HIP(hipEventRecord(t->ev[2 * t->used], ks), "hipEventRecord");
+                SPMM_TRY_HIP(hipEventRecord(t->ev[2 * t->used + 1], ks), "hipEventRecord");
+            }
             t->ids[t->used] = kid;
             t->used++;
         }
