@@ -1307,12 +1307,22 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
                 const int incl = wave_inclusive_scan(q4 == 0 ? pc : 0);
                 const int base = tv + carry + incl - pc + __popc(word & ((1u << (8 * q4)) - 1u));
                 carry += __shfl(incl, 63, 64);
+                // this lane's values are consecutive in the packed order:
+                // one (2-byte aligned) 16-byte load at `base` holds them (the
+                // plan's arrays end in at least 16 zero bytes), then set bit
+                // i takes the next value in turn
+                u32x4 raw;
+                __builtin_memcpy(&raw, P.tile_vals + max(min(base, vend), 0), 16);
+                uint64_t lo = (uint64_t)raw[0] | ((uint64_t)raw[1] << 32);
+                uint64_t hi = (uint64_t)raw[2] | ((uint64_t)raw[3] << 32);
                 unsigned short x[8];
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
-                    const int idx = base + __popc(mine & ((1u << i) - 1u));
-                    const unsigned short t = P.tile_vals[max(min(idx, vend - 1), 0)];
-                    x[i] = (mine >> i) & 1u ? t : (unsigned short)0;
+                    const bool set = (mine >> i) & 1u;
+                    x[i] = set ? (unsigned short)(lo & 0xFFFFu) : (unsigned short)0;
+                    const uint64_t nlo = (lo >> 16) | (hi << 48), nhi = hi >> 16;
+                    lo = set ? nlo : lo;
+                    hi = set ? nhi : hi;
                 }
 #pragma unroll
                 for (int i = 0; i < 4; ++i) av[rp][i] = (uint32_t)x[2 * i] | ((uint32_t)x[2 * i + 1] << 16);
