@@ -347,9 +347,19 @@ def gather_rate(K, steps, m=1 << 20, deg=16, n=128):
 
 
 def gather_probe(args):
-    """The random-gather ceiling for B of 512 MiB, 64 MiB and 4 MiB."""
+    """The random-gather ceiling for B of 512 MiB, 64 MiB and 4 MiB: the
+    vector path over uniformly random columns, and the same columns gathered
+    with nothing else done (spmm_gather_bandwidth)."""
+    import torch
+    from paper_2606_22482_amd import api
     for K in (1 << 20, 1 << 17, 1 << 13):
-        print(json.dumps(gather_rate(K, args.steps)), flush=True)
+        r = gather_rate(K, args.steps)
+        cols = torch.randint(0, K, ((1 << 20) * 16,), dtype=torch.int32, device="cuda",
+                             generator=torch.Generator(device="cuda").manual_seed(1))
+        Bg = torch.randn(K, 128, device="cuda")
+        r["gather_only_GBps"] = round(api.spmm_gather_bandwidth(cols, Bg, 128, reps=args.steps) / 1e9, 1)
+        del cols, Bg
+        print(json.dumps(r), flush=True)
 
 
 def batch_bench(args):
@@ -662,11 +672,20 @@ def main():
         # a B of the same size (the ceiling of this access pattern)
         probe = gather_rate(A.k, 10)
         g = A.nnz * n * 4 / (roof["kernel"]["avg_launch_ms"] * 1e-3) / 1e9
+        # and against the same B rows, in the same order, gathered with
+        # nothing else done (no values, no FMA, no C)
+        import torch
+        cols = torch.from_numpy(np.ascontiguousarray(A.colidx, dtype=np.int32)).cuda()
+        Bg = torch.randn(A.k, n, device="cuda")
+        only = api.spmm_gather_bandwidth(cols, Bg, n, reps=10) / 1e9
+        del cols, Bg
         roof["gather"] = {"gathered_bytes": int(A.nnz * n * 4), "GBps": round(g, 1),
                           "uniform_random_GBps": probe["gathered_GBps"],
-                          "frac_of_uniform_random": round(g / probe["gathered_GBps"], 3)}
-        log("gathers: %.1f GB/s vs %.1f GB/s uniformly random over the same B size"
-            % (g, probe["gathered_GBps"]))
+                          "frac_of_uniform_random": round(g / probe["gathered_GBps"], 3),
+                          "gather_only_GBps": round(only, 1),
+                          "frac_of_gather_only": round(g / only, 3)}
+        log("gathers: %.1f GB/s vs %.1f GB/s uniformly random over the same B size, %.1f GB/s "
+            "for the same rows gathered alone" % (g, probe["gathered_GBps"], only))
     gflops = 2.0 * A.nnz * n / (ms * 1e-3) / 1e9
     out = {
         "metric": METRIC,

@@ -459,6 +459,19 @@ spmm_status spmm_adapt_epoch(const spmm_csr *A, spmm_plan_t **plan, const void *
 /* Device copy bandwidth (read + write bytes per second) over `bytes` bytes. */
 spmm_status spmm_copy_bandwidth(int64_t bytes, void *stream, double *bytes_per_s);
 
+/* Gather ceiling of a column sequence (the B-row gathers of Eq. 1 with
+ * nothing else done): times `reps` launches (after 3 untimed ones) of a
+ * kernel that reads, for each of the n row ids in `rows` (device, int32; an
+ * id outside [0, k) is clamped), the first n_cols f32 of that row of B
+ * (device, k rows of leading dimension ldb f32, 16-byte aligned) and sums
+ * them in registers, writing nothing; on `stream`, which is synchronised.
+ * *bytes_per_s = n * n_cols * 4 * reps / time.  n_cols a multiple of 4 in
+ * [4, 128], ldb a multiple of 4 and >= n_cols, k <= 2^31 - 1; else INVALID.
+ * Allocates and frees 256 bytes of device memory. */
+spmm_status spmm_gather_bandwidth(const int32_t *rows, int64_t n, const void *B, int64_t k,
+                                  int64_t ldb, int32_t n_cols, int32_t reps, void *stream,
+                                  double *bytes_per_s);
+
 #ifdef __cplusplus
 }
 #endif

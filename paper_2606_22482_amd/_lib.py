@@ -126,6 +126,8 @@ SIGNATURES = {
     "spmm_dryrun": (_S, [C.c_int32, C.c_int32, _P, C.POINTER(C.c_double),
                          C.POINTER(C.c_double)]),
     "spmm_copy_bandwidth": (_S, [C.c_int64, _P, C.POINTER(C.c_double)]),
+    "spmm_gather_bandwidth": (_S, [_P, C.c_int64, _P, C.c_int64, C.c_int64, C.c_int32, C.c_int32, _P,
+                                   C.POINTER(C.c_double)]),
     "spmm_adapt_next": (_S, [C.POINTER(AdaptState), C.c_double, C.c_double, C.c_double,
                              C.c_double, C.c_double, C.c_double, C.c_double, C.c_float]),
     "spmm_adapt_epoch": (_S, [C.POINTER(Csr), C.POINTER(_P), _P, C.c_int64, _P, C.c_int64, _P,

@@ -14,7 +14,8 @@ import numpy as np
 from . import _lib as L
 
 __all__ = ["Plan", "Timer", "spmm_plan", "spmm_run", "spmm_submit", "spmm_poll", "spmm_wait",
-           "spmm_dryrun", "spmm_copy_bandwidth", "default_opts", "SpmmError"]
+           "spmm_dryrun", "spmm_copy_bandwidth", "spmm_gather_bandwidth", "default_opts",
+           "SpmmError"]
 
 SpmmError = L.SpmmError
 
@@ -426,6 +427,24 @@ def spmm_copy_bandwidth(nbytes: int, stream=None) -> float:
     lib = L.load()
     out = C.c_double()
     L.check(lib.spmm_copy_bandwidth(int(nbytes), _stream_handle(stream), C.byref(out)))
+    return out.value
+
+
+def spmm_gather_bandwidth(rows, B, n_cols: int = None, reps: int = 10, stream=None) -> float:
+    """Bytes per second at which the device gathers the B rows named by the
+    int32 device tensor ``rows`` (the first ``n_cols`` f32 of each row of the
+    f32 device matrix ``B``) with nothing else done."""
+    import torch
+    if rows.dtype != torch.int32 or not rows.is_cuda or not rows.is_contiguous():
+        raise ValueError("rows must be a contiguous int32 device tensor")
+    if B.dtype != torch.float32 or not B.is_cuda or B.dim() != 2 or B.stride(1) != 1:
+        raise ValueError("B must be a row-major f32 device matrix")
+    n_cols = B.shape[1] if n_cols is None else n_cols
+    lib = L.load()
+    out = C.c_double()
+    L.check(lib.spmm_gather_bandwidth(C.c_void_p(rows.data_ptr()), rows.numel(),
+                                      C.c_void_p(B.data_ptr()), B.shape[0], B.stride(0),
+                                      int(n_cols), int(reps), _stream_handle(stream), C.byref(out)))
     return out.value
 
 

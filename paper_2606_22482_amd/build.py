@@ -28,7 +28,7 @@ CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-pthread", "-I", INCLUDE, "
              "-I", "/opt/rocm/include"]
 
 HIP_SOURCES = ["kernels.hip", "fused.hip", "runtime.hip", "submit.hip", "autotune.hip", "devbuild.hip",
-               "devmixed.hip"]
+               "devmixed.hip", "probe.hip"]
 CXX_SOURCES = ["plan.cpp", "serialize.cpp"]
 
 

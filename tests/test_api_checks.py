@@ -88,3 +88,30 @@ def test_autotune_context_is_validated(plans):
     assert st == L.SPMM_ERR_INVALID
     assert b"context" in lib.spmm_last_error()
     del keep
+
+
+def test_gather_probe_argument_checks():
+    """spmm_gather_bandwidth refuses bad sizes and pointers with INVALID
+    before any device call (the pointers here are never dereferenced)."""
+    import ctypes as C
+    from paper_2606_22482_amd import _lib as L
+    lib = L.load()
+    out = C.c_double()
+    fake = C.c_void_p(0x100000)  # 16-byte aligned, never touched
+    bad = [
+        (None, 16, fake, 8, 128, 128, 1),      # no row ids
+        (fake, 16, None, 8, 128, 128, 1),      # no B
+        (fake, 0, fake, 8, 128, 128, 1),       # empty sequence
+        (fake, 16, fake, 0, 128, 128, 1),      # no rows in B
+        (fake, 16, fake, 8, 128, 130, 1),      # rows wider than 128 f32
+        (fake, 16, fake, 8, 128, 6, 1),        # not a multiple of 4
+        (fake, 16, fake, 8, 64, 128, 1),       # ldb below n_cols
+        (fake, 16, fake, 8, 130, 128, 1),      # ldb not a multiple of 4
+        (fake, 16, fake, 8, 128, 128, 0),      # no repetitions
+        (fake, 16, C.c_void_p(0x100004), 8, 128, 128, 1),  # B not 16-byte aligned
+        (fake, 16, fake, 1 << 31, 128, 128, 1),  # k beyond int32
+    ]
+    for rows, n, B, k, ldb, ncols, reps in bad:
+        st = lib.spmm_gather_bandwidth(rows, n, B, k, ldb, ncols, reps, None, C.byref(out))
+        assert st == L.SPMM_ERR_INVALID, (n, k, ldb, ncols, reps)
+    assert lib.spmm_gather_bandwidth(fake, 16, fake, 8, 128, 128, 1, None, None) == L.SPMM_ERR_INVALID

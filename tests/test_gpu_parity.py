@@ -547,3 +547,20 @@ def test_timer_and_copy_bandwidth():
     bw = api.spmm_copy_bandwidth(1 << 28)
     assert bw > 1e11
     torch.cuda.synchronize()
+
+
+def test_gather_probe():
+    """spmm_gather_bandwidth over random row ids (ids outside [0, k) are
+    clamped), at full and partial row widths; the rate is positive and the
+    caller's tensors are untouched."""
+    import torch
+    g = torch.Generator(device="cuda").manual_seed(5)
+    k = 4096
+    B = torch.randn(k, 128, device="cuda", generator=g)
+    rows = torch.randint(-50, k + 50, (1 << 18,), dtype=torch.int32, device="cuda", generator=g)
+    B0, r0 = B.clone(), rows.clone()
+    for ncols in (128, 64, 4):
+        bw = api.spmm_gather_bandwidth(rows, B, ncols, reps=3)
+        assert bw > 1e10, (ncols, bw)
+    torch.cuda.synchronize()
+    assert torch.equal(B, B0) and torch.equal(rows, r0)
