@@ -713,7 +713,7 @@ def main():
     del results
     if args.workload == "all":
         configs = {}
-        for key in ("block", "uniform"):
+        for key in ("gnn64", "block", "uniform"):
             A2, B2, bk2, wn2, n2, res2 = measure(key, args, pick(key), extra)
             b2, ms2, roof2, modes2 = summarise(A2, bk2, wn2, n2, res2, copy_gbs)
             configs[wn2] = {"best": b2, "ms_per_step": round(ms2, 5),

@@ -261,15 +261,21 @@ spmm_status spmm_plan(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_ty
                       const spmm_opts *opts, spmm_plan_t **out);
 /* Release a plan.  BUSY while batched submissions that use it are unfinished. */
 spmm_status spmm_plan_destroy(spmm_plan_t *p);
-/* A plain plan built on the device from a CSR whose rowptr, colidx and vals
- * are device pointers (sizes as in spmm_csr), work enqueued on `stream`
- * (which is synchronised): the CSR checks, row lengths (Eq. 4), the item cut,
- * the launch order and the segments run as kernels, and A's entries are
- * copied device to device; only O(m) schedule arrays are read back for
- * statistics.  The result equals spmm_plan's plain plan of the same matrix
- * and options array for array.  UNSUPPORTED for a mode other than AUTO or
- * PLAIN_F32, a cold policy, or item_cost > 4096; INVALID for a malformed CSR
- * (found on the device, before anything is indexed by it). */
+/* A plan built on the device from a CSR whose rowptr, colidx and vals are
+ * device pointers (sizes as in spmm_csr), work enqueued on `stream` (which
+ * is synchronised); AUTO means PLAIN_F32 here.  Plain plans: the CSR checks,
+ * row lengths (Eq. 4), the item cut, the launch order and the segments run
+ * as kernels, and A's entries are copied device to device; only O(m)
+ * schedule arrays are read back.  Mixed and MFMA-only plans (Sec. 5.2.2,
+ * Sec. 6.1): the row stage (Eq. 5), the window slots (original ranges, or
+ * the passing rows compacted, or those stably sorted by decreasing length),
+ * the column stage, the K-tile density test, the remainder, the bitmaps and
+ * the packed values run as kernels; O(m + windows + tiles) arrays come back
+ * for the schedule.  The result equals spmm_plan's plan of the same matrix
+ * and options array for array.  UNSUPPORTED for clustered windows or local
+ * reordering (built on the host), a cold policy, kt other than 32, or (plain)
+ * item_cost > 4096; INVALID for a malformed CSR (found on the device, before
+ * anything is indexed by it). */
 spmm_status spmm_plan_device(const spmm_csr *A, int32_t n, int32_t b_type, int32_t c_type,
                              const spmm_opts *opts, void *stream, spmm_plan_t **out);
 /* Plan images, so that a plan is built once and loaded by later processes

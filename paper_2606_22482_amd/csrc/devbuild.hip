@@ -312,12 +312,8 @@ extern "C" spmm_status spmm_plan_device(const spmm_csr *A, int32_t n, int32_t b_
         if (in.mode == SPMM_MODE_AUTO) in.mode = SPMM_MODE_PLAIN_F32;
         resolve_options(&in, A, n, b_type, &o);
     }
-    if (o.mode != SPMM_MODE_PLAIN_F32) {
-        // windows of fixed row ranges, partitioned on the device
-        if (o.row_order != SPMM_ORDER_ORIGINAL_RANGES)
-            return set_error(SPMM_ERR_UNSUPPORTED, "device-built mixed plans use original-ranges windows");
+    if (o.mode != SPMM_MODE_PLAIN_F32)  // windows and tiles partitioned on the device
         return plan_device_mixed(A, n, b_type, c_type, o, static_cast<hipStream_t>(stream), out);
-    }
     if (o.cold_policy != 0) return set_error(SPMM_ERR_UNSUPPORTED, "device-built plans gather with the default policy");
     if (o.item_cost > 4096) return set_error(SPMM_ERR_UNSUPPORTED, "device-built plans need item_cost <= 4096");
     st = validate_opts(o, err);

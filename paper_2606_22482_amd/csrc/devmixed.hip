@@ -1,12 +1,17 @@
-// devmixed.hip -- a mixed plan (windows of fixed row ranges) partitioned on
-// the device, from a CSR already in device memory (Sec. 5.2.2 and Sec. 6.1
-// preprocessing without moving A through the host; Sec. 8.6 overheads).
+// devmixed.hip -- a mixed plan partitioned on the device, from a CSR already
+// in device memory (Sec. 5.2.2 and Sec. 6.1 preprocessing without moving A
+// through the host; Sec. 8.6 overheads).
 //
 // The partition is the host builder's, step for step, so the plan equals the
 // host plan of the same matrix and options array for array:
 //   1. rows: Len(r) (Eq. 4) and the row stage Len(r) > t_row (Eq. 5); CSR
 //      checks (the host reads the error flag before anything is indexed);
-//   2. the column stage of every window w (rows [wH, wH + H)): the keys
+//      the window slots: original ranges (slot i is row i when it passes),
+//      or the passing rows compacted in row order (a stream compaction),
+//      optionally stably sorted by decreasing length (a radix sort of the
+//      lengths, which keeps equal lengths in row order) -- window w takes
+//      slots [wH, wH + H);
+//   2. the column stage of every window w (its slots' rows): the keys
 //      (w, column) of its passing rows' entries are sorted and counted, and a
 //      column whose count exceeds floor(alpha_c H) is a tile column; tile
 //      columns in ascending order are cut into K-tiles of kt, a K-tile is
@@ -97,16 +102,53 @@ __global__ __launch_bounds__(kThreads) void k_mcount_seen(int64_t k, const uint8
     if ((threadIdx.x & 63) == 0 && s) atomicAdd(count, s);
 }
 
+// row stage flags (Len(r) > t_row, Eq. 5) for the compacted slot list
+__global__ __launch_bounds__(kThreads) void k_passflag(int64_t m, int32_t t_row, const int32_t *__restrict__ rp32,
+                                                       int64_t *__restrict__ flag) {
+    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (r < m) flag[r] = (int64_t)(rp32[r + 1] - rp32[r]) > (int64_t)t_row ? 1 : 0;
+}
+
+// the passing rows in row order (flag scanned into pos)
+__global__ __launch_bounds__(kThreads) void k_compact(int64_t m, const int64_t *__restrict__ flag,
+                                                      const int64_t *__restrict__ pos, int32_t *__restrict__ D) {
+    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (r < m && flag[r]) D[pos[r]] = (int32_t)r;
+}
+
+__global__ __launch_bounds__(kThreads) void k_lenkeys(int64_t nD, const int32_t *__restrict__ D,
+                                                      const int32_t *__restrict__ rp32, int32_t *__restrict__ key) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < nD) key[i] = rp32[D[i] + 1] - rp32[D[i]];
+}
+
+// slot i of the windows holds row D[i] (-1 past the list); wpos is its inverse
+__global__ __launch_bounds__(kThreads) void k_slots(int64_t WH, int64_t nD, const int32_t *__restrict__ D,
+                                                    int32_t *__restrict__ slot_row, int32_t *__restrict__ wpos) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= WH) return;
+    const int32_t r = i < nD ? D[i] : -1;
+    slot_row[i] = r;
+    if (r >= 0) wpos[r] = (int32_t)i;
+}
+
+// window slot of a passing row: the row itself (original ranges) or its
+// position in the compacted / sorted slot list
+__device__ __forceinline__ int64_t slot_of(const int32_t *__restrict__ wpos, int64_t r) {
+    return wpos ? (int64_t)wpos[r] : r;
+}
+
 // keys (window << 32 | column) of the passing rows' entries, row by row
 __global__ __launch_bounds__(kThreads) void k_keys(int64_t m, int32_t H, const int32_t *__restrict__ rp32,
                                                    const int32_t *__restrict__ colidx,
                                                    const int64_t *__restrict__ plen,
+                                                   const int32_t *__restrict__ wpos,
                                                    const int64_t *__restrict__ kpos, uint64_t *__restrict__ keys) {
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= m || plen[r] == 0) return;
     const int lane = threadIdx.x & 63;
     const int64_t b = rp32[r], e = rp32[r + 1], o = kpos[r];
-    const uint64_t w = (uint64_t)(r / H) << 32;
+    const uint64_t w = (uint64_t)(slot_of(wpos, r) / H) << 32;
     for (int64_t p = b + lane; p < e; p += 64) keys[o + (p - b)] = w | (uint32_t)colidx[p];
 }
 
@@ -182,6 +224,7 @@ __global__ __launch_bounds__(kThreads) void k_wkept(int64_t W, const int64_t *__
 // kept windows: their row slots, first tile, and the tiles' columns
 __global__ __launch_bounds__(kThreads) void k_wfill(int64_t W, int64_t m, int32_t H, int32_t t_row,
                                                     const int32_t *__restrict__ rp32,
+                                                    const int32_t *__restrict__ slot_row,
                                                     const int64_t *__restrict__ wkeep, const int64_t *__restrict__ widx,
                                                     const int64_t *__restrict__ wtile0,
                                                     int32_t *__restrict__ windows, int32_t *__restrict__ win_tile_ptr) {
@@ -190,8 +233,12 @@ __global__ __launch_bounds__(kThreads) void k_wfill(int64_t W, int64_t m, int32_
     const int64_t x = widx[w];
     for (int s = 0; s < H; ++s) {
         const int64_t r = w * H + s;
-        const bool pass = r < m && (int64_t)(rp32[r + 1] - rp32[r]) > (int64_t)t_row;
-        windows[x * H + s] = pass ? (int32_t)r : -1;
+        if (slot_row) {
+            windows[x * H + s] = slot_row[r];
+        } else {
+            const bool pass = r < m && (int64_t)(rp32[r + 1] - rp32[r]) > (int64_t)t_row;
+            windows[x * H + s] = pass ? (int32_t)r : -1;
+        }
     }
     win_tile_ptr[x] = (int32_t)wtile0[w];
 }
@@ -212,7 +259,7 @@ __global__ __launch_bounds__(kThreads) void k_tcols(int64_t W, const int64_t *__
     }
 }
 
-// slot of entry p (row r = wH + s, column c) in a kept K-tile, or -1
+// slot of entry p (the row in window slot wH + s, column c) in a kept K-tile, or -1
 __device__ __forceinline__ int64_t entry_slot(int64_t w, int s, int32_t c, int32_t H,
                                               const int64_t *__restrict__ start, const int64_t *__restrict__ cbase,
                                               const int64_t *__restrict__ kept, const int64_t *__restrict__ tile_id,
@@ -233,15 +280,16 @@ __device__ __forceinline__ int64_t entry_slot(int64_t w, int s, int32_t c, int32
 // step 3: the winning (first) entry of every slot
 __global__ __launch_bounds__(kThreads) void k_assign(int64_t m, int32_t H, const int32_t *__restrict__ rp32,
                                                      const int32_t *__restrict__ colidx, const int64_t *__restrict__ plen,
+                                                     const int32_t *__restrict__ wpos,
                                                      const int64_t *__restrict__ wkeep, const int64_t *__restrict__ start,
                                                      const int64_t *__restrict__ cbase, const int64_t *__restrict__ kept,
                                                      const int64_t *__restrict__ tile_id,
                                                      const uint64_t *__restrict__ mkey, int32_t *__restrict__ src) {
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= m || plen[r] == 0) return;
-    const int64_t w = r / H;
+    const int64_t pos = slot_of(wpos, r), w = pos / H;
     if (!wkeep[w]) return;
-    const int s = (int)(r - w * H), lane = threadIdx.x & 63;
+    const int s = (int)(pos - w * H), lane = threadIdx.x & 63;
     for (int64_t p = rp32[r] + lane; p < rp32[r + 1]; p += 64) {
         const int64_t slot = entry_slot(w, s, colidx[p], H, start, cbase, kept, tile_id, mkey);
         if (slot >= 0) atomicMin(src + slot, (int32_t)p);
@@ -251,6 +299,7 @@ __global__ __launch_bounds__(kThreads) void k_assign(int64_t m, int32_t H, const
 // in-tile flags of every entry, and the row's remainder length
 __global__ __launch_bounds__(kThreads) void k_intile(int64_t m, int32_t H, const int32_t *__restrict__ rp32,
                                                      const int32_t *__restrict__ colidx, const int64_t *__restrict__ plen,
+                                                     const int32_t *__restrict__ wpos,
                                                      const int64_t *__restrict__ wkeep, const int64_t *__restrict__ start,
                                                      const int64_t *__restrict__ cbase, const int64_t *__restrict__ kept,
                                                      const int64_t *__restrict__ tile_id,
@@ -259,9 +308,12 @@ __global__ __launch_bounds__(kThreads) void k_intile(int64_t m, int32_t H, const
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= m) return;
     const int lane = threadIdx.x & 63;
-    const int64_t w = r / H, b = rp32[r], e = rp32[r + 1];
+    // a row with entries past the row stage has a window slot; no other row
+    // looks one up
+    const int64_t pos = plen[r] > 0 ? slot_of(wpos, r) : 0;
+    const int64_t w = pos / H, b = rp32[r], e = rp32[r + 1];
     const bool maybe = plen[r] > 0 && wkeep[w];
-    const int s = (int)(r - w * H);
+    const int s = (int)(pos - w * H);
     int64_t tin = 0;
     for (int64_t p = b + lane; p < e; p += 64) {
         bool t = false;
@@ -411,8 +463,14 @@ spmm_status plan_device_mixed(const spmm_csr *A, int32_t n, int32_t b_type, int3
     if (o.cold_policy != 0) return set_error(SPMM_ERR_UNSUPPORTED, "device-built plans gather with the default policy");
     if (o.kt != kKt) return set_error(SPMM_ERR_UNSUPPORTED, "kt must be 32");
     const int64_t m = A->m, k = A->k, nnz = A->nnz;
+    if (o.row_order != SPMM_ORDER_ORIGINAL_RANGES && o.row_order != SPMM_ORDER_COMPACTED &&
+        o.row_order != SPMM_ORDER_LENGTH_SORTED)
+        return set_error(SPMM_ERR_UNSUPPORTED, "device-built mixed plans use original-ranges, compacted or "
+                                               "length-sorted windows");
+    if (o.local_reorder > 0)
+        return set_error(SPMM_ERR_UNSUPPORTED, "device-built mixed plans take no local reordering");
     const int H = o.window_h, sval = dtype_size(A->val_type);
-    const int64_t W = (m + H - 1) / H;  // candidate windows
+    int64_t W = (m + H - 1) / H;  // candidate windows (at most one per H rows)
     const int32_t col_thr = (int32_t)std::floor((double)o.alpha_c * (double)H);
     const double keep_thr = (double)o.alpha * (double)(H * kKt);
     auto sync = [&]() { return hipStreamSynchronize(s); };
@@ -451,6 +509,51 @@ spmm_status plan_device_mixed(const spmm_csr *A, int32_t n, int32_t b_type, int3
         SPMM_TRY_HIP(sync(), "hipStreamSynchronize");
         if (bad_h & 1) return set_error(SPMM_ERR_INVALID, "rowptr not monotone from 0 to nnz");
         if (bad_h & 2) return set_error(SPMM_ERR_INVALID, "column index out of range");
+        // window slots: original ranges need no list; otherwise the passing
+        // rows compacted in row order, for length-sorted windows stably
+        // sorted by decreasing length (the radix sort keeps equal keys in
+        // their input order, i.e. row order, as the host's stable sort)
+        int32_t *wpos = nullptr, *slot_row = nullptr;
+        if (o.row_order != SPMM_ORDER_ORIGINAL_RANGES && m > 0) {
+            int64_t *pflag, *ppos;
+            SPMM_ALLOC(pflag, m);
+            SPMM_ALLOC(ppos, m);
+            hipLaunchKernelGGL(k_passflag, dim3(blocks_for(m)), dim3(kThreads), 0, s, m, o.t_row, rp32, pflag);
+            SPMM_TRY_HIP(scan64(pflag, ppos, m, 0, sums, s), "scan");
+            int64_t nD = 0;
+            SPMM_TRY_HIP(hipMemcpyAsync(&nD, sums + (scan_sums_len(m) - 1), 8, hipMemcpyDeviceToHost, s),
+                         "hipMemcpyAsync");
+            SPMM_TRY_HIP(sync(), "hipStreamSynchronize");
+            int32_t *D;
+            SPMM_ALLOC(D, nD);
+            SPMM_ALLOC(wpos, m);
+            hipLaunchKernelGGL(k_fill32, dim3((unsigned)std::min<int64_t>(blocks_for(m), 65536)), dim3(kThreads), 0, s,
+                               m, (int32_t)-1, wpos);
+            if (nD > 0)
+                hipLaunchKernelGGL(k_compact, dim3(blocks_for(m)), dim3(kThreads), 0, s, m, pflag, ppos, D);
+            const int32_t *Dord = D;
+            if (o.row_order == SPMM_ORDER_LENGTH_SORTED && nD > 1) {
+                int32_t *Ds, *lk, *lks;
+                SPMM_ALLOC(Ds, nD);
+                SPMM_ALLOC(lk, nD);
+                SPMM_ALLOC(lks, nD);
+                hipLaunchKernelGGL(k_lenkeys, dim3(blocks_for(nD)), dim3(kThreads), 0, s, nD, D, rp32, lk);
+                size_t tb = 0;
+                SPMM_TRY_HIP(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tb, lk, lks, D, Ds, (int)nD, 0, 32, s),
+                             "radix sort");
+                uint8_t *tmp;
+                SPMM_ALLOC(tmp, tb);
+                SPMM_TRY_HIP(hipcub::DeviceRadixSort::SortPairsDescending(tmp, tb, lk, lks, D, Ds, (int)nD, 0, 32, s),
+                             "radix sort");
+                Dord = Ds;
+            }
+            W = (nD + H - 1) / H;
+            SPMM_ALLOC(slot_row, W * H);
+            if (W > 0)
+                hipLaunchKernelGGL(k_slots, dim3(blocks_for(W * H)), dim3(kThreads), 0, s, W * H, nD, Dord, slot_row,
+                                   wpos);
+            SPMM_TRY_HIP(hipGetLastError(), "device plan kernels");
+        }
         // 2. column stage: sorted (window, column) keys and their counts
         int64_t npass = 0;
         if (m > 0) {
@@ -469,8 +572,8 @@ spmm_status plan_device_mixed(const spmm_csr *A, int32_t n, int32_t b_type, int3
         SPMM_ALLOC(nruns, 1);
         int64_t nrun = 0;
         if (npass > 0) {
-            hipLaunchKernelGGL(k_keys, dim3(row_blocks(m)), dim3(kThreads), 0, s, m, H, rp32, A->colidx, plen, kpos,
-                               keys);
+            hipLaunchKernelGGL(k_keys, dim3(row_blocks(m)), dim3(kThreads), 0, s, m, H, rp32, A->colidx, plen, wpos,
+                               kpos, keys);
             int end_bit = 33;
             while (end_bit < 64 && (W >> (end_bit - 32)) > 0) ++end_bit;
             size_t tb = 0, tb2 = 0;
@@ -546,16 +649,16 @@ spmm_status plan_device_mixed(const spmm_csr *A, int32_t n, int32_t b_type, int3
         SPMM_ALLOC(tile_cols, T * kKt);
         SPMM_ALLOC(src, T * H * kKt);
         if (Wk > 0) {
-            hipLaunchKernelGGL(k_wfill, dim3(blocks_for(W)), dim3(kThreads), 0, s, W, m, H, o.t_row, rp32, wkeep, widx,
-                               wtile0, windows, win_tile_ptr);
+            hipLaunchKernelGGL(k_wfill, dim3(blocks_for(W)), dim3(kThreads), 0, s, W, m, H, o.t_row, rp32, slot_row,
+                               wkeep, widx, wtile0, windows, win_tile_ptr);
             const int32_t Ti = (int32_t)T;
             SPMM_TRY_HIP(hipMemcpyAsync(win_tile_ptr + Wk, &Ti, 4, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
             hipLaunchKernelGGL(k_tcols, dim3(blocks_for(W)), dim3(kThreads), 0, s, W, start, cbase, kept, tile_id, mkey,
                                tile_cols);
             hipLaunchKernelGGL(k_fill32, dim3((unsigned)std::min<int64_t>(blocks_for(T * H * kKt), 65536)),
                                dim3(kThreads), 0, s, T * H * kKt, (int32_t)INT_MAX, src);
-            hipLaunchKernelGGL(k_assign, dim3(row_blocks(m)), dim3(kThreads), 0, s, m, H, rp32, A->colidx, plen, wkeep,
-                               start, cbase, kept, tile_id, mkey, src);
+            hipLaunchKernelGGL(k_assign, dim3(row_blocks(m)), dim3(kThreads), 0, s, m, H, rp32, A->colidx, plen, wpos,
+                               wkeep, start, cbase, kept, tile_id, mkey, src);
         }
         // 3. in-tile flags, remainder lengths and the remainder
         uint8_t *in_tile;
@@ -565,8 +668,8 @@ spmm_status plan_device_mixed(const spmm_csr *A, int32_t n, int32_t b_type, int3
         SPMM_ALLOC(rem_ptr, m + 1);
         int64_t nrem = 0;
         if (m > 0) {
-            hipLaunchKernelGGL(k_intile, dim3(row_blocks(m)), dim3(kThreads), 0, s, m, H, rp32, A->colidx, plen, wkeep,
-                               start, cbase, kept, tile_id, mkey, src, in_tile, rem_len);
+            hipLaunchKernelGGL(k_intile, dim3(row_blocks(m)), dim3(kThreads), 0, s, m, H, rp32, A->colidx, plen, wpos,
+                               wkeep, start, cbase, kept, tile_id, mkey, src, in_tile, rem_len);
             SPMM_TRY_HIP(scan64(rem_len, rem_ptr, m, 0, sums, s), "scan");
             SPMM_TRY_HIP(hipMemcpyAsync(&nrem, sums + (scan_sums_len(m) - 1), 8, hipMemcpyDeviceToHost, s),
                          "hipMemcpyAsync");

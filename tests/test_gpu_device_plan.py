@@ -131,10 +131,15 @@ def test_device_checks_refuse_a_bad_csr():
     bad_ci = ci.clone()
     bad_ci[7] = A.k                                    # column out of range
     assert _status(rp, bad_ci, vt, A.m, A.k) == (L.SPMM_ERR_INVALID, "column index out of range")
-    # mixed plans are built with original-ranges windows only
-    st, _ = _status(rp, ci, vt, A.m, A.k, api.default_opts(mode="mixed", row_order="length_sorted"))
+    # clustered windows and local reordering are built on the host only
+    st, _ = _status(rp, ci, vt, A.m, A.k, api.default_opts(mode="mixed", row_order="clustered"))
     assert st == L.SPMM_ERR_UNSUPPORTED
-    assert _status(rp, ci, vt, A.m, A.k, api.default_opts(mode="mixed"))[0] == L.SPMM_OK
+    st, _ = _status(rp, ci, vt, A.m, A.k, api.default_opts(mode="mixed", row_order="compacted",
+                                                           local_reorder=32))
+    assert st == L.SPMM_ERR_UNSUPPORTED
+    for order in ("original_ranges", "compacted", "length_sorted"):
+        opts = api.default_opts(mode="mixed", row_order=order)
+        assert _status(rp, ci, vt, A.m, A.k, opts)[0] == L.SPMM_OK, order
 
 
 MIXED_KEYS = ("windows", "tile_window", "tile_cols", "tile_bitmap", "tile_val_ptr", "tile_vals",
@@ -202,6 +207,14 @@ MIXED_CASES = [
     # windows of hundreds of tiles (partial items) and split remainders
     ("wide", "bf16", "bf16", 160, dict(mode="mixed", window_h=16, t_row=-1, alpha_c=0.0, alpha=0.2,
                                        seg_len=40)),
+    # length-sorted windows over a power-law graph (the GNN mixed plan's order)
+    ("graph", "f32", "f32", 128, dict(mode="mixed", row_order="length_sorted", t_row=8, alpha=0.05,
+                                      seg_len=24)),
+    # compacted windows, empty rows passing the row stage (t_row = -1), duplicates
+    ("random", "bf16", "bf16", 48, dict(mode="mixed", row_order="compacted", t_row=-1, alpha_c=1 / 16,
+                                        alpha=0.02, window_h=32)),
+    # length-sorted, every row in a window (many equal lengths: ties keep row order)
+    ("block", "f16", "f16", 64, dict(mode="mfma_only", row_order="length_sorted", window_h=64)),
     # no tile dense enough: every window dissolves into vector rows
     ("graph", "f32", "f32", 32, dict(mode="mixed", alpha=2.0)),
 ]
@@ -224,7 +237,7 @@ def test_device_mixed_plan_equals_host_plan(case):
     A = _int_vals(_mixed_matrix(kind, vk, 40 + case), case)
     print("case", case, kind, vk, bk, n, kw, flush=True)
     sh = _compare_mixed(A, n, bk, api.default_opts(**kw), case, exact_ints=True)
-    if case < 5:
+    if case < len(MIXED_CASES) - 1:
         assert sh["tiles"] > 0
     else:
         assert sh["tiles"] == 0 and sh["windows"] == 0
@@ -251,4 +264,31 @@ def test_device_mixed_plan_random(seed):
               pipeline=int(r.integers(0, 4)), win_sched=int(r.integers(0, 2)),
               exec=int(r.choice([1, 2, 3])))
     print("case", seed, vk, bk, m, k, n, kw, flush=True)
+    _compare_mixed(A, n, bk, api.default_opts(**kw), seed, exact_ints=True)
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_device_mixed_plan_random_orders(seed):
+    """As above with compacted and length-sorted windows: device plan = host
+    plan array for array, same C bit for bit, integer-exact."""
+    r = np.random.default_rng(1900 + seed)
+    vk, bk = [("f32", "f32"), ("f32", "bf16"), ("bf16", "bf16"), ("f16", "f16")][r.integers(4)]
+    m = int(r.choice([17, int(r.integers(200, 5000)), int(r.integers(200, 5000))]))
+    if r.integers(2):
+        k = int(r.choice([31, int(r.integers(50, 3000))]))
+        A = synth.random_csr(m, k, float(r.choice([0.02, 0.08, 0.2])), 1950 + seed, val_kind=vk,
+                             int_values=(-2, 2), dup_frac=float(r.choice([0.0, 0.05])),
+                             empty_rows=float(r.choice([0.0, 0.3])))
+    else:
+        A = _int_vals(synth.chung_lu_graph(max(m, 200), 2.1, 12.0, 800.0, 1950 + seed, val_kind=vk,
+                                           values="uniform"), seed)
+    H = int(r.choice([16, 32, 64]))
+    n = int(r.choice([1, 8, 33, 64, 128, 256, int(r.integers(1, 300))]))
+    kw = dict(mode=str(r.choice(["mixed", "mixed", "mfma_only"])), window_h=H,
+              row_order=str(r.choice(["compacted", "length_sorted"])),
+              t_row=int(r.choice([-1, 0, 2, 8])), alpha_c=float(r.choice([0.0, 1.0 / H])),
+              alpha=float(r.choice([0.0, 0.02, 0.1])), seg_len=int(r.choice([3, 17, 64, 256])),
+              pipeline=int(r.integers(0, 4)), win_sched=int(r.integers(0, 2)),
+              exec=int(r.choice([1, 2, 3])))
+    print("case", seed, vk, bk, A.m, A.k, n, kw, flush=True)
     _compare_mixed(A, n, bk, api.default_opts(**kw), seed, exact_ints=True)
