@@ -346,6 +346,28 @@ def gather_rate(K, steps, m=1 << 20, deg=16, n=128):
             "algorithmic_GBps": round(alg / ms / 1e6, 1)}
 
 
+def gather_ceilings(A, n, roof):
+    """The dominant grid's B-row gathers (entries x n x 4 bytes over its
+    average launch) against two ceilings: uniformly random gathers over a B
+    of the same size on the same path, and the same rows, in the same order,
+    gathered with nothing else done (no values, no FMA, no C)."""
+    import torch
+    from paper_2606_22482_amd import api
+    probe = gather_rate(A.k, 10, n=n)
+    g = A.nnz * n * 4 / (roof["kernel"]["avg_launch_ms"] * 1e-3) / 1e9
+    cols = torch.from_numpy(np.ascontiguousarray(A.colidx, dtype=np.int32)).cuda()
+    Bg = torch.randn(A.k, n, device="cuda")
+    only = api.spmm_gather_bandwidth(cols, Bg, n, reps=10) / 1e9
+    del cols, Bg
+    log("gathers: %.1f GB/s vs %.1f GB/s uniformly random over the same B size, %.1f GB/s "
+        "for the same rows gathered alone" % (g, probe["gathered_GBps"], only))
+    return {"gathered_bytes": int(A.nnz * n * 4), "GBps": round(g, 1),
+            "uniform_random_GBps": probe["gathered_GBps"],
+            "frac_of_uniform_random": round(g / probe["gathered_GBps"], 3),
+            "gather_only_GBps": round(only, 1),
+            "frac_of_gather_only": round(g / only, 3)}
+
+
 def gather_probe(args):
     """The random-gather ceiling for B of 512 MiB, 64 MiB and 4 MiB: the
     vector path over uniformly random columns, and the same columns gathered
@@ -667,25 +689,8 @@ def main():
     log("copy bandwidth (read + write): %.1f GB/s" % copy_gbs)
     A, B, b_kind, wname, n, results = measure(head, args, pick(head), extra)
     best, ms, roof, modes = summarise(A, b_kind, wname, n, results, copy_gbs)
-    if b_kind == "f32" and n == 128 and best == "plain":
-        # the dominant grid's B gathers against uniformly random gathers over
-        # a B of the same size (the ceiling of this access pattern)
-        probe = gather_rate(A.k, 10)
-        g = A.nnz * n * 4 / (roof["kernel"]["avg_launch_ms"] * 1e-3) / 1e9
-        # and against the same B rows, in the same order, gathered with
-        # nothing else done (no values, no FMA, no C)
-        import torch
-        cols = torch.from_numpy(np.ascontiguousarray(A.colidx, dtype=np.int32)).cuda()
-        Bg = torch.randn(A.k, n, device="cuda")
-        only = api.spmm_gather_bandwidth(cols, Bg, n, reps=10) / 1e9
-        del cols, Bg
-        roof["gather"] = {"gathered_bytes": int(A.nnz * n * 4), "GBps": round(g, 1),
-                          "uniform_random_GBps": probe["gathered_GBps"],
-                          "frac_of_uniform_random": round(g / probe["gathered_GBps"], 3),
-                          "gather_only_GBps": round(only, 1),
-                          "frac_of_gather_only": round(g / only, 3)}
-        log("gathers: %.1f GB/s vs %.1f GB/s uniformly random over the same B size, %.1f GB/s "
-            "for the same rows gathered alone" % (g, probe["gathered_GBps"], only))
+    if b_kind == "f32" and best == "plain":
+        roof["gather"] = gather_ceilings(A, n, roof)
     gflops = 2.0 * A.nnz * n / (ms * 1e-3) / 1e9
     out = {
         "metric": METRIC,
@@ -716,6 +721,8 @@ def main():
         for key in ("gnn64", "block", "uniform"):
             A2, B2, bk2, wn2, n2, res2 = measure(key, args, pick(key), extra)
             b2, ms2, roof2, modes2 = summarise(A2, bk2, wn2, n2, res2, copy_gbs)
+            if key.startswith("gnn") and bk2 == "f32" and b2 == "plain":
+                roof2["gather"] = gather_ceilings(A2, n2, roof2)
             configs[wn2] = {"best": b2, "ms_per_step": round(ms2, 5),
                             "gflops": round(2.0 * A2.nnz * n2 / (ms2 * 1e-3) / 1e9, 1),
                             "roofline": roof2, "modes": modes2,

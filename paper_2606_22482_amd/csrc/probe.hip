@@ -4,12 +4,12 @@
 // (one B row per entry, Eq. 1).  This probe measures how fast the device can
 // gather the same sequence of B rows when nothing else is done: no entry
 // values, no multiply, no C rows, as many independent loads in flight as the
-// CUs hold.  Groups of 32 lanes take sequence positions g, g + G, ... (G
-// groups in the grid), U positions per step; each lane reads one 16-byte
-// chunk of its position's row (rows of up to 128 f32) and adds it to a
-// register sum that is stored only if it equals a value no sum of finite
-// rows reaches by chance (a NaN test), so the loads cannot be dropped and
-// nothing is written.
+// CUs hold.  Groups of L lanes (a row's 16-byte chunks, rounded up to a
+// power of two; rows of up to 128 f32) take sequence positions g, g + G, ...
+// (G groups in the grid), U positions per step; each lane reads one chunk of
+// its position's row and adds it to a register sum, which is stored only if
+// it is NaN (never, for finite B): the loads cannot be dropped and nothing
+// is written.
 #include <hip/hip_runtime.h>
 
 #include "runtime.hpp"
@@ -21,13 +21,16 @@ namespace {
 constexpr int kGatherU = 8;           // positions per group per step
 constexpr int kGatherBlocks = 32768;  // 256-thread workgroups (8 groups each)
 
+// LPR lanes per row (16 bytes each): a row of up to LPR * 4 f32
+template <int LPR>
 __global__ __launch_bounds__(256) void gather_probe_kernel(const float4 *__restrict__ B, int64_t ld4,
                                                            int chunks, int32_t k,
                                                            const int32_t *__restrict__ rows,
                                                            int64_t n, float4 *__restrict__ sink) {
-    const int64_t G = (int64_t)gridDim.x * 8;
-    const int64_t g = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 5;
-    const int lane = threadIdx.x & 31;
+    constexpr int GPB = 256 / LPR;  // groups per workgroup
+    const int64_t G = (int64_t)gridDim.x * GPB;
+    const int64_t g = ((int64_t)blockIdx.x * 256 + threadIdx.x) / LPR;
+    const int lane = threadIdx.x % LPR;
     const bool on = lane < chunks;
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int64_t p = g; p < n; p += G * kGatherU) {
@@ -72,10 +75,23 @@ extern "C" spmm_status spmm_gather_bandwidth(const int32_t *rows, int64_t n, con
     if (e != hipSuccess) return set_error(SPMM_ERR_OOM, "hipMalloc(sink)");
     spmm_status st = SPMM_OK;
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    // lanes per row: the row's 16-byte chunks rounded up to a power of two
+    const int chunks = n_cols / 4;
+    const int lpr = chunks <= 1 ? 1 : chunks <= 2 ? 2 : chunks <= 4 ? 4 : chunks <= 8 ? 8 : chunks <= 16 ? 16 : 32;
     auto launch = [&]() {
-        hipLaunchKernelGGL(gather_probe_kernel, dim3(kGatherBlocks), dim3(256), 0, s,
-                           static_cast<const float4 *>(B), ldb / 4, n_cols / 4, (int32_t)k, rows, n,
-                           static_cast<float4 *>(sink));
+#define SPMM_GATHER_PROBE(L)                                                                            \
+    hipLaunchKernelGGL(gather_probe_kernel<L>, dim3(kGatherBlocks), dim3(256), 0, s,                   \
+                       static_cast<const float4 *>(B), ldb / 4, chunks, (int32_t)k, rows, n,           \
+                       static_cast<float4 *>(sink))
+        switch (lpr) {
+            case 1: SPMM_GATHER_PROBE(1); break;
+            case 2: SPMM_GATHER_PROBE(2); break;
+            case 4: SPMM_GATHER_PROBE(4); break;
+            case 8: SPMM_GATHER_PROBE(8); break;
+            case 16: SPMM_GATHER_PROBE(16); break;
+            default: SPMM_GATHER_PROBE(32); break;
+        }
+#undef SPMM_GATHER_PROBE
         return hipGetLastError();
     };
     do {
