@@ -917,6 +917,9 @@ __device__ __forceinline__ int wave_inclusive_scan(int x) {
 // remainder has at most 2U entries is summed in entry order by one group, and
 // up to G such consecutive rows are gathered at once; longer rows take the
 // whole wavefront as in vector_item.  The rule depends only on a row's length.
+// The row ids and remainder ranges of the next 64 rows are loaded once, one
+// row per lane, and handed to the groups by lane shuffles as the rows are
+// taken, so a batch of short rows starts with its entry loads.
 template <int VT, int BT, int E, int CPL, bool FUSED = false>
 __device__ __forceinline__ void vector_item_packed(const DevPlan &P, const RunArgs &a, int wid) {
     constexpr int U = unroll_of<E, CPL>();
@@ -927,64 +930,64 @@ __device__ __forceinline__ void vector_item_packed(const DevPlan &P, const RunAr
     const int lane = threadIdx.x & 63;
     int sid = P.vitem_seg[item];
     const int i0 = P.vitem_ptr[item], i1 = P.vitem_ptr[item + 1];
-    int i = i0;
-    while (i < i1) {
-        // lengths of the next (up to 64) rows, one per lane
+    for (int i = i0; i < i1; i += 64) {
+        // the next (up to 64) rows, one per lane: id and remainder range
         const int li_row = i + lane;
-        int len = 0x7FFFFFFF;
-        if (lane < 64 && li_row < i1) {
-            const int rr = P.vec_rows ? P.vec_rows[li_row] : li_row;
-            len = P.rem_ptr[rr + 1] - P.rem_ptr[rr];
+        int rr = 0, rb = 0, re = 0, len = 0x7FFFFFFF;
+        if (li_row < i1) {
+            rr = P.vec_rows ? P.vec_rows[li_row] : li_row;
+            rb = P.rem_ptr[rr];
+            re = P.rem_ptr[rr + 1];
+            len = re - rb;
         }
-        // k = consecutive short rows from i, at most G
         const uint64_t longmask = __ballot(len > SHORT || len > P.seg_len || li_row >= i1);
-        int k = longmask ? __builtin_ctzll(longmask) : 64;
-        k = min(k, L.groups);
-        if (k > 0) {
-            const int my = i + L.group;
+        const int avail = min(64, i1 - i);
+        int j = 0;
+        while (j < avail) {
+            // k = consecutive short rows from j, at most G
+            const uint64_t lm = longmask >> j;
+            int k = lm ? __builtin_ctzll(lm) : 64 - j;
+            k = min(k, L.groups);
+            if (k > 0) {
+                const int src = min(j + L.group, 63);
+                const int r = __shfl(rr, src, 64), b = __shfl(rb, src, 64), e = __shfl(re, src, 64);
+                float acc[CPL][E];
+#pragma unroll
+                for (int c = 0; c < CPL; ++c)
+#pragma unroll
+                    for (int x = 0; x < E; ++x) acc[c][x] = 0.0f;
+                if (L.group < k) {
+                    row_accumulate_group<VT, BT, E, CPL, U>(P.rem_col, P.rem_val, b, e, a.B, a.ldb, a.b_rec,
+                                                            ncol0, ncols, L, a.cold_aux, acc);
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        const int q = c * L.lpr + L.li;
+                        if (q * E < ncols) store_chunk<E>(a.C, (int64_t)r * a.ldc + ncol0 + (int64_t)q * E, acc[c]);
+                    }
+                }
+                j += k;
+                continue;
+            }
+            // a long row: the whole wavefront, as in vector_item
+            const int r = __shfl(rr, j, 64), b = __shfl(rb, j, 64), e = __shfl(re, j, 64);
+            ++j;
             float acc[CPL][E];
 #pragma unroll
             for (int c = 0; c < CPL; ++c)
 #pragma unroll
                 for (int x = 0; x < E; ++x) acc[c][x] = 0.0f;
-            int r = -1;
-            if (L.group < k) {
-                r = P.vec_rows ? P.vec_rows[my] : my;
-                row_accumulate_group<VT, BT, E, CPL, U>(P.rem_col, P.rem_val, P.rem_ptr[r],
-                                                        P.rem_ptr[r + 1], a.B, a.ldb, a.b_rec, ncol0, ncols,
-                                                        L, a.cold_aux, acc);
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) {
-                    const int q = c * L.lpr + L.li;
-                    if (q * E < ncols) store_chunk<E>(a.C, (int64_t)r * a.ldc + ncol0 + (int64_t)q * E, acc[c]);
-                }
+            if (e - b <= P.seg_len) {
+                seg_accumulate<VT, BT, E, CPL, U>(P.rem_col, P.rem_val, b, e, a.B, a.ldb, a.b_rec, ncol0, ncols,
+                                                  L, a.cold_aux, acc);
+                group_reduce<E, CPL>(acc, L);
+            } else {
+                if constexpr (FUSED) continue;
+                const int ns = (e - b + P.seg_len - 1) / P.seg_len;
+                sum_partials<E, CPL>(a.work, a.work_ld, sid, ns, ncol0, ncols, L, acc);
+                sid += ns;
             }
-            i += k;
-            continue;
+            store_row<E, CPL>(a.C, (int64_t)r * a.ldc, ncol0, ncols, L, acc);
         }
-        // a long row: the whole wavefront, as in vector_item
-        const int r = P.vec_rows ? P.vec_rows[i] : i;
-        const int b = P.rem_ptr[r], e = P.rem_ptr[r + 1];
-        float acc[CPL][E];
-#pragma unroll
-        for (int c = 0; c < CPL; ++c)
-#pragma unroll
-            for (int x = 0; x < E; ++x) acc[c][x] = 0.0f;
-        if (e - b <= P.seg_len) {
-            seg_accumulate<VT, BT, E, CPL, U>(P.rem_col, P.rem_val, b, e, a.B, a.ldb, a.b_rec, ncol0, ncols,
-                                              L, a.cold_aux, acc);
-            group_reduce<E, CPL>(acc, L);
-        } else {
-            if constexpr (FUSED) {
-                ++i;
-                continue;
-            }
-            const int ns = (e - b + P.seg_len - 1) / P.seg_len;
-            sum_partials<E, CPL>(a.work, a.work_ld, sid, ns, ncol0, ncols, L, acc);
-            sid += ns;
-        }
-        store_row<E, CPL>(a.C, (int64_t)r * a.ldc, ncol0, ncols, L, acc);
-        ++i;
     }
 }
 
