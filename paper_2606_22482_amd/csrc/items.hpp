@@ -1029,24 +1029,40 @@ __device__ __forceinline__ void vector_item_classed(const DevPlan &P, const RunA
     chunk_layout<E, CPL>(ncol0, ncols, L, cok, coff);
     int sid = P.vitem_seg[item];
     const int i0 = P.vitem_ptr[item], i1 = P.vitem_ptr[item + 1];
+    // id, remainder range, class and segments of rows base .. base + 63, one
+    // per lane, loaded again only when fewer rows than a full pass takes
+    // (L.groups) remain loaded
+    int base = i0 - 64;
+    int wr = -1, wb = 0, we = 0, wcls = 1, wns = 0;
     for (int i = i0; i < i1;) {
-        // row i + lane: id, remainder range, class, segments
-        const int j_row = i + lane;
-        int r = -1, b = 0, e = 0, cls = 1, ns = 0;
-        if (j_row < i1) {
-            r = P.vec_rows ? P.vec_rows[j_row] : j_row;
-            b = P.rem_ptr[r];
-            e = P.rem_ptr[r + 1];
-            if (e - b > P.seg_len) {
-                ns = (e - b + P.seg_len - 1) / P.seg_len;
-                e = b;  // the entries were summed by the segment kernel
-            } else {
-                cls = size_class(e - b, 2 * U, L.groups);
+        if (i - base + L.groups > 64) {
+            base = i;
+            const int l_row = i + lane;
+            wr = -1; wb = 0; we = 0; wcls = 1; wns = 0;
+            if (l_row < i1) {
+                wr = P.vec_rows ? P.vec_rows[l_row] : l_row;
+                wb = P.rem_ptr[wr];
+                we = P.rem_ptr[wr + 1];
+                if (we - wb > P.seg_len) {
+                    wns = (we - wb + P.seg_len - 1) / P.seg_len;
+                    we = wb;  // the entries were summed by the segment kernel
+                } else {
+                    wcls = size_class(we - wb, 2 * U, L.groups);
+                }
             }
+        }
+        // row i + lane, from the loaded rows (a lane past them ends the pass)
+        const int j_row = i + lane, off = i - base;
+        const bool have = lane + off < 64;
+        const int srcl = min(lane + off, 63);
+        int r = __shfl(wr, srcl, 64), b = __shfl(wb, srcl, 64), e = __shfl(we, srcl, 64);
+        int cls = __shfl(wcls, srcl, 64), ns = __shfl(wns, srcl, 64);
+        if (!have) {
+            r = -1; b = 0; e = 0; cls = 1; ns = 0;
         }
         // the pass: rows before the first class increase whose blocks fit
         const int prev = __shfl_up(cls, 1, 64);
-        const uint64_t cut = __ballot(j_row >= i1 || (lane > 0 && cls > prev));
+        const uint64_t cut = __ballot(j_row >= i1 || !have || (lane > 0 && cls > prev));
         const int kmax = cut ? __builtin_ctzll(cut) : 64;
         const int cin = lane < kmax ? cls : 0;
         const int incl = wave_inclusive_scan(cin);
