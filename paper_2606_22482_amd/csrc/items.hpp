@@ -920,10 +920,13 @@ __device__ __forceinline__ int wave_inclusive_scan(int x) {
 // The row ids and remainder ranges of the next 64 rows are loaded once, one
 // row per lane, and handed to the groups by lane shuffles as the rows are
 // taken, so a batch of short rows starts with its entry loads.
-template <int VT, int BT, int E, int CPL, bool FUSED = false>
+// UL: entries per group and step; the short-row bound stays 2 unroll_of, so
+// the summation order (which depends only on a row's length) is the same for
+// any UL.
+template <int VT, int BT, int E, int CPL, bool FUSED = false, int UL = unroll_of<E, CPL>()>
 __device__ __forceinline__ void vector_item_packed(const DevPlan &P, const RunArgs &a, int wid) {
-    constexpr int U = unroll_of<E, CPL>();
-    constexpr int SHORT = 2 * U;
+    constexpr int U = UL;
+    constexpr int SHORT = 2 * unroll_of<E, CPL>();
     const int panel = wid / P.n_vitems, item = wid - panel * P.n_vitems;
     const int ncol0 = panel * a.np, ncols = min(a.np, P.n - ncol0);
     const Lanes L(a.lpr_log2);
@@ -1016,9 +1019,12 @@ __device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
 // consecutive rows while their classes do not grow and the blocks fit in the
 // wavefront; with rows ordered longest first every block is aligned.  Split
 // rows (class 1) sum their segment partials in segment order.
-template <int VT, int BT, int E, int CPL, bool FUSED = false>
+// UL: entries per group and step; size classes are counted in units of
+// 2 unroll_of entries for any UL, and a class-S row's entry p goes to group
+// p mod S in entry order whatever the step, so the result does not depend on UL.
+template <int VT, int BT, int E, int CPL, bool FUSED = false, int UL = unroll_of<E, CPL>()>
 __device__ __forceinline__ void vector_item_classed(const DevPlan &P, const RunArgs &a, int wid) {
-    constexpr int U = unroll_of<E, CPL>();
+    constexpr int U = UL;
     const int panel = wid / P.n_vitems, item = wid - panel * P.n_vitems;
     const int ncol0 = panel * a.np, ncols = min(a.np, P.n - ncol0);
     const Lanes L(a.lpr_log2);
@@ -1047,7 +1053,7 @@ __device__ __forceinline__ void vector_item_classed(const DevPlan &P, const RunA
                     wns = (we - wb + P.seg_len - 1) / P.seg_len;
                     we = wb;  // the entries were summed by the segment kernel
                 } else {
-                    wcls = size_class(we - wb, 2 * U, L.groups);
+                    wcls = size_class(we - wb, 2 * unroll_of<E, CPL>(), L.groups);
                 }
             }
         }
@@ -1129,10 +1135,10 @@ __device__ __forceinline__ void vector_item_classed(const DevPlan &P, const RunA
         i += k;
     }
 }
-template <int VT, int BT, int E, int CPL, int VAR, bool FUSED = false>
+template <int VT, int BT, int E, int CPL, int VAR, bool FUSED = false, int UL = unroll_of<E, CPL>()>
 __device__ __forceinline__ void vector_item_var(const DevPlan &P, const RunArgs &a, int wid) {
-    if constexpr (VAR == 3) vector_item_classed<VT, BT, E, CPL, FUSED>(P, a, wid);
-    else if constexpr (VAR == 2) vector_item_packed<VT, BT, E, CPL, FUSED>(P, a, wid);
+    if constexpr (VAR == 3) vector_item_classed<VT, BT, E, CPL, FUSED, UL>(P, a, wid);
+    else if constexpr (VAR == 2) vector_item_packed<VT, BT, E, CPL, FUSED, UL>(P, a, wid);
     else if constexpr (VAR == 1) vector_item_pipelined<VT, BT, E, CPL, FUSED>(P, a, wid);
     else vector_item<VT, BT, E, CPL, FUSED>(P, a, wid);
 }
