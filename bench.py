@@ -264,8 +264,8 @@ def parse_opts(text):
 
 def serve_bench(args):
     """Serving stream: Poisson arrivals at 0.7x the closed-loop saturation rate
-    measured on the first requests of the same list (after an untimed pass
-    over 300 of them); plans pre-built (resident)."""
+    measured on the first requests of the same list (the best of three passes,
+    after an untimed one); plans pre-built (resident)."""
     from paper_2606_22482_amd import serve, synth
     t0 = time.perf_counter()
     pool = synth.serving_pool(n_graphs=args.pool_graphs, n_masks=args.pool_masks, seed=5,
@@ -284,12 +284,25 @@ def serve_bench(args):
         if i % 100 == 99:
             log("serving prewarm: %d of %d plans (%.1f s)" % (i + 1, len(keys), time.perf_counter() - t0))
     log("serving prewarm: %d plans (%.1f s)" % (len(keys), time.perf_counter() - t0))
-    # untimed pass: every stream's run context and batch workspace reach their sizes
-    srv.run(reqs[: min(len(reqs), 300)], realtime=False)
-    closed = srv.run(reqs[: min(len(reqs), args.closed_loop)], realtime=False).summary()
+    # untimed pass over the closed-loop requests: every stream's run context
+    # and batch workspace reach their sizes
+    nc = min(len(reqs), args.closed_loop)
+    warm = srv.run(reqs[:nc], realtime=False).summary()
+    log("serving warm-up: %d requests in %.2f s, %d plan builds, %d evictions"
+        % (warm["completed"], warm["wall_s"], warm["plan_builds"], warm["plan_evictions"]))
+    # the saturation rate: the best of three closed-loop passes (a pass takes
+    # a fraction of a second, so one host-side stall would otherwise set it)
+    passes = [srv.run(reqs[:nc], realtime=False).summary() for _ in range(3)]
+    closed = max(passes, key=lambda x: x["throughput_req_s"])
+    log("closed-loop passes: %s req/s" % [round(x["throughput_req_s"], 1) for x in passes])
     rate = 0.7 * closed["throughput_req_s"]
-    log("closed loop: %.1f req/s -> rate %.1f req/s" % (closed["throughput_req_s"], rate))
+    log("closed loop: %.1f req/s -> rate %.1f req/s (%.2f s, %d plan builds, %d evictions, mean batch "
+        "%.2f, max queue %d)" % (closed["throughput_req_s"], rate, closed["wall_s"], closed["plan_builds"],
+                                 closed["plan_evictions"], closed["mean_batch"], closed["max_queue"]))
     timed = synth.serving_requests(args.requests, len(pool), args.pool_graphs, seed=5, rate=rate)
+    # plans of the timed list that the closed-loop list did not need: built before the clock starts
+    for k in sorted({(d["matrix"], d["n"], d["b_kind"]) for d in timed} - set(keys)):
+        srv.plans.get(k, st)
     s = srv.run(timed, realtime=True).summary()
     log("serving: p50 %.3f ms, p99 %.3f ms, %.0f req/s, %.0f GFLOP/s; %d large (p50 %.3f, p99 %.3f "
         "ms), small p50 %.3f, p99 %.3f ms"
@@ -306,7 +319,9 @@ def serve_bench(args):
             "p50_large_ms": round(s["p50_large_ms"], 3), "p99_large_ms": round(s["p99_large_ms"], 3),
             "throughput_req_s": round(s["throughput_req_s"], 2), "gflops": round(s["gflops"], 1),
             "rejected": s["rejected"], "mean_batch": round(s["mean_batch"], 2),
-            "closed_loop_req_s": round(closed["throughput_req_s"], 2)}
+            "closed_loop_req_s": round(closed["throughput_req_s"], 2),
+            "closed_loop_plan_builds": closed["plan_builds"], "plan_builds": s["plan_builds"],
+            "plan_evictions": s["plan_evictions"]}
 
 
 def _batch_item(job):
