@@ -19,7 +19,7 @@ namespace spmm {
 namespace {
 
 constexpr int kGatherU = 8;           // positions per group per step
-constexpr int kGatherBlocks = 32768;  // 256-thread workgroups (8 groups each)
+constexpr int kGatherBlocks = 32768;  // 256-thread workgroups
 
 // LPR lanes per row (16 bytes each): a row of up to LPR * 4 f32
 template <int LPR>
