@@ -57,6 +57,12 @@ def workload(name):
     if name == "uniform":
         A, B = synth.uniform_rows()
         return A, B, "f32", "uniform_4096_16perrow_n32"
+    if name == "mask":
+        # block-sparse attention mask of the serving stream's kind: 64x64
+        # blocks at 10% block density plus a 512-wide sliding window
+        A = synth.attention_mask(32768, seed=3, val_kind="bf16")
+        B = synth.dense_values(np.random.default_rng(11), (A.k, 256), "bf16")
+        return A, B, "bf16", "attention_mask_32768_n256_bf16"
     raise SystemExit("unknown workload " + name)
 
 
@@ -609,6 +615,7 @@ MODES = {
     "block": {"mixed": dict(mode="mixed", row_order="original_ranges"), "plain": dict(mode="plain")},
     "block_shuffled": {"mixed": dict(mode="mixed", row_order="compacted"), "plain": dict(mode="plain")},
     "uniform": {"plain": dict(mode="plain"), "mixed": dict(mode="mixed")},
+    "mask": {"mixed": dict(mode="mixed", row_order="original_ranges", window_h=64), "plain": dict(mode="plain")},
 }
 
 
@@ -619,7 +626,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="all",
                     help="all (default: every configuration in one line), gnn, gnn64, block, "
-                         "block_shuffled, uniform, batch, serve")
+                         "block_shuffled, uniform, mask, batch, serve")
     ap.add_argument("--modes", default="", help="comma-separated subset of the workload's modes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--opts", default="", help="extra plan options, k=v[,k=v]")
@@ -733,7 +740,7 @@ def main():
     del results
     if args.workload == "all":
         configs = {}
-        for key in ("gnn64", "block", "uniform"):
+        for key in ("gnn64", "block", "mask", "uniform"):
             A2, B2, bk2, wn2, n2, res2 = measure(key, args, pick(key), extra)
             b2, ms2, roof2, modes2 = summarise(A2, bk2, wn2, n2, res2, copy_gbs)
             if key.startswith("gnn") and bk2 == "f32" and b2 == "plain":

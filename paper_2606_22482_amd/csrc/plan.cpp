@@ -418,6 +418,14 @@ spmm_status validate_opts(const spmm_opts &o, std::string &err) {
 // vector items, window segment ids, window partial items and the window
 // launch order (Sec. 7).  Shared by the host builder and the device builder,
 // which computes the partition on the device and the schedule here.
+int32_t window_item_tiles(int64_t tiles, int32_t n) {
+    const int64_t panels = ((int64_t)n + 127) / 128;
+    const int64_t want = (tiles * panels + kWindowItems - 1) / kWindowItems;
+    int32_t k = kWinTiles;
+    while (k < kWinTilesMax && k < want) k *= 2;
+    return k;
+}
+
 void build_schedule(HostPlan &P) {
     const spmm_opts &o = P.opts;
     const int64_t m = P.m;
@@ -481,18 +489,19 @@ void build_schedule(HostPlan &P) {
     }
     // windows: segment ids in slot order; launch order by window id or heaviest first
     std::vector<int64_t> wcost(W, 0);
+    P.win_tiles = window_item_tiles(P.win_tile_ptr.empty() ? 0 : P.win_tile_ptr.back(), P.n);
     P.win_part.push_back(0);
     for (int64_t w = 0; w < W; ++w) {
         P.win_seg.push_back((int32_t)P.seg_row.size());
         const int32_t ta = P.win_tile_ptr[w], tb = P.win_tile_ptr[w + 1];
-        // tiles beyond the first kWinTiles become partial items of kWinTiles each
-        for (int32_t t = ta + kWinTiles; t < tb; t += kWinTiles) {
+        // tiles beyond the first win_tiles become partial items of win_tiles each
+        for (int32_t t = ta + P.win_tiles; t < tb; t += P.win_tiles) {
             P.wpart_win.push_back((int32_t)w);
             P.wpart_t0.push_back(t);
-            P.wpart_t1.push_back(std::min(t + kWinTiles, tb));
+            P.wpart_t1.push_back(std::min(t + P.win_tiles, tb));
         }
         P.win_part.push_back((int32_t)P.wpart_win.size());
-        wcost[w] = (int64_t)std::min(tb - ta, kWinTiles) * kt +
+        wcost[w] = (int64_t)std::min(tb - ta, P.win_tiles) * kt +
                    (int64_t)(P.win_part[w + 1] - P.win_part[w]) * H;
         for (int s = 0; s < H; ++s) {
             int32_t r = P.windows[w * H + s];

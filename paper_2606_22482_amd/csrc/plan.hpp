@@ -14,7 +14,17 @@ namespace spmm {
 
 constexpr int kWave = 64;
 constexpr int kRowCost = 4;  // per-row overhead of a vector item, in entry units
-constexpr int kWinTiles = 16;  // tiles a window item computes itself; the rest go to partial items
+// Tiles a window item computes itself (the rest of a window's tiles go to
+// partial items of as many tiles each): the least power of two in
+// [kWinTiles, kWinTilesMax] that brings the plan's tiles over all 128-column
+// panels down to about kWindowItems items, i.e. about as many as the CUs
+// hold at once (window_item_tiles).  More, smaller items only add partial
+// results that go through memory and back (an item's partial C tile is as
+// large as its whole result).
+constexpr int kWinTiles = 16;
+constexpr int kWinTilesMax = 128;
+constexpr int64_t kWindowItems = 1024;
+int32_t window_item_tiles(int64_t tiles, int32_t n);
 
 struct HostPlan {
     // ---- problem and resolved options ----
@@ -46,6 +56,7 @@ struct HostPlan {
     std::vector<int32_t> win_order;     // [W]
     std::vector<int32_t> win_part;      // [W+1]: partial items of window w are [win_part[w], win_part[w+1])
     std::vector<int32_t> wpart_win, wpart_t0, wpart_t1;  // [n_wparts]
+    int32_t win_tiles = kWinTiles;      // tiles an owner item computes; partial items take as many
     bool identity_rows = false;         // vector_rows == 0..m-1
 
     // ---- co-scheduled execution (derive_exec_tables, from the schedule) ----
@@ -109,7 +120,7 @@ void build_schedule(HostPlan &P);
 
 // The tables of co-scheduled execution: which window each segment's row
 // belongs to, and a slot for every window whose result needs other items
-// (partial tiles beyond its first kWinTiles, or rows split into segments).
+// (partial tiles beyond its first win_tiles, or rows split into segments).
 void derive_exec_tables(HostPlan &P);
 
 // float -> bfloat16 bits, round to nearest even (NaN stays a quiet NaN).

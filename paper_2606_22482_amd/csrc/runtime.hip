@@ -265,7 +265,7 @@ spmm_status upload_plan(spmm_plan_t *p, const DeviceArrays *da) {
         dp.tile_val_ptr = reinterpret_cast<const int32_t *>(at(i_tile_val_ptr));
         dp.tile_vals = reinterpret_cast<const uint16_t *>(at(i_tile_vals));
         dp.n_wpart = (int32_t)h.wpart_win.size();
-        dp.win_tmax = kWinTiles;
+        dp.win_tmax = h.win_tiles;
         dp.win_part = reinterpret_cast<const int32_t *>(at(i_win_part));
         dp.wpart_win = reinterpret_cast<const int32_t *>(at(i_wpart_win));
         dp.wpart_t0 = reinterpret_cast<const int32_t *>(at(i_wpart_t0));

@@ -85,7 +85,7 @@ bool monotone_from_zero(const std::vector<T> &v, int64_t last) {
     return true;
 }
 
-spmm_status check_plan(const HostPlan &P, std::string &err) {
+spmm_status check_plan(const HostPlan &P, std::string &err, int32_t *win_tiles) {
     SPMM_CHECK(P.m >= 0 && P.k >= 0 && P.nnz >= 0 && P.m < INT32_MAX && P.k < INT32_MAX &&
                    P.nnz < INT32_MAX && P.n >= 1,
                "plan image: sizes");
@@ -221,15 +221,27 @@ spmm_status check_plan(const HostPlan &P, std::string &err) {
                "plan image: window partial items");
     SPMM_CHECK((int64_t)P.win_part.size() == W + 1 && monotone_from_zero(P.win_part, NP),
                "plan image: window partial items");
+    // tiles per window item: the first partial item's offset in its window,
+    // else (no partial item) enough for the largest window
+    int64_t K = kWinTiles;
+    if (NP > 0) {
+        const int32_t w0 = P.wpart_win[0];
+        SPMM_CHECK(w0 >= 0 && w0 < W, "plan image: window partial items");
+        K = (int64_t)P.wpart_t0[0] - P.win_tile_ptr[w0];
+        SPMM_CHECK(K >= kWinTiles && K <= kWinTilesMax && (K & (K - 1)) == 0, "plan image: window partial items");
+    } else {
+        for (int64_t w = 0; w < W; ++w) K = std::max<int64_t>(K, (int64_t)P.win_tile_ptr[w + 1] - P.win_tile_ptr[w]);
+    }
+    *win_tiles = (int32_t)std::min<int64_t>(K, INT32_MAX);
     for (int64_t w = 0; w < W; ++w)
         for (int32_t q = P.win_part[w]; q < P.win_part[w + 1]; ++q)
-            SPMM_CHECK(P.wpart_win[q] == w && P.wpart_t0[q] >= P.win_tile_ptr[w] + kWinTiles &&
+            SPMM_CHECK(P.wpart_win[q] == w && P.wpart_t0[q] >= P.win_tile_ptr[w] + K &&
                            P.wpart_t0[q] < P.wpart_t1[q] && P.wpart_t1[q] <= P.win_tile_ptr[w + 1] &&
-                           P.wpart_t1[q] - P.wpart_t0[q] <= kWinTiles,
+                           P.wpart_t1[q] - P.wpart_t0[q] <= K,
                        "plan image: window partial items");
     for (int64_t w = 0; w < W; ++w) {
-        // tiles beyond an owner's first kWinTiles are exactly covered by its partial items
-        int64_t t = P.win_tile_ptr[w] + kWinTiles;
+        // tiles beyond an owner's first K are exactly covered by its partial items
+        int64_t t = P.win_tile_ptr[w] + K;
         for (int32_t q = P.win_part[w]; q < P.win_part[w + 1]; ++q) {
             SPMM_CHECK(P.wpart_t0[q] == t, "plan image: window partial items");
             t = P.wpart_t1[q];
@@ -289,8 +301,10 @@ spmm_status deserialize_host_plan(const uint8_t *buf, size_t size, HostPlan &P, 
         return SPMM_ERR_INVALID;
     }
     Q.identity_rows = ident != 0;
-    spmm_status st = check_plan(Q, err);
+    int32_t win_tiles = kWinTiles;
+    spmm_status st = check_plan(Q, err, &win_tiles);
     if (st != SPMM_OK) return st;
+    Q.win_tiles = win_tiles;
     if (Q.identity_rows != ((int64_t)Q.vector_rows.size() == Q.m)) {
         err = "plan image: identity flag";
         return SPMM_ERR_INVALID;

@@ -113,7 +113,18 @@ def _cmp_plan(A, dump, ref):
     assert np.array_equal(dump["nseg"], ref.nseg)
 
 
-def _check_schedule(A, d, seg_len, pipeline=2):
+def _win_tiles(d, n):
+    """Tiles an owner window item computes, by the scheduling rule: the least
+    power of two in [16, 128] that is at least the plan's tiles times its
+    128-column panels over 1024."""
+    want = -(-d["tile_window"].size * ((n + 127) // 128) // 1024)
+    k = 16
+    while k < 128 and k < want:
+        k *= 2
+    return k
+
+
+def _check_schedule(A, d, seg_len, pipeline=2, n=8):
     m = A.m
     vr = d["vector_rows"]
     ve = d["vexec_rows"]
@@ -149,15 +160,16 @@ def _check_schedule(A, d, seg_len, pipeline=2):
                 sid += d["nseg"][r]
     assert sid == d["seg_row"].size
     assert np.array_equal(np.sort(d["win_order"]), np.arange(d["windows"].shape[0]))
-    # window partial items: tiles beyond a window's first 16, in chunks of 16, in order
+    # window partial items: tiles beyond a window's first K, in chunks of K, in order
+    K = _win_tiles(d, n)
     wt = np.bincount(d["tile_window"], minlength=d["windows"].shape[0])
     tstart = np.concatenate([[0], np.cumsum(wt)])
     k = 0
     for w in range(d["windows"].shape[0]):
         assert d["win_part"][w] == k
-        for t in range(tstart[w] + 16, tstart[w + 1], 16):
+        for t in range(tstart[w] + K, tstart[w + 1], K):
             assert d["wpart_win"][k] == w and d["wpart_t0"][k] == t
-            assert d["wpart_t1"][k] == min(t + 16, tstart[w + 1])
+            assert d["wpart_t1"][k] == min(t + K, tstart[w + 1])
             k += 1
     assert d["win_part"][-1] == k == d["wpart_win"].size
     # every row is owned exactly once
@@ -231,16 +243,34 @@ def test_many_tiles_make_window_partials(lib):
     p = api.Plan(A, 32, "f32", api.default_opts(mode="mfma_only", window_h=16), upload=False)
     d = p.export()
     assert d["wpart_win"].size > 0
-    _check_schedule(A, d, p.stats()["opts"]["seg_len"], p.stats()["opts"]["pipeline"])
+    _check_schedule(A, d, p.stats()["opts"]["seg_len"], p.stats()["opts"]["pipeline"], n=32)
 
 
-def _window_costs(d, kt, h):
-    """Per-window work estimate of the schedule: the owner's tiles (at most 16)
+@pytest.mark.parametrize("n, K", [(128, 32), (256, 64)])
+def test_window_items_grow_with_the_tile_count(lib, n, K):
+    """A plan of 32,768 tiles: window items of K tiles (the least power of
+    two in [16, 128] that brings tiles x panels down to about 1024 items);
+    the partial items cover the rest exactly, and a plan image keeps them."""
+    A = synth.random_csr(2048, 8192, 0.5, 12)
+    p = api.Plan(A, n, "bf16", api.default_opts(mode="mfma_only", window_h=16), upload=False)
+    d = p.export()
+    assert d["tile_window"].size == 32768
+    assert _win_tiles(d, n) == K
+    assert d["wpart_win"].size == 128 * (256 // K - 1)
+    _check_schedule(A, d, p.stats()["opts"]["seg_len"], p.stats()["opts"]["pipeline"], n=n)
+    q = api.Plan.deserialize(p.serialize(), upload=False)
+    dq = q.export()
+    for key in ("win_part", "wpart_win", "wpart_t0", "wpart_t1", "win_order"):
+        assert np.array_equal(d[key], dq[key]), key
+
+
+def _window_costs(d, kt, h, n):
+    """Per-window work estimate of the schedule: the owner's tiles (at most K)
     times kt, H per partial item, and 4 + entries (or segments) per row."""
     nw = d["windows"].shape[0]
     wt = np.bincount(d["tile_window"], minlength=nw)
     rem_len = np.diff(d["rem_ptr"])
-    cost = np.minimum(wt, 16) * kt + np.diff(d["win_part"]) * h
+    cost = np.minimum(wt, _win_tiles(d, n)) * kt + np.diff(d["win_part"]) * h
     for w in range(nw):
         for r in d["windows"][w]:
             if r >= 0:
@@ -260,13 +290,13 @@ def test_window_launch_order(lib, sched):
     if sched == 0:
         assert np.array_equal(d["win_order"], np.arange(nw))
     else:
-        cost = _window_costs(d, ro["kt"], ro["window_h"])
+        cost = _window_costs(d, ro["kt"], ro["window_h"], 64)
         c = cost[d["win_order"]]
         assert np.all(np.diff(c) <= 0) and np.unique(c).size > 1
         # stable: equal costs keep window id order
         same = np.diff(c) == 0
         assert np.all(np.diff(d["win_order"])[same] > 0)
-    _check_schedule(A, d, ro["seg_len"], ro["pipeline"])
+    _check_schedule(A, d, ro["seg_len"], ro["pipeline"], n=64)
 
 
 @pytest.mark.parametrize("pipeline", [2, 3])
