@@ -643,7 +643,7 @@ def main():
     ap.add_argument("--large-ms", type=float, default=1.0,
                     help="serving: requests estimated above this many ms run alone (spmm_run)")
     ap.add_argument("--large-streams", type=int, default=None,
-                    help="serving: streams that may run large requests at once (default half)")
+                    help="serving: streams that may run large requests at once (default 1)")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--batch-tune-ms", type=float, default=60.0,

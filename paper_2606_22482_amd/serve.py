@@ -20,7 +20,9 @@ arrive on a Poisson clock.  The scheduler:
   ``est_rate`` bytes/s) runs alone, as an ``spmm_run`` (one workgroup per
   item, so the device interleaves other streams' work with it, which the
   persistent batched kernels would lock out), on at most ``large_streams``
-  streams at once (half of them by default), so small requests always have a
+  streams at once (one by default: measured at 0.7x saturation with four
+  streams, two large streams left small requests a p99 of 13.5 ms against
+  5.6 ms with one, for 3% less throughput), so small requests always have a
   stream; small ones batch together
   (up to ``max_batch``), overtaking large ones that wait for a stream;
 * polls tickets (an event for a large request) and retires finished
@@ -182,7 +184,7 @@ class Server:
         self.used = 0
         self.large_ms = large_ms
         # streams that may run a large request at once (at least one stays for small ones)
-        self.large_streams = max(1, min(n_streams - 1, n_streams // 2 if large_streams is None
+        self.large_streams = max(1, min(n_streams - 1, 1 if large_streams is None
                                         else large_streams)) if n_streams > 1 else 1
         self.large_bytes = large_ms * 1e-3 * est_rate
 

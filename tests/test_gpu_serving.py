@@ -120,7 +120,7 @@ def test_device_mask_pool_mix_equals_solo_and_oracle():
 
 def test_large_requests_run_alone_and_small_ones_keep_a_stream(pool):
     """With every request classed large (threshold 0), each request runs
-    alone (as a run, on at most half the streams at once); results equal the
+    alone (as a run, on one stream at a time by default); results equal the
     solo runs.  With no request large the classes do not change the results."""
     import torch
     reqs = synth.serving_requests(24, len(pool), 4, seed=12, rate=None)
