@@ -133,6 +133,31 @@ def test_timed_run_reports_both_paths(cases):
     exact(C, A, B, bk)
 
 
+def test_window_only_plan_runs_the_window_kernel():
+    """A mixed plan whose rows all sit in windows without partial items (the
+    block-community shape): every execution form launches the window kernel
+    alone and gives the serial form's C bit for bit, within tolerance of the
+    oracle."""
+    import torch
+    A, B = synth.block_community(n=4096, band=4, n_cols=64, seed=3)
+    Bd = device_B(B, "bf16")
+    ref = None
+    for ex in EXECS:
+        p = api.Plan(A, 64, "bf16", api.default_opts(mode="mixed", exec=ex))
+        st = p.stats()
+        assert st["vector_items"] == 0 and st["segments"] == 0 and st["tiles"] > 0
+        C = device_C(A.m, 64)
+        t = api.Timer(4)
+        p.run_timed(Bd, C, t)
+        torch.cuda.synchronize()
+        assert [name for name, _ in t.read()] == ["window"], ex
+        if ref is None:
+            ref = C.clone()
+            parity(C, A, B, "bf16", TOL_16)
+        else:
+            assert torch.equal(C, ref), ex
+
+
 def test_graph_capture_replays_match_eager(cases):
     """A co-scheduled run (fork to the second stream and join) captured in a
     graph: each replay, with eager work and synchronisations in between,
