@@ -242,3 +242,33 @@ def test_narrow_panels_bitwise_across_forms_and_batch(n):
         for C in outs[1:] + [Cb]:
             assert torch.equal(outs[0], C), (n, bk)
         exact(outs[0], A, B, bk)
+
+
+@pytest.mark.parametrize("n", [128, 256])
+def test_large_window_items_bitwise_across_forms_and_batch(n):
+    """A plan of 32,768 tiles, whose window items take 32 (N = 128) or 64
+    (N = 256) tiles each with the rest in partial items: every execution form
+    and the batched kernels give C bitwise equal, integer-exact against the
+    oracle."""
+    import torch
+    A = synth.random_csr(2048, 8192, 0.5, 12, val_kind="bf16", int_values=(-2, 2))
+    B = synth.int_dense(19, (A.k, n), -4, 4, kind="bf16")
+    Bd = device_B(B, "bf16")
+    opts = dict(mode="mfma_only", window_h=16)
+    outs = []
+    for ex in EXECS:
+        print("large window items n", n, "exec", ex, flush=True)
+        p = api.Plan(A, n, "bf16", api.default_opts(exec=ex, **opts))
+        d = p.export()
+        assert d["tile_window"].size == 32768
+        assert d["wpart_win"].size == 128 * (256 // (32 if n == 128 else 64) - 1)
+        C = device_C(A.m, n)
+        p.run(Bd, C)
+        torch.cuda.synchronize()
+        outs.append(C)
+    p = api.Plan(A, n, "bf16", api.default_opts(**opts))
+    Cb = device_C(A.m, n)
+    api.spmm_wait(api.spmm_submit([api.WorkItem(p, Bd, Cb)]))
+    for C in outs[1:] + [Cb]:
+        assert torch.equal(outs[0], C), n
+    exact(outs[0], A, B, "bf16")
