@@ -66,6 +66,23 @@ def test_block_community_262144(mode):
     print("block", mode, err, flush=True)
 
 
+@pytest.mark.parametrize("mode", ["mixed", "plain"])
+def test_attention_mask_32768(mode):
+    """The attention-mask workload as bench.py times it: 32,768 rows, 124 M
+    entries, N = 256 bf16; mixed with 64-row windows whose items take 128
+    tiles (no partial item), or plain."""
+    import numpy as np
+    A = synth.attention_mask(32768, seed=3, val_kind="bf16")
+    B = synth.dense_values(np.random.default_rng(11), (A.k, 256), "bf16")
+    kw = dict(mode=mode)
+    if mode == "mixed":
+        kw.update(row_order="original_ranges", window_h=64)
+    p, err = run_sampled(A, B, "bf16", api.default_opts(**kw), TOL_16 if mode == "mixed" else TOL_F32)
+    if mode == "mixed":
+        assert p.stats()["nnz_tiles"] > 0.99 * A.nnz and p.export()["wpart_win"].size == 0
+    print("mask", mode, err, flush=True)
+
+
 def test_batch_512_uneven():
     """All 512 matrices in one submission (as bench.py times it); sampled rows
     of every 16th matrix against the oracle, and one matrix against its solo
