@@ -78,10 +78,13 @@ void resolve_options(const spmm_opts *in, const spmm_csr *A, int32_t n, int32_t 
     if (d.item_cost <= 0) {
         double total = (double)(A ? A->nnz : 0) + (double)kRowCost * (double)(A ? A->m : 0);
         // about 2048 items per matrix, so that a matrix run alone (or in a
-        // small batch) still fills the device, with items of 32 to 512
-        // entries (measured on gfx950: larger items lose on the GNN graph and
-        // on the uneven batch, smaller ones lose on both as well)
-        d.item_cost = (int32_t)std::min(512.0, std::max(32.0, total / 2048.0));
+        // small batch) still fills the device, with items of 32 to 256
+        // entries for f32 B and 32 to 512 for 16-bit B (measured on gfx950:
+        // 256-entry items beat 512 on the 2^20-vertex power-law graph, 0.962
+        // vs 0.970 ms at N = 128 and 0.488 vs 0.492 ms at N = 64, 1024 lost;
+        // on the uneven f16 batch 256 lost to 512)
+        const double cap = b_type == SPMM_F32 ? 256.0 : 512.0;
+        d.item_cost = (int32_t)std::min(cap, std::max(32.0, total / 2048.0));
     }
     if (d.xcd_remap < 0) d.xcd_remap = 1;
     // Measured on gfx950: streaming (non-temporal) gathers of cold rows raise the
