@@ -290,6 +290,12 @@ def serve_bench(args):
         if i % 100 == 99:
             log("serving prewarm: %d of %d plans (%.1f s)" % (i + 1, len(keys), time.perf_counter() - t0))
     log("serving prewarm: %d plans (%.1f s)" % (len(keys), time.perf_counter() - t0))
+    # the objects of everything built so far leave the collector's view, so
+    # that a full collection inside a timed pass walks only the serving
+    # loop's own objects (a closed-loop pass takes about 0.15 s)
+    import gc
+    gc.collect()
+    gc.freeze()
     # untimed pass over the closed-loop requests: every stream's run context
     # and batch workspace reach their sizes
     nc = min(len(reqs), args.closed_loop)
@@ -298,9 +304,18 @@ def serve_bench(args):
         % (warm["completed"], warm["wall_s"], warm["plan_builds"], warm["plan_evictions"]))
     # the saturation rate: the best of three closed-loop passes (a pass takes
     # a fraction of a second, so one host-side stall would otherwise set it)
-    passes = [srv.run(reqs[:nc], realtime=False).summary() for _ in range(3)]
+    import torch
+
+    def mem():
+        ms = torch.cuda.memory_stats()
+        return "alloc retries %d, reserved %.1f GB" % (ms.get("num_alloc_retries", 0),
+                                                       ms.get("reserved_bytes.all.current", 0) / 1e9)
+    log("serving memory after warm-up: %s" % mem())
+    passes = []
+    for _ in range(3):
+        passes.append(srv.run(reqs[:nc], realtime=False).summary())
+        log("closed-loop pass: %.1f req/s (%s)" % (passes[-1]["throughput_req_s"], mem()))
     closed = max(passes, key=lambda x: x["throughput_req_s"])
-    log("closed-loop passes: %s req/s" % [round(x["throughput_req_s"], 1) for x in passes])
     rate = 0.7 * closed["throughput_req_s"]
     log("closed loop: %.1f req/s -> rate %.1f req/s (%.2f s, %d plan builds, %d evictions, mean batch "
         "%.2f, max queue %d)" % (closed["throughput_req_s"], rate, closed["wall_s"], closed["plan_builds"],
@@ -310,6 +325,8 @@ def serve_bench(args):
     for k in sorted({(d["matrix"], d["n"], d["b_kind"]) for d in timed} - set(keys)):
         srv.plans.get(k, st)
     s = srv.run(timed, realtime=True).summary()
+    log("serving memory after the timed run: %s" % mem())
+    gc.unfreeze()
     log("serving: p50 %.3f ms, p99 %.3f ms, %.0f req/s, %.0f GFLOP/s; %d large (p50 %.3f, p99 %.3f "
         "ms), small p50 %.3f, p99 %.3f ms"
         % (s["p50_ms"], s["p99_ms"], s["throughput_req_s"], s["gflops"], s["large"],
