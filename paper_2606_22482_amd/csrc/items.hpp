@@ -1292,25 +1292,40 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
 #pragma unroll
         for (int j = 0; j < NBW; ++j) acc[mb][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    auto round = [&](auto first_tag, int tc0) {
-        constexpr bool FIRST = decltype(first_tag)::value;
-        const int nt = min(TC, t1 - tc0);
-        // level 2: tile columns, bitmap words, value offsets, row ranges
+    // level 2 of a round: the tile columns of this thread's staging chunks,
+    // and the bitmap words and value offsets of the tile this wave expands
+    // (wave w expands tile w of the round).  The next round's are loaded
+    // alongside this round's staging loads, so a round after the first
+    // starts with its tile values and B rows.
+    struct RoundMeta {
         int colr[PER];
+        uint32_t wrd[MB];
+        int tv, vend;
+    };
+    auto fetch_meta = [&](int tc0, RoundMeta &m) {
+        const int nt = min(TC, t1 - tc0);
 #pragma unroll
         for (int it = 0; it < PER; ++it) {
             const int kr = (tid + it * 256) / NCH;
             const int c = P.tile_cols[(int64_t)tc0 * 32 + min(kr, nt * 32 - 1)];
-            colr[it] = kr < nt * 32 ? c : -1;
+            m.colr[it] = kr < nt * 32 ? c : -1;
         }
-        // wave w expands tile w of the round: lane (r, q) = (lane / 4, lane % 4)
-        // takes columns 8q .. 8q+7 of rows r, r + 16, .. of the tile
-        const int wv = min(wave, nt - 1), q4 = lane & 3;
-        const int vend = P.tile_val_ptr[tc0 + nt];
-        const int tv = P.tile_val_ptr[tc0 + wv];
-        uint32_t wrd[MB];
+        const int wv = min(wave, nt - 1);
+        m.vend = P.tile_val_ptr[tc0 + nt];
+        m.tv = P.tile_val_ptr[tc0 + wv];
 #pragma unroll
-        for (int rp = 0; rp < MB; ++rp) wrd[rp] = P.tile_bitmap[(int64_t)(tc0 + wv) * H + rp * 16 + (lane >> 2)];
+        for (int rp = 0; rp < MB; ++rp) m.wrd[rp] = P.tile_bitmap[(int64_t)(tc0 + wv) * H + rp * 16 + (lane >> 2)];
+    };
+
+    auto round = [&](auto first_tag, int tc0, const RoundMeta &m, RoundMeta &next) {
+        constexpr bool FIRST = decltype(first_tag)::value;
+        const int nt = min(TC, t1 - tc0);
+        const int(&colr)[PER] = m.colr;
+        const uint32_t(&wrd)[MB] = m.wrd;
+        const int tv = m.tv, vend = m.vend;
+        // lane (r, q) = (lane / 4, lane % 4) of wave w takes columns
+        // 8q .. 8q+7 of rows r, r + 16, .. of tile w
+        const int q4 = lane & 3;
         int bm_ = 0, em_ = 0;
         if constexpr (FIRST) {
             bm_ = P.rem_ptr[max(rm, 0)];
@@ -1429,6 +1444,8 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
                         u32x4{w[q][0], w[q][1], w[q][2], w[q][3]};
             }
         }
+        // the next round's level 2, in flight with this round's staging
+        if (tc0 + TC < t1) fetch_meta(tc0 + TC, next);
         // LDS: expanded tiles (tile w, row r, columns 8q ..: 16 bytes at
         // ((w H + r) 32 + 8q) elements), row metadata
         if (wave < nt) {
@@ -1496,10 +1513,13 @@ __device__ __forceinline__ void window_item(const DevPlan &P, const RunArgs &a, 
         return q1;
     };
     // a valid plan gives every window and partial item at least one tile
-    const int q1 = round(std::true_type{}, t0);
+    RoundMeta cur, nxt;
+    fetch_meta(t0, cur);
+    const int q1 = round(std::true_type{}, t0, cur, nxt);
     for (int tc0 = t0 + TC; tc0 < t1; tc0 += TC) {
         __syncthreads();  // the previous round's LDS reads are done
-        (void)round(std::false_type{}, tc0);
+        cur = nxt;
+        (void)round(std::false_type{}, tc0, cur, nxt);
     }
     // fused: the window's slot when its result needs other items' parts
     const int dep = FUSED ? P.win_dep[wi] : -1;
