@@ -101,14 +101,18 @@ struct BatchHeader {
     int32_t x_entry[9], x_seg[9], x_vec[9], x_win[9], x_wpart[9];
 };
 
+// Workgroup counts of the batched kernels: segment kernel, vector kernel and
+// the two window kernels (partial items, then owners).
+struct BatchGrids {
+    unsigned seg = 0, vec = 0, win = 0;
+};
 // Persistent batched launches over a device table (header + entries).
-// `grid_*` are the workgroup counts of the three kernels.
 hipError_t launch_batch(const BatchHeader *hdr, const BatchEntry *tab, int32_t val_t, int32_t b_t,
-                        int32_t tile_t, int vec_ok, int cpl, int var, unsigned grid_wave,
-                        unsigned grid_win, hipStream_t s);
-// Resident workgroups per CU of the batched kernels of this variant.
+                        int32_t tile_t, int vec_ok, int cpl, int var, const BatchGrids &grids,
+                        hipStream_t s);
+// Resident workgroups per CU of each batched kernel of this variant.
 hipError_t batch_occupancy(int32_t val_t, int32_t b_t, int32_t tile_t, int vec_ok, int cpl,
-                           int var, int *wave_kernels, int *win_kernel);
+                           int var, BatchGrids *per_cu);
 
 // dtype codes as in spmm.h
 hipError_t launch_segment(const DevPlan &P, int32_t val_t, int32_t b_t, const RunArgs &a,

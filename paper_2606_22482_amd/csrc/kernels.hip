@@ -244,69 +244,73 @@ hipError_t launch_window_partial(const DevPlan &P, int32_t vt, int32_t bt, int32
 }
 
 template <int VT, int BT, int TT, int E, int CPL, int VAR>
-static hipError_t batch_variant(const BatchHeader *hdr, const BatchEntry *tab, unsigned gw,
-                                unsigned gwin, hipStream_t s, int *occ_wave, int *occ_win) {
-    if (occ_wave) {
+static hipError_t batch_variant(const BatchHeader *hdr, const BatchEntry *tab, const BatchGrids &g,
+                                hipStream_t s, BatchGrids *occ) {
+    if (occ) {
+        int o = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            occ_wave, batch_vector_kernel<VT, BT, E, CPL, VAR>, 256, 0);
+            &o, batch_segment_kernel<VT, BT, E, CPL, VAR == 0>, 256, 0);
         if (e != hipSuccess) return e;
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            occ_win, batch_window_kernel<VT, BT, TT, E, CPL, false>, 256, 0);
+        occ->seg = (unsigned)o;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, batch_vector_kernel<VT, BT, E, CPL, VAR>, 256, 0);
+        if (e != hipSuccess) return e;
+        occ->vec = (unsigned)o;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &o, batch_window_kernel<VT, BT, TT, E, CPL, false>, 256, 0);
+        occ->win = (unsigned)o;
+        return e;
     }
     // phase 1: partial sums (segments, window tile chunks); phase 2: owners
-    hipLaunchKernelGGL((batch_segment_kernel<VT, BT, E, CPL, VAR == 0>), dim3(gw), dim3(256), 0, s, hdr, tab);
-    hipLaunchKernelGGL((batch_window_kernel<VT, BT, TT, E, CPL, true>), dim3(gwin), dim3(256), 0, s,
+    hipLaunchKernelGGL((batch_segment_kernel<VT, BT, E, CPL, VAR == 0>), dim3(g.seg), dim3(256), 0, s, hdr, tab);
+    hipLaunchKernelGGL((batch_window_kernel<VT, BT, TT, E, CPL, true>), dim3(g.win), dim3(256), 0, s,
                        hdr, tab);
-    hipLaunchKernelGGL((batch_vector_kernel<VT, BT, E, CPL, VAR>), dim3(gw), dim3(256), 0, s, hdr, tab);
-    hipLaunchKernelGGL((batch_window_kernel<VT, BT, TT, E, CPL, false>), dim3(gwin), dim3(256), 0,
+    hipLaunchKernelGGL((batch_vector_kernel<VT, BT, E, CPL, VAR>), dim3(g.vec), dim3(256), 0, s, hdr, tab);
+    hipLaunchKernelGGL((batch_window_kernel<VT, BT, TT, E, CPL, false>), dim3(g.win), dim3(256), 0,
                        s, hdr, tab);
     return hipGetLastError();
 }
 
 template <int VT, int BT, int TT, int VAR>
 static hipError_t batch_types_var(const BatchHeader *hdr, const BatchEntry *tab, int vec_ok,
-                                  int cpl, unsigned gw, unsigned gwin, hipStream_t s, int *ow,
-                                  int *oc) {
+                                  int cpl, const BatchGrids &g, hipStream_t s, BatchGrids *occ) {
     constexpr int EV = BT == DT_F32 ? 4 : 8;
-    if (!vec_ok) return batch_variant<VT, BT, TT, 1, 2, VAR>(hdr, tab, gw, gwin, s, ow, oc);
-    if (cpl == 1) return batch_variant<VT, BT, TT, EV, 1, VAR>(hdr, tab, gw, gwin, s, ow, oc);
-    return batch_variant<VT, BT, TT, EV, 2, VAR>(hdr, tab, gw, gwin, s, ow, oc);
+    if (!vec_ok) return batch_variant<VT, BT, TT, 1, 2, VAR>(hdr, tab, g, s, occ);
+    if (cpl == 1) return batch_variant<VT, BT, TT, EV, 1, VAR>(hdr, tab, g, s, occ);
+    return batch_variant<VT, BT, TT, EV, 2, VAR>(hdr, tab, g, s, occ);
 }
 
 template <int VT, int BT, int TT>
 static hipError_t batch_types(const BatchHeader *hdr, const BatchEntry *tab, int vec_ok, int cpl,
-                              int var, unsigned gw, unsigned gwin, hipStream_t s, int *ow, int *oc) {
-    if (var == 3) return batch_types_var<VT, BT, TT, 3>(hdr, tab, vec_ok, cpl, gw, gwin, s, ow, oc);
-    if (var == 2) return batch_types_var<VT, BT, TT, 2>(hdr, tab, vec_ok, cpl, gw, gwin, s, ow, oc);
-    if (var == 1) return batch_types_var<VT, BT, TT, 1>(hdr, tab, vec_ok, cpl, gw, gwin, s, ow, oc);
-    return batch_types_var<VT, BT, TT, 0>(hdr, tab, vec_ok, cpl, gw, gwin, s, ow, oc);
+                              int var, const BatchGrids &g, hipStream_t s, BatchGrids *occ) {
+    if (var == 3) return batch_types_var<VT, BT, TT, 3>(hdr, tab, vec_ok, cpl, g, s, occ);
+    if (var == 2) return batch_types_var<VT, BT, TT, 2>(hdr, tab, vec_ok, cpl, g, s, occ);
+    if (var == 1) return batch_types_var<VT, BT, TT, 1>(hdr, tab, vec_ok, cpl, g, s, occ);
+    return batch_types_var<VT, BT, TT, 0>(hdr, tab, vec_ok, cpl, g, s, occ);
 }
 
 static hipError_t batch_any(const BatchHeader *hdr, const BatchEntry *tab, int32_t vt, int32_t bt,
-                            int32_t tt, int vec_ok, int cpl, int var, unsigned gw, unsigned gwin,
-                            hipStream_t s, int *ow, int *oc) {
+                            int32_t tt, int vec_ok, int cpl, int var, const BatchGrids &g,
+                            hipStream_t s, BatchGrids *occ) {
     if (vt == DT_F32 && bt == DT_F32 && tt == DT_BF16)
-        return batch_types<DT_F32, DT_F32, DT_BF16>(hdr, tab, vec_ok, cpl, var, gw, gwin, s, ow, oc);
+        return batch_types<DT_F32, DT_F32, DT_BF16>(hdr, tab, vec_ok, cpl, var, g, s, occ);
     if (vt == DT_F32 && bt == DT_BF16 && tt == DT_BF16)
-        return batch_types<DT_F32, DT_BF16, DT_BF16>(hdr, tab, vec_ok, cpl, var, gw, gwin, s, ow, oc);
+        return batch_types<DT_F32, DT_BF16, DT_BF16>(hdr, tab, vec_ok, cpl, var, g, s, occ);
     if (vt == DT_BF16 && bt == DT_BF16 && tt == DT_BF16)
-        return batch_types<DT_BF16, DT_BF16, DT_BF16>(hdr, tab, vec_ok, cpl, var, gw, gwin, s, ow, oc);
+        return batch_types<DT_BF16, DT_BF16, DT_BF16>(hdr, tab, vec_ok, cpl, var, g, s, occ);
     if (vt == DT_F16 && bt == DT_F16 && tt == DT_F16)
-        return batch_types<DT_F16, DT_F16, DT_F16>(hdr, tab, vec_ok, cpl, var, gw, gwin, s, ow, oc);
+        return batch_types<DT_F16, DT_F16, DT_F16>(hdr, tab, vec_ok, cpl, var, g, s, occ);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_batch(const BatchHeader *hdr, const BatchEntry *tab, int32_t vt, int32_t bt,
-                        int32_t tt, int vec_ok, int cpl, int var, unsigned grid_wave,
-                        unsigned grid_win, hipStream_t s) {
-    return batch_any(hdr, tab, vt, bt, tt, vec_ok, cpl, var, grid_wave, grid_win, s, nullptr,
-                     nullptr);
+                        int32_t tt, int vec_ok, int cpl, int var, const BatchGrids &grids,
+                        hipStream_t s) {
+    return batch_any(hdr, tab, vt, bt, tt, vec_ok, cpl, var, grids, s, nullptr);
 }
 
 hipError_t batch_occupancy(int32_t vt, int32_t bt, int32_t tt, int vec_ok, int cpl, int var,
-                           int *wave_kernels, int *win_kernel) {
-    return batch_any(nullptr, nullptr, vt, bt, tt, vec_ok, cpl, var, 0, 0, nullptr, wave_kernels,
-                     win_kernel);
+                           BatchGrids *per_cu) {
+    return batch_any(nullptr, nullptr, vt, bt, tt, vec_ok, cpl, var, BatchGrids{}, nullptr, per_cu);
 }
 
 hipError_t launch_copy(const float4 *src, float4 *dst, int64_t n4, hipStream_t s) {

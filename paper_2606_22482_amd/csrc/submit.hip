@@ -59,11 +59,13 @@ void retire(std::map<spmm_ticket, std::shared_ptr<Ticket>>::iterator it) {
 
 namespace {
 
+constexpr unsigned kBatchSegPerCu = 3;
+
 struct VariantGraph {
     void *dtab = nullptr;  // BatchHeader (padded to 256 B) followed by entries
     size_t dcap = 0;
     hipGraphExec_t exec = nullptr;
-    unsigned grid_wave = 0, grid_win = 0;
+    BatchGrids grids;
 };
 
 struct BatchCtx {
@@ -307,17 +309,25 @@ extern "C" spmm_status spmm_submit(const spmm_work *items, int32_t count, void *
             if (st != SPMM_OK) return st;
         }
         if (!vg.exec) {
-            int ow = 0, oc = 0;
-            SPMM_TRY_HIP(batch_occupancy(vt, bt, tt, vec_ok, cpl, var, &ow, &oc), "occupancy");
-            // a multiple of 8 so that every XCD gets the same number of workgroups
-            vg.grid_wave = std::max(8u, ((unsigned)std::max(1, ow) * (unsigned)ncu) & ~7u);
-            vg.grid_win = std::max(8u, ((unsigned)std::max(1, oc) * (unsigned)ncu) & ~7u);
+            BatchGrids occ;
+            SPMM_TRY_HIP(batch_occupancy(vt, bt, tt, vec_ok, cpl, var, &occ), "occupancy");
+            // each kernel's grid is its resident workgroups per CU times the CUs,
+            // in a multiple of 8 so that every XCD gets the same number; the
+            // segment kernel takes at most 3 per CU, its fastest measured grid
+            // (512 uneven f16 matrices: 1.72 / 1.40 / 1.43 / 1.56 / 1.64 ms at
+            // 2 / 3 / 4 / 5 / 8 per CU, where it had shared the vector kernel's
+            // 5; the vector kernel at 4 per CU, or at 6 with fewer registers,
+            // was slower than at its own 5)
+            auto fill = [&](unsigned per_cu) { return std::max(8u, (std::max(1u, per_cu) * (unsigned)ncu) & ~7u); };
+            vg.grids.seg = fill(std::min(occ.seg, kBatchSegPerCu));
+            vg.grids.vec = fill(occ.vec);
+            vg.grids.win = fill(occ.win);
             if (!ctx.capture)
                 SPMM_TRY_HIP(hipStreamCreateWithFlags(&ctx.capture, hipStreamNonBlocking), "hipStreamCreate");
             const auto *dh = static_cast<const BatchHeader *>(vg.dtab);
             const auto *dt = reinterpret_cast<const BatchEntry *>(static_cast<uint8_t *>(vg.dtab) + kHeaderBytes);
             SPMM_TRY_HIP(hipStreamBeginCapture(ctx.capture, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-            hipError_t le = launch_batch(dh, dt, vt, bt, tt, vec_ok, cpl, var, vg.grid_wave, vg.grid_win, ctx.capture);
+            hipError_t le = launch_batch(dh, dt, vt, bt, tt, vec_ok, cpl, var, vg.grids, ctx.capture);
             hipGraph_t graph = nullptr;
             hipError_t ce = hipStreamEndCapture(ctx.capture, &graph);
             if (le != hipSuccess) return hip_error(le, "batched launch (capture)");
