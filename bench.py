@@ -554,15 +554,17 @@ def measure(wkey, args, modes, extra=None):
                 if not ast.replanned:
                     break
             st = plan.stats()
+        # runs on `stream` given explicitly: a run without one asks torch for
+        # its current stream, which builds a stream object per call
         for _ in range(args.warmup):
-            plan.run(Bd, Cd)
+            plan.run(Bd, Cd, stream)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         # the step time: plain runs, as a caller makes them
         e0.record(stream)
         for _ in range(args.steps):
-            plan.run(Bd, Cd)
+            plan.run(Bd, Cd, stream)
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / args.steps
@@ -571,7 +573,7 @@ def measure(wkey, args, modes, extra=None):
         timer = api.Timer(capacity=8 * args.steps + 8)
         e0.record(stream)
         for _ in range(args.steps):
-            plan.run_timed(Bd, Cd, timer)
+            plan.run_timed(Bd, Cd, timer, stream)
         e1.record(stream)
         torch.cuda.synchronize()
         ms_timed = e0.elapsed_time(e1) / args.steps
